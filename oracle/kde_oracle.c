@@ -1,0 +1,343 @@
+/*
+ * kde_oracle.c -- plain FP64 reference for exact KDE bandwidth-selection sums.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU library is
+ * compared against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg load it; the library never links, calls or falls back to it.
+ * It shares no code, header, table or constant with the GPU path.
+ *
+ * Source: Andrzejewski, Gramacki, Gramacki, "Density Estimations for
+ * Approximate Query Processing on SIMD Architectures" (arXiv 1505.01998),
+ * Section 4.4 (formulas for bandwidth selection).  Every function below cites
+ * the equation it writes out.  Sums are exact FP64 sums written as plain loops:
+ * each row i of the pair triangle (j > i) is summed in FP64, and the row sums
+ * are combined by Neumaier compensated summation in row order, so the result
+ * does not depend on the thread count.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled):
+ *  - psi-hat normalisation: the n*K^(r)(0) diagonal term is inside the
+ *    1/(n^2 g^(r+1)) factor, i.e. psi_r(g) = n^-2 sum_{i,j} K^(r)_g(X_i-X_j).
+ *  - LSCV_h in one dimension is written in data units: the kernel at h is
+ *    N(0, h^2); R(K) = (4 pi)^(-1/2).  (The paper works in sphered units; the
+ *    two are related by g_data(sigma*h) = g_sphered(h) / sigma.)
+ *  - variance: two-pass form, equal in exact arithmetic to the one-pass form
+ *    of eq. (PLUGIN-VarianceEstimator), same n-1 denominator.
+ *  - K^(r) for r = 8 (three-stage plug-in) follows from the Hermite recurrence;
+ *    the paper prints only r = 4 and r = 6.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_INVAL 1
+#define ORC_DEGENERATE 2
+#define ORC_NOMEM 3
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* Neumaier's improvement of Kahan summation over v[0..m), in index order. */
+static double neumaier_sum(const double* v, long m) {
+  double s = 0.0, c = 0.0;
+  for (long k = 0; k < m; ++k) {
+    double t = s + v[k];
+    if (fabs(s) >= fabs(v[k]))
+      c += (s - t) + v[k];
+    else
+      c += (v[k] - t) + s;
+    s = t;
+  }
+  return s + c;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
+
+/* Input check: n >= 2 and every sample finite. */
+int orc_validate(const double* x, long n) {
+  if (n < 2 || x == NULL) return ORC_INVAL;
+  for (long i = 0; i < n; ++i)
+    if (!isfinite(x[i])) return ORC_INVAL;
+  return ORC_OK;
+}
+
+/* Sample mean and variance estimator, eq. (PLUGIN-VarianceEstimator) and
+ * (PLUGIN-StdDevEstimator) (also eq. (LSCV-variance) with d = 1).
+ * Two-pass: mean first, then sum of squared deviations over n-1. */
+int orc_moments(const double* x, long n, double* mean, double* var) {
+  int st = orc_validate(x, n);
+  if (st) return st;
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!tmp) return ORC_NOMEM;
+  memcpy(tmp, x, sizeof(double) * (size_t)n);
+  double m = neumaier_sum(tmp, n) / (double)n;
+  for (long i = 0; i < n; ++i) tmp[i] = (x[i] - m) * (x[i] - m);
+  double v = neumaier_sum(tmp, n) / (double)(n - 1);
+  free(tmp);
+  *mean = m;
+  *var = v;
+  return ORC_OK;
+}
+
+/* Normal-reference bandwidth.  With d = 1, eq. (LSCV-H-start) gives
+ * h = (4/3)^(1/5) n^(-1/5) sigma, the same value as sigma * h0 of
+ * eq. (LSCV-h0). */
+int orc_rot(const double* x, long n, double* sigma_out, double* h_out) {
+  double m, v;
+  int st = orc_moments(x, n, &m, &v);
+  if (st) return st;
+  double s = sqrt(v);
+  if (!(s > 0.0)) return ORC_DEGENERATE;
+  *sigma_out = s;
+  *h_out = pow(4.0 / 3.0, 0.2) * pow((double)n, -0.2) * s;
+  return ORC_OK;
+}
+
+/* Probabilists' Hermite polynomial He_r(u) by the three-term recurrence
+ * He_{k+1}(u) = u He_k(u) - k He_{k-1}(u), He_0 = 1, He_1 = u.
+ * K^(r)(u) = He_r(u) phi(u) for the Gaussian kernel; the paper prints
+ * He_6 with eq. (PLUGIN-Psi6Estimate) and He_4 with eq. (PLUGIN-Psi4Estimate). */
+double orc_hermite_e(int r, double u) {
+  double a = 1.0, b = u;
+  if (r == 0) return a;
+  for (int k = 1; k < r; ++k) {
+    double c = u * b - (double)k * a;
+    a = b;
+    b = c;
+  }
+  return b;
+}
+
+/* r-th derivative of the standard normal density K at u. */
+double orc_kernel_deriv(int r, double u) {
+  return orc_hermite_e(r, u) * exp(-0.5 * u * u) / sqrt(2.0 * ORC_PI);
+}
+
+/* Pair sum of K^(r)((X_i - X_j)/g) over i < j, and of its absolute value.
+ * This is the double sum of eq. (PLUGIN-Psi6Estimate)/(PLUGIN-Psi4Estimate). */
+int orc_pair_sum_kr(const double* x, long n, int r, double g, double* sum_out, double* abs_out) {
+  int st = orc_validate(x, n);
+  if (st) return st;
+  if (!(g > 0.0) || !isfinite(g)) return ORC_INVAL;
+  double* rs = (double*)malloc(sizeof(double) * (size_t)n);
+  double* ra = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!rs || !ra) { free(rs); free(ra); return ORC_NOMEM; }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < n; ++i) {
+    double s = 0.0, a = 0.0;
+    for (long j = i + 1; j < n; ++j) {
+      double t = orc_kernel_deriv(r, (x[i] - x[j]) / g);
+      s += t;
+      a += fabs(t);
+    }
+    rs[i] = s;
+    ra[i] = a;
+  }
+  *sum_out = neumaier_sum(rs, n);
+  *abs_out = neumaier_sum(ra, n);
+  free(rs);
+  free(ra);
+  return ORC_OK;
+}
+
+/* Functional estimate psi_r(g) = [2 sum_{i<j} K^(r)((X_i-X_j)/g) + n K^(r)(0)]
+ *                               / (n^2 g^(r+1)),
+ * eq. (PLUGIN-Psi6Estimate) (r = 6) and (PLUGIN-Psi4Estimate) (r = 4), read
+ * with the diagonal term inside the normalisation.  kappa = sum|t| / |sum t|
+ * over the pair terms (the condition number of the pair sum). */
+int orc_psi(const double* x, long n, int r, double g, double* psi_out, double* kappa_out,
+            double* pair_sum_out, double* pair_abs_out) {
+  double s, a;
+  int st = orc_pair_sum_kr(x, n, r, g, &s, &a);
+  if (st) return st;
+  double nn = (double)n;
+  *psi_out = (2.0 * s + nn * orc_kernel_deriv(r, 0.0)) / (nn * nn * pow(g, r + 1));
+  if (kappa_out) *kappa_out = (s != 0.0) ? a / fabs(s) : INFINITY;
+  if (pair_sum_out) *pair_sum_out = s;
+  if (pair_abs_out) *pair_abs_out = a;
+  return ORC_OK;
+}
+
+/* Normal-scale functional psi_r^NS = (-1)^(r/2) r! / ((2 sigma)^(r+1) (r/2)! sqrt(pi)),
+ * the value of psi_r for N(0, sigma^2); r = 8 gives eq. (PLUGIN-Psi8Estimate). */
+double orc_psi_ns(int r, double sigma) {
+  double num = 1.0, den = 1.0;
+  for (int k = 2; k <= r; ++k) num *= (double)k;
+  for (int k = 2; k <= r / 2; ++k) den *= (double)k;
+  double sgn = ((r / 2) % 2 == 0) ? 1.0 : -1.0;
+  return sgn * num / (pow(2.0 * sigma, r + 1) * den * sqrt(ORC_PI));
+}
+
+/* AMSE pilot bandwidth for estimating psi_r, given an estimate of psi_{r+2}:
+ * g = [-2 K^(r)(0) / (mu_2(K) psi_{r+2} n)]^(1/(r+3)), mu_2(K) = 1;
+ * eq. (PLUGIN-g1) (r = 6) and (PLUGIN-g2) (r = 4). */
+int orc_pilot(int r, double psi_next, long n, double* g_out) {
+  double rad = -2.0 * orc_kernel_deriv(r, 0.0) / (psi_next * (double)n);
+  if (!(rad > 0.0) || !isfinite(rad)) return ORC_DEGENERATE;
+  *g_out = pow(rad, 1.0 / (double)(r + 3));
+  return ORC_OK;
+}
+
+typedef struct {
+  double sigma, h_rot;
+  int stages;
+  double g[3], psi[3], kappa[3]; /* stage order: psi8, psi6, psi4 */
+  double h;
+} orc_plugin_info;
+
+/* Direct plug-in selector, Section 4.4.1: variance -> normal-scale psi ->
+ * pilot g -> pairwise psi-hat -> ... -> eq. (PLUGIN-Final_h).
+ * stages = 2 is the paper's chain (psi_8 by its normal-scale value, then
+ * pairwise psi_6 and psi_4); stages = 3 starts one level higher (psi_10
+ * normal scale, then pairwise psi_8, psi_6, psi_4).  Unused slots hold NaN. */
+int orc_plugin(const double* x, long n, int stages, orc_plugin_info* info) {
+  if (stages != 2 && stages != 3) return ORC_INVAL;
+  memset(info, 0, sizeof(*info));
+  for (int k = 0; k < 3; ++k) info->g[k] = info->psi[k] = info->kappa[k] = NAN;
+  info->stages = stages;
+  int st = orc_rot(x, n, &info->sigma, &info->h_rot);
+  if (st) return st;
+  double psi_next;
+  if (stages == 3) {
+    double g8;
+    st = orc_pilot(8, orc_psi_ns(10, info->sigma), n, &g8);
+    if (st) return st;
+    info->g[0] = g8;
+    st = orc_psi(x, n, 8, g8, &info->psi[0], &info->kappa[0], NULL, NULL);
+    if (st) return st;
+    psi_next = info->psi[0];
+  } else {
+    psi_next = orc_psi_ns(8, info->sigma);
+    info->psi[0] = psi_next;
+  }
+  double g6, g4;
+  st = orc_pilot(6, psi_next, n, &g6);
+  if (st) return st;
+  info->g[1] = g6;
+  st = orc_psi(x, n, 6, g6, &info->psi[1], &info->kappa[1], NULL, NULL);
+  if (st) return st;
+  st = orc_pilot(4, info->psi[1], n, &g4);
+  if (st) return st;
+  info->g[2] = g4;
+  st = orc_psi(x, n, 4, g4, &info->psi[2], &info->kappa[2], NULL, NULL);
+  if (st) return st;
+  double rk = 1.0 / (2.0 * sqrt(ORC_PI));
+  double rad = rk / (info->psi[2] * (double)n);
+  if (!(rad > 0.0) || !isfinite(rad)) return ORC_DEGENERATE;
+  info->h = pow(rad, 0.2);
+  return ORC_OK;
+}
+
+/* Default LSCV grid: n_h points (150 when n_h <= 0) spaced linearly over
+ * sigma * Z(h0) = sigma * [h0/4, 4 h0], eq. (LSCV-Zh0), with
+ * h0 = (4/(3n))^(1/5), eq. (LSCV-h0) for d = 1. */
+int orc_default_grid(const double* x, long n, int n_h, double* grid_out) {
+  double s, hr;
+  int st = orc_rot(x, n, &s, &hr);
+  if (st) return st;
+  if (n_h <= 0) n_h = 150;
+  double lo = hr / 4.0, hi = 4.0 * hr;
+  for (int k = 0; k < n_h; ++k)
+    grid_out[k] = (n_h == 1) ? lo : lo + (hi - lo) * (double)k / (double)(n_h - 1);
+  return ORC_OK;
+}
+
+/* LSCV objective, eq. (LSCV-gh) with eq. (LSCV-Tx), (LSCV-Kx), (LSCV-KKx), in
+ * data units for d = 1:
+ *   g(h) = h^-1 [ 2 n^-2 sum_{i<j} T((X_i - X_j)/h) + n^-1 R(K) ],
+ *   T(u) = (K*K)(u) - 2 K(u),  K*K = N(0,2) density,  R(K) = (4 pi)^(-1/2).
+ * A = sum (4pi)^(-1/2) exp(-D^2/(4h^2)), B = sum (2pi)^(-1/2) exp(-D^2/(2h^2))
+ * are computed with separate exp calls; g = h^-1 [2 n^-2 (A - 2B) + n^-1 R(K)].
+ * gscale(h) is the same expression with A + 2B: the magnitude g is a
+ * difference of, used to express errors in g relative to its terms.
+ * Optional outputs a_out / b_out receive the pair sums of exp(-D^2/(4h^2)) and
+ * exp(-D^2/(2h^2)) without the constant factors. */
+int orc_lscv_curve(const double* x, long n, const double* grid, int n_h, double* g_out,
+                   double* gscale_out, double* a_out, double* b_out) {
+  int st = orc_validate(x, n);
+  if (st) return st;
+  if (n_h < 1 || grid == NULL) return ORC_INVAL;
+  for (int k = 0; k < n_h; ++k) {
+    if (!(grid[k] > 0.0) || !isfinite(grid[k])) return ORC_INVAL;
+    if (k > 0 && !(grid[k] > grid[k - 1])) return ORC_INVAL;
+  }
+  double* ra = (double*)malloc(sizeof(double) * (size_t)n);
+  double* rb = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!ra || !rb) { free(ra); free(rb); return ORC_NOMEM; }
+  double nn = (double)n;
+  double c_kk = 1.0 / sqrt(4.0 * ORC_PI), c_k = 1.0 / sqrt(2.0 * ORC_PI);
+  for (int k = 0; k < n_h; ++k) {
+    double h = grid[k];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < n; ++i) {
+      double sa = 0.0, sb = 0.0;
+      for (long j = i + 1; j < n; ++j) {
+        double d = x[i] - x[j];
+        sa += exp(-d * d / (4.0 * h * h));
+        sb += exp(-d * d / (2.0 * h * h));
+      }
+      ra[i] = sa;
+      rb[i] = sb;
+    }
+    double s1 = neumaier_sum(ra, n), s2 = neumaier_sum(rb, n);
+    double A = c_kk * s1, B = c_k * s2;
+    g_out[k] = (2.0 / (nn * nn) * (A - 2.0 * B) + c_kk / nn) / h;
+    if (gscale_out) gscale_out[k] = (2.0 / (nn * nn) * (A + 2.0 * B) + c_kk / nn) / h;
+    if (a_out) a_out[k] = s1;
+    if (b_out) b_out[k] = s2;
+  }
+  free(ra);
+  free(rb);
+  return ORC_OK;
+}
+
+/* Brute-force grid minimum, eq. (LSCV-finalH): lowest index among equal
+ * minima; at_edge = 1 when it is the first or last grid point; margin is the
+ * gap to the second-smallest value (0 if n_h == 1). */
+int orc_argmin(const double* g, int n_h, int* k_out, int* at_edge, double* margin) {
+  if (n_h < 1) return ORC_INVAL;
+  int kb = 0;
+  for (int k = 1; k < n_h; ++k)
+    if (g[k] < g[kb]) kb = k;
+  double second = INFINITY;
+  for (int k = 0; k < n_h; ++k)
+    if (k != kb && g[k] < second) second = g[k];
+  *k_out = kb;
+  if (at_edge) *at_edge = (kb == 0 || kb == n_h - 1) ? 1 : 0;
+  if (margin) *margin = (n_h > 1) ? second - g[kb] : 0.0;
+  return ORC_OK;
+}
+
+/* LSCV selector: the grid point minimising g(h). */
+int orc_lscv(const double* x, long n, const double* grid, int n_h, double* h_out, int* k_out,
+             int* at_edge) {
+  double* g = (double*)malloc(sizeof(double) * (size_t)(n_h > 0 ? n_h : 1));
+  if (!g) return ORC_NOMEM;
+  int st = orc_lscv_curve(x, n, grid, n_h, g, NULL, NULL, NULL);
+  if (!st) {
+    int k;
+    st = orc_argmin(g, n_h, &k, at_edge, NULL);
+    if (!st) {
+      *h_out = grid[k];
+      if (k_out) *k_out = k;
+    }
+  }
+  free(g);
+  return st;
+}

@@ -1,0 +1,302 @@
+"""Pins for the FP64 oracle against facts other than itself.
+
+Each test checks an oracle function against something the paper prints
+(tests/golden/paper_values.json), a closed form, a library routine (numpy's
+Hermite module, numpy.var, scipy quadrature), an expectation over seeds, or a
+brute-force computation that takes a different route (full n x n matrix
+instead of the i < j triangle).  None of these re-types the oracle's formula.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e as He
+from scipy import integrate
+
+import oracle
+import workloads
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+SQRT2PI = math.sqrt(2.0 * math.pi)
+
+
+def phi(u):
+    return np.exp(-0.5 * np.asarray(u) ** 2) / SQRT2PI
+
+
+def kr_numpy(r, u):
+    """K^(r)(u) = He_r(u) phi(u) through numpy's Hermite_e module."""
+    c = np.zeros(r + 1)
+    c[r] = 1.0
+    return He.hermeval(np.asarray(u, dtype=np.float64), c) * phi(u)
+
+
+# ---------------------------------------------------------------- kernel derivatives
+@pytest.mark.parametrize("r", range(0, 11))
+def test_hermite_matches_numpy(r):
+    c = np.zeros(r + 1)
+    c[r] = 1.0
+    for u in (-3.7, -1.0, -0.3, 0.0, 0.25, 1.5, 2.9, 6.0):
+        ref = He.hermeval(u, c)
+        assert oracle.hermite_e(r, u) == pytest.approx(ref, rel=1e-13, abs=1e-12)
+
+
+@pytest.mark.parametrize("name,r", [("He6_coefficients_high_to_low", 6), ("He4_coefficients_high_to_low", 4)])
+def test_kernel_deriv_matches_printed_polynomial(name, r):
+    coef = GOLD[name]["c"]
+    for u in np.linspace(-5, 5, 41):
+        printed = np.polyval(coef, u) * phi(u)
+        assert oracle.kernel_deriv(r, u) == pytest.approx(printed, rel=1e-12, abs=1e-14)
+
+
+def test_kernel_deriv_at_zero_matches_printed():
+    k6 = GOLD["K6_at_0"]["numerator"] / SQRT2PI
+    k4 = GOLD["K4_at_0"]["numerator"] / SQRT2PI
+    assert oracle.kernel_deriv(6, 0.0) == pytest.approx(k6, rel=1e-15)
+    assert oracle.kernel_deriv(4, 0.0) == pytest.approx(k4, rel=1e-15)
+
+
+@pytest.mark.parametrize("r", [4, 6, 8])
+def test_kernel_deriv_moments(r):
+    """Integration by parts: int u^k phi^(r)(u) du = 0 for k < r and r! for k = r (r even)."""
+    for k in range(0, r + 1):
+        val, _ = integrate.quad(lambda u: u**k * oracle.kernel_deriv(r, u), -40, 40, limit=400)
+        ref = float(math.factorial(r)) if k == r else 0.0
+        assert val == pytest.approx(ref, abs=1e-8 * max(1.0, ref))
+
+
+# ---------------------------------------------------------------- moments and rule of thumb
+@pytest.mark.parametrize("family", ["normal", "lognormal", "uniform"])
+def test_moments_match_numpy(family):
+    x = workloads.draw(family, 5003, 11, np.float64)
+    m, v = oracle.moments(x)
+    assert m == pytest.approx(float(np.mean(x)), rel=1e-14, abs=1e-15)
+    assert v == pytest.approx(float(np.var(x, ddof=1)), rel=1e-13)
+
+
+def test_moments_large_offset_is_stable():
+    """Two-pass variance keeps accuracy where the one-pass printed form would cancel."""
+    x = 1e8 + workloads.draw("normal", 4000, 5, np.float64)
+    _, v = oracle.moments(x)
+    assert v == pytest.approx(float(np.var(x, ddof=1)), rel=1e-9)
+
+
+def test_rot_matches_both_printed_forms_and_quadrature():
+    x = workloads.draw("normal", 1000, 1998001, np.float64)
+    n = x.size
+    sigma, h = oracle.bw_rot(x)
+    assert sigma == pytest.approx(float(np.std(x, ddof=1)), rel=1e-13)
+    # eq. (LSCV-h0), d = 1, with the printed constants
+    d = GOLD["h0_constants_d1"]["d"]
+    rk_mu = 1.0 / (2**d * math.pi ** (d / 2) * d**2)
+    rf2 = d * (d + 2) / (2 ** (d + 2) * math.pi ** (d / 2))
+    h0 = (rk_mu / (rf2 * n)) ** (1.0 / (d + 4))
+    assert h == pytest.approx(sigma * h0, rel=1e-14)
+    # eq. (LSCV-H-start), d = 1
+    hs = (4.0 / (d + 2)) ** (1.0 / (d + 4)) * n ** (-1.0 / (d + 4)) * sigma
+    assert h == pytest.approx(hs, rel=1e-14)
+    # AMISE-optimal h for a N(0, sigma^2) density: R(f'') by quadrature
+    rf2_q, _ = integrate.quad(lambda t: (kr_numpy(2, t)) ** 2, -30, 30)
+    h_amise = ((1.0 / (2.0 * math.sqrt(math.pi))) / (rf2_q * n)) ** 0.2 * sigma
+    assert h == pytest.approx(h_amise, rel=1e-9)
+    # worked value: h0 = 0.266065 for n = 1000 (to the printed digits)
+    assert h0 == pytest.approx(0.266065, abs=5e-7)
+
+
+# ---------------------------------------------------------------- normal-scale functionals and pilots
+@pytest.mark.parametrize("r", [4, 6, 8, 10])
+@pytest.mark.parametrize("sigma", [0.37, 1.0, 2.5])
+def test_psi_ns_matches_quadrature(r, sigma):
+    """psi_r = int f^(r) f dx for the N(0, sigma^2) density, by scipy quadrature."""
+    f = lambda t: phi(t / sigma) / sigma
+    fr = lambda t: kr_numpy(r, t / sigma) / sigma ** (r + 1)
+    val, _ = integrate.quad(lambda t: fr(t) * f(t), -40 * sigma, 40 * sigma, limit=400)
+    assert oracle.psi_ns(r, sigma) == pytest.approx(val, rel=1e-9)
+
+
+def test_psi8_ns_matches_printed():
+    g = GOLD["psi8_NS"]
+    for s in (0.5, 1.0, 3.0):
+        printed = g["numerator"] / (g["denominator"] * math.sqrt(math.pi) * s ** g["sigma_power"])
+        assert oracle.psi_ns(8, s) == pytest.approx(printed, rel=1e-14)
+
+
+@pytest.mark.parametrize("r", [4, 6, 8])
+def test_pilot_cancels_amse_leading_terms(r):
+    """The AMSE-optimal pilot makes the variance-like and bias terms cancel:
+    K^(r)(0) / (n g^(r+1)) + mu_2 g^2 psi_{r+2} / 2 = 0 (K^(r)(0) from numpy)."""
+    n = 12345
+    psi_next = oracle.psi_ns(r + 2, 1.3)
+    g = oracle.pilot(r, psi_next, n)
+    k0 = float(kr_numpy(r, 0.0))
+    lead = k0 / (n * g ** (r + 1))
+    bias = 0.5 * GOLD["mu2_K"]["value"] * g**2 * psi_next
+    assert lead + bias == pytest.approx(0.0, abs=1e-12 * abs(lead))
+
+
+def test_pilot_rejects_wrong_sign():
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.pilot(6, -1.0, 100)  # psi_8 must be positive
+    assert e.value.code == oracle.DEGENERATE
+
+
+# ---------------------------------------------------------------- pairwise functionals
+@pytest.mark.parametrize("r", [4, 6, 8])
+@pytest.mark.parametrize("family", ["normal", "bimodal"])
+def test_psi_hat_brute_force_full_matrix(r, family):
+    """n^-2 g^-(r+1) sum over ALL (i, j), diagonal included, by numpy on the full matrix."""
+    x = workloads.draw(family, 301, 7, np.float64)
+    g = 0.41
+    u = (x[:, None] - x[None, :]) / g
+    full = kr_numpy(r, u)
+    ref = full.sum() / (x.size**2 * g ** (r + 1))
+    val, kappa, s, a = oracle.psi(x, r, g)
+    assert val == pytest.approx(ref, rel=1e-11)
+    off = full[np.triu_indices(x.size, 1)]
+    assert s == pytest.approx(off.sum(), rel=1e-11, abs=1e-9)
+    assert a == pytest.approx(np.abs(off).sum(), rel=1e-12)
+    assert kappa == pytest.approx(np.abs(off).sum() / abs(off.sum()), rel=1e-9)
+
+
+@pytest.mark.parametrize("r", [4, 6])
+def test_psi_hat_expectation_on_normal_data(r):
+    """E[psi_r(g)] = n^-1 g^-(r+1) K^(r)(0) + (1 - n^-1) (g^2 + 2 s^2)^(-(r+1)/2) K^(r)(0)
+    for N(0, s^2) samples; the printed form with n K^(r)(0) outside the
+    normalisation would be off by orders of magnitude."""
+    n, g, s, reps = 200, 0.6, 1.0, 120
+    vals = np.array([oracle.psi(workloads.draw("normal", n, 1000 + k, np.float64), r, g)[0] for k in range(reps)])
+    k0 = float(kr_numpy(r, 0.0))
+    expect = k0 / (n * g ** (r + 1)) + (1 - 1 / n) * (g * g + 2 * s * s) ** (-(r + 1) / 2) * k0
+    se = vals.std(ddof=1) / math.sqrt(reps)
+    assert abs(vals.mean() - expect) < 4 * se + 1e-12
+
+
+def test_plugin_approaches_amise_bandwidth():
+    """For large n the plug-in h approaches the AMISE-optimal h of the true
+    density: (R(K) / (psi_4 n))^(1/5) with psi_4 = int (f'')^2 by quadrature."""
+    n = 20000
+    for family, dens in [
+        ("normal", lambda t: phi(t)),
+        ("mixture", lambda t: 0.5 * phi((t + 2) / 0.5) / 0.5 + 0.5 * phi(t - 1)),
+    ]:
+        x = workloads.draw(family, n, 424242, np.float64)
+        if family == "normal":
+            f2 = lambda t: kr_numpy(2, t)
+        else:
+            f2 = lambda t: 0.5 * kr_numpy(2, (t + 2) / 0.5) / 0.5**3 + 0.5 * kr_numpy(2, t - 1)
+        psi4, _ = integrate.quad(lambda t: f2(t) ** 2, -30, 30, limit=400)
+        h_amise = (1.0 / (2 * math.sqrt(math.pi)) / (psi4 * n)) ** 0.2
+        for stages in (2, 3):
+            info = oracle.bw_plugin(x, stages)
+            assert info.h == pytest.approx(h_amise, rel=0.08), (family, stages, info.h, h_amise)
+
+
+# ---------------------------------------------------------------- LSCV objective
+def _fhat_sq_integral(x, h):
+    f = lambda t: phi((t - x) / h).sum() / (x.size * h)
+    lo, hi = x.min() - 12 * h, x.max() + 12 * h
+    pts = np.sort(x)
+    val, _ = integrate.quad(lambda t: f(t) ** 2, lo, hi, points=pts, limit=800, epsabs=1e-14, epsrel=1e-13)
+    return val
+
+
+@pytest.mark.parametrize("h", [0.05, 0.2, 0.45, 1.0, 3.0])
+def test_lscv_toy_dataset_by_quadrature(h):
+    """g(h) = int fhat^2 - 2 n^-2 sum_{i != j} K_h(X_i - X_j) on the paper's
+    8-point toy sample, with the integral by adaptive quadrature."""
+    x = np.array(GOLD["toy_dataset"]["x"], dtype=np.float64)
+    n = x.size
+    d = x[:, None] - x[None, :]
+    kh = phi(d / h) / h
+    np.fill_diagonal(kh, 0.0)
+    ref = _fhat_sq_integral(x, h) - 2.0 / n**2 * kh.sum()
+    g = oracle.lscv_curve(x, [h]).g[0]
+    assert g == pytest.approx(ref, rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("family", ["normal", "lognormal"])
+def test_lscv_brute_force_full_matrix(family):
+    x = workloads.draw(family, 400, 99, np.float64)
+    grid = np.geomspace(0.01, 2.0, 17)
+    cur = oracle.lscv_curve(x, grid)
+    d2 = (x[:, None] - x[None, :]) ** 2
+    iu = np.triu_indices(x.size, 1)
+    n = x.size
+    for k, h in enumerate(grid):
+        kk = np.exp(-d2 / (4 * h * h)) / math.sqrt(4 * math.pi) / h  # (K_h * K_h)
+        kh = np.exp(-d2 / (2 * h * h)) / math.sqrt(2 * math.pi) / h
+        np.fill_diagonal(kk, 0.0)
+        np.fill_diagonal(kh, 0.0)
+        ref = (kk.sum() - 2 * kh.sum()) / n**2 + 1.0 / (n * h * math.sqrt(4 * math.pi))
+        assert cur.g[k] == pytest.approx(ref, rel=1e-10, abs=1e-14)
+        assert cur.s1[k] == pytest.approx(np.exp(-d2[iu] / (4 * h * h)).sum(), rel=1e-12)
+        assert cur.s2[k] == pytest.approx(np.exp(-d2[iu] / (2 * h * h)).sum(), rel=1e-12)
+
+
+def test_lscv_expectation_on_normal_data():
+    """E[g(h)] = 1/(2 sqrt(pi) n h) + (1 - 1/n) [(4 pi (h^2 + s^2))^(-1/2) - 2 (2 pi (h^2 + 2 s^2))^(-1/2)]."""
+    n, reps = 150, 150
+    grid = np.array([0.1, 0.35, 0.8])
+    vals = np.array([oracle.lscv_curve(workloads.draw("normal", n, 5000 + k, np.float64), grid).g for k in range(reps)])
+    for k, h in enumerate(grid):
+        e = 1 / (2 * math.sqrt(math.pi) * n * h) + (1 - 1 / n) * (
+            (4 * math.pi * (h * h + 1)) ** -0.5 - 2 * (2 * math.pi * (h * h + 2)) ** -0.5)
+        se = vals[:, k].std(ddof=1) / math.sqrt(reps)
+        assert abs(vals[:, k].mean() - e) < 4 * se
+
+
+def test_default_grid_spans_printed_range():
+    x = workloads.draw("gamma", 777, 3, np.float64)
+    s, hr = oracle.bw_rot(x)
+    grid = oracle.default_grid(x, 0)
+    assert grid.size == GOLD["grid_points_experiments"]["n_h"]
+    assert grid[0] == pytest.approx(GOLD["search_range"]["lo_factor"] * hr, rel=1e-14)
+    assert grid[-1] == pytest.approx(GOLD["search_range"]["hi_factor"] * hr, rel=1e-14)
+    assert np.allclose(np.diff(grid), np.diff(grid)[0], rtol=1e-9)
+
+
+def test_argmin_ties_edges_and_margin():
+    assert oracle.argmin([3.0, 1.0, 1.0, 2.0]) == (1, False, 0.0)
+    k, e, m = oracle.argmin([0.5, 1.0, 2.0])
+    assert (k, e, m) == (0, True, 0.5)
+    g = workloads.draw("normal", 50, 1, np.float64)
+    assert oracle.argmin(g)[0] == int(np.argmin(g))
+
+
+# ---------------------------------------------------------------- invariances and error paths
+def test_invariances():
+    x = workloads.draw("bimodal", 257, 17, np.float64)
+    grid = np.geomspace(0.05, 1.5, 9)
+    base = oracle.lscv_curve(x, grid).g
+    p2 = oracle.bw_plugin(x, 3)
+    perm = np.random.Generator(np.random.PCG64(3)).permutation(x.size)
+    for y in (x + 1234.5, -x, x[perm]):
+        assert np.allclose(oracle.lscv_curve(y, grid).g, base, rtol=1e-9, atol=1e-13)
+        q = oracle.bw_plugin(y, 3)
+        assert q.h == pytest.approx(p2.h, rel=1e-9)
+        assert np.allclose(q.psi, p2.psi, rtol=1e-8)
+    a = 3.7
+    scaled = oracle.lscv_curve(a * x, a * grid).g
+    assert np.allclose(scaled, base / a, rtol=1e-10, atol=1e-14)
+    assert oracle.bw_plugin(a * x, 3).h == pytest.approx(a * p2.h, rel=1e-10)
+    assert oracle.bw_rot(a * x)[1] == pytest.approx(a * oracle.bw_rot(x)[1], rel=1e-13)
+
+
+def test_error_paths():
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bw_rot([1.0])
+    assert e.value.code == oracle.INVAL
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bw_rot([1.0, float("nan"), 2.0])
+    assert e.value.code == oracle.INVAL
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bw_plugin([2.0] * 10, 2)
+    assert e.value.code == oracle.DEGENERATE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.lscv_curve([0.0, 1.0, 2.0], [0.5, 0.2])
+    assert e.value.code == oracle.INVAL
+    # duplicates are allowed: the pair contributes exp(0) = 1
+    c = oracle.lscv_curve([1.0, 1.0], [0.5])
+    assert c.s1[0] == 1.0 and c.s2[0] == 1.0
