@@ -281,6 +281,11 @@ def test_invariances():
     scaled = oracle.lscv_curve(a * x, a * grid).g
     assert np.allclose(scaled, base / a, rtol=1e-10, atol=1e-14)
     assert oracle.bw_plugin(a * x, 3).h == pytest.approx(a * p2.h, rel=1e-10)
+    assert oracle.bw_plugin(a * x, 2).h == pytest.approx(a * oracle.bw_plugin(x, 2).h, rel=1e-10)
+    for r_idx, r in enumerate((8, 6, 4)):
+        if r_idx == 0:
+            continue
+        assert oracle.bw_plugin(a * x, 3).psi[r_idx] == pytest.approx(p2.psi[r_idx] / a ** (r + 1), rel=1e-9)
     assert oracle.bw_rot(a * x)[1] == pytest.approx(a * oracle.bw_rot(x)[1], rel=1e-13)
 
 
