@@ -1,0 +1,171 @@
+/*
+ * kde_bw.h -- C ABI of the MI355X (gfx950) engine for exact bandwidth-selection
+ * pair sums of univariate Gaussian kernel density estimates.
+ *
+ * Method: Andrzejewski, Gramacki, Gramacki, "Density Estimations for
+ * Approximate Query Processing on SIMD Architectures" (arXiv 1505.01998).
+ * The selectors are those of its Section 4.4: the normal-reference rule, the
+ * direct plug-in chain of Section 4.4.1 and the least-squares cross-validation
+ * objective g(h) of Section 4.4.2 minimised over a grid, with the O(n^2) pair
+ * sums of Section 5.4 evaluated on the GPU.
+ *
+ * Conventions shared by every call
+ *  - Every call returns a kde_status; nothing throws across the ABI.  On any
+ *    status other than KDE_OK, kde_last_error() describes the failure.
+ *  - A context is bound to one device and is not thread-safe: calls on one
+ *    context must not overlap.  Independent contexts may be used from
+ *    different threads.
+ *  - Synchronous calls borrow their inputs for the duration of the call only
+ *    and return after the results are in the caller's (host) output buffers.
+ *  - A sample column is n >= 2 finite values, float32 or float64, contiguous,
+ *    in host memory (on_device = 0) or in device memory of the context's
+ *    device (on_device = 1; the pointer must be valid on the context's stream).
+ *    n is limited to KDE_MAX_N.  A non-finite sample or n < 2 gives
+ *    KDE_E_INVAL.
+ *  - Bandwidth grids are float64 host arrays in data units: the kernel at h is
+ *    the N(0, h^2) density, the same h as the estimator of Section 4.2
+ *    (eq. kde-def).  Entries must be finite, > 0 and strictly ascending, else
+ *    KDE_E_INVAL.  1 <= n_h <= KDE_MAX_NH.
+ *  - Device failures (launch or copy errors) give KDE_E_DEVICE; the context
+ *    must then be destroyed.
+ */
+#ifndef KDE_BW_H
+#define KDE_BW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KDE_MAX_N ((int64_t)1 << 30)
+#define KDE_MAX_NH 65536
+
+typedef enum {
+  KDE_OK = 0,
+  KDE_E_INVAL = 1,      /* bad argument or sample column */
+  KDE_E_DEGENERATE = 2, /* sigma = 0, or a functional estimate of the wrong sign */
+  KDE_E_NOMEM = 3,      /* device or host allocation failed */
+  KDE_E_DEVICE = 4,     /* HIP runtime error */
+  KDE_E_BUSY = 5,       /* reserved: result not ready */
+  KDE_E_CANCELLED = 6   /* reserved: request cancelled */
+} kde_status;
+
+typedef enum { KDE_F32 = 0, KDE_F64 = 1 } kde_dtype;
+
+typedef enum {
+  /* Pair terms in FP32 (hardware exp2), FP32 running sums folded into
+   * Kahan-compensated FP32 per-lane accumulators, FP64 across lanes, tiles and
+   * blocks, FP64 for every scalar step and for g(h) = difference of sums.  A
+   * plug-in stage whose pair sum is badly conditioned is re-run in FP64. */
+  KDE_PREC_MIXED = 0,
+  /* Every pair term and every sum in FP64. */
+  KDE_PREC_FP64 = 1
+} kde_prec;
+
+typedef struct kde_ctx kde_ctx;
+
+typedef struct {
+  const void* data; /* n samples */
+  int64_t n;
+  kde_dtype dtype;
+  int on_device; /* 0: host pointer, 1: device pointer */
+} kde_column;
+
+/* Plug-in diagnostics.  Stage order is (psi_8, psi_6, psi_4); for stages = 2
+ * slot 0 holds the normal-scale psi_8 of eq. (PLUGIN-Psi8Estimate) and g[0],
+ * kappa[0] are NaN.  g[s] is the pilot bandwidth of stage s (eq. PLUGIN-g1,
+ * PLUGIN-g2), psi[s] its estimate (eq. PLUGIN-Psi6Estimate, PLUGIN-Psi4Estimate),
+ * kappa[s] = sum|t| / |sum t| over its pair terms (condition number of the
+ * pair sum), precision_used[s] the kde_prec the stage's pair sum was taken in
+ * (-1 where no pair sum was taken). */
+typedef struct {
+  double sigma, h_rot;
+  int stages;
+  double g[3], psi[3], kappa[3];
+  int precision_used[3];
+  double h;
+} kde_plugin_info;
+
+/* Create a context on HIP device `device` computing in precision `prec`.
+ * The context owns a HIP stream of default priority, a device workspace that
+ * grows on demand, and per-kernel timing counters. */
+kde_status kde_ctx_create(int device, kde_prec prec, kde_ctx** out);
+void kde_ctx_destroy(kde_ctx* ctx);
+
+/* Text of the last failure on this context; owned by the context and valid
+ * until its next call.  Never NULL. */
+const char* kde_last_error(const kde_ctx* ctx);
+
+/* Run on an external stream (a hipStream_t of the context's device, e.g. the
+ * caller's framework stream) instead of the context's own; NULL restores it. */
+kde_status kde_ctx_set_stream(kde_ctx* ctx, void* hip_stream);
+
+/* Change the precision used by later calls. */
+kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
+
+/* Tuning knobs by name (value < 0 restores the default):
+ *   "lscv_hc"      bandwidths per pass of the LSCV pair kernel (8, 16 or 32)
+ *   "seg"          j-range per work item, rounded to the tile (0 = whole row)
+ *   "launch_evals" pair-term evaluations per kernel launch (launch splitting)
+ *   "fp64_kappa"   mixed precision: kappa above which a plug-in stage is re-run
+ *                  in FP64 (0 = never)
+ * Unknown keys give KDE_E_INVAL. */
+kde_status kde_ctx_set_option(kde_ctx* ctx, const char* key, int64_t value);
+
+/* Kernel timing.  While enabled, every launch of the pair kernels is bracketed
+ * by HIP events on the stream it runs on.  kde_ctx_kernel_time reports, for
+ * kernel family "lscv_pairs" or "psi_pairs", the number of launches, their
+ * summed duration in ms and the summed pair-term evaluations since timing was
+ * last enabled. */
+kde_status kde_ctx_set_timing(kde_ctx* ctx, int enable);
+kde_status kde_ctx_kernel_time(kde_ctx* ctx, const char* family, int64_t* launches, double* total_ms,
+                               double* evals);
+
+/* Normal-reference bandwidth h = (4/3)^(1/5) sigma n^(-1/5): eq. (LSCV-H-start)
+ * with d = 1, equal to sigma * h0 of eq. (LSCV-h0); sigma from
+ * eq. (PLUGIN-VarianceEstimator)/(PLUGIN-StdDevEstimator), n-1 denominator.
+ * KDE_E_DEGENERATE when sigma = 0. */
+kde_status kde_bw_rot(kde_ctx* ctx, kde_column x, double* h_out);
+
+/* Direct plug-in bandwidth, Section 4.4.1, eq. (PLUGIN-VarianceEstimator)
+ * through (PLUGIN-Final_h).  stages = 2 is the printed chain (normal-scale
+ * psi_8, pairwise psi_6 and psi_4); stages = 3 starts from the normal-scale
+ * psi_10 and estimates psi_8 pairwise as well.  psi_r(g) is read as
+ * n^-2 g^-(r+1) sum over all (i, j) of K^(r)((X_i - X_j)/g), i.e. the diagonal
+ * term n K^(r)(0) inside the normalisation.  info may be NULL.
+ * KDE_E_DEGENERATE when sigma = 0 or a pilot/final radicand is not positive. */
+kde_status kde_bw_plugin(kde_ctx* ctx, kde_column x, int stages, double* h_out, kde_plugin_info* info);
+
+/* LSCV objective over a grid, eq. (LSCV-gh) with (LSCV-Tx), (LSCV-Kx),
+ * (LSCV-KKx), in data units for d = 1:
+ *   g(h) = h^-1 [ 2 n^-2 sum_{i<j} T((X_i - X_j)/h) + n^-1 (4 pi)^(-1/2) ],
+ *   T = K*K - 2K.
+ * The pair distance is formed once per pair and reused for every h of the grid
+ * (the rewrite of Section 4.5), nothing is stored per pair.
+ * h_grid == NULL selects the default grid: n_h points (150 if n_h <= 0)
+ * spaced linearly over sigma * [h0/4, 4 h0] (eq. LSCV-Zh0, LSCV-h0).
+ * g_out[n_h] receives g(h); gscale_out[n_h] (may be NULL) receives the same
+ * expression with the two pair sums added instead of subtracted, the scale
+ * against which errors in g are measured.  grid_out[n_h] (may be NULL)
+ * receives the grid used. */
+kde_status kde_lscv_curve(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, double* g_out,
+                          double* gscale_out, double* grid_out);
+
+/* The two raw pair sums behind g(h): s1[k] = sum_{i<j} exp(-D^2/(4 h_k^2)),
+ * s2[k] = sum_{i<j} exp(-D^2/(2 h_k^2)), D = X_i - X_j.  h_grid must not be
+ * NULL. */
+kde_status kde_lscv_sums(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, double* s1_out,
+                         double* s2_out);
+
+/* LSCV bandwidth: the grid point minimising g(h), eq. (LSCV-finalH); ties go
+ * to the lowest index.  k_out (may be NULL) receives its index, at_edge (may
+ * be NULL) 1 when it is the first or last grid point. */
+kde_status kde_bw_lscv(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, double* h_out,
+                       int32_t* k_out, int* at_edge);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDE_BW_H */

@@ -1,0 +1,310 @@
+"""MI355X engine for exact KDE bandwidth-selection pair sums.
+
+A thin ctypes binding over the C ABI declared in include/kde_bw.h (built as
+libkde_bw.so next to this file).  Every function named ``kde_*`` here has the
+same name, arguments and meaning as the C entry point; this module only
+marshals arguments.  All arithmetic of the selectors runs in the library's
+HIP kernels: there is no Python or CPU fallback, and importing the package
+fails if the library has not been built.
+
+Method: Andrzejewski, Gramacki, Gramacki, arXiv 1505.01998, Section 4.4
+(normal-reference rule, direct plug-in, LSCV_h objective over a grid).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkde_bw.so")
+
+KDE_OK, KDE_E_INVAL, KDE_E_DEGENERATE, KDE_E_NOMEM, KDE_E_DEVICE, KDE_E_BUSY, KDE_E_CANCELLED = range(7)
+KDE_F32, KDE_F64 = 0, 1
+KDE_PREC_MIXED, KDE_PREC_FP64 = 0, 1
+KDE_MAX_N = 1 << 30
+KDE_MAX_NH = 65536
+
+STATUS_NAMES = {
+    KDE_OK: "KDE_OK",
+    KDE_E_INVAL: "KDE_E_INVAL",
+    KDE_E_DEGENERATE: "KDE_E_DEGENERATE",
+    KDE_E_NOMEM: "KDE_E_NOMEM",
+    KDE_E_DEVICE: "KDE_E_DEVICE",
+    KDE_E_BUSY: "KDE_E_BUSY",
+    KDE_E_CANCELLED: "KDE_E_CANCELLED",
+}
+
+# Every symbol the header declares; tests check that the library exports them.
+EXPORTS = (
+    "kde_ctx_create", "kde_ctx_destroy", "kde_last_error", "kde_ctx_set_stream", "kde_ctx_set_precision",
+    "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
+    "kde_lscv_curve", "kde_lscv_sums", "kde_bw_lscv",
+)
+
+
+class KdeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class kde_column(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("dtype", ctypes.c_int),
+                ("on_device", ctypes.c_int)]
+
+
+class kde_plugin_info(ctypes.Structure):
+    _fields_ = [
+        ("sigma", ctypes.c_double),
+        ("h_rot", ctypes.c_double),
+        ("stages", ctypes.c_int),
+        ("g", ctypes.c_double * 3),
+        ("psi", ctypes.c_double * 3),
+        ("kappa", ctypes.c_double * 3),
+        ("precision_used", ctypes.c_int * 3),
+        ("h", ctypes.c_double),
+    ]
+
+
+def _load():
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one.  Loading torch first makes the dynamic loader bind this library to
+    # that already-loaded runtime, so a process that also uses torch for
+    # device buffers and streams holds exactly one HIP runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    PD = ctypes.POINTER(ctypes.c_double)
+    I = ctypes.c_int
+    I32 = ctypes.c_int32
+    I64 = ctypes.c_int64
+    lib.kde_ctx_create.argtypes = [I, I, ctypes.POINTER(P)]
+    lib.kde_ctx_destroy.argtypes = [P]
+    lib.kde_ctx_destroy.restype = None
+    lib.kde_last_error.argtypes = [P]
+    lib.kde_last_error.restype = ctypes.c_char_p
+    lib.kde_ctx_set_stream.argtypes = [P, P]
+    lib.kde_ctx_set_precision.argtypes = [P, I]
+    lib.kde_ctx_set_option.argtypes = [P, ctypes.c_char_p, I64]
+    lib.kde_ctx_set_timing.argtypes = [P, I]
+    lib.kde_ctx_kernel_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I64), PD, PD]
+    lib.kde_bw_rot.argtypes = [P, kde_column, PD]
+    lib.kde_bw_plugin.argtypes = [P, kde_column, I, PD, ctypes.POINTER(kde_plugin_info)]
+    lib.kde_lscv_curve.argtypes = [P, kde_column, PD, I32, PD, PD, PD]
+    lib.kde_lscv_sums.argtypes = [P, kde_column, PD, I32, PD, PD]
+    lib.kde_bw_lscv.argtypes = [P, kde_column, PD, I32, PD, ctypes.POINTER(I32), ctypes.POINTER(I)]
+    for name in EXPORTS:
+        if name not in ("kde_ctx_destroy", "kde_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+# ---------------------------------------------------------------- argument marshalling
+def _pd(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_column(x):
+    """Return (kde_column, keepalive) for a numpy array (host) or a torch CUDA tensor (device)."""
+    if hasattr(x, "data_ptr") and hasattr(x, "is_cuda"):
+        if x.dim() != 1 or not x.is_contiguous():
+            raise ValueError("device column must be a contiguous 1-D tensor")
+        import torch
+
+        if x.dtype == torch.float32:
+            dt = KDE_F32
+        elif x.dtype == torch.float64:
+            dt = KDE_F64
+        else:
+            raise ValueError("device column must be float32 or float64")
+        return kde_column(x.data_ptr(), x.numel(), dt, 1 if x.is_cuda else 0), x
+    a = np.asarray(x)
+    if a.dtype not in (np.float32, np.float64):
+        a = a.astype(np.float64)
+    a = np.ascontiguousarray(a)
+    if a.ndim != 1:
+        raise ValueError("sample column must be one-dimensional")
+    return kde_column(a.ctypes.data, a.size, KDE_F32 if a.dtype == np.float32 else KDE_F64, 0), a
+
+
+def _grid(h_grid):
+    if h_grid is None:
+        return None
+    return np.ascontiguousarray(np.asarray(h_grid, dtype=np.float64).ravel())
+
+
+# ---------------------------------------------------------------- C-ABI functions, same names
+def kde_ctx_create(device: int = 0, prec: int = KDE_PREC_MIXED) -> ctypes.c_void_p:
+    out = ctypes.c_void_p()
+    st = lib.kde_ctx_create(int(device), int(prec), ctypes.byref(out))
+    if st != KDE_OK:
+        raise KdeError(st, "kde_ctx_create failed")
+    return out
+
+
+def kde_ctx_destroy(ctx) -> None:
+    lib.kde_ctx_destroy(ctx)
+
+
+def kde_last_error(ctx) -> str:
+    return lib.kde_last_error(ctx).decode()
+
+
+def _check(ctx, st):
+    if st != KDE_OK:
+        raise KdeError(st, kde_last_error(ctx))
+
+
+def kde_ctx_set_stream(ctx, hip_stream) -> None:
+    _check(ctx, lib.kde_ctx_set_stream(ctx, hip_stream))
+
+
+def kde_ctx_set_precision(ctx, prec: int) -> None:
+    _check(ctx, lib.kde_ctx_set_precision(ctx, int(prec)))
+
+
+def kde_ctx_set_option(ctx, key: str, value: int) -> None:
+    _check(ctx, lib.kde_ctx_set_option(ctx, key.encode(), int(value)))
+
+
+def kde_ctx_set_timing(ctx, enable: bool) -> None:
+    _check(ctx, lib.kde_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def kde_ctx_kernel_time(ctx, family: str):
+    """(launches, total_ms, evals) of a pair-kernel family since timing was enabled."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    ev = ctypes.c_double()
+    _check(ctx, lib.kde_ctx_kernel_time(ctx, family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ev)))
+    return n.value, ms.value, ev.value
+
+
+def kde_bw_rot(ctx, x) -> float:
+    col, keep = make_column(x)
+    h = ctypes.c_double()
+    _check(ctx, lib.kde_bw_rot(ctx, col, ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+@dataclass
+class PluginInfo:
+    sigma: float
+    h_rot: float
+    stages: int
+    g: tuple
+    psi: tuple
+    kappa: tuple
+    precision_used: tuple
+    h: float
+
+
+def kde_bw_plugin(ctx, x, stages: int = 2):
+    """(h, PluginInfo)."""
+    col, keep = make_column(x)
+    h = ctypes.c_double()
+    info = kde_plugin_info()
+    _check(ctx, lib.kde_bw_plugin(ctx, col, int(stages), ctypes.byref(h), ctypes.byref(info)))
+    del keep
+    return h.value, PluginInfo(info.sigma, info.h_rot, info.stages, tuple(info.g), tuple(info.psi),
+                               tuple(info.kappa), tuple(info.precision_used), info.h)
+
+
+def kde_lscv_curve(ctx, x, h_grid=None, n_h: int = 0):
+    """(g, gscale, grid) as float64 arrays."""
+    col, keep = make_column(x)
+    gr = _grid(h_grid)
+    m = gr.size if gr is not None else (n_h if n_h > 0 else 150)
+    g = np.empty(m, np.float64)
+    gs = np.empty(m, np.float64)
+    grid_used = np.empty(m, np.float64)
+    _check(ctx, lib.kde_lscv_curve(ctx, col, _pd(gr), int(m), _pd(g), _pd(gs), _pd(grid_used)))
+    del keep
+    return g, gs, grid_used
+
+
+def kde_lscv_sums(ctx, x, h_grid):
+    """(s1, s2): pair sums of exp(-D^2/(4h^2)) and exp(-D^2/(2h^2))."""
+    col, keep = make_column(x)
+    gr = _grid(h_grid)
+    s1 = np.empty(gr.size, np.float64)
+    s2 = np.empty(gr.size, np.float64)
+    _check(ctx, lib.kde_lscv_sums(ctx, col, _pd(gr), int(gr.size), _pd(s1), _pd(s2)))
+    del keep
+    return s1, s2
+
+
+def kde_bw_lscv(ctx, x, h_grid=None, n_h: int = 0):
+    """(h, k, at_edge)."""
+    col, keep = make_column(x)
+    gr = _grid(h_grid)
+    m = gr.size if gr is not None else n_h
+    h = ctypes.c_double()
+    k = ctypes.c_int32()
+    e = ctypes.c_int()
+    _check(ctx, lib.kde_bw_lscv(ctx, col, _pd(gr), int(m), ctypes.byref(h), ctypes.byref(k), ctypes.byref(e)))
+    del keep
+    return h.value, k.value, bool(e.value)
+
+
+class Context:
+    """Owns a kde_ctx; methods forward to the kde_* functions above."""
+
+    def __init__(self, device: int = 0, precision: str = "mixed"):
+        self.ctx = kde_ctx_create(device, KDE_PREC_FP64 if precision == "fp64" else KDE_PREC_MIXED)
+
+    def close(self):
+        if self.ctx:
+            kde_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_precision(self, precision: str):
+        kde_ctx_set_precision(self.ctx, KDE_PREC_FP64 if precision == "fp64" else KDE_PREC_MIXED)
+
+    def set_option(self, key, value):
+        kde_ctx_set_option(self.ctx, key, value)
+
+    def set_timing(self, enable=True):
+        kde_ctx_set_timing(self.ctx, enable)
+
+    def kernel_time(self, family):
+        return kde_ctx_kernel_time(self.ctx, family)
+
+    def bw_rot(self, x):
+        return kde_bw_rot(self.ctx, x)
+
+    def bw_plugin(self, x, stages=2):
+        return kde_bw_plugin(self.ctx, x, stages)
+
+    def lscv_curve(self, x, h_grid=None, n_h=0):
+        return kde_lscv_curve(self.ctx, x, h_grid, n_h)
+
+    def lscv_sums(self, x, h_grid):
+        return kde_lscv_sums(self.ctx, x, h_grid)
+
+    def bw_lscv(self, x, h_grid=None, n_h=0):
+        return kde_bw_lscv(self.ctx, x, h_grid, n_h)

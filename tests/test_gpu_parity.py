@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (mixed precision):
+  * h_rot, sigma: FP64 on both sides, 1e-12 relative.
+  * psi_r, pilot g, plug-in h: 1e-5 relative.
+  * g(h): |g_gpu - g_oracle| <= 1e-5 * gscale(h), where gscale is the same
+    expression with the two pair sums added (the magnitude g is a difference
+    of); |dg|/|g| is reported alongside.
+  * raw pair sums s1, s2 (positive terms): 1e-5 relative, plus the FP32 range
+    limit of the mixed form (pairs * 2^-126: a term below the smallest normal
+    FP32 may flush to zero).
+  * chosen grid index: equal, or a near tie: g_oracle[k_gpu] - min g_oracle
+    <= 2 max|dg| (reported).
+FP64 form: 1e-10 on the same quantities.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def kde():
+    import paper_1505_01998_amd as kde
+
+    return kde
+
+
+@pytest.fixture(scope="module")
+def ctx(kde):
+    c = kde.Context(0, "mixed")
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx64(kde):
+    c = kde.Context(0, "fp64")
+    yield c
+    c.close()
+
+
+def check_curve(g, gs, oc, tol, label=""):
+    err = np.abs(g - oc.g) / oc.gscale
+    assert np.all(np.isfinite(g)), label
+    assert err.max() <= tol, (label, float(err.max()), int(err.argmax()))
+    assert np.allclose(gs, oc.gscale, rtol=tol, atol=0), label
+    return float(err.max())
+
+
+def check_argmin(k_gpu, g_gpu, oc, label=""):
+    k_or, _, _ = oracle.argmin(oc.g)
+    if k_gpu == k_or:
+        return
+    dg = np.abs(g_gpu - oc.g).max()
+    assert oc.g[k_gpu] - oc.g[k_or] <= 2 * dg, (label, k_gpu, k_or)
+
+
+# ---------------------------------------------------------------- rule of thumb
+@pytest.mark.parametrize("family,n,dtype", [
+    ("normal", 1000, np.float64), ("mixture", 4097, np.float32), ("lognormal", 2, np.float32),
+    ("gamma", 777, np.float64), ("uniform", 65536 + 3, np.float32)])
+def test_rot(ctx, family, n, dtype):
+    x = workloads.draw(family, n, 77 + n, dtype)
+    s, h = oracle.bw_rot(x)
+    assert ctx.bw_rot(x) == pytest.approx(h, rel=1e-12)
+
+
+# ---------------------------------------------------------------- plug-in
+@pytest.mark.parametrize("family,n,dtype,stages", [
+    ("normal", 1000, np.float64, 2),      # the plain 1k workload
+    ("normal", 1000, np.float64, 3),
+    ("mixture", 5003, np.float32, 3),
+    ("lognormal", 4096, np.float32, 3),
+    ("bimodal", 257, np.float32, 2),
+    ("uniform", 3, np.float64, 2),
+    ("gamma", 12345, np.float32, 3),
+])
+def test_plugin(ctx, family, n, dtype, stages):
+    x = workloads.draw(family, n, 1000 + n + stages, dtype)
+    o = oracle.bw_plugin(x, stages)
+    h, info = ctx.bw_plugin(x, stages)
+    first = 0 if stages == 3 else 1
+    for s in range(first, 3):
+        assert info.g[s] == pytest.approx(o.g[s], rel=TOL), ("g", s)
+        assert info.psi[s] == pytest.approx(o.psi[s], rel=TOL), ("psi", s, info.kappa[s])
+        assert info.precision_used[s] in (0, 1)
+    assert info.sigma == pytest.approx(o.sigma, rel=1e-12)
+    assert h == pytest.approx(o.h, rel=TOL)
+
+
+def test_plugin_fp64_form(ctx64):
+    x = workloads.draw("mixture", 6001, 5, np.float32)
+    o = oracle.bw_plugin(x, 3)
+    h, info = ctx64.bw_plugin(x, 3)
+    for s in range(3):
+        assert info.psi[s] == pytest.approx(o.psi[s], rel=TOL64)
+        assert info.precision_used[s] == 1
+    assert h == pytest.approx(o.h, rel=TOL64)
+
+
+# ---------------------------------------------------------------- LSCV
+def test_lscv_plain_1k(ctx):
+    w = workloads.workload("plain-1k")
+    x = w.column()
+    oc = oracle.lscv_curve(x, w.grid)
+    g, gs, grid = ctx.lscv_curve(x, w.grid)
+    assert np.array_equal(grid, w.grid)
+    err = check_curve(g, gs, oc, TOL, "plain-1k")
+    h, k, _ = ctx.bw_lscv(x, w.grid)
+    check_argmin(k, g, oc, "plain-1k")
+    assert h == w.grid[k]
+    print(f"plain-1k max|dg|/gscale = {err:.3e}")
+
+
+@pytest.mark.parametrize("family,n,dtype", [
+    ("mixture", 3001, np.float32), ("lognormal", 10007, np.float32), ("bimodal", 256, np.float64),
+    ("gamma", 513, np.float32), ("normal", 2, np.float32), ("uniform", 65, np.float64)])
+def test_lscv_curve_and_sums(ctx, family, n, dtype):
+    x = workloads.draw(family, n, 31 + n, dtype)
+    grid = np.geomspace(0.004, 3.0, 37)
+    oc = oracle.lscv_curve(x, grid)
+    g, gs, _ = ctx.lscv_curve(x, grid)
+    check_curve(g, gs, oc, TOL, family)
+    s1, s2 = ctx.lscv_sums(x, grid)
+    # FP32 terms: a term below the smallest normal FP32 (2^-126) may flush to zero
+    atol = n * (n - 1) / 2 * 2.0**-126
+    assert np.allclose(s1, oc.s1, rtol=TOL, atol=atol)
+    assert np.allclose(s2, oc.s2, rtol=TOL, atol=atol)
+    _, k, _ = ctx.bw_lscv(x, grid)
+    check_argmin(k, g, oc, family)
+
+
+@pytest.mark.parametrize("hc", [8, 16, 32])
+@pytest.mark.parametrize("seg", [0, 512, 1536])
+def test_lscv_tile_configs_agree(kde, hc, seg):
+    """Every tuning configuration meets the oracle bar (n spans several rows and items)."""
+    x = workloads.draw("mixture", 4099, 8, np.float32)
+    grid = np.geomspace(0.01, 2.0, 41)
+    oc = oracle.lscv_curve(x, grid)
+    with kde.Context(0) as c:
+        c.set_option("lscv_hc", hc)
+        c.set_option("seg", seg)
+        g, gs, _ = c.lscv_curve(x, grid)
+    check_curve(g, gs, oc, TOL, f"hc={hc} seg={seg}")
+
+
+def test_lscv_fp64_form(ctx64):
+    x = workloads.draw("lognormal", 3333, 12, np.float32)
+    grid = np.geomspace(0.003, 2.0, 19)
+    oc = oracle.lscv_curve(x, grid)
+    g, gs, _ = ctx64.lscv_curve(x, grid)
+    check_curve(g, gs, oc, TOL64, "fp64")
+
+
+def test_lscv_default_grid(ctx):
+    x = workloads.draw("gamma", 2500, 4, np.float64)
+    og = oracle.default_grid(x, 0)
+    g, gs, grid = ctx.lscv_curve(x, None, 0)
+    assert grid.size == 150
+    assert np.allclose(grid, og, rtol=1e-12)
+    oc = oracle.lscv_curve(x, og)
+    check_curve(g, gs, oc, TOL, "default grid")
+
+
+def test_lscv_mixture_100k_sampled(ctx):
+    """Full-size mixture workload (n = 100,000, 256 h): the whole curve on the
+    GPU, the oracle on sampled grid points (each one by one)."""
+    w = workloads.workload("mixture-100k")
+    x = w.column()
+    g, gs, _ = ctx.lscv_curve(x, w.grid)
+    k = int(np.argmin(g))
+    idx = sorted({0, 128, 255, max(0, k - 1), k, min(255, k + 1)})
+    oc = oracle.lscv_curve(x, w.grid[idx])
+    err = np.abs(g[idx] - oc.g) / oc.gscale
+    assert err.max() <= TOL, err
+    assert oc.g[idx.index(k)] <= oc.g.min() + 2 * np.abs(g[idx] - oc.g).max()
+    print(f"mixture-100k sampled max|dg|/gscale = {err.max():.3e}")
+
+
+# ---------------------------------------------------------------- device columns, determinism, errors
+def test_device_column_matches_host(ctx):
+    import torch
+
+    x = workloads.draw("bimodal", 5000, 2, np.float32)
+    grid = np.geomspace(0.02, 1.0, 16)
+    g_host, _, _ = ctx.lscv_curve(x, grid)
+    xd = torch.from_numpy(x).to("cuda:0")
+    torch.cuda.synchronize()
+    g_dev, _, _ = ctx.lscv_curve(xd, grid)
+    assert np.array_equal(g_host, g_dev)
+    assert ctx.bw_plugin(xd, 3)[0] == ctx.bw_plugin(x, 3)[0]
+
+
+def test_deterministic(ctx):
+    x = workloads.draw("lognormal", 7777, 3, np.float32)
+    grid = np.geomspace(0.01, 1.0, 23)
+    a = ctx.lscv_curve(x, grid)[0]
+    b = ctx.lscv_curve(x, grid)[0]
+    assert np.array_equal(a, b)
+    assert ctx.bw_plugin(x, 3)[1].psi == ctx.bw_plugin(x, 3)[1].psi
+
+
+def test_error_paths(ctx, kde):
+    with pytest.raises(kde.KdeError) as e:
+        ctx.bw_rot(np.array([1.0]))
+    assert e.value.status == kde.KDE_E_INVAL
+    with pytest.raises(kde.KdeError) as e:
+        ctx.bw_plugin(np.array([0.0, np.nan, 1.0]), 2)
+    assert e.value.status == kde.KDE_E_INVAL
+    with pytest.raises(kde.KdeError) as e:
+        ctx.bw_plugin(np.full(100, 3.0), 2)
+    assert e.value.status == kde.KDE_E_DEGENERATE
+    with pytest.raises(kde.KdeError) as e:
+        ctx.lscv_curve(np.arange(10.0), [0.5, 0.2])
+    assert e.value.status == kde.KDE_E_INVAL
+    with pytest.raises(kde.KdeError) as e:
+        ctx.lscv_curve(np.arange(10.0), [0.5, -1.0])
+    assert e.value.status == kde.KDE_E_INVAL
+    with pytest.raises(kde.KdeError) as e:
+        ctx.bw_plugin(np.arange(10.0), 4)
+    assert e.value.status == kde.KDE_E_INVAL
+    # the context still works after errors
+    x = workloads.draw("normal", 100, 1, np.float64)
+    assert ctx.bw_rot(x) == pytest.approx(oracle.bw_rot(x)[1], rel=1e-12)
+
+
+def test_duplicates_contribute_kernel_at_zero(ctx):
+    x = np.array([0.5, 0.5, 0.5, 2.0], dtype=np.float32)
+    grid = np.array([0.1, 0.7])
+    s1, s2 = ctx.lscv_sums(x, grid)
+    oc = oracle.lscv_curve(x, grid)
+    assert np.allclose(s1, oc.s1, rtol=1e-6) and np.allclose(s2, oc.s2, rtol=1e-6)
+
+
+def test_timing_counters(kde):
+    x = workloads.draw("normal", 20000, 9, np.float32)
+    grid = np.geomspace(0.01, 1.0, 32)
+    with kde.Context(0) as c:
+        c.set_timing(True)
+        c.lscv_curve(x, grid)
+        launches, ms, evals = c.kernel_time("lscv_pairs")
+    assert launches >= 1 and ms > 0
+    assert evals == pytest.approx(20000 * 19999 / 2 * 32, rel=1e-12)
