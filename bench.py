@@ -7,7 +7,7 @@ The metric counts pair-term evaluations: n(n-1)/2 per psi stage plus
 n(n-1)/2 per LSCV grid point.
 
 Prints one JSON line.  `roofline` reports the LSCV pair kernel (the dominant
-kernel) against the transcendental issue rate of the chip, measured live with
+kernel) against the issue-rate bound of its instruction mix, measured live with
 HIP events around every launch of it; `cpu_baseline` times the FP64 oracle on
 a bounded sample of the same workload.
 """
@@ -27,12 +27,39 @@ if ROOT not in sys.path:
 
 import workloads  # noqa: E402
 
-# MI355X: 256 CUs at 2.4 GHz.  v_exp_f32 issues at a quarter of the 64-lane
-# VALU rate: 16 lanes per clock per CU.  One LSCV (pair, h) term needs one exp.
+# MI355X: 256 CUs at 2.4 GHz.  Per CU and clock the vector units retire 128
+# FP32 lanes of add/mul/fma (157.3 TFLOP/s counting an FMA as 2) and 32 lanes
+# of v_exp_f32.  Microbenchmarks on gfx950 show the two do not overlap: an
+# exp occupies issue like ~3 plain FP32 ops.  One LSCV (pair, h) term is
+# 1 mul + 1 exp + 1 add + 1 fma, so the term rate is bounded by
+#   1 / (3 / (CUS * 128 * f) + 1 / (CUS * 32 * f)).
 CUS, CLOCK_HZ = 256, 2.4e9
-EXP_PEAK = CUS * 16 * CLOCK_HZ            # 9.83e12 exp/s
-FP32_PEAK_TFLOPS = 157.3                  # dense FP32 vector, packed issue
+VALU_LANES, TRANS_LANES = 128, 32
+LSCV_PEAK = 1.0 / (3.0 / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ))  # 11.23e12/s
+FP32_PEAK_TFLOPS = 157.3
 LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
+
+# HBM bytes per LSCV launch of this workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes, each scaled by the ratio the same counter shows for a
+# plain 1 GiB copy (fetch x2.0, write x1.0).  Valid only for the kernel
+# source they were taken on; reported as null once that source changes.
+MEASURED_TRAFFIC = {
+    "workload": "lognormal-1m",
+    "kernels_sha256": "15e425ddff1f835919f6ed65dfd1992272f796e9c7fbe7784d404a3687a72d85",
+    "fetch_bytes": 1.5053e7,
+    "write_bytes": 3.2968e6,
+}
+
+
+def measured_traffic(workload: str):
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1505_01998_amd", "csrc", "kde_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    t = MEASURED_TRAFFIC
+    if sha != t["kernels_sha256"] or workload != t["workload"]:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
 def log(*a):
@@ -73,7 +100,21 @@ def main():
     ap.add_argument("--workload", default="lognormal-1m", choices=workloads.WORKLOADS)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--hc", type=int, default=-1, help="bandwidths per LSCV pass (8, 16, 32; -1 = default)")
+    ap.add_argument("--seg", type=int, default=-1, help="j-range per work item (-1 = automatic, 0 = whole rows)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+
+        a = torch.empty(args.copy_calibration // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the path is not sharded across GPUs",
                           "n_gpus": args.gpus}))
@@ -91,6 +132,10 @@ def main():
     xd = torch.from_numpy(x).to("cuda:0")
     torch.cuda.synchronize()
     ctx = kde.Context(0, args.precision)
+    if args.hc > 0:
+        ctx.set_option("lscv_hc", args.hc)
+    if args.seg >= 0:
+        ctx.set_option("seg", args.seg)
 
     def step():
         h_pi, info = ctx.bw_plugin(xd, w.stages)
@@ -133,10 +178,11 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": EXP_PEAK / 1e12,
+            "peak": LSCV_PEAK / 1e12,
             "unit": "Teval/s",
-            "frac": achieved / EXP_PEAK,
-            "traffic": None,
+            "frac": achieved / LSCV_PEAK,
+            "traffic": measured_traffic(w.name),
+            "traffic_unit": "bytes per launch",
             "kernel": "k_lscv_pairs_f32" if args.precision == "mixed" else "k_lscv_pairs_f64",
             "launches": launches,
             "avg_launch_ms": ms / max(launches, 1),
