@@ -158,6 +158,19 @@ kde_status kde_lscv_curve(kde_ctx* ctx, kde_column x, const double* h_grid, int3
 kde_status kde_lscv_sums(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, double* s1_out,
                          double* s2_out);
 
+/* Diagnostic view of the LSCV pass: runs exactly the pass kde_lscv_sums runs
+ * (same work list and launch slicing for this n, grid and context options)
+ * and returns the FP64 partial sums of selected work items.  A work item is
+ * one block of the i < j triangle: samples i in [i_begin, i_begin + 256) and
+ * j in [j_begin, j_end), pairs with j <= i or an index >= n excluded.
+ * sel[n_sel] are item indices in [0, n_items), or negative to count from the
+ * end (-1 = last); items are ordered longest first.  n_items_out receives
+ * the item count.  ranges_out[3*k..3*k+2] receives
+ * (i_begin, j_begin, j_end) of item sel[k]; sums_out[(k*n_h + h)*2 + {0,1}]
+ * receives its s1/s2 partials for grid point h. */
+kde_status kde_lscv_item_sums(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, const int32_t* sel,
+                              int32_t n_sel, int32_t* n_items_out, int32_t* ranges_out, double* sums_out);
+
 /* LSCV bandwidth: the grid point minimising g(h), eq. (LSCV-finalH); ties go
  * to the lowest index.  k_out (may be NULL) receives its index, at_edge (may
  * be NULL) 1 when it is the first or last grid point. */

@@ -87,6 +87,7 @@ def _load():
     lib.orc_plugin.argtypes = [PD, L, I, ctypes.POINTER(_PluginInfo)]
     lib.orc_default_grid.argtypes = [PD, L, I, PD]
     lib.orc_lscv_curve.argtypes = [PD, L, PD, I, PD, PD, PD, PD]
+    lib.orc_lscv_block_sums.argtypes = [PD, L, L, L, L, L, PD, I, PD, PD]
     lib.orc_argmin.argtypes = [PD, I, PI, PI, PD]
     lib.orc_lscv.argtypes = [PD, L, PD, I, PD, PI, PI]
     _lib = lib
@@ -216,6 +217,17 @@ def lscv_curve(x, grid) -> LscvCurve:
     g, gs, s1, s2 = (np.empty(m, dtype=np.float64) for _ in range(4))
     _check(_load().orc_lscv_curve(_p(a), a.size, _p(gr), m, _p(g), _p(gs), _p(s1), _p(s2)), "lscv_curve")
     return LscvCurve(g, gs, s1, s2)
+
+
+def lscv_block_sums(x, i0: int, i1: int, j0: int, j1: int, grid):
+    """(s1, s2) over the triangle block i in [i0, i1), j in [j0, j1), j > i."""
+    a = _col(x)
+    gr = _col(grid)
+    s1 = np.empty(gr.size, np.float64)
+    s2 = np.empty(gr.size, np.float64)
+    _check(_load().orc_lscv_block_sums(_p(a), a.size, int(i0), int(i1), int(j0), int(j1), _p(gr), gr.size,
+                                       _p(s1), _p(s2)), "lscv_block_sums")
+    return s1, s2
 
 
 def argmin(g):

@@ -307,6 +307,45 @@ int orc_lscv_curve(const double* x, long n, const double* grid, int n_h, double*
   return ORC_OK;
 }
 
+/* The two LSCV pair sums of eq. (LSCV-gh) restricted to one block of the
+ * i < j triangle: i in [i0, i1), j in [j0, j1), pairs with j <= i or an index
+ * >= n excluded.  s1 sums exp(-D^2/(4h^2)), s2 sums exp(-D^2/(2h^2)), with
+ * separate exp calls, per grid point.  Summing the blocks of any partition of
+ * the triangle gives the sums of orc_lscv_curve. */
+int orc_lscv_block_sums(const double* x, long n, long i0, long i1, long j0, long j1, const double* grid, int n_h,
+                        double* s1_out, double* s2_out) {
+  int st = orc_validate(x, n);
+  if (st) return st;
+  if (n_h < 1 || grid == NULL || i0 < 0 || j0 < 0) return ORC_INVAL;
+  if (i1 > n) i1 = n;
+  if (j1 > n) j1 = n;
+  long rows = (i1 > i0) ? i1 - i0 : 0;
+  double* ra = (double*)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1));
+  double* rb = (double*)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1));
+  if (!ra || !rb) { free(ra); free(rb); return ORC_NOMEM; }
+  for (int k = 0; k < n_h; ++k) {
+    double h = grid[k];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long r = 0; r < rows; ++r) {
+      long i = i0 + r;
+      long jb = (j0 > i + 1) ? j0 : i + 1;
+      double sa = 0.0, sb = 0.0;
+      for (long j = jb; j < j1; ++j) {
+        double d = x[i] - x[j];
+        sa += exp(-d * d / (4.0 * h * h));
+        sb += exp(-d * d / (2.0 * h * h));
+      }
+      ra[r] = sa;
+      rb[r] = sb;
+    }
+    s1_out[k] = neumaier_sum(ra, rows);
+    s2_out[k] = neumaier_sum(rb, rows);
+  }
+  free(ra);
+  free(rb);
+  return ORC_OK;
+}
+
 /* Brute-force grid minimum, eq. (LSCV-finalH): lowest index among equal
  * minima; at_edge = 1 when it is the first or last grid point; margin is the
  * gap to the second-smallest value (0 if n_h == 1). */

@@ -41,7 +41,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "kde_ctx_create", "kde_ctx_destroy", "kde_last_error", "kde_ctx_set_stream", "kde_ctx_set_precision",
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
-    "kde_lscv_curve", "kde_lscv_sums", "kde_bw_lscv",
+    "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv",
 )
 
 
@@ -100,6 +100,8 @@ def _load():
     lib.kde_bw_plugin.argtypes = [P, kde_column, I, PD, ctypes.POINTER(kde_plugin_info)]
     lib.kde_lscv_curve.argtypes = [P, kde_column, PD, I32, PD, PD, PD]
     lib.kde_lscv_sums.argtypes = [P, kde_column, PD, I32, PD, PD]
+    lib.kde_lscv_item_sums.argtypes = [P, kde_column, PD, I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32),
+                                       ctypes.POINTER(I32), PD]
     lib.kde_bw_lscv.argtypes = [P, kde_column, PD, I32, PD, ctypes.POINTER(I32), ctypes.POINTER(I)]
     for name in EXPORTS:
         if name not in ("kde_ctx_destroy", "kde_last_error"):
@@ -246,6 +248,23 @@ def kde_lscv_sums(ctx, x, h_grid):
     return s1, s2
 
 
+def kde_lscv_item_sums(ctx, x, h_grid, sel=()):
+    """(n_items, ranges[n_sel, 3] = (i_begin, j_begin, j_end), sums[n_sel, n_h, 2]) of selected work items."""
+    col, keep = make_column(x)
+    gr = _grid(h_grid)
+    sel_a = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+    m = sel_a.size
+    n_items = ctypes.c_int32()
+    ranges = np.zeros((max(m, 1), 3), np.int32)
+    sums = np.zeros((max(m, 1), gr.size, 2), np.float64)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    _check(ctx, lib.kde_lscv_item_sums(ctx, col, _pd(gr), int(gr.size), sel_a.ctypes.data_as(P32) if m else None,
+                                       int(m), ctypes.byref(n_items), ranges.ctypes.data_as(P32),
+                                       sums.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    del keep
+    return n_items.value, ranges[:m], sums[:m]
+
+
 def kde_bw_lscv(ctx, x, h_grid=None, n_h: int = 0):
     """(h, k, at_edge)."""
     col, keep = make_column(x)
@@ -305,6 +324,9 @@ class Context:
 
     def lscv_sums(self, x, h_grid):
         return kde_lscv_sums(self.ctx, x, h_grid)
+
+    def lscv_item_sums(self, x, h_grid, sel=()):
+        return kde_lscv_item_sums(self.ctx, x, h_grid, sel)
 
     def bw_lscv(self, x, h_grid=None, n_h=0):
         return kde_bw_lscv(self.ctx, x, h_grid, n_h)

@@ -324,14 +324,16 @@ int64_t pick_seg(kde_ctx* c, int64_t n, int hc) {
 }
 
 // Launch ranges over items [i0, i1) whose summed evaluations stay within budget.
+// FP64 terms cost about five times the FP32 ones, so their budget is smaller.
 template <typename F>
-kde_status for_each_launch(kde_ctx* c, const Plan& p, double evals_per_pair, F&& launch) {
+kde_status for_each_launch(kde_ctx* c, const Plan& p, double evals_per_pair, bool f64, F&& launch) {
+  const double budget = f64 ? c->opt_launch_evals / 5.0 : c->opt_launch_evals;
   const size_t m = p.items.size();
   size_t i0 = 0;
   while (i0 < m) {
     double acc = p.pairs[i0] * evals_per_pair;
     size_t i1 = i0 + 1;
-    while (i1 < m && acc + p.pairs[i1] * evals_per_pair <= c->opt_launch_evals) {
+    while (i1 < m && acc + p.pairs[i1] * evals_per_pair <= budget) {
       acc += p.pairs[i1] * evals_per_pair;
       ++i1;
     }
@@ -352,7 +354,7 @@ kde_status run_psi_stage(kde_ctx* c, int n, int stage, bool f64, bool conditiona
   const int r = 8 - 2 * stage;
   kde_status s;
   if ((s = ensure(c, c->part, 2 * p.items.size()))) return s;
-  s = for_each_launch(c, p, 1.0, [&](int i0, int cnt, double evals) -> kde_status {
+  s = for_each_launch(c, p, 1.0, f64, [&](int i0, int cnt, double evals) -> kde_status {
     // A conditional pass may exit at once on the device, so it is not timed.
     Pending pd{nullptr, nullptr, kFamPsi, evals};
     kde_status s2 = conditional ? KDE_OK : timed_begin(c, pd);
@@ -398,7 +400,7 @@ kde_status check_grid(kde_ctx* c, const double* h, int32_t n_h) {
 }
 
 // Runs the LSCV pass; results stay on the device (sums, g, gscale, hdev, state).
-kde_status run_lscv(kde_ctx* c, const kde_column& x, const double* h_grid, int32_t n_h) {
+kde_status run_lscv(kde_ctx* c, const kde_column& x, const double* h_grid, int32_t n_h, Plan** plan_out = nullptr) {
   kde_status s;
   if (h_grid) {
     if ((s = check_grid(c, h_grid, n_h))) return s;
@@ -426,7 +428,7 @@ kde_status run_lscv(kde_ctx* c, const kde_column& x, const double* h_grid, int32
   if ((s = get_plan(c, n, pick_seg(c, n, hc), &p))) return s;
   const size_t n_items = p->items.size();
   if ((s = ensure(c, c->part, (size_t)2 * n_h * n_items))) return s;
-  s = for_each_launch(c, *p, (double)n_h, [&](int i0, int cnt, double evals) -> kde_status {
+  s = for_each_launch(c, *p, (double)n_h, all64, [&](int i0, int cnt, double evals) -> kde_status {
     Pending pd{nullptr, nullptr, kFamLscv, evals};
     kde_status s2 = timed_begin(c, pd);
     if (s2) return s2;
@@ -438,6 +440,7 @@ kde_status run_lscv(kde_ctx* c, const kde_column& x, const double* h_grid, int32
   kde::launch_reduce_rows(c->stream, c->part.p, (int)n_items, 2 * n_h, c->sums.p);
   kde::launch_lscv_finalize(c->stream, c->sums.p, n_h, c->hdev.p, c->d_st, c->g.p, c->gs.p);
   HIP_TRY(c, hipGetLastError());
+  if (plan_out) *plan_out = p;
   return KDE_OK;
 }
 
@@ -636,6 +639,43 @@ kde_status kde_lscv_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t
   for (int32_t k = 0; k < n_h; ++k) {
     s1_out[k] = c->h_out[2 * k];
     s2_out[k] = c->h_out[2 * k + 1];
+  }
+  return KDE_OK;
+}
+
+kde_status kde_lscv_item_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, const int32_t* sel,
+                              int32_t n_sel, int32_t* n_items_out, int32_t* ranges_out, double* sums_out) {
+  if (!c || !h_grid || !n_items_out || n_sel < 0) return KDE_E_INVAL;
+  if (n_sel > 0 && (!sel || !ranges_out || !sums_out)) return fail(c, KDE_E_INVAL, "NULL selection buffers");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  kde_status s;
+  Plan* p = nullptr;
+  if ((s = run_lscv(c, x, h_grid, n_h, &p))) return s;
+  const int32_t n_items = (int32_t)p->items.size();
+  std::vector<int32_t> idx((size_t)n_sel);
+  for (int32_t k = 0; k < n_sel; ++k) {
+    idx[k] = sel[k] < 0 ? n_items + sel[k] : sel[k];
+    if (idx[k] < 0 || idx[k] >= n_items) {
+      (void)hipStreamSynchronize(c->stream);
+      return fail(c, KDE_E_INVAL, "item index out of range");
+    }
+  }
+  if ((s = ensure_host_out(c, (size_t)2 * n_h * (n_sel > 0 ? n_sel : 1)))) return s;
+  // part is laid out [2*n_h][n_items]: one strided column per selected item
+  for (int32_t k = 0; k < n_sel; ++k)
+    HIP_TRY(c, hipMemcpy2DAsync(c->h_out + (size_t)k * 2 * n_h, sizeof(double), c->part.p + idx[k],
+                                sizeof(double) * (size_t)n_items, sizeof(double), (size_t)2 * n_h,
+                                hipMemcpyDeviceToHost, c->stream));
+  if ((s = read_state(c))) return s;
+  if ((s = sync_and_check(c))) return s;
+  if ((s = map_status(c, c->h_st->status))) return s;
+  *n_items_out = n_items;
+  for (int32_t k = 0; k < n_sel; ++k) {
+    const Item& it = p->items[idx[k]];
+    ranges_out[3 * k] = it.row * kde::kBI;
+    ranges_out[3 * k + 1] = it.j_begin;
+    ranges_out[3 * k + 2] = it.j_end;
+    std::memcpy(sums_out + (size_t)k * 2 * n_h, c->h_out + (size_t)k * 2 * n_h, sizeof(double) * 2 * n_h);
   }
   return KDE_OK;
 }

@@ -250,3 +250,28 @@ def test_timing_counters(kde):
         launches, ms, evals = c.kernel_time("lscv_pairs")
     assert launches >= 1 and ms > 0
     assert evals == pytest.approx(20000 * 19999 / 2 * 32, rel=1e-12)
+
+
+def test_lscv_lognormal_1m_sampled_items(kde):
+    """The bench workload at full size (n = 1,000,000, 512 h) in the bench's
+    launch configuration: the GPU's FP64 partial sums of sampled work items
+    (blocks of the pair triangle) against the oracle's sums over the same
+    blocks, on every 16th grid point."""
+    w = workloads.workload("lognormal-1m")
+    x = w.column()
+    sel = [0, 1, 5000, -2, -1]
+    with kde.Context(0) as c:
+        n_items, ranges, sums = c.lscv_item_sums(x, w.grid, sel)
+    assert n_items > 5000
+    hk = np.arange(0, w.grid.size, 16)
+    worst = 0.0
+    for k, (i0, j0, j1) in enumerate(ranges):
+        o1, o2 = oracle.lscv_block_sums(x, int(i0), int(i0) + 256, int(j0), int(j1), w.grid[hk])
+        pairs = 256 * (min(int(j1), x.size) - int(j0))
+        atol = pairs * 2.0**-126
+        g1, g2 = sums[k, hk, 0], sums[k, hk, 1]
+        assert np.allclose(g1, o1, rtol=TOL, atol=atol), (k, i0, j0, j1)
+        assert np.allclose(g2, o2, rtol=TOL, atol=atol), (k, i0, j0, j1)
+        m = o1 > 1e-20
+        worst = max(worst, float(np.max(np.abs(g1[m] - o1[m]) / o1[m])))
+    print(f"lognormal-1m sampled items: max rel err {worst:.3e} over {len(sel)} items x {hk.size} h")

@@ -235,6 +235,29 @@ def test_lscv_brute_force_full_matrix(family):
         assert cur.s2[k] == pytest.approx(np.exp(-d2[iu] / (2 * h * h)).sum(), rel=1e-12)
 
 
+def test_lscv_block_sums_partition_the_triangle():
+    """Blocks of any partition of the i < j triangle add up to the full pair
+    sums, and one block matches a numpy brute force."""
+    x = workloads.draw("lognormal", 700, 21, np.float64)
+    grid = np.geomspace(0.02, 1.5, 7)
+    full = oracle.lscv_curve(x, grid)
+    acc1 = np.zeros(grid.size)
+    acc2 = np.zeros(grid.size)
+    for i0 in range(0, 700, 256):
+        for j0 in range(i0, 700, 300):
+            s1, s2 = oracle.lscv_block_sums(x, i0, i0 + 256, j0, j0 + 300, grid)
+            acc1 += s1
+            acc2 += s2
+    assert np.allclose(acc1, full.s1, rtol=1e-12)
+    assert np.allclose(acc2, full.s2, rtol=1e-12)
+    s1, s2 = oracle.lscv_block_sums(x, 256, 512, 300, 600, grid)
+    d2 = (x[256:512, None] - x[None, 300:600]) ** 2
+    mask = np.arange(300, 600)[None, :] > np.arange(256, 512)[:, None]
+    for k, h in enumerate(grid):
+        assert s1[k] == pytest.approx((np.exp(-d2 / (4 * h * h)) * mask).sum(), rel=1e-12)
+        assert s2[k] == pytest.approx((np.exp(-d2 / (2 * h * h)) * mask).sum(), rel=1e-12)
+
+
 def test_lscv_expectation_on_normal_data():
     """E[g(h)] = 1/(2 sqrt(pi) n h) + (1 - 1/n) [(4 pi (h^2 + s^2))^(-1/2) - 2 (2 pi (h^2 + 2 s^2))^(-1/2)]."""
     n, reps = 150, 150
