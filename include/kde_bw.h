@@ -40,6 +40,7 @@ extern "C" {
 
 #define KDE_MAX_N ((int64_t)1 << 30)
 #define KDE_MAX_NH 65536
+#define KDE_MAX_BATCH 65535
 
 typedef enum {
   KDE_OK = 0,
@@ -170,6 +171,56 @@ kde_status kde_lscv_sums(kde_ctx* ctx, kde_column x, const double* h_grid, int32
  * receives its s1/s2 partials for grid point h. */
 kde_status kde_lscv_item_sums(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, const int32_t* sel,
                               int32_t n_sel, int32_t* n_items_out, int32_t* ranges_out, double* sums_out);
+
+/* ---------------------------------------------------------------- batches
+ * Many columns in one job: their moment passes, plug-in stages and LSCV
+ * passes run as shared launches whose work units mix columns, largest first.
+ * Each column keeps the work decomposition and reduction order it has when
+ * run alone, so every result of a batch is bitwise identical to the same
+ * request made on its own. */
+
+typedef enum {
+  KDE_GRID_EXPLICIT = 0, /* h[n_h], host float64, finite, > 0, strictly ascending */
+  KDE_GRID_PAPER = 1,    /* n_h points linear over sigma * [h0/4, 4 h0], eq. (LSCV-Zh0) */
+  KDE_GRID_LOG_ROT = 2   /* n_h points log-spaced over h_rot * [lo, hi], 0 < lo < hi */
+} kde_grid_kind;
+
+typedef struct {
+  kde_grid_kind kind;
+  const double* h;
+  int32_t n_h;
+  double lo, hi;
+} kde_grid;
+
+#define KDE_METHOD_ROT 1u
+#define KDE_METHOD_PLUGIN 2u
+#define KDE_METHOD_LSCV 4u
+
+typedef struct {
+  kde_column x;
+  unsigned methods; /* KDE_METHOD_* bits; ROT is always computed */
+  int stages;       /* plug-in stages, 2 or 3 */
+  kde_grid grid;    /* LSCV grid */
+} kde_request;
+
+typedef struct {
+  kde_status status;       /* per request */
+  double sigma, h_rot, h_plugin, h_lscv;
+  int32_t k_lscv;
+  int at_edge;
+  kde_plugin_info plugin;
+  double* g_out;           /* caller-owned [n_h] for g(h), or NULL */
+  double* gscale_out;      /* caller-owned [n_h], or NULL */
+  double t_queue_s, t_service_s; /* served requests: time queued, time admitted to done */
+} kde_result;
+
+/* Run n_req (<= KDE_MAX_BATCH) requests as one job.  Per-request argument errors and degenerate
+ * samples are reported in out[k].status (the other requests still run); a
+ * degenerate plug-in chain does not stop the LSCV pass of the same request
+ * (its h_lscv is still filled).  The call itself returns KDE_OK unless the
+ * device fails or an argument of the call is invalid.  out[k].g_out / gscale_out, when not NULL, must hold n_h
+ * doubles and are filled for LSCV requests. */
+kde_status kde_batch(kde_ctx* ctx, const kde_request* reqs, int32_t n_req, kde_result* out);
 
 /* LSCV bandwidth: the grid point minimising g(h), eq. (LSCV-finalH); ties go
  * to the lowest index.  k_out (may be NULL) receives its index, at_edge (may

@@ -26,6 +26,9 @@ KDE_F32, KDE_F64 = 0, 1
 KDE_PREC_MIXED, KDE_PREC_FP64 = 0, 1
 KDE_MAX_N = 1 << 30
 KDE_MAX_NH = 65536
+KDE_MAX_BATCH = 65535
+KDE_GRID_EXPLICIT, KDE_GRID_PAPER, KDE_GRID_LOG_ROT = 0, 1, 2
+KDE_METHOD_ROT, KDE_METHOD_PLUGIN, KDE_METHOD_LSCV = 1, 2, 4
 
 STATUS_NAMES = {
     KDE_OK: "KDE_OK",
@@ -41,7 +44,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "kde_ctx_create", "kde_ctx_destroy", "kde_last_error", "kde_ctx_set_stream", "kde_ctx_set_precision",
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
-    "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv",
+    "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
 )
 
 
@@ -66,6 +69,32 @@ class kde_plugin_info(ctypes.Structure):
         ("kappa", ctypes.c_double * 3),
         ("precision_used", ctypes.c_int * 3),
         ("h", ctypes.c_double),
+    ]
+
+
+class kde_grid(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("h", ctypes.POINTER(ctypes.c_double)), ("n_h", ctypes.c_int32),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
+class kde_request(ctypes.Structure):
+    _fields_ = [("x", kde_column), ("methods", ctypes.c_uint), ("stages", ctypes.c_int), ("grid", kde_grid)]
+
+
+class kde_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("sigma", ctypes.c_double),
+        ("h_rot", ctypes.c_double),
+        ("h_plugin", ctypes.c_double),
+        ("h_lscv", ctypes.c_double),
+        ("k_lscv", ctypes.c_int32),
+        ("at_edge", ctypes.c_int),
+        ("plugin", kde_plugin_info),
+        ("g_out", ctypes.POINTER(ctypes.c_double)),
+        ("gscale_out", ctypes.POINTER(ctypes.c_double)),
+        ("t_queue_s", ctypes.c_double),
+        ("t_service_s", ctypes.c_double),
     ]
 
 
@@ -103,6 +132,7 @@ def _load():
     lib.kde_lscv_item_sums.argtypes = [P, kde_column, PD, I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32),
                                        ctypes.POINTER(I32), PD]
     lib.kde_bw_lscv.argtypes = [P, kde_column, PD, I32, PD, ctypes.POINTER(I32), ctypes.POINTER(I)]
+    lib.kde_batch.argtypes = [P, ctypes.POINTER(kde_request), I32, ctypes.POINTER(kde_result)]
     for name in EXPORTS:
         if name not in ("kde_ctx_destroy", "kde_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -278,6 +308,89 @@ def kde_bw_lscv(ctx, x, h_grid=None, n_h: int = 0):
     return h.value, k.value, bool(e.value)
 
 
+@dataclass
+class Request:
+    """One bandwidth-selection request: a sample column and what to compute.
+
+    grid: an explicit array of h (data units), or ("log_rot", lo, hi, n_h) for
+    n_h log-spaced points over h_rot * [lo, hi], or ("paper", n_h) for the
+    paper's default grid.
+    """
+    x: object
+    methods: int = KDE_METHOD_ROT | KDE_METHOD_PLUGIN | KDE_METHOD_LSCV
+    stages: int = 3
+    grid: object = ("paper", 150)
+
+
+@dataclass
+class Result:
+    status: int
+    sigma: float
+    h_rot: float
+    h_plugin: float
+    h_lscv: float
+    k_lscv: int
+    at_edge: bool
+    plugin: PluginInfo
+    g: np.ndarray
+    gscale: np.ndarray
+    t_queue_s: float = 0.0
+    t_service_s: float = 0.0
+
+
+def _make_request(r: Request):
+    """(kde_request, keepalive list, n_h)."""
+    col, keep = make_column(r.x)
+    req = kde_request()
+    req.x = col
+    req.methods = int(r.methods)
+    req.stages = int(r.stages)
+    keeps = [keep]
+    g = r.grid
+    if isinstance(g, tuple) and g and g[0] == "log_rot":
+        req.grid.kind = KDE_GRID_LOG_ROT
+        req.grid.lo, req.grid.hi, req.grid.n_h = float(g[1]), float(g[2]), int(g[3])
+    elif isinstance(g, tuple) and g and g[0] == "paper":
+        req.grid.kind = KDE_GRID_PAPER
+        req.grid.n_h = int(g[1])
+    else:
+        ga = _grid(g)
+        req.grid.kind = KDE_GRID_EXPLICIT
+        req.grid.h = _pd(ga)
+        req.grid.n_h = ga.size
+        keeps.append(ga)
+    return req, keeps, int(req.grid.n_h)
+
+
+def _unpack_result(res: kde_result, g, gs) -> Result:
+    p = res.plugin
+    info = PluginInfo(p.sigma, p.h_rot, p.stages, tuple(p.g), tuple(p.psi), tuple(p.kappa),
+                      tuple(p.precision_used), p.h)
+    return Result(res.status, res.sigma, res.h_rot, res.h_plugin, res.h_lscv, res.k_lscv, bool(res.at_edge), info,
+                  g, gs, res.t_queue_s, res.t_service_s)
+
+
+def kde_batch(ctx, requests):
+    """Run a list of Request as one job; returns a list of Result (per-request status)."""
+    m = len(requests)
+    reqs = (kde_request * max(m, 1))()
+    outs = (kde_result * max(m, 1))()
+    keeps, bufs = [], []
+    for k, r in enumerate(requests):
+        req, kp, n_h = _make_request(r)
+        reqs[k] = req
+        keeps.append(kp)
+        lscv = (r.methods & KDE_METHOD_LSCV) != 0
+        g = np.full(n_h, np.nan) if lscv else None
+        gs = np.full(n_h, np.nan) if lscv else None
+        bufs.append((g, gs))
+        outs[k].g_out = _pd(g)
+        outs[k].gscale_out = _pd(gs)
+    _check(ctx, lib.kde_batch(ctx, reqs, m, outs))
+    del keeps
+    return [_unpack_result(outs[k], *bufs[k]) for k in range(m)]
+
+
 class Context:
     """Owns a kde_ctx; methods forward to the kde_* functions above."""
 
@@ -330,3 +443,6 @@ class Context:
 
     def bw_lscv(self, x, h_grid=None, n_h=0):
         return kde_bw_lscv(self.ctx, x, h_grid, n_h)
+
+    def batch(self, requests):
+        return kde_batch(self.ctx, requests)

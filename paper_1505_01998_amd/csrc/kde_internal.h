@@ -8,30 +8,41 @@
 namespace kde {
 
 // Threads per block of every pair kernel: four 64-wide waves.  Each block
-// owns one "row" of BI consecutive samples i (one per lane).
+// owns one "row" of kBI consecutive samples i (one per lane).
 constexpr int kThreads = 256;
 constexpr int kBI = kThreads;
 // j-tile staged in LDS per step; item j-ranges are whole multiples of it.
 constexpr int kBJ = 512;
-// Samples are padded with +inf up to at least n + kPad so that every tile
-// read stays in bounds and padded j contribute exactly zero.
+// Every column is padded with +inf up to at least n + kPad so that every
+// tile read stays in bounds and padded j contribute exactly zero.
 constexpr int kPad = kBJ + kBI;
+// Blocks per column of the moment passes (a column of n samples uses
+// min(kStatBlocks, ceil(n / 2048)) of them).
+constexpr int kStatBlocks = 1024;
 
 // Status values written by device code (same numbers as kde_status).
 constexpr int kStOk = 0;
 constexpr int kStInval = 1;
 constexpr int kStDegenerate = 2;
 
-// Device-resident state of one selector call.  All scalar steps of the
-// method run on the device and read/write this struct, so a whole call is a
-// chain of kernels on one stream with a single copy back at the end.
+// Grid kinds of an LSCV request (match kde_grid_kind in kde_bw.h).
+constexpr int kGridExplicit = 0;
+constexpr int kGridPaper = 1;    // linear over sigma * [h0/4, 4 h0]
+constexpr int kGridLogRot = 2;   // log-spaced over h_rot * [lo, hi]
+
+// Device-resident state of one column of a job.  All scalar steps of the
+// method run on the device and read/write this struct, so a whole job is a
+// chain of kernels on one stream with one copy back at the end.
 struct DevState {
-  int status;
+  int status;       // column status (invalid sample, zero spread)
+  int pstatus;      // plug-in status (a pilot or final radicand not positive)
+  int active;       // the current plug-in stage applies to this column
   int need_f64;     // mixed precision: current plug-in stage is re-run in FP64
   int k_best;
   int at_edge;
   int prec_used[3];
-  int stages;
+  int stages;       // plug-in stages (2 or 3); 0 when the column has no plug-in
+  int pad0;
   double n;
   double shift;     // subtracted from float64 samples before rounding to float32
   double mean, var, sigma, h_rot;
@@ -43,35 +54,59 @@ struct DevState {
   double cd[2];     // FP64 pair coefficients: 1/g^2, -1/(2 g^2)
 };
 
-// One work item of a pair kernel: block row (samples i in [row*kBI, row*kBI+kBI)),
-// and the j-range [j_begin, j_end) it sweeps.  j_end - j_begin is a multiple
-// of kBJ; the last item of a row may run past n into the +inf padding.
-struct Item {
-  int row, j_begin, j_end, pad;
+// One column of a job: where its data, coefficients and partial sums live.
+struct ColDesc {
+  const void* raw;      // input samples (device address), float32 or float64
+  int64_t x_off;        // offset of the column in the packed x32/x64 arrays
+  int64_t c_off;        // offset in the per-grid-point arrays (h, c32, c64, g, gscale, sums/2)
+  int64_t part_off;     // LSCV partial slab: part[part_off + row * n_items + item], row = 2 h + {0, 1}
+  int64_t psi_part_off; // psi partials: part[psi_part_off + {0, 1} * n_items_psi + item]
+  int n;
+  int raw_f64;
+  int n_h;              // LSCV grid points (0: no LSCV for this column)
+  int n_chunks;         // ceil(n_h / HC)
+  int n_items;          // LSCV work items
+  int n_items_psi;      // psi work items
+  int grid_kind;        // kGridExplicit / kGridPaper / kGridLogRot
+  int pad0;
+  double grid_lo, grid_hi;
+};
+
+// One block of a pair kernel: the samples i in [row*kBI, row*kBI + kBI) of
+// column `col` against j in [j_begin, j_end) (a multiple of kBJ long; a
+// column's last item may run past n into the +inf padding).  `item` is the
+// item's index within its column, `chunk` the bandwidth chunk (LSCV).
+struct Unit {
+  int col, row, j_begin, j_end, item, chunk;
+};
+
+// One row of a segmented reduction: out[dst] = sum of part[src .. src + n).
+struct RowDesc {
+  int64_t src;
+  int64_t dst;
+  int n;
+  int pad0;
 };
 
 // ---- launchers (kde_kernels.hip); all asynchronous on `s` ----
-void launch_stats_sum(hipStream_t s, const void* x, int is_f64, int n, double* part, int* part_nf, int nblk);
-void launch_stats_mean(hipStream_t s, const double* part, const int* part_nf, int nblk, int n, int shift_by_mean,
-                       DevState* st);
-void launch_stats_dev(hipStream_t s, const void* x, int is_f64, int n, int n_pad, double* part, float* x32,
-                      double* x64, int nblk, DevState* st);
-void launch_stats_final(hipStream_t s, const double* part, int nblk, DevState* st);
+void launch_stats(hipStream_t s, int n_cols, int max_blocks, const ColDesc* cols, double* part, int* part_nf,
+                  float* x32, double* x64, DevState* st);
 
-void launch_psi_begin(hipStream_t s, DevState* st, int stage);
-void launch_psi_finish(hipStream_t s, DevState* st, int stage, const double* sums, int was_f64, int conditional);
-void launch_plugin_final(hipStream_t s, DevState* st);
-void launch_psi_pairs(hipStream_t s, int r, int f64, int conditional, const float* x32, const double* x64, int n,
-                      const Item* items, int n_items, int bid0, int nblk, double* part, const DevState* st);
+void launch_psi_begin(hipStream_t s, int n_cols, DevState* st, int stage);
+void launch_psi_finish(hipStream_t s, int n_cols, const ColDesc* cols, DevState* st, int stage, const double* sums,
+                       int was_f64, int conditional);
+void launch_plugin_final(hipStream_t s, int n_cols, DevState* st);
+void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const float* x32, const double* x64,
+                      const ColDesc* cols, const Unit* units, int u0, int n_units, double* part, const DevState* st);
 
-void launch_lscv_prep(hipStream_t s, const double* h_in, int n_h, int n_h_pad, DevState* st, double* h_dev,
-                      float* c32, double* c64);
-void launch_lscv_pairs(hipStream_t s, int hc, int f64, const float* x32, const double* x64, int n,
-                       const Item* items, int n_items, int n_chunks, const float* c32, const double* c64, int n_h,
-                       int bid0, int nblk, double* part, const DevState* st);
-void launch_lscv_finalize(hipStream_t s, const double* sums, int n_h, const double* h_dev, DevState* st,
-                          double* g, double* gscale);
+void launch_lscv_prep(hipStream_t s, int n_cols, int hc, const ColDesc* cols, const double* h_in, DevState* st,
+                      double* h_dev, float* c32, double* c64);
+void launch_lscv_units(hipStream_t s, int hc, int f64, const float* x32, const double* x64, const ColDesc* cols,
+                       const Unit* units, int u0, int n_units, const float* c32, const double* c64, double* part,
+                       const DevState* st);
+void launch_lscv_finalize(hipStream_t s, int n_cols, const ColDesc* cols, const double* sums, const double* h_dev,
+                          DevState* st, double* g, double* gscale);
 
-void launch_reduce_rows(hipStream_t s, const double* part, int n_cols, int n_rows, double* out);
+void launch_reduce_rows(hipStream_t s, const double* part, const RowDesc* rows, int n_rows, double* out);
 
 }  // namespace kde

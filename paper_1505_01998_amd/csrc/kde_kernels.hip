@@ -4,6 +4,12 @@
 // (selectors), Section 4.5 (pair distance reused across bandwidths) and
 // Section 5.4 (sums of a function of X_i - X_j over the i < j triangle).
 //
+// Jobs.  Every call works on a set of columns (one for the single-column
+// selectors, many for a batch).  Column descriptors (ColDesc) say where each
+// column's samples, grid coefficients and partial sums live; every pair
+// kernel block decodes one work unit (Unit: column, row of samples i, j-range,
+// bandwidth chunk), so units of different columns share a launch.
+//
 // Pair kernels.  A block of 256 threads (four 64-wide waves) owns a "row" of
 // 256 consecutive samples i, one per lane, held in a register for the whole
 // block.  The block sweeps a j-range of the triangle in tiles of kBJ samples
@@ -119,34 +125,48 @@ __device__ double psi_normal_scale(int r, double sigma) {
   return sgn * num / (pow(2.0 * sigma, (double)(r + 1)) * den * sqrt(kPi));
 }
 
+
 // ------------------------------------------------------------------ statistics
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_stats_sum(const T* __restrict__ x, int n, double* __restrict__ part,
+__device__ __forceinline__ double load_raw(const ColDesc& c, int i) {
+  return c.raw_f64 ? reinterpret_cast<const double*>(c.raw)[i] : (double)reinterpret_cast<const float*>(c.raw)[i];
+}
+
+__device__ __forceinline__ int stat_blocks(int n) { return min(kStatBlocks, (n + 2047) / 2048); }
+
+// Pass 1: per-block FP64 sum of the samples and count of non-finite values.
+// Grid (max blocks, columns); part[col * kStatBlocks + b].
+__global__ __launch_bounds__(kThreads) void k_stats_sum(const ColDesc* __restrict__ cols, double* __restrict__ part,
                                                         int* __restrict__ part_nf) {
+  const ColDesc c = cols[blockIdx.y];
+  const int nblk = stat_blocks(c.n);
+  if ((int)blockIdx.x >= nblk) return;
   __shared__ double sh[kThreads];
   __shared__ int nf_sh;
-  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int chunk = (c.n + nblk - 1) / nblk;
   const int b0 = blockIdx.x * chunk;
-  const int b1 = min(n, b0 + chunk);
+  const int b1 = min(c.n, b0 + chunk);
   if (threadIdx.x == 0) nf_sh = 0;
   __syncthreads();
   double s = 0.0;
   int nf = 0;
   for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
-    const double v = (double)x[i];
+    const double v = load_raw(c, i);
     if (!isfinite(v)) ++nf; else s += v;
   }
   if (nf) atomicAdd(&nf_sh, nf);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s;
-    part_nf[blockIdx.x] = nf_sh;
+    part[(size_t)blockIdx.y * kStatBlocks + blockIdx.x] = s;
+    part_nf[(size_t)blockIdx.y * kStatBlocks + blockIdx.x] = nf_sh;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_stats_mean(const double* __restrict__ part,
-                                                         const int* __restrict__ part_nf, int nblk, int n,
-                                                         int shift_by_mean, DevState* st) {
+// Mean of each column (block per column); float64 columns are shifted by it.
+__global__ __launch_bounds__(kThreads) void k_stats_mean(const ColDesc* __restrict__ cols,
+                                                         const double* __restrict__ part,
+                                                         const int* __restrict__ part_nf, DevState* st) {
+  const ColDesc c = cols[blockIdx.x];
+  const int nblk = stat_blocks(c.n);
   __shared__ double sh[kThreads];
   __shared__ int nf_sh;
   if (threadIdx.x == 0) nf_sh = 0;
@@ -154,120 +174,143 @@ __global__ __launch_bounds__(kThreads) void k_stats_mean(const double* __restric
   double s = 0.0;
   int nf = 0;
   for (int b = threadIdx.x; b < nblk; b += kThreads) {
-    s += part[b];
-    nf += part_nf[b];
+    s += part[(size_t)blockIdx.x * kStatBlocks + b];
+    nf += part_nf[(size_t)blockIdx.x * kStatBlocks + b];
   }
   if (nf) atomicAdd(&nf_sh, nf);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    st->n = (double)n;
-    st->status = nf_sh ? kStInval : kStOk;
-    st->mean = s / (double)n;
-    st->shift = shift_by_mean ? st->mean : 0.0;
+    DevState& d = st[blockIdx.x];
+    d.n = (double)c.n;
+    d.status = nf_sh ? kStInval : kStOk;
+    d.mean = s / (double)c.n;
+    d.shift = c.raw_f64 ? d.mean : 0.0;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_stats_dev(const T* __restrict__ x, int n, int n_pad,
-                                                        double* __restrict__ part, float* __restrict__ x32,
-                                                        double* __restrict__ x64, const DevState* st) {
+// Pass 2: per-block sum of squared deviations; writes the padded FP32 (and
+// FP64) working copies of the column.
+__global__ __launch_bounds__(kThreads) void k_stats_dev(const ColDesc* __restrict__ cols, double* __restrict__ part,
+                                                        float* __restrict__ x32, double* __restrict__ x64,
+                                                        const DevState* __restrict__ st) {
+  const ColDesc c = cols[blockIdx.y];
+  const int nblk = stat_blocks(c.n);
+  if ((int)blockIdx.x >= nblk) return;
   __shared__ double sh[kThreads];
-  const double mean = st->mean, shift = st->shift;
-  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const double mean = st[blockIdx.y].mean, shift = st[blockIdx.y].shift;
+  float* y32 = x32 + c.x_off;
+  double* y64 = x64 ? x64 + c.x_off : nullptr;
+  const int chunk = (c.n + nblk - 1) / nblk;
   const int b0 = blockIdx.x * chunk;
-  const int b1 = min(n, b0 + chunk);
+  const int b1 = min(c.n, b0 + chunk);
   double s = 0.0;
   for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
-    const double v = (double)x[i];
+    const double v = load_raw(c, i);
     const double d = v - mean;
     s += d * d;
-    x32[i] = (float)(v - shift);
-    if (x64) x64[i] = v;
+    y32[i] = (float)(v - shift);
+    if (y64) y64[i] = v;
   }
-  for (int i = n + blockIdx.x * kThreads + threadIdx.x; i < n_pad; i += gridDim.x * kThreads) {
-    x32[i] = kInfF;
-    if (x64) x64[i] = kInfD;
+  for (int i = c.n + blockIdx.x * kThreads + threadIdx.x; i < c.n + kPad; i += nblk * kThreads) {
+    y32[i] = kInfF;
+    if (y64) y64[i] = kInfD;
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * kStatBlocks + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void k_stats_final(const double* __restrict__ part, int nblk, DevState* st) {
+__global__ __launch_bounds__(kThreads) void k_stats_final(const ColDesc* __restrict__ cols,
+                                                          const double* __restrict__ part, DevState* st) {
+  const ColDesc c = cols[blockIdx.x];
+  const int nblk = stat_blocks(c.n);
   __shared__ double sh[kThreads];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[b];
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(size_t)blockIdx.x * kStatBlocks + b];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    const double n = st->n;
-    st->var = s / (n - 1.0);
-    st->sigma = sqrt(st->var);
+    DevState& d = st[blockIdx.x];
+    const double n = d.n;
+    d.var = s / (n - 1.0);
+    d.sigma = sqrt(d.var);
     // normal-reference rule: (4/3)^(1/5) sigma n^(-1/5)
-    st->h_rot = pow(4.0 / 3.0, 0.2) * pow(n, -0.2) * st->sigma;
-    if (st->status == kStOk && !(st->sigma > 0.0 && isfinite(st->sigma))) st->status = kStDegenerate;
+    d.h_rot = pow(4.0 / 3.0, 0.2) * pow(n, -0.2) * d.sigma;
+    if (d.status == kStOk && !(d.sigma > 0.0 && isfinite(d.sigma))) d.status = kStDegenerate;
   }
 }
 
 // ------------------------------------------------------------------ plug-in scalar steps
-// Stage s in {0, 1, 2} estimates psi_r with r = 8 - 2 s.
-__global__ void k_psi_begin(DevState* st, int stage) {
-  if (st->status != kStOk) return;
+// One thread per column.  Stage s in {0, 1, 2} estimates psi_r, r = 8 - 2 s.
+__global__ void k_psi_begin(int n_cols, DevState* st, int stage) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n_cols) return;
+  DevState& d = st[col];
+  d.active = 0;
+  d.need_f64 = 0;
+  if (d.status != kStOk || d.pstatus != kStOk || d.stages == 0) return;
+  if (stage == 0 && d.stages != 3) return;
   const int r = 8 - 2 * stage;
   double psi_next;
   if (stage == 0) {
-    psi_next = psi_normal_scale(10, st->sigma);
+    psi_next = psi_normal_scale(10, d.sigma);
   } else if (stage == 1) {
-    if (st->stages == 2) st->psi[0] = psi_normal_scale(8, st->sigma);
-    psi_next = st->psi[0];
+    if (d.stages == 2) d.psi[0] = psi_normal_scale(8, d.sigma);
+    psi_next = d.psi[0];
   } else {
-    psi_next = st->psi[1];
+    psi_next = d.psi[1];
   }
   // AMSE pilot: g = [-2 K^(r)(0) / (mu_2 psi_{r+2} n)]^(1/(r+3)), mu_2 = 1
   const double k0 = herm_at0(r) / sqrt(2.0 * kPi);
-  const double rad = -2.0 * k0 / (psi_next * st->n);
+  const double rad = -2.0 * k0 / (psi_next * d.n);
   if (!(rad > 0.0) || !isfinite(rad)) {
-    st->status = kStDegenerate;
+    d.pstatus = kStDegenerate;
     return;
   }
   const double g = pow(rad, 1.0 / (double)(r + 3));
-  st->g[stage] = g;
+  d.active = 1;
+  d.g[stage] = g;
   const double ig2 = 1.0 / (g * g);
-  st->cf[0] = (float)ig2;
-  st->cf[1] = (float)(-0.5 * kLog2E * ig2);
-  st->cd[0] = ig2;
-  st->cd[1] = -0.5 * ig2;
-  st->need_f64 = 0;
+  d.cf[0] = (float)ig2;
+  d.cf[1] = (float)(-0.5 * kLog2E * ig2);
+  d.cd[0] = ig2;
+  d.cd[1] = -0.5 * ig2;
 }
 
-// sums[0] = sum_{i<j} He_r(u) e^{-u^2/2}, sums[1] = sum of its absolute value,
-// u = (X_i - X_j)/g.  psi_r = [2 sum K^(r) + n K^(r)(0)] / (n^2 g^(r+1)).
+// sums[2 col] = sum_{i<j} He_r(u) e^{-u^2/2}, sums[2 col + 1] = sum of its
+// absolute value, u = (X_i - X_j)/g.  psi_r = [2 sum K^(r) + n K^(r)(0)] / (n^2 g^(r+1)).
 // conditional: this is the FP64 re-run of the mixed form; skip unless flagged.
-__global__ void k_psi_finish(DevState* st, int stage, const double* __restrict__ sums, int was_f64,
+__global__ void k_psi_finish(int n_cols, DevState* st, int stage, const double* __restrict__ sums, int was_f64,
                              int conditional) {
-  if (st->status != kStOk) return;
-  if (conditional && !st->need_f64) return;
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n_cols) return;
+  DevState& d = st[col];
+  if (!d.active) return;
+  if (conditional && !d.need_f64) return;
   const int r = 8 - 2 * stage;
   const double inv_s2pi = 1.0 / sqrt(2.0 * kPi);
-  const double n = st->n, g = st->g[stage];
-  const double s = sums[0] * inv_s2pi, a = sums[1] * inv_s2pi;
-  st->psi[stage] = (2.0 * s + n * herm_at0(r) * inv_s2pi) / (n * n * pow(g, (double)(r + 1)));
-  st->kappa[stage] = (s != 0.0) ? a / fabs(s) : kInfD;
-  st->prec_used[stage] = was_f64 ? 1 : 0;
+  const double n = d.n, g = d.g[stage];
+  const double s = sums[2 * col] * inv_s2pi, a = sums[2 * col + 1] * inv_s2pi;
+  d.psi[stage] = (2.0 * s + n * herm_at0(r) * inv_s2pi) / (n * n * pow(g, (double)(r + 1)));
+  d.kappa[stage] = (s != 0.0) ? a / fabs(s) : kInfD;
+  d.prec_used[stage] = was_f64 ? 1 : 0;
   if (was_f64) {
-    st->need_f64 = 0;
+    d.need_f64 = 0;
   } else {
-    st->need_f64 = (st->fp64_kappa > 0.0 && st->kappa[stage] > st->fp64_kappa) ? 1 : 0;
+    d.need_f64 = (d.fp64_kappa > 0.0 && d.kappa[stage] > d.fp64_kappa) ? 1 : 0;
   }
 }
 
-__global__ void k_plugin_final(DevState* st) {
-  if (st->status != kStOk) return;
+__global__ void k_plugin_final(int n_cols, DevState* st) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n_cols) return;
+  DevState& d = st[col];
+  if (d.status != kStOk || d.pstatus != kStOk || d.stages == 0) return;
   // h = [R(K) / (mu_2^2 psi_4 n)]^(1/5), R(K) = 1/(2 sqrt(pi))
-  const double rad = (0.5 / sqrt(kPi)) / (st->psi[2] * st->n);
+  const double rad = (0.5 / sqrt(kPi)) / (d.psi[2] * d.n);
   if (!(rad > 0.0) || !isfinite(rad)) {
-    st->status = kStDegenerate;
+    d.pstatus = kStDegenerate;
     return;
   }
-  st->h_plugin = pow(rad, 0.2);
+  d.h_plugin = pow(rad, 0.2);
 }
 
 // ------------------------------------------------------------------ psi pair kernels
@@ -295,25 +338,29 @@ __device__ __forceinline__ void psi_run(const float4* __restrict__ tile, int jl,
   kahan_add(aA, cA, ra);
 }
 
+
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_psi_pairs_f32(const float* __restrict__ x, int n,
-                                                            const Item* __restrict__ items, int n_items, int bid0,
+__global__ __launch_bounds__(kThreads) void k_psi_units_f32(const float* __restrict__ x32,
+                                                            const ColDesc* __restrict__ cols,
+                                                            const Unit* __restrict__ units, int u0,
                                                             double* __restrict__ part,
                                                             const DevState* __restrict__ st) {
-  if (st->status != kStOk) return;
+  const Unit u = units[u0 + blockIdx.x];
+  if (!st[u.col].active) return;
+  const ColDesc c = cols[u.col];
+  const float* x = x32 + c.x_off;
+  const int n = c.n;
   __shared__ float4 tile[kBJ / 4];
   __shared__ double red[2][4];
-  const int item = bid0 + blockIdx.x;
-  const Item it = items[item];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int row0 = it.row * kBI;
+  const int row0 = u.row * kBI;
   const int i = row0 + tid;
   const float xi = (i < n) ? x[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
-  const float ig2 = st->cf[0], cg = st->cf[1];
+  const float ig2 = st[u.col].cf[0], cg = st[u.col].cf[1];
   float aS = 0.f, cS = 0.f, aA = 0.f, cA = 0.f;
-  for (int t0 = it.j_begin; t0 < it.j_end; t0 += kBJ) {
+  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
     for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
     __syncthreads();
@@ -337,7 +384,9 @@ __global__ __launch_bounds__(kThreads) void k_psi_pairs_f32(const float* __restr
     red[1][wave] = va;
   }
   __syncthreads();
-  if (tid < 2) part[(size_t)tid * n_items + item] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+  if (tid < 2)
+    part[c.psi_part_off + (int64_t)tid * c.n_items_psi + u.item] =
+        ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
 }
 
 template <int R, bool MASK>
@@ -355,27 +404,30 @@ __device__ __forceinline__ void psi_run64(const double* __restrict__ tile, int j
   }
 }
 
-// conditional: run only when the FP32 pass flagged this stage (mixed form).
+// conditional: run only when the FP32 pass flagged this column's stage (mixed form).
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_psi_pairs_f64(const double* __restrict__ x, int n,
-                                                            const Item* __restrict__ items, int n_items, int bid0,
-                                                            double* __restrict__ part, const DevState* __restrict__ st,
-                                                            int conditional) {
-  if (st->status != kStOk) return;
-  if (conditional && !st->need_f64) return;
+__global__ __launch_bounds__(kThreads) void k_psi_units_f64(const double* __restrict__ x64,
+                                                            const ColDesc* __restrict__ cols,
+                                                            const Unit* __restrict__ units, int u0,
+                                                            double* __restrict__ part,
+                                                            const DevState* __restrict__ st, int conditional) {
+  const Unit u = units[u0 + blockIdx.x];
+  if (!st[u.col].active) return;
+  if (conditional && !st[u.col].need_f64) return;
+  const ColDesc c = cols[u.col];
+  const double* x = x64 + c.x_off;
+  const int n = c.n;
   __shared__ double tile[kBJ];
   __shared__ double red[2][4];
-  const int item = bid0 + blockIdx.x;
-  const Item it = items[item];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int row0 = it.row * kBI;
+  const int row0 = u.row * kBI;
   const int i = row0 + tid;
   const double xi = (i < n) ? x[i] : 0.0;
   const int wave_i0 = row0 + wave * 64;
-  const double ig2 = st->cd[0], cg = st->cd[1];
+  const double ig2 = st[u.col].cd[0], cg = st[u.col].cd[1];
   double s = 0.0, a = 0.0;
-  for (int t0 = it.j_begin; t0 < it.j_end; t0 += kBJ) {
+  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
     for (int q = tid; q < kBJ / 2; q += kThreads)
       reinterpret_cast<double2*>(tile)[q] = reinterpret_cast<const double2*>(x + t0)[q];
@@ -398,31 +450,43 @@ __global__ __launch_bounds__(kThreads) void k_psi_pairs_f64(const double* __rest
     red[1][wave] = va;
   }
   __syncthreads();
-  if (tid < 2) part[(size_t)tid * n_items + item] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+  if (tid < 2)
+    part[c.psi_part_off + (int64_t)tid * c.n_items_psi + u.item] =
+        ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
 }
 
 // ------------------------------------------------------------------ LSCV kernels
-// c32[k] = -log2(e) / (4 h_k^2), so exp2(D^2 c32[k]) = exp(-D^2/(4 h^2)) and its
-// square is exp(-D^2/(2 h^2)).  Padded chunk entries hold -1 (finite, unused).
-__global__ __launch_bounds__(kThreads) void k_lscv_prep(const double* __restrict__ h_in, int n_h, int n_h_pad,
-                                                        DevState* st, double* __restrict__ h_dev,
-                                                        float* __restrict__ c32, double* __restrict__ c64) {
-  const bool dflt = (h_in == nullptr);
-  const double lo = st->h_rot * 0.25, hi = st->h_rot * 4.0;
-  for (int k = threadIdx.x; k < n_h_pad; k += kThreads) {
-    if (k < n_h) {
+// Block per column.  Grid point k of the column: explicit h_in[c_off + k], the
+// paper's default (linear over sigma [h0/4, 4 h0] = h_rot [1/4, 4]) or log-spaced
+// over h_rot [lo, hi].  c32 = -log2(e) / (4 h^2), so exp2(D^2 c32) =
+// exp(-D^2/(4 h^2)) and its square is exp(-D^2/(2 h^2)); c64 = -1/(4 h^2).
+// Entries past n_h up to the chunk multiple hold -1 (finite, unused).
+__global__ __launch_bounds__(kThreads) void k_lscv_prep(const ColDesc* __restrict__ cols, int hc,
+                                                        const double* __restrict__ h_in, DevState* st,
+                                                        double* __restrict__ h_dev, float* __restrict__ c32,
+                                                        double* __restrict__ c64) {
+  const ColDesc c = cols[blockIdx.x];
+  if (c.n_h <= 0) return;
+  const double hr = st[blockIdx.x].h_rot;
+  const int m = c.n_chunks * hc;
+  for (int k = threadIdx.x; k < m; k += kThreads) {
+    const int64_t o = c.c_off + k;
+    if (k < c.n_h) {
       double h;
-      if (dflt)
-        h = (n_h == 1) ? lo : lo + (hi - lo) * (double)k / (double)(n_h - 1);
+      const double t = (c.n_h == 1) ? 0.0 : (double)k / (double)(c.n_h - 1);
+      if (c.grid_kind == kGridExplicit)
+        h = h_in[o];
+      else if (c.grid_kind == kGridPaper)
+        h = hr * 0.25 + (hr * 4.0 - hr * 0.25) * t;
       else
-        h = h_in[k];
-      h_dev[k] = h;
+        h = hr * exp(log(c.grid_lo) + (log(c.grid_hi) - log(c.grid_lo)) * t);
+      h_dev[o] = h;
       const double q = 1.0 / (4.0 * h * h);
-      c32[k] = (float)(-kLog2E * q);
-      c64[k] = -q;
+      c32[o] = (float)(-kLog2E * q);
+      c64[o] = -q;
     } else {
-      c32[k] = -1.0f;
-      c64[k] = -1.0;
+      c32[o] = -1.0f;
+      c64[o] = -1.0;
     }
   }
 }
@@ -462,31 +526,33 @@ __device__ __forceinline__ void lscv_run(const float4* __restrict__ tile, int jl
 }
 
 template <int HC>
-__global__ __launch_bounds__(kThreads) void k_lscv_pairs_f32(const float* __restrict__ x, int n,
-                                                             const Item* __restrict__ items, int n_items,
-                                                             int n_chunks, const float* __restrict__ c32, int n_h,
-                                                             int bid0, double* __restrict__ part,
+__global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const float* __restrict__ x32,
+                                                             const ColDesc* __restrict__ cols,
+                                                             const Unit* __restrict__ units, int u0,
+                                                             const float* __restrict__ c32,
+                                                             double* __restrict__ part,
                                                              const DevState* __restrict__ st) {
-  if (st->status != kStOk) return;
+  const Unit u = units[u0 + blockIdx.x];
+  if (st[u.col].status != kStOk) return;
+  const ColDesc c = cols[u.col];
+  const float* x = x32 + c.x_off;
+  const int n = c.n;
   __shared__ float4 tile[kBJ / 4];
   __shared__ double red[4][2 * HC];
-  const int bid = bid0 + blockIdx.x;
-  const int item = bid / n_chunks;
-  const int chunk = bid - item * n_chunks;
-  const Item it = items[item];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int row0 = it.row * kBI;
+  const int row0 = u.row * kBI;
   const int i = row0 + tid;
   const float xi = (i < n) ? x[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
+  const float* cc = c32 + c.c_off + u.chunk * HC;
   float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    ck[k] = c32[chunk * HC + k];
+    ck[k] = cc[k];
     a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
   }
-  for (int t0 = it.j_begin; t0 < it.j_end; t0 += kBJ) {
+  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
     for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
     __syncthreads();
@@ -512,10 +578,10 @@ __global__ __launch_bounds__(kThreads) void k_lscv_pairs_f32(const float* __rest
   }
   __syncthreads();
   if (tid < 2 * HC) {
-    const int h = chunk * HC + (tid >> 1);
-    if (h < n_h) {
+    const int h = u.chunk * HC + (tid >> 1);
+    if (h < c.n_h) {
       const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      part[(size_t)(2 * h + (tid & 1)) * n_items + item] = v;
+      part[c.part_off + (int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
     }
   }
 }
@@ -538,31 +604,33 @@ __device__ __forceinline__ void lscv_run64(const double* __restrict__ tile, int 
 }
 
 template <int HC>
-__global__ __launch_bounds__(kThreads) void k_lscv_pairs_f64(const double* __restrict__ x, int n,
-                                                             const Item* __restrict__ items, int n_items,
-                                                             int n_chunks, const double* __restrict__ c64, int n_h,
-                                                             int bid0, double* __restrict__ part,
+__global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const double* __restrict__ x64,
+                                                             const ColDesc* __restrict__ cols,
+                                                             const Unit* __restrict__ units, int u0,
+                                                             const double* __restrict__ c64,
+                                                             double* __restrict__ part,
                                                              const DevState* __restrict__ st) {
-  if (st->status != kStOk) return;
+  const Unit u = units[u0 + blockIdx.x];
+  if (st[u.col].status != kStOk) return;
+  const ColDesc c = cols[u.col];
+  const double* x = x64 + c.x_off;
+  const int n = c.n;
   __shared__ double tile[kBJ];
   __shared__ double red[4][2 * HC];
-  const int bid = bid0 + blockIdx.x;
-  const int item = bid / n_chunks;
-  const int chunk = bid - item * n_chunks;
-  const Item it = items[item];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int row0 = it.row * kBI;
+  const int row0 = u.row * kBI;
   const int i = row0 + tid;
   const double xi = (i < n) ? x[i] : 0.0;
   const int wave_i0 = row0 + wave * 64;
+  const double* cc = c64 + c.c_off + u.chunk * HC;
   double ck[HC], s1[HC], s2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    ck[k] = c64[chunk * HC + k];
+    ck[k] = cc[k];
     s1[k] = s2[k] = 0.0;
   }
-  for (int t0 = it.j_begin; t0 < it.j_end; t0 += kBJ) {
+  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
     for (int q = tid; q < kBJ / 2; q += kThreads)
       reinterpret_cast<double2*>(tile)[q] = reinterpret_cast<const double2*>(x + t0)[q];
@@ -589,25 +657,34 @@ __global__ __launch_bounds__(kThreads) void k_lscv_pairs_f64(const double* __res
   }
   __syncthreads();
   if (tid < 2 * HC) {
-    const int h = chunk * HC + (tid >> 1);
-    if (h < n_h) {
+    const int h = u.chunk * HC + (tid >> 1);
+    if (h < c.n_h) {
       const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      part[(size_t)(2 * h + (tid & 1)) * n_items + item] = v;
+      part[c.part_off + (int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
     }
   }
 }
 
-// g(h) = h^-1 [2 n^-2 ((4pi)^-1/2 S1 - 2 (2pi)^-1/2 S2) + n^-1 (4pi)^-1/2]; gscale with +.
-// Grid argmin with ties to the lowest index.
-__global__ __launch_bounds__(1024) void k_lscv_finalize(const double* __restrict__ sums, int n_h,
-                                                        const double* __restrict__ h_dev, DevState* st,
-                                                        double* __restrict__ g, double* __restrict__ gscale) {
+// Block per column.  g(h) = h^-1 [2 n^-2 ((4pi)^-1/2 S1 - 2 (2pi)^-1/2 S2) + n^-1 (4pi)^-1/2];
+// gscale with +.  Grid argmin with ties to the lowest index.
+__global__ __launch_bounds__(1024) void k_lscv_finalize(const ColDesc* __restrict__ cols,
+                                                        const double* __restrict__ sums_all,
+                                                        const double* __restrict__ h_all, DevState* st,
+                                                        double* __restrict__ g_all, double* __restrict__ gs_all) {
+  const ColDesc c = cols[blockIdx.x];
+  if (c.n_h <= 0) return;
+  DevState& d = st[blockIdx.x];
+  const int n_h = c.n_h;
+  const double* sums = sums_all + 2 * c.c_off;
+  const double* h_dev = h_all + c.c_off;
+  double* g = g_all + c.c_off;
+  double* gscale = gs_all + c.c_off;
   __shared__ double bv[1024];
   __shared__ int bk[1024];
   const int t = threadIdx.x;
-  const double n = st->n;
+  const double n = d.n;
   const double ckk = 1.0 / sqrt(4.0 * kPi), ck = 1.0 / sqrt(2.0 * kPi);
-  const bool ok = st->status == kStOk;
+  const bool ok = d.status == kStOk;
   double best = kInfD;
   int kbest = 0x7fffffff;
   for (int k = t; k < n_h; k += blockDim.x) {
@@ -649,108 +726,103 @@ __global__ __launch_bounds__(1024) void k_lscv_finalize(const double* __restrict
   }
   if (t == 0 && ok) {
     if (kb < n_h) {
-      st->k_best = kb;
-      st->h_best = h_dev[kb];
-      st->at_edge = (kb == 0 || kb == n_h - 1) ? 1 : 0;
-      st->margin = (n_h > 1) ? bv[0] - vb : 0.0;
+      d.k_best = kb;
+      d.h_best = h_dev[kb];
+      d.at_edge = (kb == 0 || kb == n_h - 1) ? 1 : 0;
+      d.margin = (n_h > 1) ? bv[0] - vb : 0.0;
     } else {
-      st->status = kStDegenerate;  // every g(h) was NaN
+      d.status = kStDegenerate;  // every g(h) was NaN
     }
   }
 }
 
-// out[r] = sum_c part[r * n_cols + c], in a fixed order.
-__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* __restrict__ part, int n_cols,
+// Segmented sum, block per row: out[dst] = sum_c part[src + c], fixed order.
+__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* __restrict__ part,
+                                                          const RowDesc* __restrict__ rows,
                                                           double* __restrict__ out) {
   __shared__ double sh[kThreads];
-  const double* p = part + (size_t)blockIdx.x * n_cols;
+  const RowDesc r = rows[blockIdx.x];
+  const double* p = part + r.src;
   double s = 0.0;
-  for (int c = threadIdx.x; c < n_cols; c += kThreads) s += p[c];
+  for (int c = threadIdx.x; c < r.n; c += kThreads) s += p[c];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = s;
+  if (threadIdx.x == 0) out[r.dst] = s;
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-void launch_stats_sum(hipStream_t s, const void* x, int is_f64, int n, double* part, int* part_nf, int nblk) {
-  if (is_f64)
-    k_stats_sum<double><<<nblk, kThreads, 0, s>>>((const double*)x, n, part, part_nf);
-  else
-    k_stats_sum<float><<<nblk, kThreads, 0, s>>>((const float*)x, n, part, part_nf);
+void launch_stats(hipStream_t s, int n_cols, int max_blocks, const ColDesc* cols, double* part, int* part_nf,
+                  float* x32, double* x64, DevState* st) {
+  const dim3 grid2(max_blocks, n_cols);
+  k_stats_sum<<<grid2, kThreads, 0, s>>>(cols, part, part_nf);
+  k_stats_mean<<<n_cols, kThreads, 0, s>>>(cols, part, part_nf, st);
+  k_stats_dev<<<grid2, kThreads, 0, s>>>(cols, part, x32, x64, st);
+  k_stats_final<<<n_cols, kThreads, 0, s>>>(cols, part, st);
 }
 
-void launch_stats_mean(hipStream_t s, const double* part, const int* part_nf, int nblk, int n, int shift_by_mean,
-                       DevState* st) {
-  k_stats_mean<<<1, kThreads, 0, s>>>(part, part_nf, nblk, n, shift_by_mean, st);
+static inline int col_blocks(int n_cols) { return (n_cols + kThreads - 1) / kThreads; }
+
+void launch_psi_begin(hipStream_t s, int n_cols, DevState* st, int stage) {
+  k_psi_begin<<<col_blocks(n_cols), kThreads, 0, s>>>(n_cols, st, stage);
 }
 
-void launch_stats_dev(hipStream_t s, const void* x, int is_f64, int n, int n_pad, double* part, float* x32,
-                      double* x64, int nblk, DevState* st) {
-  if (is_f64)
-    k_stats_dev<double><<<nblk, kThreads, 0, s>>>((const double*)x, n, n_pad, part, x32, x64, st);
-  else
-    k_stats_dev<float><<<nblk, kThreads, 0, s>>>((const float*)x, n, n_pad, part, x32, x64, st);
+void launch_psi_finish(hipStream_t s, int n_cols, const ColDesc* cols, DevState* st, int stage, const double* sums,
+                       int was_f64, int conditional) {
+  (void)cols;
+  k_psi_finish<<<col_blocks(n_cols), kThreads, 0, s>>>(n_cols, st, stage, sums, was_f64, conditional);
 }
 
-void launch_stats_final(hipStream_t s, const double* part, int nblk, DevState* st) {
-  k_stats_final<<<1, kThreads, 0, s>>>(part, nblk, st);
+void launch_plugin_final(hipStream_t s, int n_cols, DevState* st) {
+  k_plugin_final<<<col_blocks(n_cols), kThreads, 0, s>>>(n_cols, st);
 }
 
-void launch_psi_begin(hipStream_t s, DevState* st, int stage) { k_psi_begin<<<1, 1, 0, s>>>(st, stage); }
-
-void launch_psi_finish(hipStream_t s, DevState* st, int stage, const double* sums, int was_f64, int conditional) {
-  k_psi_finish<<<1, 1, 0, s>>>(st, stage, sums, was_f64, conditional);
-}
-
-void launch_plugin_final(hipStream_t s, DevState* st) { k_plugin_final<<<1, 1, 0, s>>>(st); }
-
-void launch_psi_pairs(hipStream_t s, int r, int f64, int conditional, const float* x32, const double* x64, int n,
-                      const Item* items, int n_items, int bid0, int nblk, double* part, const DevState* st) {
+void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const float* x32, const double* x64,
+                      const ColDesc* cols, const Unit* units, int u0, int n_units, double* part, const DevState* st) {
   if (f64) {
     switch (r) {
-      case 8: k_psi_pairs_f64<8><<<nblk, kThreads, 0, s>>>(x64, n, items, n_items, bid0, part, st, conditional); break;
-      case 6: k_psi_pairs_f64<6><<<nblk, kThreads, 0, s>>>(x64, n, items, n_items, bid0, part, st, conditional); break;
-      default: k_psi_pairs_f64<4><<<nblk, kThreads, 0, s>>>(x64, n, items, n_items, bid0, part, st, conditional); break;
+      case 8: k_psi_units_f64<8><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, part, st, conditional); break;
+      case 6: k_psi_units_f64<6><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, part, st, conditional); break;
+      default: k_psi_units_f64<4><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, part, st, conditional); break;
     }
   } else {
     switch (r) {
-      case 8: k_psi_pairs_f32<8><<<nblk, kThreads, 0, s>>>(x32, n, items, n_items, bid0, part, st); break;
-      case 6: k_psi_pairs_f32<6><<<nblk, kThreads, 0, s>>>(x32, n, items, n_items, bid0, part, st); break;
-      default: k_psi_pairs_f32<4><<<nblk, kThreads, 0, s>>>(x32, n, items, n_items, bid0, part, st); break;
+      case 8: k_psi_units_f32<8><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, part, st); break;
+      case 6: k_psi_units_f32<6><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, part, st); break;
+      default: k_psi_units_f32<4><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, part, st); break;
     }
   }
 }
 
-void launch_lscv_prep(hipStream_t s, const double* h_in, int n_h, int n_h_pad, DevState* st, double* h_dev,
-                      float* c32, double* c64) {
-  k_lscv_prep<<<1, kThreads, 0, s>>>(h_in, n_h, n_h_pad, st, h_dev, c32, c64);
+void launch_lscv_prep(hipStream_t s, int n_cols, int hc, const ColDesc* cols, const double* h_in, DevState* st,
+                      double* h_dev, float* c32, double* c64) {
+  k_lscv_prep<<<n_cols, kThreads, 0, s>>>(cols, hc, h_in, st, h_dev, c32, c64);
 }
 
-void launch_lscv_pairs(hipStream_t s, int hc, int f64, const float* x32, const double* x64, int n,
-                       const Item* items, int n_items, int n_chunks, const float* c32, const double* c64, int n_h,
-                       int bid0, int nblk, double* part, const DevState* st) {
+void launch_lscv_units(hipStream_t s, int hc, int f64, const float* x32, const double* x64, const ColDesc* cols,
+                       const Unit* units, int u0, int n_units, const float* c32, const double* c64, double* part,
+                       const DevState* st) {
   if (f64) {
     switch (hc) {
-      case 4: k_lscv_pairs_f64<4><<<nblk, kThreads, 0, s>>>(x64, n, items, n_items, n_chunks, c64, n_h, bid0, part, st); break;
-      default: k_lscv_pairs_f64<8><<<nblk, kThreads, 0, s>>>(x64, n, items, n_items, n_chunks, c64, n_h, bid0, part, st); break;
+      case 4: k_lscv_units_f64<4><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, c64, part, st); break;
+      default: k_lscv_units_f64<8><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, c64, part, st); break;
     }
   } else {
     switch (hc) {
-      case 8: k_lscv_pairs_f32<8><<<nblk, kThreads, 0, s>>>(x32, n, items, n_items, n_chunks, c32, n_h, bid0, part, st); break;
-      case 32: k_lscv_pairs_f32<32><<<nblk, kThreads, 0, s>>>(x32, n, items, n_items, n_chunks, c32, n_h, bid0, part, st); break;
-      default: k_lscv_pairs_f32<16><<<nblk, kThreads, 0, s>>>(x32, n, items, n_items, n_chunks, c32, n_h, bid0, part, st); break;
+      case 8: k_lscv_units_f32<8><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, c32, part, st); break;
+      case 32: k_lscv_units_f32<32><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, c32, part, st); break;
+      default: k_lscv_units_f32<16><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, c32, part, st); break;
     }
   }
 }
 
-void launch_lscv_finalize(hipStream_t s, const double* sums, int n_h, const double* h_dev, DevState* st, double* g,
-                          double* gscale) {
-  k_lscv_finalize<<<1, 1024, 0, s>>>(sums, n_h, h_dev, st, g, gscale);
+void launch_lscv_finalize(hipStream_t s, int n_cols, const ColDesc* cols, const double* sums, const double* h_dev,
+                          DevState* st, double* g, double* gscale) {
+  k_lscv_finalize<<<n_cols, 1024, 0, s>>>(cols, sums, h_dev, st, g, gscale);
 }
 
-void launch_reduce_rows(hipStream_t s, const double* part, int n_cols, int n_rows, double* out) {
-  k_reduce_rows<<<n_rows, kThreads, 0, s>>>(part, n_cols, out);
+void launch_reduce_rows(hipStream_t s, const double* part, const RowDesc* rows, int n_rows, double* out) {
+  if (n_rows > 0) k_reduce_rows<<<n_rows, kThreads, 0, s>>>(part, rows, out);
 }
 
 }  // namespace kde

@@ -1,10 +1,13 @@
 // kde_runtime.hip -- host runtime and C ABI of the bandwidth-selection library.
 //
-// A call is a chain of kernels on one stream: ingest + moments (FP64, two
-// passes), the device-side scalar steps of the selector, the pair kernels
-// (split into launches of bounded work), fixed-order FP64 reductions and a
-// finalize kernel; one device-to-host copy at the end returns the results.
-// No step runs on the host except argument checks and work-list planning.
+// Every call is a job over a set of columns (one for the single-column
+// selectors, many for kde_batch).  A job is a chain of kernels on one stream:
+// moments for all columns (FP64, two passes), the device-side scalar steps of
+// the selectors, the pair kernels over work units that mix columns (split into
+// launches of bounded work), fixed-order FP64 segmented reductions and the
+// finalize kernels; one round of device-to-host copies returns the results.
+// No step of the method runs on the host: the host checks arguments and plans
+// the work units.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,8 +20,10 @@
 #include "kde_bw.h"
 #include "kde_internal.h"
 
+using kde::ColDesc;
 using kde::DevState;
-using kde::Item;
+using kde::RowDesc;
+using kde::Unit;
 
 namespace {
 
@@ -28,20 +33,35 @@ struct Pending {
   double evals;
 };
 
-struct Plan {
-  int64_t n = -1;
-  int64_t seg = -1;
-  std::vector<Item> items;
-  std::vector<double> pairs;  // algorithmic i<j pairs of each item
-  double total_pairs = 0.0;
-  Item* d_items = nullptr;
-  size_t cap = 0;
-};
-
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t cap = 0;
+};
+
+// Work items of one column for one pass: blocks of the i < j triangle.
+struct ColItems {
+  std::vector<int> row, jb, je;
+  std::vector<double> pairs;
+};
+
+// One column of a job as the host plans it.
+struct JobCol {
+  int req;            // index of the request it came from
+  const void* data;   // caller's samples (host or device)
+  int on_device;
+  int n;
+  int f64;
+  bool plugin, lscv;
+  int stages;
+  kde_grid grid;
+  ColDesc d;          // device descriptor (raw pointer filled at run time)
+  ColItems lscv_items, psi_items;
+};
+
+struct UnitCost {
+  double pairs;   // algorithmic i<j pairs of the unit's item
+  double evals;   // pair-term evaluations of the unit
 };
 
 }  // namespace
@@ -54,7 +74,7 @@ struct kde_ctx {
   std::string err;
   // options
   int opt_hc = 16;
-  int64_t opt_seg = -1;           // <0 automatic, 0 whole rows, >0 explicit
+  int64_t opt_seg = -1;            // <0 automatic, 0 whole rows, >0 explicit
   double opt_launch_evals = 4e12;  // pair-term evaluations per launch
   double opt_fp64_kappa = 1e3;
   // device workspace
@@ -64,17 +84,26 @@ struct kde_ctx {
   DevBuf<double> part;
   DevBuf<int> part_nf;
   DevBuf<double> stat_part;
-  DevBuf<double> sums;
+  DevBuf<double> psi_sums, lscv_sums;
   DevBuf<double> hin, hdev, c64, g, gs;
   DevBuf<float> c32;
-  DevState* d_st = nullptr;
+  DevBuf<ColDesc> cols;
+  DevBuf<Unit> units;
+  DevBuf<RowDesc> rows;
+  DevBuf<DevState> st;
   // pinned host staging
   DevState* h_st = nullptr;
+  size_t h_st_cap = 0;
   double* h_out = nullptr;
   size_t h_out_cap = 0;
-  // work lists (one per segment length in use)
-  Plan plans[2];
-  int plan_next = 0;
+  // host-side plan of the current job (kept alive until the job's copies finish)
+  std::vector<JobCol> jcols;
+  std::vector<ColDesc> h_cols;
+  std::vector<Unit> h_units;       // psi units, then LSCV units
+  std::vector<UnitCost> h_cost;
+  std::vector<RowDesc> h_rows;     // psi rows, then LSCV rows
+  std::vector<double> h_hin;
+  size_t n_psi_units = 0, n_lscv_units = 0, n_psi_rows = 0, n_lscv_rows = 0;
   // timing
   bool timing = false;
   int64_t t_launches[2] = {0, 0};
@@ -93,9 +122,9 @@ kde_status fail(kde_ctx* c, kde_status st, const std::string& msg) {
   return st;
 }
 
-#define HIP_TRY(ctx, expr)                                                                         \
-  do {                                                                                             \
-    hipError_t e_ = (expr);                                                                        \
+#define HIP_TRY(ctx, expr)                                                                                    \
+  do {                                                                                                        \
+    hipError_t e_ = (expr);                                                                                   \
     if (e_ != hipSuccess) return fail((ctx), KDE_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
@@ -115,18 +144,28 @@ kde_status ensure(kde_ctx* c, DevBuf<T>& b, size_t count) {
   return KDE_OK;
 }
 
-kde_status ensure_host_out(kde_ctx* c, size_t count) {
-  if (c->h_out_cap >= count) return KDE_OK;
-  if (c->h_out) (void)hipHostFree(c->h_out);
-  c->h_out = nullptr;
-  c->h_out_cap = 0;
-  size_t want = std::max<size_t>(count, 4096);
-  if (hipHostMalloc((void**)&c->h_out, want * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    c->h_out = nullptr;
+template <typename T>
+kde_status ensure_pinned(kde_ctx* c, T*& p, size_t& cap, size_t count) {
+  if (cap >= count) return KDE_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+  size_t want = std::max<size_t>(count, 64);
+  if (hipHostMalloc((void**)&p, want * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+    p = nullptr;
     return fail(c, KDE_E_NOMEM, "pinned host allocation failed");
   }
-  c->h_out_cap = want;
+  cap = want;
   return KDE_OK;
+}
+
+kde_status status_of(int st) {
+  switch (st) {
+    case kde::kStOk: return KDE_OK;
+    case kde::kStInval: return KDE_E_INVAL;
+    case kde::kStDegenerate: return KDE_E_DEGENERATE;
+    default: return KDE_E_DEVICE;
+  }
 }
 
 kde_status map_status(kde_ctx* c, int st) {
@@ -183,137 +222,82 @@ kde_status sync_and_check(kde_ctx* c) {
   return collect_timing(c);
 }
 
-// ---- column ingest and moments
-kde_status check_column(kde_ctx* c, const kde_column& x) {
-  if (!x.data) return fail(c, KDE_E_INVAL, "column data is NULL");
-  if (x.n < 2) return fail(c, KDE_E_INVAL, "a sample column needs n >= 2");
-  if (x.n > KDE_MAX_N) return fail(c, KDE_E_INVAL, "n exceeds KDE_MAX_N");
-  if (x.dtype != KDE_F32 && x.dtype != KDE_F64) return fail(c, KDE_E_INVAL, "dtype must be KDE_F32 or KDE_F64");
-  return KDE_OK;
+// ---- argument checks
+std::string check_column(const kde_column& x) {
+  if (!x.data) return "column data is NULL";
+  if (x.n < 2) return "a sample column needs n >= 2";
+  if (x.n > KDE_MAX_N) return "n exceeds KDE_MAX_N";
+  if (x.dtype != KDE_F32 && x.dtype != KDE_F64) return "dtype must be KDE_F32 or KDE_F64";
+  return "";
 }
 
-kde_status init_state(kde_ctx* c, int stages) {
-  DevState& h = *c->h_st;
-  std::memset(&h, 0, sizeof(h));
-  const double nan = std::nan("");
-  h.stages = stages;
-  for (int k = 0; k < 3; ++k) {
-    h.g[k] = h.psi[k] = h.kappa[k] = nan;
-    h.prec_used[k] = -1;
+std::string check_grid(const kde_grid& g) {
+  if (g.n_h < 1 || g.n_h > KDE_MAX_NH) return "n_h out of range";
+  if (g.kind == KDE_GRID_EXPLICIT) {
+    if (!g.h) return "explicit grid is NULL";
+    for (int32_t k = 0; k < g.n_h; ++k) {
+      if (!(g.h[k] > 0.0) || !std::isfinite(g.h[k])) return "grid values must be finite and > 0";
+      if (k > 0 && !(g.h[k] > g.h[k - 1])) return "grid must be strictly ascending";
+    }
+  } else if (g.kind == KDE_GRID_LOG_ROT) {
+    if (!(g.lo > 0.0) || !(g.hi > g.lo) || !std::isfinite(g.hi)) return "log grid needs 0 < lo < hi";
+  } else if (g.kind != KDE_GRID_PAPER) {
+    return "unknown grid kind";
   }
-  h.h_plugin = h.h_best = h.margin = nan;
-  h.k_best = -1;
-  h.fp64_kappa = c->opt_fp64_kappa;
-  HIP_TRY(c, hipMemcpyAsync(c->d_st, c->h_st, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
-  return KDE_OK;
+  return "";
 }
 
-// Stages the column on the device and runs the two moment passes; afterwards
-// x32 (and x64 when requested) hold the padded sample.  Host copies of the
-// state are not refreshed here.
-kde_status prepare_column(kde_ctx* c, const kde_column& x, bool want_x64, int stages) {
-  kde_status s = check_column(c, x);
-  if (s) return s;
-  const int n = (int)x.n;
-  const int is_f64 = x.dtype == KDE_F64;
-  const size_t esz = is_f64 ? 8 : 4;
-  const int n_pad = n + kde::kPad;
-  if ((s = init_state(c, stages))) return s;
-  const void* src = x.data;
-  if (!x.on_device) {
-    if ((s = ensure(c, c->stage, (size_t)n * esz))) return s;
-    HIP_TRY(c, hipMemcpyAsync(c->stage.p, x.data, (size_t)n * esz, hipMemcpyHostToDevice, c->stream));
-    src = c->stage.p;
-  }
-  if ((s = ensure(c, c->x32, (size_t)n_pad))) return s;
-  if (want_x64 && (s = ensure(c, c->x64, (size_t)n_pad))) return s;
-  const int nblk = std::max(1, std::min(1024, (n + 2047) / 2048));
-  if ((s = ensure(c, c->stat_part, (size_t)nblk))) return s;
-  if ((s = ensure(c, c->part_nf, (size_t)nblk))) return s;
-  kde::launch_stats_sum(c->stream, src, is_f64, n, c->stat_part.p, c->part_nf.p, nblk);
-  kde::launch_stats_mean(c->stream, c->stat_part.p, c->part_nf.p, nblk, n, is_f64, c->d_st);
-  kde::launch_stats_dev(c->stream, src, is_f64, n, n_pad, c->stat_part.p, c->x32.p, want_x64 ? c->x64.p : nullptr,
-                        nblk, c->d_st);
-  kde::launch_stats_final(c->stream, c->stat_part.p, nblk, c->d_st);
-  HIP_TRY(c, hipGetLastError());
-  return KDE_OK;
-}
-
-// ---- work lists
-double item_pairs(int64_t n, const Item& it) {
-  const int64_t i0 = (int64_t)it.row * kde::kBI;
+// ---- work items
+double item_pairs(int64_t n, int64_t row, int64_t jb, int64_t je) {
+  const int64_t i0 = row * kde::kBI;
   const int64_t i1 = std::min<int64_t>(n, i0 + kde::kBI);
-  const int64_t je = std::min<int64_t>(it.j_end, n);
+  je = std::min<int64_t>(je, n);
   double p = 0.0;
   for (int64_t i = i0; i < i1; ++i) {
-    const int64_t jb = std::max<int64_t>(it.j_begin, i + 1);
-    if (je > jb) p += (double)(je - jb);
+    const int64_t b = std::max<int64_t>(jb, i + 1);
+    if (je > b) p += (double)(je - b);
   }
   return p;
 }
 
-// seg: j-range per item in samples (multiple of kBJ), or 0 for whole rows.
-kde_status get_plan(kde_ctx* c, int64_t n, int64_t seg, Plan** out) {
-  for (Plan& p : c->plans)
-    if (p.n == n && p.seg == seg) {
-      *out = &p;
-      return KDE_OK;
-    }
-  Plan& p = c->plans[c->plan_next];
-  c->plan_next ^= 1;
-  p.n = -1;
-  p.items.clear();
-  p.pairs.clear();
-  p.total_pairs = 0.0;
+// Items of one column: row r sweeps j in [r*kBI, n) rounded up to kBJ, cut
+// into pieces of `seg` samples (0: one piece).  Ordered longest first.
+void make_items(int64_t n, int64_t seg, ColItems& out) {
+  std::vector<int> row, jb, je;
+  std::vector<double> pr;
   const int64_t rows = (n + kde::kBI - 1) / kde::kBI;
   for (int64_t r = 0; r < rows; ++r) {
     const int64_t row0 = r * kde::kBI;
     const int64_t len = ((n - row0) + kde::kBJ - 1) / kde::kBJ * kde::kBJ;
     const int64_t step = seg > 0 ? seg : len;
-    for (int64_t jb = row0; jb < row0 + len; jb += step) {
-      Item it;
-      it.row = (int)r;
-      it.j_begin = (int)jb;
-      it.j_end = (int)std::min(jb + step, row0 + len);
-      it.pad = 0;
-      const double pr = item_pairs(n, it);
-      if (pr <= 0.0) continue;
-      p.items.push_back(it);
-      p.pairs.push_back(pr);
-      p.total_pairs += pr;
+    for (int64_t b = row0; b < row0 + len; b += step) {
+      const int64_t e = std::min(b + step, row0 + len);
+      const double p = item_pairs(n, r, b, e);
+      if (p <= 0.0) continue;
+      row.push_back((int)r);
+      jb.push_back((int)b);
+      je.push_back((int)e);
+      pr.push_back(p);
     }
   }
-  // longest first: the block scheduler then drains the triangle largest-first
-  std::vector<size_t> order(p.items.size());
+  std::vector<size_t> order(pr.size());
   for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return p.pairs[a] > p.pairs[b]; });
-  std::vector<Item> items(order.size());
-  std::vector<double> pairs(order.size());
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return pr[a] > pr[b]; });
+  out.row.resize(order.size());
+  out.jb.resize(order.size());
+  out.je.resize(order.size());
+  out.pairs.resize(order.size());
   for (size_t k = 0; k < order.size(); ++k) {
-    items[k] = p.items[order[k]];
-    pairs[k] = p.pairs[order[k]];
+    out.row[k] = row[order[k]];
+    out.jb[k] = jb[order[k]];
+    out.je[k] = je[order[k]];
+    out.pairs[k] = pr[order[k]];
   }
-  p.items.swap(items);
-  p.pairs.swap(pairs);
-  if (p.cap < p.items.size()) {
-    if (p.d_items) (void)hipFree(p.d_items);
-    p.d_items = nullptr;
-    p.cap = 0;
-    if (hipMalloc((void**)&p.d_items, p.items.size() * sizeof(Item)) != hipSuccess)
-      return fail(c, KDE_E_NOMEM, "device allocation of the work list failed");
-    p.cap = p.items.size();
-  }
-  // The stream is idle between calls, so the host vector outlives the copy.
-  HIP_TRY(c, hipMemcpyAsync(p.d_items, p.items.data(), p.items.size() * sizeof(Item), hipMemcpyHostToDevice,
-                            c->stream));
-  p.n = n;
-  p.seg = seg;
-  *out = &p;
-  return KDE_OK;
 }
 
-// Item length for a pass whose blocks each evaluate `hc` terms per pair.
-int64_t pick_seg(kde_ctx* c, int64_t n, int hc) {
+// Item length for a pass whose blocks each evaluate `hc` terms per pair.  It
+// depends only on n and the context options, never on the rest of a batch.
+int64_t pick_seg(const kde_ctx* c, int64_t n, int hc) {
   if (c->opt_seg >= 0) return c->opt_seg == 0 ? 0 : (c->opt_seg + kde::kBJ - 1) / kde::kBJ * kde::kBJ;
   // Aim for ~8192 blocks per launch so each launch fills the chip many times.
   const double per_block_pairs = c->opt_launch_evals / 8192.0 / (double)hc;
@@ -323,125 +307,350 @@ int64_t pick_seg(kde_ctx* c, int64_t n, int hc) {
   return seg;
 }
 
-// Launch ranges over items [i0, i1) whose summed evaluations stay within budget.
-// FP64 terms cost about five times the FP32 ones, so their budget is smaller.
-template <typename F>
-kde_status for_each_launch(kde_ctx* c, const Plan& p, double evals_per_pair, bool f64, F&& launch) {
-  const double budget = f64 ? c->opt_launch_evals / 5.0 : c->opt_launch_evals;
-  const size_t m = p.items.size();
-  size_t i0 = 0;
-  while (i0 < m) {
-    double acc = p.pairs[i0] * evals_per_pair;
-    size_t i1 = i0 + 1;
-    while (i1 < m && acc + p.pairs[i1] * evals_per_pair <= budget) {
-      acc += p.pairs[i1] * evals_per_pair;
-      ++i1;
+int lscv_hc(const kde_ctx* c) { return c->prec == KDE_PREC_FP64 ? 8 : c->opt_hc; }
+
+// Plans a job from the requests: columns, offsets, work units and reduction
+// rows.  Requests with bad arguments get status INVAL in `st` and no column.
+void plan_job(kde_ctx* c, const kde_request* reqs, int32_t n_req, std::vector<kde_status>& st,
+              std::vector<std::string>& msg) {
+  c->jcols.clear();
+  c->h_cols.clear();
+  c->h_units.clear();
+  c->h_cost.clear();
+  c->h_rows.clear();
+  c->h_hin.clear();
+  const int hc = lscv_hc(c);
+  st.assign(n_req, KDE_OK);
+  msg.assign(n_req, "");
+  int64_t x_off = 0, c_off = 0, part_off = 0;
+  for (int32_t k = 0; k < n_req; ++k) {
+    const kde_request& r = reqs[k];
+    std::string e = check_column(r.x);
+    const bool plugin = (r.methods & KDE_METHOD_PLUGIN) != 0;
+    const bool lscv = (r.methods & KDE_METHOD_LSCV) != 0;
+    if (e.empty() && plugin && r.stages != 2 && r.stages != 3) e = "stages must be 2 or 3";
+    if (e.empty() && lscv) e = check_grid(r.grid);
+    if (!e.empty()) {
+      st[k] = KDE_E_INVAL;
+      msg[k] = e;
+      continue;
     }
-    kde_status s = launch((int)i0, (int)(i1 - i0), acc);
+    JobCol jc;
+    jc.req = k;
+    jc.data = r.x.data;
+    jc.on_device = r.x.on_device;
+    jc.n = (int)r.x.n;
+    jc.f64 = r.x.dtype == KDE_F64;
+    jc.plugin = plugin;
+    jc.lscv = lscv;
+    jc.stages = plugin ? r.stages : 2;
+    jc.grid = r.grid;
+    std::memset(&jc.d, 0, sizeof(jc.d));
+    jc.d.n = jc.n;
+    jc.d.raw_f64 = jc.f64;
+    jc.d.x_off = x_off;
+    x_off += ((int64_t)jc.n + kde::kPad + 63) / 64 * 64;
+    if (plugin) {
+      make_items(jc.n, pick_seg(c, jc.n, 1), jc.psi_items);
+      jc.d.n_items_psi = (int)jc.psi_items.pairs.size();
+      jc.d.psi_part_off = part_off;
+      part_off += 2 * (int64_t)jc.d.n_items_psi;
+    }
+    if (lscv) {
+      make_items(jc.n, pick_seg(c, jc.n, hc), jc.lscv_items);
+      jc.d.n_h = r.grid.n_h;
+      jc.d.n_chunks = (r.grid.n_h + hc - 1) / hc;
+      jc.d.n_items = (int)jc.lscv_items.pairs.size();
+      jc.d.c_off = c_off;
+      c_off += (int64_t)jc.d.n_chunks * hc;
+      jc.d.part_off = part_off;
+      part_off += 2 * (int64_t)r.grid.n_h * jc.d.n_items;
+      jc.d.grid_kind = (int)r.grid.kind;
+      jc.d.grid_lo = r.grid.lo;
+      jc.d.grid_hi = r.grid.hi;
+    }
+    c->jcols.push_back(std::move(jc));
+  }
+  const int n_cols = (int)c->jcols.size();
+  // explicit grids, at each column's c_off
+  c->h_hin.assign((size_t)std::max<int64_t>(c_off, 1), 0.0);
+  for (const JobCol& jc : c->jcols)
+    if (jc.lscv && jc.grid.kind == KDE_GRID_EXPLICIT)
+      std::memcpy(c->h_hin.data() + jc.d.c_off, jc.grid.h, sizeof(double) * jc.grid.n_h);
+  struct Tmp {
+    Unit u;
+    UnitCost cost;
+  };
+  // psi units of all columns, largest first
+  std::vector<Tmp> tmp;
+  for (int col = 0; col < n_cols; ++col) {
+    const JobCol& jc = c->jcols[col];
+    if (!jc.plugin) continue;
+    for (size_t it = 0; it < jc.psi_items.pairs.size(); ++it) {
+      Tmp t;
+      t.u = Unit{col, jc.psi_items.row[it], jc.psi_items.jb[it], jc.psi_items.je[it], (int)it, 0};
+      t.cost = UnitCost{jc.psi_items.pairs[it], jc.psi_items.pairs[it]};
+      tmp.push_back(t);
+    }
+  }
+  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost.pairs > b.cost.pairs; });
+  for (const Tmp& t : tmp) {
+    c->h_units.push_back(t.u);
+    c->h_cost.push_back(t.cost);
+  }
+  c->n_psi_units = tmp.size();
+  // LSCV units: item-major, chunks inner, largest items first
+  tmp.clear();
+  for (int col = 0; col < n_cols; ++col) {
+    const JobCol& jc = c->jcols[col];
+    if (!jc.lscv) continue;
+    for (size_t it = 0; it < jc.lscv_items.pairs.size(); ++it)
+      for (int ch = 0; ch < jc.d.n_chunks; ++ch) {
+        Tmp t;
+        t.u = Unit{col, jc.lscv_items.row[it], jc.lscv_items.jb[it], jc.lscv_items.je[it], (int)it, ch};
+        const int valid = std::min(hc, jc.d.n_h - ch * hc);
+        t.cost = UnitCost{jc.lscv_items.pairs[it], jc.lscv_items.pairs[it] * valid};
+        tmp.push_back(t);
+      }
+  }
+  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost.pairs > b.cost.pairs; });
+  for (const Tmp& t : tmp) {
+    c->h_units.push_back(t.u);
+    c->h_cost.push_back(t.cost);
+  }
+  c->n_lscv_units = tmp.size();
+  // reduction rows
+  for (int col = 0; col < n_cols; ++col) {
+    const JobCol& jc = c->jcols[col];
+    if (!jc.plugin) continue;
+    for (int w = 0; w < 2; ++w)
+      c->h_rows.push_back(RowDesc{jc.d.psi_part_off + (int64_t)w * jc.d.n_items_psi, 2 * (int64_t)col + w,
+                                  jc.d.n_items_psi, 0});
+  }
+  c->n_psi_rows = c->h_rows.size();
+  for (int col = 0; col < n_cols; ++col) {
+    const JobCol& jc = c->jcols[col];
+    if (!jc.lscv) continue;
+    for (int r = 0; r < 2 * jc.d.n_h; ++r)
+      c->h_rows.push_back(RowDesc{jc.d.part_off + (int64_t)r * jc.d.n_items, 2 * jc.d.c_off + r, jc.d.n_items, 0});
+  }
+  c->n_lscv_rows = c->h_rows.size() - c->n_psi_rows;
+}
+
+int64_t job_part_size(const kde_ctx* c) {
+  int64_t m = 0;
+  for (const JobCol& jc : c->jcols) {
+    if (jc.plugin) m = std::max(m, jc.d.psi_part_off + 2 * (int64_t)jc.d.n_items_psi);
+    if (jc.lscv) m = std::max(m, jc.d.part_off + 2 * (int64_t)jc.d.n_h * jc.d.n_items);
+  }
+  return m;
+}
+
+int64_t job_x_size(const kde_ctx* c) {
+  int64_t m = 0;
+  for (const JobCol& jc : c->jcols) m = std::max(m, jc.d.x_off + (int64_t)jc.n + kde::kPad);
+  return m;
+}
+
+int64_t job_c_size(const kde_ctx* c, int hc) {
+  int64_t m = 0;
+  for (const JobCol& jc : c->jcols)
+    if (jc.lscv) m = std::max(m, jc.d.c_off + (int64_t)jc.d.n_chunks * hc);
+  return m;
+}
+
+// Launch ranges over units [u0, u1) of one pass whose summed evaluations stay
+// within budget (at least 2048 blocks per launch when the pass has them, so a
+// launch fills the chip).  FP64 terms cost about five times the FP32 ones.
+template <typename F>
+kde_status for_each_launch(kde_ctx* c, size_t first, size_t count, bool f64, F&& launch) {
+  const double budget = f64 ? c->opt_launch_evals / 5.0 : c->opt_launch_evals;
+  size_t u0 = first;
+  const size_t end = first + count;
+  while (u0 < end) {
+    double acc = c->h_cost[u0].evals;
+    size_t u1 = u0 + 1;
+    while (u1 < end && (acc + c->h_cost[u1].evals <= budget || u1 - u0 < 2048)) {
+      acc += c->h_cost[u1].evals;
+      ++u1;
+    }
+    kde_status s = launch((int)u0, (int)(u1 - u0), acc);
     if (s) return s;
-    i0 = i1;
+    u0 = u1;
   }
   return KDE_OK;
 }
 
-kde_status read_state(kde_ctx* c) {
-  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->d_st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
-  return KDE_OK;
-}
-
-// ---- plug-in
-kde_status run_psi_stage(kde_ctx* c, int n, int stage, bool f64, bool conditional, const Plan& p) {
+kde_status run_psi_stage(kde_ctx* c, int n_cols, int stage, bool f64, bool conditional) {
   const int r = 8 - 2 * stage;
-  kde_status s;
-  if ((s = ensure(c, c->part, 2 * p.items.size()))) return s;
-  s = for_each_launch(c, p, 1.0, f64, [&](int i0, int cnt, double evals) -> kde_status {
+  kde_status s = for_each_launch(c, 0, c->n_psi_units, f64, [&](int u0, int cnt, double evals) -> kde_status {
     // A conditional pass may exit at once on the device, so it is not timed.
     Pending pd{nullptr, nullptr, kFamPsi, evals};
     kde_status s2 = conditional ? KDE_OK : timed_begin(c, pd);
     if (s2) return s2;
-    kde::launch_psi_pairs(c->stream, r, f64 ? 1 : 0, conditional ? 1 : 0, c->x32.p, c->x64.p, n, p.d_items,
-                          (int)p.items.size(), i0, cnt, c->part.p, c->d_st);
+    kde::launch_psi_units(c->stream, r, f64 ? 1 : 0, conditional ? 1 : 0, c->x32.p, c->x64.p, c->cols.p,
+                          c->units.p, u0, cnt, c->part.p, c->st.p);
     return conditional ? KDE_OK : timed_end(c, pd);
   });
   if (s) return s;
-  kde::launch_reduce_rows(c->stream, c->part.p, (int)p.items.size(), 2, c->sums.p);
-  kde::launch_psi_finish(c->stream, c->d_st, stage, c->sums.p, f64 ? 1 : 0, conditional ? 1 : 0);
+  kde::launch_reduce_rows(c->stream, c->part.p, c->rows.p, (int)c->n_psi_rows, c->psi_sums.p);
+  kde::launch_psi_finish(c->stream, n_cols, c->cols.p, c->st.p, stage, c->psi_sums.p, f64 ? 1 : 0,
+                         conditional ? 1 : 0);
   HIP_TRY(c, hipGetLastError());
   return KDE_OK;
 }
 
-kde_status run_plugin(kde_ctx* c, const kde_column& x, int stages) {
-  if (stages != 2 && stages != 3) return fail(c, KDE_E_INVAL, "stages must be 2 or 3");
+// Enqueues the whole job planned by plan_job.  Results stay on the device
+// except the per-column states, whose copy back is enqueued last.
+kde_status run_job(kde_ctx* c) {
   kde_status s;
-  if ((s = prepare_column(c, x, true, stages))) return s;
-  const int n = (int)x.n;
-  if ((s = ensure(c, c->sums, 64))) return s;
-  Plan* p = nullptr;
-  if ((s = get_plan(c, n, pick_seg(c, n, 1), &p))) return s;
+  const int n_cols = (int)c->jcols.size();
+  if (n_cols == 0) return KDE_OK;
   const bool all64 = c->prec == KDE_PREC_FP64;
-  for (int stage = (stages == 3 ? 0 : 1); stage < 3; ++stage) {
-    kde::launch_psi_begin(c->stream, c->d_st, stage);
-    if ((s = run_psi_stage(c, n, stage, all64, false, *p))) return s;
-    if (!all64 && c->opt_fp64_kappa > 0.0 && (s = run_psi_stage(c, n, stage, true, true, *p))) return s;
+  const int hc = lscv_hc(c);
+  bool any_plugin = false, any_lscv = false;
+  int max_stages = 2;
+  for (const JobCol& jc : c->jcols) {
+    any_plugin |= jc.plugin;
+    any_lscv |= jc.lscv;
+    if (jc.plugin) max_stages = std::max(max_stages, jc.stages);
   }
-  kde::launch_plugin_final(c->stream, c->d_st);
+  const bool want_x64 = all64 || (any_plugin && c->opt_fp64_kappa > 0.0);
+  // stage host columns on the device
+  size_t stage_bytes = 0;
+  for (const JobCol& jc : c->jcols)
+    if (!jc.on_device) stage_bytes += ((size_t)jc.n * (jc.f64 ? 8 : 4) + 255) / 256 * 256;
+  if ((s = ensure(c, c->stage, std::max<size_t>(stage_bytes, 1)))) return s;
+  size_t so = 0;
+  for (JobCol& jc : c->jcols) {
+    if (jc.on_device) {
+      jc.d.raw = jc.data;
+    } else {
+      const size_t bytes = (size_t)jc.n * (jc.f64 ? 8 : 4);
+      HIP_TRY(c, hipMemcpyAsync(c->stage.p + so, jc.data, bytes, hipMemcpyHostToDevice, c->stream));
+      jc.d.raw = c->stage.p + so;
+      so += (bytes + 255) / 256 * 256;
+    }
+  }
+  c->h_cols.resize(n_cols);
+  for (int k = 0; k < n_cols; ++k) c->h_cols[k] = c->jcols[k].d;
+  // buffers
+  const int64_t xs = job_x_size(c), cs = std::max<int64_t>(job_c_size(c, hc), 1);
+  if ((s = ensure(c, c->x32, (size_t)xs))) return s;
+  if (want_x64 && (s = ensure(c, c->x64, (size_t)xs))) return s;
+  if ((s = ensure(c, c->stat_part, (size_t)n_cols * kde::kStatBlocks))) return s;
+  if ((s = ensure(c, c->part_nf, (size_t)n_cols * kde::kStatBlocks))) return s;
+  if ((s = ensure(c, c->part, (size_t)std::max<int64_t>(job_part_size(c), 1)))) return s;
+  if ((s = ensure(c, c->psi_sums, (size_t)2 * n_cols))) return s;
+  if ((s = ensure(c, c->lscv_sums, (size_t)2 * cs))) return s;
+  for (auto* b : {&c->hin, &c->hdev, &c->c64, &c->g, &c->gs})
+    if ((s = ensure(c, *b, (size_t)cs))) return s;
+  if ((s = ensure(c, c->c32, (size_t)cs))) return s;
+  if ((s = ensure(c, c->cols, (size_t)n_cols))) return s;
+  if ((s = ensure(c, c->units, std::max<size_t>(c->h_units.size(), 1)))) return s;
+  if ((s = ensure(c, c->rows, std::max<size_t>(c->h_rows.size(), 1)))) return s;
+  if ((s = ensure(c, c->st, (size_t)n_cols))) return s;
+  if ((s = ensure_pinned(c, c->h_st, c->h_st_cap, (size_t)n_cols))) return s;
+  // initial per-column state
+  for (int k = 0; k < n_cols; ++k) {
+    DevState& h = c->h_st[k];
+    std::memset(&h, 0, sizeof(h));
+    const double nan = std::nan("");
+    h.stages = c->jcols[k].plugin ? c->jcols[k].stages : 0;
+    for (int q = 0; q < 3; ++q) {
+      h.g[q] = h.psi[q] = h.kappa[q] = nan;
+      h.prec_used[q] = -1;
+    }
+    h.h_plugin = h.h_best = h.margin = nan;
+    h.k_best = -1;
+    h.fp64_kappa = c->opt_fp64_kappa;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(DevState) * n_cols, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->cols.p, c->h_cols.data(), sizeof(ColDesc) * n_cols, hipMemcpyHostToDevice,
+                            c->stream));
+  if (!c->h_units.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->units.p, c->h_units.data(), sizeof(Unit) * c->h_units.size(),
+                              hipMemcpyHostToDevice, c->stream));
+  if (!c->h_rows.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->rows.p, c->h_rows.data(), sizeof(RowDesc) * c->h_rows.size(),
+                              hipMemcpyHostToDevice, c->stream));
+  // moments of every column
+  int max_blocks = 1;
+  for (const JobCol& jc : c->jcols)
+    max_blocks = std::max(max_blocks, std::min(kde::kStatBlocks, (jc.n + 2047) / 2048));
+  kde::launch_stats(c->stream, n_cols, max_blocks, c->cols.p, c->stat_part.p, c->part_nf.p, c->x32.p,
+                    want_x64 ? c->x64.p : nullptr, c->st.p);
   HIP_TRY(c, hipGetLastError());
-  return KDE_OK;
-}
-
-// ---- LSCV
-kde_status check_grid(kde_ctx* c, const double* h, int32_t n_h) {
-  if (n_h < 1 || n_h > KDE_MAX_NH) return fail(c, KDE_E_INVAL, "n_h out of range");
-  for (int32_t k = 0; k < n_h; ++k) {
-    if (!(h[k] > 0.0) || !std::isfinite(h[k])) return fail(c, KDE_E_INVAL, "grid values must be finite and > 0");
-    if (k > 0 && !(h[k] > h[k - 1])) return fail(c, KDE_E_INVAL, "grid must be strictly ascending");
+  // plug-in stages (columns without the plug-in have no psi units; their
+  // scalar steps run harmlessly and are not reported)
+  if (any_plugin) {
+    for (int stage = (max_stages == 3 ? 0 : 1); stage < 3; ++stage) {
+      kde::launch_psi_begin(c->stream, n_cols, c->st.p, stage);
+      if ((s = run_psi_stage(c, n_cols, stage, all64, false))) return s;
+      if (!all64 && c->opt_fp64_kappa > 0.0 && (s = run_psi_stage(c, n_cols, stage, true, true))) return s;
+    }
+    kde::launch_plugin_final(c->stream, n_cols, c->st.p);
   }
+  // LSCV
+  if (any_lscv) {
+    HIP_TRY(c, hipMemcpyAsync(c->hin.p, c->h_hin.data(), sizeof(double) * c->h_hin.size(), hipMemcpyHostToDevice,
+                              c->stream));
+    kde::launch_lscv_prep(c->stream, n_cols, hc, c->cols.p, c->hin.p, c->st.p, c->hdev.p, c->c32.p, c->c64.p);
+    s = for_each_launch(c, c->n_psi_units, c->n_lscv_units, all64,
+                        [&](int u0, int cnt, double evals) -> kde_status {
+                          Pending pd{nullptr, nullptr, kFamLscv, evals};
+                          kde_status s2 = timed_begin(c, pd);
+                          if (s2) return s2;
+                          kde::launch_lscv_units(c->stream, hc, all64 ? 1 : 0, c->x32.p, c->x64.p, c->cols.p,
+                                                 c->units.p, u0, cnt, c->c32.p, c->c64.p, c->part.p, c->st.p);
+                          return timed_end(c, pd);
+                        });
+    if (s) return s;
+    kde::launch_reduce_rows(c->stream, c->part.p, c->rows.p + c->n_psi_rows, (int)c->n_lscv_rows, c->lscv_sums.p);
+    kde::launch_lscv_finalize(c->stream, n_cols, c->cols.p, c->lscv_sums.p, c->hdev.p, c->st.p, c->g.p, c->gs.p);
+  }
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(DevState) * n_cols, hipMemcpyDeviceToHost, c->stream));
   return KDE_OK;
 }
 
-// Runs the LSCV pass; results stay on the device (sums, g, gscale, hdev, state).
-kde_status run_lscv(kde_ctx* c, const kde_column& x, const double* h_grid, int32_t n_h, Plan** plan_out = nullptr) {
-  kde_status s;
+// Single-column helpers ------------------------------------------------------
+kde_status run_single(kde_ctx* c, const kde_request& r) {
+  std::vector<kde_status> st;
+  std::vector<std::string> msg;
+  plan_job(c, &r, 1, st, msg);
+  if (st[0] != KDE_OK) return fail(c, st[0], msg[0]);
+  return run_job(c);
+}
+
+kde_request make_req(kde_column x, unsigned methods, int stages, const double* h_grid, int32_t n_h) {
+  kde_request r;
+  std::memset(&r, 0, sizeof(r));
+  r.x = x;
+  r.methods = methods;
+  r.stages = stages;
   if (h_grid) {
-    if ((s = check_grid(c, h_grid, n_h))) return s;
+    r.grid.kind = KDE_GRID_EXPLICIT;
+    r.grid.h = h_grid;
+    r.grid.n_h = n_h;
   } else {
-    if (n_h <= 0) n_h = 150;
-    if (n_h > KDE_MAX_NH) return fail(c, KDE_E_INVAL, "n_h out of range");
+    r.grid.kind = KDE_GRID_PAPER;
+    r.grid.n_h = n_h <= 0 ? 150 : n_h;
   }
-  const bool all64 = c->prec == KDE_PREC_FP64;
-  if ((s = prepare_column(c, x, all64, 2))) return s;
-  const int n = (int)x.n;
-  const int hc = all64 ? 8 : c->opt_hc;
-  const int n_chunks = (n_h + hc - 1) / hc;
-  const int n_h_pad = n_chunks * hc;
-  if ((s = ensure(c, c->hin, (size_t)n_h))) return s;
-  if ((s = ensure(c, c->hdev, (size_t)n_h))) return s;
-  if ((s = ensure(c, c->c32, (size_t)n_h_pad))) return s;
-  if ((s = ensure(c, c->c64, (size_t)n_h_pad))) return s;
-  if ((s = ensure(c, c->g, (size_t)n_h))) return s;
-  if ((s = ensure(c, c->gs, (size_t)n_h))) return s;
-  if ((s = ensure(c, c->sums, (size_t)2 * n_h + 64))) return s;
-  if (h_grid) HIP_TRY(c, hipMemcpyAsync(c->hin.p, h_grid, sizeof(double) * n_h, hipMemcpyHostToDevice, c->stream));
-  kde::launch_lscv_prep(c->stream, h_grid ? c->hin.p : nullptr, n_h, n_h_pad, c->d_st, c->hdev.p, c->c32.p,
-                        c->c64.p);
-  Plan* p = nullptr;
-  if ((s = get_plan(c, n, pick_seg(c, n, hc), &p))) return s;
-  const size_t n_items = p->items.size();
-  if ((s = ensure(c, c->part, (size_t)2 * n_h * n_items))) return s;
-  s = for_each_launch(c, *p, (double)n_h, all64, [&](int i0, int cnt, double evals) -> kde_status {
-    Pending pd{nullptr, nullptr, kFamLscv, evals};
-    kde_status s2 = timed_begin(c, pd);
-    if (s2) return s2;
-    kde::launch_lscv_pairs(c->stream, hc, all64 ? 1 : 0, c->x32.p, c->x64.p, n, p->d_items, (int)n_items, n_chunks,
-                           c->c32.p, c->c64.p, n_h, i0 * n_chunks, cnt * n_chunks, c->part.p, c->d_st);
-    return timed_end(c, pd);
-  });
-  if (s) return s;
-  kde::launch_reduce_rows(c->stream, c->part.p, (int)n_items, 2 * n_h, c->sums.p);
-  kde::launch_lscv_finalize(c->stream, c->sums.p, n_h, c->hdev.p, c->d_st, c->g.p, c->gs.p);
-  HIP_TRY(c, hipGetLastError());
-  if (plan_out) *plan_out = p;
-  return KDE_OK;
+  return r;
+}
+
+void fill_plugin_info(const DevState& h, int stages, kde_plugin_info* info) {
+  info->sigma = h.sigma;
+  info->h_rot = h.h_rot;
+  info->stages = stages;
+  for (int k = 0; k < 3; ++k) {
+    info->g[k] = h.g[k];
+    info->psi[k] = h.psi[k];
+    info->kappa[k] = h.kappa[k];
+    info->precision_used[k] = h.prec_used[k];
+  }
+  info->h = h.h_plugin;
 }
 
 }  // namespace
@@ -465,11 +674,6 @@ kde_status kde_ctx_create(int device, kde_prec prec, kde_ctx** out) {
     return KDE_E_DEVICE;
   }
   c->stream = c->own;
-  if (hipMalloc((void**)&c->d_st, sizeof(DevState)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_st, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
-    kde_ctx_destroy(c);
-    return KDE_E_NOMEM;
-  }
   *out = c;
   return KDE_OK;
 }
@@ -478,21 +682,24 @@ void kde_ctx_destroy(kde_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (auto* b : {&c->stage}) (void)hipFree(b->p);
+  (void)hipFree(c->stage.p);
   (void)hipFree(c->x32.p);
   (void)hipFree(c->x64.p);
   (void)hipFree(c->part.p);
   (void)hipFree(c->part_nf.p);
   (void)hipFree(c->stat_part.p);
-  (void)hipFree(c->sums.p);
+  (void)hipFree(c->psi_sums.p);
+  (void)hipFree(c->lscv_sums.p);
   (void)hipFree(c->hin.p);
   (void)hipFree(c->hdev.p);
   (void)hipFree(c->c64.p);
   (void)hipFree(c->c32.p);
   (void)hipFree(c->g.p);
   (void)hipFree(c->gs.p);
-  for (Plan& p : c->plans) (void)hipFree(p.d_items);
-  (void)hipFree(c->d_st);
+  (void)hipFree(c->cols.p);
+  (void)hipFree(c->units.p);
+  (void)hipFree(c->rows.p);
+  (void)hipFree(c->st.p);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_out) (void)hipHostFree(c->h_out);
   for (Pending& p : c->pending) {
@@ -571,11 +778,10 @@ kde_status kde_bw_rot(kde_ctx* c, kde_column x, double* h_out) {
   if (!c || !h_out) return KDE_E_INVAL;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
-  if ((s = prepare_column(c, x, false, 2))) return s;
-  if ((s = read_state(c))) return s;
+  if ((s = run_single(c, make_req(x, KDE_METHOD_ROT, 2, nullptr, 0)))) return s;
   if ((s = sync_and_check(c))) return s;
-  if ((s = map_status(c, c->h_st->status))) return s;
-  *h_out = c->h_st->h_rot;
+  if ((s = map_status(c, c->h_st[0].status))) return s;
+  *h_out = c->h_st[0].h_rot;
   return KDE_OK;
 }
 
@@ -583,23 +789,12 @@ kde_status kde_bw_plugin(kde_ctx* c, kde_column x, int stages, double* h_out, kd
   if (!c || !h_out) return KDE_E_INVAL;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
-  if ((s = run_plugin(c, x, stages))) return s;
-  if ((s = read_state(c))) return s;
+  if ((s = run_single(c, make_req(x, KDE_METHOD_PLUGIN, stages, nullptr, 0)))) return s;
   if ((s = sync_and_check(c))) return s;
-  const DevState& h = *c->h_st;
-  if (info) {
-    info->sigma = h.sigma;
-    info->h_rot = h.h_rot;
-    info->stages = stages;
-    for (int k = 0; k < 3; ++k) {
-      info->g[k] = h.g[k];
-      info->psi[k] = h.psi[k];
-      info->kappa[k] = h.kappa[k];
-      info->precision_used[k] = h.prec_used[k];
-    }
-    info->h = h.h_plugin;
-  }
+  const DevState& h = c->h_st[0];
+  if (info) fill_plugin_info(h, stages, info);
   if ((s = map_status(c, h.status))) return s;
+  if ((s = map_status(c, h.pstatus))) return s;
   *h_out = h.h_plugin;
   return KDE_OK;
 }
@@ -610,15 +805,15 @@ kde_status kde_lscv_curve(kde_ctx* c, kde_column x, const double* h_grid, int32_
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if (!h_grid && n_h <= 0) n_h = 150;
-  if ((s = run_lscv(c, x, h_grid, n_h))) return s;
-  if ((s = ensure_host_out(c, (size_t)3 * n_h))) return s;
-  HIP_TRY(c, hipMemcpyAsync(c->h_out, c->g.p, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->h_out + n_h, c->gs.p, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->h_out + 2 * (size_t)n_h, c->hdev.p, sizeof(double) * n_h, hipMemcpyDeviceToHost,
+  if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
+  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, (size_t)3 * n_h))) return s;
+  const int64_t o = c->jcols[0].d.c_off;
+  HIP_TRY(c, hipMemcpyAsync(c->h_out, c->g.p + o, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_out + n_h, c->gs.p + o, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_out + 2 * (size_t)n_h, c->hdev.p + o, sizeof(double) * n_h, hipMemcpyDeviceToHost,
                             c->stream));
-  if ((s = read_state(c))) return s;
   if ((s = sync_and_check(c))) return s;
-  if ((s = map_status(c, c->h_st->status))) return s;
+  if ((s = map_status(c, c->h_st[0].status))) return s;
   std::memcpy(g_out, c->h_out, sizeof(double) * n_h);
   if (gscale_out) std::memcpy(gscale_out, c->h_out + n_h, sizeof(double) * n_h);
   if (grid_out) std::memcpy(grid_out, c->h_out + 2 * (size_t)n_h, sizeof(double) * n_h);
@@ -630,12 +825,12 @@ kde_status kde_lscv_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t
   if (!c || !h_grid || !s1_out || !s2_out) return KDE_E_INVAL;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
-  if ((s = run_lscv(c, x, h_grid, n_h))) return s;
-  if ((s = ensure_host_out(c, (size_t)2 * n_h))) return s;
-  HIP_TRY(c, hipMemcpyAsync(c->h_out, c->sums.p, sizeof(double) * 2 * n_h, hipMemcpyDeviceToHost, c->stream));
-  if ((s = read_state(c))) return s;
+  if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
+  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, (size_t)2 * n_h))) return s;
+  HIP_TRY(c, hipMemcpyAsync(c->h_out, c->lscv_sums.p + 2 * c->jcols[0].d.c_off, sizeof(double) * 2 * n_h,
+                            hipMemcpyDeviceToHost, c->stream));
   if ((s = sync_and_check(c))) return s;
-  if ((s = map_status(c, c->h_st->status))) return s;
+  if ((s = map_status(c, c->h_st[0].status))) return s;
   for (int32_t k = 0; k < n_h; ++k) {
     s1_out[k] = c->h_out[2 * k];
     s2_out[k] = c->h_out[2 * k + 1];
@@ -649,9 +844,9 @@ kde_status kde_lscv_item_sums(kde_ctx* c, kde_column x, const double* h_grid, in
   if (n_sel > 0 && (!sel || !ranges_out || !sums_out)) return fail(c, KDE_E_INVAL, "NULL selection buffers");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
-  Plan* p = nullptr;
-  if ((s = run_lscv(c, x, h_grid, n_h, &p))) return s;
-  const int32_t n_items = (int32_t)p->items.size();
+  if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
+  const JobCol& jc = c->jcols[0];
+  const int32_t n_items = jc.d.n_items;
   std::vector<int32_t> idx((size_t)n_sel);
   for (int32_t k = 0; k < n_sel; ++k) {
     idx[k] = sel[k] < 0 ? n_items + sel[k] : sel[k];
@@ -660,21 +855,19 @@ kde_status kde_lscv_item_sums(kde_ctx* c, kde_column x, const double* h_grid, in
       return fail(c, KDE_E_INVAL, "item index out of range");
     }
   }
-  if ((s = ensure_host_out(c, (size_t)2 * n_h * (n_sel > 0 ? n_sel : 1)))) return s;
-  // part is laid out [2*n_h][n_items]: one strided column per selected item
+  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, (size_t)2 * n_h * (n_sel > 0 ? n_sel : 1)))) return s;
+  // the column's partials are laid out [2*n_h][n_items]: one strided column per selected item
   for (int32_t k = 0; k < n_sel; ++k)
-    HIP_TRY(c, hipMemcpy2DAsync(c->h_out + (size_t)k * 2 * n_h, sizeof(double), c->part.p + idx[k],
+    HIP_TRY(c, hipMemcpy2DAsync(c->h_out + (size_t)k * 2 * n_h, sizeof(double), c->part.p + jc.d.part_off + idx[k],
                                 sizeof(double) * (size_t)n_items, sizeof(double), (size_t)2 * n_h,
                                 hipMemcpyDeviceToHost, c->stream));
-  if ((s = read_state(c))) return s;
   if ((s = sync_and_check(c))) return s;
-  if ((s = map_status(c, c->h_st->status))) return s;
+  if ((s = map_status(c, c->h_st[0].status))) return s;
   *n_items_out = n_items;
   for (int32_t k = 0; k < n_sel; ++k) {
-    const Item& it = p->items[idx[k]];
-    ranges_out[3 * k] = it.row * kde::kBI;
-    ranges_out[3 * k + 1] = it.j_begin;
-    ranges_out[3 * k + 2] = it.j_end;
+    ranges_out[3 * k] = jc.lscv_items.row[idx[k]] * kde::kBI;
+    ranges_out[3 * k + 1] = jc.lscv_items.jb[idx[k]];
+    ranges_out[3 * k + 2] = jc.lscv_items.je[idx[k]];
     std::memcpy(sums_out + (size_t)k * 2 * n_h, c->h_out + (size_t)k * 2 * n_h, sizeof(double) * 2 * n_h);
   }
   return KDE_OK;
@@ -686,13 +879,74 @@ kde_status kde_bw_lscv(kde_ctx* c, kde_column x, const double* h_grid, int32_t n
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if (!h_grid && n_h <= 0) n_h = 150;
-  if ((s = run_lscv(c, x, h_grid, n_h))) return s;
-  if ((s = read_state(c))) return s;
+  if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
   if ((s = sync_and_check(c))) return s;
-  if ((s = map_status(c, c->h_st->status))) return s;
-  *h_out = c->h_st->h_best;
-  if (k_out) *k_out = c->h_st->k_best;
-  if (at_edge) *at_edge = c->h_st->at_edge;
+  if ((s = map_status(c, c->h_st[0].status))) return s;
+  *h_out = c->h_st[0].h_best;
+  if (k_out) *k_out = c->h_st[0].k_best;
+  if (at_edge) *at_edge = c->h_st[0].at_edge;
+  return KDE_OK;
+}
+
+kde_status kde_batch(kde_ctx* c, const kde_request* reqs, int32_t n_req, kde_result* out) {
+  if (!c || n_req < 0 || (n_req > 0 && (!reqs || !out))) return KDE_E_INVAL;
+  if (n_req > KDE_MAX_BATCH) return fail(c, KDE_E_INVAL, "more than KDE_MAX_BATCH requests");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  std::vector<kde_status> st;
+  std::vector<std::string> msg;
+  plan_job(c, reqs, n_req, st, msg);
+  kde_status s;
+  if ((s = run_job(c))) return s;
+  // g / gscale of LSCV requests into pinned staging, then to the caller
+  size_t total = 0;
+  for (const JobCol& jc : c->jcols)
+    if (jc.lscv) total += 2 * (size_t)jc.d.n_h;
+  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, std::max<size_t>(total, 1)))) return s;
+  size_t o = 0;
+  std::vector<size_t> at(c->jcols.size(), 0);
+  for (size_t k = 0; k < c->jcols.size(); ++k) {
+    const JobCol& jc = c->jcols[k];
+    if (!jc.lscv) continue;
+    at[k] = o;
+    HIP_TRY(c, hipMemcpyAsync(c->h_out + o, c->g.p + jc.d.c_off, sizeof(double) * jc.d.n_h, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->h_out + o + jc.d.n_h, c->gs.p + jc.d.c_off, sizeof(double) * jc.d.n_h,
+                              hipMemcpyDeviceToHost, c->stream));
+    o += 2 * (size_t)jc.d.n_h;
+  }
+  if ((s = sync_and_check(c))) return s;
+  const double nan = std::nan("");
+  for (int32_t k = 0; k < n_req; ++k) {
+    kde_result& r = out[k];
+    double* g_keep = r.g_out;
+    double* gs_keep = r.gscale_out;
+    std::memset(&r, 0, sizeof(r));
+    r.g_out = g_keep;
+    r.gscale_out = gs_keep;
+    r.status = st[k];
+    r.sigma = r.h_rot = r.h_plugin = r.h_lscv = nan;
+    r.k_lscv = -1;
+  }
+  for (size_t k = 0; k < c->jcols.size(); ++k) {
+    const JobCol& jc = c->jcols[k];
+    const DevState& h = c->h_st[k];
+    kde_result& r = out[jc.req];
+    r.status = status_of(h.status);
+    if (r.status == KDE_OK && jc.plugin) r.status = status_of(h.pstatus);
+    r.sigma = h.sigma;
+    r.h_rot = h.h_rot;
+    if (jc.plugin) {
+      fill_plugin_info(h, jc.stages, &r.plugin);
+      r.h_plugin = h.h_plugin;
+    }
+    if (jc.lscv) {
+      r.h_lscv = h.h_best;
+      r.k_lscv = h.k_best;
+      r.at_edge = h.at_edge;
+      if (r.g_out) std::memcpy(r.g_out, c->h_out + at[k], sizeof(double) * jc.d.n_h);
+      if (r.gscale_out) std::memcpy(r.gscale_out, c->h_out + at[k] + jc.d.n_h, sizeof(double) * jc.d.n_h);
+    }
+  }
   return KDE_OK;
 }
 

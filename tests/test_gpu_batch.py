@@ -1,0 +1,143 @@
+"""Batched jobs through kde_batch: every result equals the same request run
+alone (bitwise), and matches the FP64 oracle to the single-column bar.
+
+Tolerances as in test_gpu_parity.py: psi_r, pilots, plug-in h within 1e-5
+relative; |g_gpu - g_oracle| <= 1e-5 gscale; sigma and h_rot 1e-12."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def kde():
+    import paper_1505_01998_amd as kde
+
+    return kde
+
+
+def _requests(kde):
+    A = kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV
+    R = kde.Request
+    d = workloads.draw
+    return [
+        R(d("normal", 1000, 1998001, np.float64), A, 2, np.geomspace(0.01, 1.0, 100)),
+        R(d("bimodal", 3001, 11, np.float32), A, 3, ("log_rot", 1 / 64, 4.0, 128)),
+        R(d("uniform", 257, 12, np.float32), kde.KDE_METHOD_LSCV, 3, ("paper", 150)),
+        R(d("gamma", 5003, 13, np.float32), kde.KDE_METHOD_PLUGIN, 3),
+        R(d("normal", 2, 14, np.float32), kde.KDE_METHOD_ROT),
+        R(d("lognormal", 12000, 15, np.float32), A, 3, ("log_rot", 1 / 64, 4.0, 33)),
+        R(d("mixture", 700, 16, np.float64), A, 2, np.geomspace(0.005, 2.0, 77)),
+        R(np.array([1.0]), A, 3),                                    # n < 2
+        R(np.array([0.0, np.nan, 1.0, 2.0], np.float32), A, 3),        # non-finite
+        R(np.full(50, 2.5), A, 3),                                   # zero spread
+        R(d("normal", 100, 17, np.float32), A, 3, np.array([0.5, 0.2])),  # descending grid
+    ]
+
+
+def _oracle_grid(x, grid):
+    if isinstance(grid, tuple) and grid[0] == "log_rot":
+        _, hr = oracle.bw_rot(x)
+        return hr * np.geomspace(grid[1], grid[2], grid[3])
+    if isinstance(grid, tuple) and grid[0] == "paper":
+        return oracle.default_grid(x, grid[1])
+    return np.asarray(grid, np.float64)
+
+
+def _same(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return a.shape == b.shape and np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)],
+                                                                                               b[~np.isnan(b)])
+
+
+def _check_vs_oracle(kde, req, res):
+    x = np.asarray(req.x)
+    _, hr = oracle.bw_rot(x)
+    assert res.h_rot == pytest.approx(hr, rel=1e-12)
+    if req.methods & kde.KDE_METHOD_PLUGIN:
+        o = oracle.bw_plugin(x, req.stages)
+        for s in range(0 if req.stages == 3 else 1, 3):
+            assert res.plugin.psi[s] == pytest.approx(o.psi[s], rel=TOL)
+        assert res.h_plugin == pytest.approx(o.h, rel=TOL)
+    if req.methods & kde.KDE_METHOD_LSCV:
+        grid = _oracle_grid(x, req.grid)
+        oc = oracle.lscv_curve(x, grid)
+        err = np.abs(res.g - oc.g) / oc.gscale
+        assert err.max() <= TOL, err.max()
+        k_or = int(np.argmin(oc.g))
+        if res.k_lscv != k_or:
+            assert oc.g[res.k_lscv] - oc.g[k_or] <= 2 * np.abs(res.g - oc.g).max()
+        assert res.h_lscv == pytest.approx(grid[res.k_lscv], rel=1e-12)
+
+
+def test_batch_statuses_and_oracle(kde):
+    reqs = _requests(kde)
+    with kde.Context(0) as c:
+        out = c.batch(reqs)
+    st = [r.status for r in out]
+    assert st[:7] == [kde.KDE_OK] * 7
+    assert st[7] == kde.KDE_E_INVAL and st[8] == kde.KDE_E_INVAL and st[10] == kde.KDE_E_INVAL
+    assert st[9] == kde.KDE_E_DEGENERATE
+    for req, res in zip(reqs[:7], out[:7]):
+        _check_vs_oracle(kde, req, res)
+
+
+def test_batch_equals_alone_bitwise(kde):
+    reqs = _requests(kde)[:7]
+    with kde.Context(0) as c:
+        mixed = c.batch(reqs)
+        alone = [c.batch([r])[0] for r in reqs]
+        rev = c.batch(list(reversed(reqs)))[::-1]
+    for m, a, r in zip(mixed, alone, rev):
+        for res in (a, r):
+            assert m.status == res.status
+            assert _same([m.h_rot, m.h_plugin, m.h_lscv], [res.h_rot, res.h_plugin, res.h_lscv])
+            assert _same(m.plugin.psi, res.plugin.psi)
+            assert m.k_lscv == res.k_lscv
+            if m.g is not None:
+                assert _same(m.g, res.g) and _same(m.gscale, res.gscale)
+
+
+def test_single_column_calls_equal_batch_of_one(kde):
+    x = workloads.draw("bimodal", 4099, 5, np.float32)
+    grid = np.geomspace(0.01, 2.0, 41)
+    with kde.Context(0) as c:
+        h_pi, info = c.bw_plugin(x, 3)
+        g, gs, _ = c.lscv_curve(x, grid)
+        b = c.batch([kde.Request(x, kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, 3, grid)])[0]
+    assert b.h_plugin == h_pi and _same(b.plugin.psi, info.psi)
+    assert _same(b.g, g) and _same(b.gscale, gs)
+
+
+def test_batch_512_uneven_columns(kde):
+    """The batched workload at full size: 512 columns, n log-uniform in
+    [1e3, 2e5], four families, plug-in (3 stages) + LSCV over 128 h each, one
+    job.  Sampled columns are checked bitwise against the same request alone,
+    small ones against the oracle."""
+    import time
+
+    specs = workloads.batch_columns()
+    cols = [s.column() for s in specs]
+    A = kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV
+    reqs = [kde.Request(x, A, workloads.BATCH_STAGES, workloads.BATCH_GRID) for x in cols]
+    with kde.Context(0) as c:
+        t0 = time.perf_counter()
+        out = c.batch(reqs)
+        t_batch = time.perf_counter() - t0
+        assert all(r.status == kde.KDE_OK for r in out)
+        rng = np.random.Generator(np.random.PCG64(7))
+        picks = sorted(set(rng.choice(len(reqs), 6, replace=False).tolist()) | {int(np.argmax([s.n for s in specs]))})
+        for k in picks:
+            a = c.batch([reqs[k]])[0]
+            assert _same(out[k].g, a.g) and out[k].h_plugin == a.h_plugin, k
+    small = [k for k, s in enumerate(specs) if s.n <= 2500][:4]
+    for k in small:
+        _check_vs_oracle(kde, reqs[k], out[k])
+    pairs = sum(s.n * (s.n - 1) / 2 for s in specs)
+    print(f"batch-512: {t_batch:.2f} s, {pairs * (128 + 3) / t_batch:.3e} pair-evals/s")

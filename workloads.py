@@ -95,3 +95,33 @@ def workload(name: str) -> Workload:
 
 
 WORKLOADS = ("plain-1k", "mixture-100k", "lognormal-1m")
+
+BATCH_FAMILIES = ("uniform", "normal", "gamma", "bimodal")
+
+
+@dataclass
+class ColumnSpec:
+    family: str
+    n: int
+    seed: int
+
+    def column(self, dtype=np.float32) -> np.ndarray:
+        return draw(self.family, self.n, self.seed, dtype)
+
+
+def batch_columns(count: int = 512, seed: int = 1998004, n_lo: float = 1e3, n_hi: float = 2e5):
+    """Uneven columns for the batched workload: n = round(exp(U(ln n_lo, ln n_hi))),
+    family uniform over uniform(0,1), N(0,1), Gamma(2,1), 0.3N(-3,1)+0.7N(2,0.5^2);
+    each column draws from its own child of SeedSequence(seed)."""
+    rng = _rng(seed)
+    ns = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count))).astype(np.int64)
+    fam = rng.integers(0, len(BATCH_FAMILIES), count)
+    kids = np.random.SeedSequence(seed).spawn(count)
+    return [ColumnSpec(BATCH_FAMILIES[int(f)], int(n), int(k.generate_state(1)[0])) for n, f, k in zip(ns, fam, kids)]
+
+
+# Batched and served requests: plug-in with three stages and LSCV over 128
+# points log-spaced over h_rot * [1/64, 4] (the optimum of skewed and
+# multimodal columns lies well below h_rot).
+BATCH_GRID = ("log_rot", 1.0 / 64.0, 4.0, 128)
+BATCH_STAGES = 3
