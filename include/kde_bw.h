@@ -111,6 +111,7 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *   "launch_evals" pair-term evaluations per kernel launch (launch splitting)
  *   "fp64_kappa"   mixed precision: kappa above which a plug-in stage is re-run
  *                  in FP64 (0 = never)
+ *   "serve_iter_evals" server: pair-term evaluations per scheduler iteration
  * Unknown keys give KDE_E_INVAL. */
 kde_status kde_ctx_set_option(kde_ctx* ctx, const char* key, int64_t value);
 
@@ -221,6 +222,34 @@ typedef struct {
  * device fails or an argument of the call is invalid.  out[k].g_out / gscale_out, when not NULL, must hold n_h
  * doubles and are filled for LSCV requests. */
 kde_status kde_batch(kde_ctx* ctx, const kde_request* reqs, int32_t n_req, kde_result* out);
+
+/* ---------------------------------------------------------------- serving
+ * A server runs on a context (one at a time; while it runs, the synchronous
+ * calls and option setters of that context return KDE_E_BUSY).  Requests
+ * submitted from any thread queue in FIFO order and are admitted while the
+ * sum of the device footprints of admitted requests stays within
+ * hbm_budget_bytes and fewer than max_slots are resident (a request larger
+ * than the whole budget is rejected with KDE_E_NOMEM).  Admitted requests
+ * stay resident on the device (samples, partial sums, state) until done.
+ * Continuous batching: every scheduler iteration launches, in shared
+ * launches, the next work units of every resident request, smallest
+ * remaining work first, within serve_iter_evals pair-term evaluations;
+ * requests admitted while others run join the next iteration.  Each result
+ * is bitwise identical to the same request run alone through kde_batch. */
+kde_status kde_server_start(kde_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots);
+/* Copies the column (host or device) and grid; the caller may free them on
+ * return.  Invalid requests are rejected here with KDE_E_INVAL. */
+kde_status kde_submit(kde_ctx* ctx, const kde_request* req, uint64_t* ticket);
+/* KDE_E_BUSY while pending.  When done, fills *out (out->g_out/gscale_out, if
+ * not NULL, receive n_h values), forgets the ticket and returns KDE_OK; the
+ * request's own outcome is out->status.  Unknown tickets give KDE_E_INVAL. */
+kde_status kde_poll(kde_ctx* ctx, uint64_t ticket, kde_result* out);
+/* As kde_poll, blocking up to timeout_s seconds (< 0: no limit). */
+kde_status kde_wait(kde_ctx* ctx, uint64_t ticket, kde_result* out, double timeout_s);
+/* Cancels queued requests (status KDE_E_CANCELLED), finishes admitted ones,
+ * stops the scheduler thread.  Results not yet collected stay pollable until
+ * the context is destroyed or a new server starts. */
+kde_status kde_server_stop(kde_ctx* ctx);
 
 /* LSCV bandwidth: the grid point minimising g(h), eq. (LSCV-finalH); ties go
  * to the lowest index.  k_out (may be NULL) receives its index, at_edge (may

@@ -45,6 +45,7 @@ EXPORTS = (
     "kde_ctx_create", "kde_ctx_destroy", "kde_last_error", "kde_ctx_set_stream", "kde_ctx_set_precision",
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
+    "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop",
 )
 
 
@@ -133,6 +134,11 @@ def _load():
                                        ctypes.POINTER(I32), PD]
     lib.kde_bw_lscv.argtypes = [P, kde_column, PD, I32, PD, ctypes.POINTER(I32), ctypes.POINTER(I)]
     lib.kde_batch.argtypes = [P, ctypes.POINTER(kde_request), I32, ctypes.POINTER(kde_result)]
+    lib.kde_server_start.argtypes = [P, ctypes.c_uint64, I32]
+    lib.kde_submit.argtypes = [P, ctypes.POINTER(kde_request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.kde_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result)]
+    lib.kde_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result), ctypes.c_double]
+    lib.kde_server_stop.argtypes = [P]
     for name in EXPORTS:
         if name not in ("kde_ctx_destroy", "kde_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -391,6 +397,46 @@ def kde_batch(ctx, requests):
     return [_unpack_result(outs[k], *bufs[k]) for k in range(m)]
 
 
+def kde_server_start(ctx, hbm_budget_bytes: int, max_slots: int) -> None:
+    _check(ctx, lib.kde_server_start(ctx, int(hbm_budget_bytes), int(max_slots)))
+
+
+def kde_submit(ctx, request: Request):
+    """Submit a Request to the context's server; returns (ticket, n_h or 0). Inputs are copied."""
+    req, keep, n_h = _make_request(request)
+    t = ctypes.c_uint64()
+    _check(ctx, lib.kde_submit(ctx, ctypes.byref(req), ctypes.byref(t)))
+    del keep
+    return t.value, (n_h if request.methods & KDE_METHOD_LSCV else 0)
+
+
+def _collect(ctx, fn, ticket, n_h, *extra):
+    out = kde_result()
+    g = np.full(n_h, np.nan) if n_h else None
+    gs = np.full(n_h, np.nan) if n_h else None
+    out.g_out = _pd(g)
+    out.gscale_out = _pd(gs)
+    st = fn(ctx, ticket, ctypes.byref(out), *extra)
+    if st == KDE_E_BUSY:
+        return None
+    _check(ctx, st)
+    return _unpack_result(out, g, gs)
+
+
+def kde_poll(ctx, ticket: int, n_h: int = 0):
+    """Result when done, None while pending."""
+    return _collect(ctx, lib.kde_poll, ticket, n_h)
+
+
+def kde_wait(ctx, ticket: int, n_h: int = 0, timeout_s: float = -1.0):
+    """Result when done (blocking up to timeout_s; < 0 = no limit), None on timeout."""
+    return _collect(ctx, lib.kde_wait, ticket, n_h, float(timeout_s))
+
+
+def kde_server_stop(ctx) -> None:
+    _check(ctx, lib.kde_server_stop(ctx))
+
+
 class Context:
     """Owns a kde_ctx; methods forward to the kde_* functions above."""
 
@@ -446,3 +492,28 @@ class Context:
 
     def batch(self, requests):
         return kde_batch(self.ctx, requests)
+
+    # serving
+    def server_start(self, hbm_budget_bytes: int, max_slots: int):
+        self._tickets = {}
+        kde_server_start(self.ctx, hbm_budget_bytes, max_slots)
+
+    def submit(self, request: Request) -> int:
+        t, n_h = kde_submit(self.ctx, request)
+        self._tickets[t] = n_h
+        return t
+
+    def poll(self, ticket: int):
+        r = kde_poll(self.ctx, ticket, self._tickets.get(ticket, 0))
+        if r is not None:
+            self._tickets.pop(ticket, None)
+        return r
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        r = kde_wait(self.ctx, ticket, self._tickets.get(ticket, 0), timeout_s)
+        if r is not None:
+            self._tickets.pop(ticket, None)
+        return r
+
+    def server_stop(self):
+        kde_server_stop(self.ctx)

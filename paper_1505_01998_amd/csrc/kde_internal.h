@@ -54,13 +54,26 @@ struct DevState {
   double cd[2];     // FP64 pair coefficients: 1/g^2, -1/(2 g^2)
 };
 
-// One column of a job: where its data, coefficients and partial sums live.
+// One column of a job: where its data, coefficients, partial sums and state
+// live (absolute device addresses, so resident columns of a server and the
+// packed columns of a batch are described the same way).
 struct ColDesc {
-  const void* raw;      // input samples (device address), float32 or float64
-  int64_t x_off;        // offset of the column in the packed x32/x64 arrays
-  int64_t c_off;        // offset in the per-grid-point arrays (h, c32, c64, g, gscale, sums/2)
-  int64_t part_off;     // LSCV partial slab: part[part_off + row * n_items + item], row = 2 h + {0, 1}
-  int64_t psi_part_off; // psi partials: part[psi_part_off + {0, 1} * n_items_psi + item]
+  const void* raw;      // input samples, float32 or float64
+  float* x32;           // padded FP32 working copy [n + kPad]
+  double* x64;          // padded FP64 working copy [n + kPad] (may be null)
+  double* stat;         // moment partials [kStatBlocks]
+  int* stat_nf;         // non-finite counts [kStatBlocks]
+  double* psi_part;     // psi partials [2][n_items_psi]
+  double* psi_sums;     // [2]
+  const double* h_in;   // explicit grid [n_h]
+  double* h;            // grid used [n_chunks * HC]
+  float* c32;           // FP32 exponent coefficients [n_chunks * HC]
+  double* c64;          // FP64 exponent coefficients [n_chunks * HC]
+  double* part;         // LSCV partials [2 n_h][n_items], row = 2 h + {0, 1}
+  double* sums;         // LSCV pair sums [2 n_h]
+  double* g;            // g(h) [n_h]
+  double* gs;           // gscale(h) [n_h]
+  DevState* st;
   int n;
   int raw_f64;
   int n_h;              // LSCV grid points (0: no LSCV for this column)
@@ -80,33 +93,27 @@ struct Unit {
   int col, row, j_begin, j_end, item, chunk;
 };
 
-// One row of a segmented reduction: out[dst] = sum of part[src .. src + n).
+// One row of a segmented reduction: *dst = sum of src[0 .. n).
 struct RowDesc {
-  int64_t src;
-  int64_t dst;
+  const double* src;
+  double* dst;
   int n;
   int pad0;
 };
 
 // ---- launchers (kde_kernels.hip); all asynchronous on `s` ----
-void launch_stats(hipStream_t s, int n_cols, int max_blocks, const ColDesc* cols, double* part, int* part_nf,
-                  float* x32, double* x64, DevState* st);
-
-void launch_psi_begin(hipStream_t s, int n_cols, DevState* st, int stage);
-void launch_psi_finish(hipStream_t s, int n_cols, const ColDesc* cols, DevState* st, int stage, const double* sums,
-                       int was_f64, int conditional);
-void launch_plugin_final(hipStream_t s, int n_cols, DevState* st);
-void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const float* x32, const double* x64,
-                      const ColDesc* cols, const Unit* units, int u0, int n_units, double* part, const DevState* st);
-
-void launch_lscv_prep(hipStream_t s, int n_cols, int hc, const ColDesc* cols, const double* h_in, DevState* st,
-                      double* h_dev, float* c32, double* c64);
-void launch_lscv_units(hipStream_t s, int hc, int f64, const float* x32, const double* x64, const ColDesc* cols,
-                       const Unit* units, int u0, int n_units, const float* c32, const double* c64, double* part,
-                       const DevState* st);
-void launch_lscv_finalize(hipStream_t s, int n_cols, const ColDesc* cols, const double* sums, const double* h_dev,
-                          DevState* st, double* g, double* gscale);
-
-void launch_reduce_rows(hipStream_t s, const double* part, const RowDesc* rows, int n_rows, double* out);
+// Column-level launches act on the columns cols[ids[0 .. n_ids)].
+void launch_stats(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int max_blocks);
+void launch_psi_begin(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage);
+void launch_psi_finish(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage, int was_f64,
+                       int conditional);
+void launch_plugin_final(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids);
+void launch_lscv_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int hc);
+void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids);
+// Pair kernels act on units[u0 .. u0 + n_units).
+void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColDesc* cols, const Unit* units, int u0,
+                      int n_units);
+void launch_lscv_units(hipStream_t s, int hc, int f64, const ColDesc* cols, const Unit* units, int u0, int n_units);
+void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows);
 
 }  // namespace kde

@@ -134,10 +134,9 @@ __device__ __forceinline__ double load_raw(const ColDesc& c, int i) {
 __device__ __forceinline__ int stat_blocks(int n) { return min(kStatBlocks, (n + 2047) / 2048); }
 
 // Pass 1: per-block FP64 sum of the samples and count of non-finite values.
-// Grid (max blocks, columns); part[col * kStatBlocks + b].
-__global__ __launch_bounds__(kThreads) void k_stats_sum(const ColDesc* __restrict__ cols, double* __restrict__ part,
-                                                        int* __restrict__ part_nf) {
-  const ColDesc c = cols[blockIdx.y];
+// Grid (max blocks, columns).
+__global__ __launch_bounds__(kThreads) void k_stats_sum(const ColDesc* __restrict__ cols, const int* __restrict__ ids) {
+  const ColDesc c = cols[ids[blockIdx.y]];
   const int nblk = stat_blocks(c.n);
   if ((int)blockIdx.x >= nblk) return;
   __shared__ double sh[kThreads];
@@ -156,16 +155,15 @@ __global__ __launch_bounds__(kThreads) void k_stats_sum(const ColDesc* __restric
   if (nf) atomicAdd(&nf_sh, nf);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    part[(size_t)blockIdx.y * kStatBlocks + blockIdx.x] = s;
-    part_nf[(size_t)blockIdx.y * kStatBlocks + blockIdx.x] = nf_sh;
+    c.stat[blockIdx.x] = s;
+    c.stat_nf[blockIdx.x] = nf_sh;
   }
 }
 
 // Mean of each column (block per column); float64 columns are shifted by it.
 __global__ __launch_bounds__(kThreads) void k_stats_mean(const ColDesc* __restrict__ cols,
-                                                         const double* __restrict__ part,
-                                                         const int* __restrict__ part_nf, DevState* st) {
-  const ColDesc c = cols[blockIdx.x];
+                                                         const int* __restrict__ ids) {
+  const ColDesc c = cols[ids[blockIdx.x]];
   const int nblk = stat_blocks(c.n);
   __shared__ double sh[kThreads];
   __shared__ int nf_sh;
@@ -174,13 +172,13 @@ __global__ __launch_bounds__(kThreads) void k_stats_mean(const ColDesc* __restri
   double s = 0.0;
   int nf = 0;
   for (int b = threadIdx.x; b < nblk; b += kThreads) {
-    s += part[(size_t)blockIdx.x * kStatBlocks + b];
-    nf += part_nf[(size_t)blockIdx.x * kStatBlocks + b];
+    s += c.stat[b];
+    nf += c.stat_nf[b];
   }
   if (nf) atomicAdd(&nf_sh, nf);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    DevState& d = st[blockIdx.x];
+    DevState& d = *c.st;
     d.n = (double)c.n;
     d.status = nf_sh ? kStInval : kStOk;
     d.mean = s / (double)c.n;
@@ -190,16 +188,14 @@ __global__ __launch_bounds__(kThreads) void k_stats_mean(const ColDesc* __restri
 
 // Pass 2: per-block sum of squared deviations; writes the padded FP32 (and
 // FP64) working copies of the column.
-__global__ __launch_bounds__(kThreads) void k_stats_dev(const ColDesc* __restrict__ cols, double* __restrict__ part,
-                                                        float* __restrict__ x32, double* __restrict__ x64,
-                                                        const DevState* __restrict__ st) {
-  const ColDesc c = cols[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void k_stats_dev(const ColDesc* __restrict__ cols, const int* __restrict__ ids) {
+  const ColDesc c = cols[ids[blockIdx.y]];
   const int nblk = stat_blocks(c.n);
   if ((int)blockIdx.x >= nblk) return;
   __shared__ double sh[kThreads];
-  const double mean = st[blockIdx.y].mean, shift = st[blockIdx.y].shift;
-  float* y32 = x32 + c.x_off;
-  double* y64 = x64 ? x64 + c.x_off : nullptr;
+  const double mean = c.st->mean, shift = c.st->shift;
+  float* y32 = c.x32;
+  double* y64 = c.x64;
   const int chunk = (c.n + nblk - 1) / nblk;
   const int b0 = blockIdx.x * chunk;
   const int b1 = min(c.n, b0 + chunk);
@@ -216,19 +212,19 @@ __global__ __launch_bounds__(kThreads) void k_stats_dev(const ColDesc* __restric
     if (y64) y64[i] = kInfD;
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[(size_t)blockIdx.y * kStatBlocks + blockIdx.x] = s;
+  if (threadIdx.x == 0) c.stat[blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(kThreads) void k_stats_final(const ColDesc* __restrict__ cols,
-                                                          const double* __restrict__ part, DevState* st) {
-  const ColDesc c = cols[blockIdx.x];
+                                                          const int* __restrict__ ids) {
+  const ColDesc c = cols[ids[blockIdx.x]];
   const int nblk = stat_blocks(c.n);
   __shared__ double sh[kThreads];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(size_t)blockIdx.x * kStatBlocks + b];
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s += c.stat[b];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    DevState& d = st[blockIdx.x];
+    DevState& d = *c.st;
     const double n = d.n;
     d.var = s / (n - 1.0);
     d.sigma = sqrt(d.var);
@@ -240,10 +236,10 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(const ColDesc* __restr
 
 // ------------------------------------------------------------------ plug-in scalar steps
 // One thread per column.  Stage s in {0, 1, 2} estimates psi_r, r = 8 - 2 s.
-__global__ void k_psi_begin(int n_cols, DevState* st, int stage) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= n_cols) return;
-  DevState& d = st[col];
+__global__ void k_psi_begin(const ColDesc* __restrict__ cols, const int* __restrict__ ids, int n_ids, int stage) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_ids) return;
+  DevState& d = *cols[ids[k]].st;
   d.active = 0;
   d.need_f64 = 0;
   if (d.status != kStOk || d.pstatus != kStOk || d.stages == 0) return;
@@ -275,20 +271,22 @@ __global__ void k_psi_begin(int n_cols, DevState* st, int stage) {
   d.cd[1] = -0.5 * ig2;
 }
 
-// sums[2 col] = sum_{i<j} He_r(u) e^{-u^2/2}, sums[2 col + 1] = sum of its
+// psi_sums[0] = sum_{i<j} He_r(u) e^{-u^2/2}, psi_sums[1] = sum of its
 // absolute value, u = (X_i - X_j)/g.  psi_r = [2 sum K^(r) + n K^(r)(0)] / (n^2 g^(r+1)).
 // conditional: this is the FP64 re-run of the mixed form; skip unless flagged.
-__global__ void k_psi_finish(int n_cols, DevState* st, int stage, const double* __restrict__ sums, int was_f64,
-                             int conditional) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= n_cols) return;
-  DevState& d = st[col];
+__global__ void k_psi_finish(const ColDesc* __restrict__ cols, const int* __restrict__ ids, int n_ids, int stage,
+                             int was_f64, int conditional) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_ids) return;
+  const ColDesc& c = cols[ids[k]];
+  DevState& d = *c.st;
+  const double* sums = c.psi_sums;
   if (!d.active) return;
   if (conditional && !d.need_f64) return;
   const int r = 8 - 2 * stage;
   const double inv_s2pi = 1.0 / sqrt(2.0 * kPi);
   const double n = d.n, g = d.g[stage];
-  const double s = sums[2 * col] * inv_s2pi, a = sums[2 * col + 1] * inv_s2pi;
+  const double s = sums[0] * inv_s2pi, a = sums[1] * inv_s2pi;
   d.psi[stage] = (2.0 * s + n * herm_at0(r) * inv_s2pi) / (n * n * pow(g, (double)(r + 1)));
   d.kappa[stage] = (s != 0.0) ? a / fabs(s) : kInfD;
   d.prec_used[stage] = was_f64 ? 1 : 0;
@@ -299,10 +297,10 @@ __global__ void k_psi_finish(int n_cols, DevState* st, int stage, const double* 
   }
 }
 
-__global__ void k_plugin_final(int n_cols, DevState* st) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= n_cols) return;
-  DevState& d = st[col];
+__global__ void k_plugin_final(const ColDesc* __restrict__ cols, const int* __restrict__ ids, int n_ids) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_ids) return;
+  DevState& d = *cols[ids[k]].st;
   if (d.status != kStOk || d.pstatus != kStOk || d.stages == 0) return;
   // h = [R(K) / (mu_2^2 psi_4 n)]^(1/5), R(K) = 1/(2 sqrt(pi))
   const double rad = (0.5 / sqrt(kPi)) / (d.psi[2] * d.n);
@@ -340,15 +338,12 @@ __device__ __forceinline__ void psi_run(const float4* __restrict__ tile, int jl,
 
 
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_psi_units_f32(const float* __restrict__ x32,
-                                                            const ColDesc* __restrict__ cols,
-                                                            const Unit* __restrict__ units, int u0,
-                                                            double* __restrict__ part,
-                                                            const DevState* __restrict__ st) {
+__global__ __launch_bounds__(kThreads) void k_psi_units_f32(const ColDesc* __restrict__ cols,
+                                                            const Unit* __restrict__ units, int u0) {
   const Unit u = units[u0 + blockIdx.x];
-  if (!st[u.col].active) return;
   const ColDesc c = cols[u.col];
-  const float* x = x32 + c.x_off;
+  if (!c.st->active) return;
+  const float* x = c.x32;
   const int n = c.n;
   __shared__ float4 tile[kBJ / 4];
   __shared__ double red[2][4];
@@ -358,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_psi_units_f32(const float* __restr
   const int i = row0 + tid;
   const float xi = (i < n) ? x[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
-  const float ig2 = st[u.col].cf[0], cg = st[u.col].cf[1];
+  const float ig2 = c.st->cf[0], cg = c.st->cf[1];
   float aS = 0.f, cS = 0.f, aA = 0.f, cA = 0.f;
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
@@ -385,8 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_psi_units_f32(const float* __restr
   }
   __syncthreads();
   if (tid < 2)
-    part[c.psi_part_off + (int64_t)tid * c.n_items_psi + u.item] =
-        ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+    c.psi_part[(int64_t)tid * c.n_items_psi + u.item] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
 }
 
 template <int R, bool MASK>
@@ -406,16 +400,14 @@ __device__ __forceinline__ void psi_run64(const double* __restrict__ tile, int j
 
 // conditional: run only when the FP32 pass flagged this column's stage (mixed form).
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_psi_units_f64(const double* __restrict__ x64,
-                                                            const ColDesc* __restrict__ cols,
+__global__ __launch_bounds__(kThreads) void k_psi_units_f64(const ColDesc* __restrict__ cols,
                                                             const Unit* __restrict__ units, int u0,
-                                                            double* __restrict__ part,
-                                                            const DevState* __restrict__ st, int conditional) {
+                                                            int conditional) {
   const Unit u = units[u0 + blockIdx.x];
-  if (!st[u.col].active) return;
-  if (conditional && !st[u.col].need_f64) return;
   const ColDesc c = cols[u.col];
-  const double* x = x64 + c.x_off;
+  if (!c.st->active) return;
+  if (conditional && !c.st->need_f64) return;
+  const double* x = c.x64;
   const int n = c.n;
   __shared__ double tile[kBJ];
   __shared__ double red[2][4];
@@ -425,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void k_psi_units_f64(const double* __rest
   const int i = row0 + tid;
   const double xi = (i < n) ? x[i] : 0.0;
   const int wave_i0 = row0 + wave * 64;
-  const double ig2 = st[u.col].cd[0], cg = st[u.col].cd[1];
+  const double ig2 = c.st->cd[0], cg = c.st->cd[1];
   double s = 0.0, a = 0.0;
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
@@ -451,42 +443,40 @@ __global__ __launch_bounds__(kThreads) void k_psi_units_f64(const double* __rest
   }
   __syncthreads();
   if (tid < 2)
-    part[c.psi_part_off + (int64_t)tid * c.n_items_psi + u.item] =
-        ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+    c.psi_part[(int64_t)tid * c.n_items_psi + u.item] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
 }
 
 // ------------------------------------------------------------------ LSCV kernels
-// Block per column.  Grid point k of the column: explicit h_in[c_off + k], the
+// Block per column.  Grid point k of the column: explicit h_in[k], the
 // paper's default (linear over sigma [h0/4, 4 h0] = h_rot [1/4, 4]) or log-spaced
 // over h_rot [lo, hi].  c32 = -log2(e) / (4 h^2), so exp2(D^2 c32) =
 // exp(-D^2/(4 h^2)) and its square is exp(-D^2/(2 h^2)); c64 = -1/(4 h^2).
 // Entries past n_h up to the chunk multiple hold -1 (finite, unused).
-__global__ __launch_bounds__(kThreads) void k_lscv_prep(const ColDesc* __restrict__ cols, int hc,
-                                                        const double* __restrict__ h_in, DevState* st,
-                                                        double* __restrict__ h_dev, float* __restrict__ c32,
-                                                        double* __restrict__ c64) {
-  const ColDesc c = cols[blockIdx.x];
+__global__ __launch_bounds__(kThreads) void k_lscv_prep(const ColDesc* __restrict__ cols,
+                                                        const int* __restrict__ ids, int hc) {
+  const ColDesc c = cols[ids[blockIdx.x]];
   if (c.n_h <= 0) return;
-  const double hr = st[blockIdx.x].h_rot;
+  const double hr = c.st->h_rot;
   const int m = c.n_chunks * hc;
   for (int k = threadIdx.x; k < m; k += kThreads) {
-    const int64_t o = c.c_off + k;
+    const int o = k;
     if (k < c.n_h) {
       double h;
       const double t = (c.n_h == 1) ? 0.0 : (double)k / (double)(c.n_h - 1);
       if (c.grid_kind == kGridExplicit)
-        h = h_in[o];
+        h = c.h_in[o];
       else if (c.grid_kind == kGridPaper)
         h = hr * 0.25 + (hr * 4.0 - hr * 0.25) * t;
       else
         h = hr * exp(log(c.grid_lo) + (log(c.grid_hi) - log(c.grid_lo)) * t);
-      h_dev[o] = h;
+      c.h[o] = h;
       const double q = 1.0 / (4.0 * h * h);
-      c32[o] = (float)(-kLog2E * q);
-      c64[o] = -q;
+      c.c32[o] = (float)(-kLog2E * q);
+      c.c64[o] = -q;
     } else {
-      c32[o] = -1.0f;
-      c64[o] = -1.0;
+      c.h[o] = 0.0;
+      c.c32[o] = -1.0f;
+      c.c64[o] = -1.0;
     }
   }
 }
@@ -526,16 +516,12 @@ __device__ __forceinline__ void lscv_run(const float4* __restrict__ tile, int jl
 }
 
 template <int HC>
-__global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const float* __restrict__ x32,
-                                                             const ColDesc* __restrict__ cols,
-                                                             const Unit* __restrict__ units, int u0,
-                                                             const float* __restrict__ c32,
-                                                             double* __restrict__ part,
-                                                             const DevState* __restrict__ st) {
+__global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __restrict__ cols,
+                                                             const Unit* __restrict__ units, int u0) {
   const Unit u = units[u0 + blockIdx.x];
-  if (st[u.col].status != kStOk) return;
   const ColDesc c = cols[u.col];
-  const float* x = x32 + c.x_off;
+  if (c.st->status != kStOk) return;
+  const float* x = c.x32;
   const int n = c.n;
   __shared__ float4 tile[kBJ / 4];
   __shared__ double red[4][2 * HC];
@@ -545,7 +531,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const float* __rest
   const int i = row0 + tid;
   const float xi = (i < n) ? x[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
-  const float* cc = c32 + c.c_off + u.chunk * HC;
+  const float* cc = c.c32 + u.chunk * HC;
   float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
@@ -581,7 +567,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const float* __rest
     const int h = u.chunk * HC + (tid >> 1);
     if (h < c.n_h) {
       const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      part[c.part_off + (int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
+      c.part[(int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
     }
   }
 }
@@ -604,16 +590,12 @@ __device__ __forceinline__ void lscv_run64(const double* __restrict__ tile, int 
 }
 
 template <int HC>
-__global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const double* __restrict__ x64,
-                                                             const ColDesc* __restrict__ cols,
-                                                             const Unit* __restrict__ units, int u0,
-                                                             const double* __restrict__ c64,
-                                                             double* __restrict__ part,
-                                                             const DevState* __restrict__ st) {
+__global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const ColDesc* __restrict__ cols,
+                                                             const Unit* __restrict__ units, int u0) {
   const Unit u = units[u0 + blockIdx.x];
-  if (st[u.col].status != kStOk) return;
   const ColDesc c = cols[u.col];
-  const double* x = x64 + c.x_off;
+  if (c.st->status != kStOk) return;
+  const double* x = c.x64;
   const int n = c.n;
   __shared__ double tile[kBJ];
   __shared__ double red[4][2 * HC];
@@ -623,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const double* __res
   const int i = row0 + tid;
   const double xi = (i < n) ? x[i] : 0.0;
   const int wave_i0 = row0 + wave * 64;
-  const double* cc = c64 + c.c_off + u.chunk * HC;
+  const double* cc = c.c64 + u.chunk * HC;
   double ck[HC], s1[HC], s2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
@@ -660,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const double* __res
     const int h = u.chunk * HC + (tid >> 1);
     if (h < c.n_h) {
       const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      part[c.part_off + (int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
+      c.part[(int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
     }
   }
 }
@@ -668,17 +650,15 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const double* __res
 // Block per column.  g(h) = h^-1 [2 n^-2 ((4pi)^-1/2 S1 - 2 (2pi)^-1/2 S2) + n^-1 (4pi)^-1/2];
 // gscale with +.  Grid argmin with ties to the lowest index.
 __global__ __launch_bounds__(1024) void k_lscv_finalize(const ColDesc* __restrict__ cols,
-                                                        const double* __restrict__ sums_all,
-                                                        const double* __restrict__ h_all, DevState* st,
-                                                        double* __restrict__ g_all, double* __restrict__ gs_all) {
-  const ColDesc c = cols[blockIdx.x];
+                                                        const int* __restrict__ ids) {
+  const ColDesc c = cols[ids[blockIdx.x]];
   if (c.n_h <= 0) return;
-  DevState& d = st[blockIdx.x];
+  DevState& d = *c.st;
   const int n_h = c.n_h;
-  const double* sums = sums_all + 2 * c.c_off;
-  const double* h_dev = h_all + c.c_off;
-  double* g = g_all + c.c_off;
-  double* gscale = gs_all + c.c_off;
+  const double* sums = c.sums;
+  const double* h_dev = c.h;
+  double* g = c.g;
+  double* gscale = c.gs;
   __shared__ double bv[1024];
   __shared__ int bk[1024];
   const int t = threadIdx.x;
@@ -736,93 +716,87 @@ __global__ __launch_bounds__(1024) void k_lscv_finalize(const ColDesc* __restric
   }
 }
 
-// Segmented sum, block per row: out[dst] = sum_c part[src + c], fixed order.
-__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* __restrict__ part,
-                                                          const RowDesc* __restrict__ rows,
-                                                          double* __restrict__ out) {
+// Segmented sum, block per row: *dst = sum_c src[c], fixed order.
+__global__ __launch_bounds__(kThreads) void k_reduce_rows(const RowDesc* __restrict__ rows) {
   __shared__ double sh[kThreads];
   const RowDesc r = rows[blockIdx.x];
-  const double* p = part + r.src;
   double s = 0.0;
-  for (int c = threadIdx.x; c < r.n; c += kThreads) s += p[c];
+  for (int c = threadIdx.x; c < r.n; c += kThreads) s += r.src[c];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[r.dst] = s;
+  if (threadIdx.x == 0) *r.dst = s;
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-void launch_stats(hipStream_t s, int n_cols, int max_blocks, const ColDesc* cols, double* part, int* part_nf,
-                  float* x32, double* x64, DevState* st) {
-  const dim3 grid2(max_blocks, n_cols);
-  k_stats_sum<<<grid2, kThreads, 0, s>>>(cols, part, part_nf);
-  k_stats_mean<<<n_cols, kThreads, 0, s>>>(cols, part, part_nf, st);
-  k_stats_dev<<<grid2, kThreads, 0, s>>>(cols, part, x32, x64, st);
-  k_stats_final<<<n_cols, kThreads, 0, s>>>(cols, part, st);
+static inline int id_blocks(int n_ids) { return (n_ids + kThreads - 1) / kThreads; }
+
+void launch_stats(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int max_blocks) {
+  if (n_ids <= 0) return;
+  const dim3 grid2(max_blocks, n_ids);
+  k_stats_sum<<<grid2, kThreads, 0, s>>>(cols, ids);
+  k_stats_mean<<<n_ids, kThreads, 0, s>>>(cols, ids);
+  k_stats_dev<<<grid2, kThreads, 0, s>>>(cols, ids);
+  k_stats_final<<<n_ids, kThreads, 0, s>>>(cols, ids);
 }
 
-static inline int col_blocks(int n_cols) { return (n_cols + kThreads - 1) / kThreads; }
-
-void launch_psi_begin(hipStream_t s, int n_cols, DevState* st, int stage) {
-  k_psi_begin<<<col_blocks(n_cols), kThreads, 0, s>>>(n_cols, st, stage);
+void launch_psi_begin(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage) {
+  if (n_ids > 0) k_psi_begin<<<id_blocks(n_ids), kThreads, 0, s>>>(cols, ids, n_ids, stage);
 }
 
-void launch_psi_finish(hipStream_t s, int n_cols, const ColDesc* cols, DevState* st, int stage, const double* sums,
-                       int was_f64, int conditional) {
-  (void)cols;
-  k_psi_finish<<<col_blocks(n_cols), kThreads, 0, s>>>(n_cols, st, stage, sums, was_f64, conditional);
+void launch_psi_finish(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage, int was_f64,
+                       int conditional) {
+  if (n_ids > 0) k_psi_finish<<<id_blocks(n_ids), kThreads, 0, s>>>(cols, ids, n_ids, stage, was_f64, conditional);
 }
 
-void launch_plugin_final(hipStream_t s, int n_cols, DevState* st) {
-  k_plugin_final<<<col_blocks(n_cols), kThreads, 0, s>>>(n_cols, st);
+void launch_plugin_final(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids) {
+  if (n_ids > 0) k_plugin_final<<<id_blocks(n_ids), kThreads, 0, s>>>(cols, ids, n_ids);
 }
 
-void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const float* x32, const double* x64,
-                      const ColDesc* cols, const Unit* units, int u0, int n_units, double* part, const DevState* st) {
+void launch_lscv_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int hc) {
+  if (n_ids > 0) k_lscv_prep<<<n_ids, kThreads, 0, s>>>(cols, ids, hc);
+}
+
+void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids) {
+  if (n_ids > 0) k_lscv_finalize<<<n_ids, 1024, 0, s>>>(cols, ids);
+}
+
+void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColDesc* cols, const Unit* units, int u0,
+                      int n_units) {
+  if (n_units <= 0) return;
   if (f64) {
     switch (r) {
-      case 8: k_psi_units_f64<8><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, part, st, conditional); break;
-      case 6: k_psi_units_f64<6><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, part, st, conditional); break;
-      default: k_psi_units_f64<4><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, part, st, conditional); break;
+      case 8: k_psi_units_f64<8><<<n_units, kThreads, 0, s>>>(cols, units, u0, conditional); break;
+      case 6: k_psi_units_f64<6><<<n_units, kThreads, 0, s>>>(cols, units, u0, conditional); break;
+      default: k_psi_units_f64<4><<<n_units, kThreads, 0, s>>>(cols, units, u0, conditional); break;
     }
   } else {
     switch (r) {
-      case 8: k_psi_units_f32<8><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, part, st); break;
-      case 6: k_psi_units_f32<6><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, part, st); break;
-      default: k_psi_units_f32<4><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, part, st); break;
+      case 8: k_psi_units_f32<8><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      case 6: k_psi_units_f32<6><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      default: k_psi_units_f32<4><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
     }
   }
 }
 
-void launch_lscv_prep(hipStream_t s, int n_cols, int hc, const ColDesc* cols, const double* h_in, DevState* st,
-                      double* h_dev, float* c32, double* c64) {
-  k_lscv_prep<<<n_cols, kThreads, 0, s>>>(cols, hc, h_in, st, h_dev, c32, c64);
-}
-
-void launch_lscv_units(hipStream_t s, int hc, int f64, const float* x32, const double* x64, const ColDesc* cols,
-                       const Unit* units, int u0, int n_units, const float* c32, const double* c64, double* part,
-                       const DevState* st) {
+void launch_lscv_units(hipStream_t s, int hc, int f64, const ColDesc* cols, const Unit* units, int u0, int n_units) {
+  if (n_units <= 0) return;
   if (f64) {
     switch (hc) {
-      case 4: k_lscv_units_f64<4><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, c64, part, st); break;
-      default: k_lscv_units_f64<8><<<n_units, kThreads, 0, s>>>(x64, cols, units, u0, c64, part, st); break;
+      case 4: k_lscv_units_f64<4><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      default: k_lscv_units_f64<8><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
     }
   } else {
     switch (hc) {
-      case 8: k_lscv_units_f32<8><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, c32, part, st); break;
-      case 32: k_lscv_units_f32<32><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, c32, part, st); break;
-      default: k_lscv_units_f32<16><<<n_units, kThreads, 0, s>>>(x32, cols, units, u0, c32, part, st); break;
+      case 8: k_lscv_units_f32<8><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      case 32: k_lscv_units_f32<32><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      default: k_lscv_units_f32<16><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
     }
   }
 }
 
-void launch_lscv_finalize(hipStream_t s, int n_cols, const ColDesc* cols, const double* sums, const double* h_dev,
-                          DevState* st, double* g, double* gscale) {
-  k_lscv_finalize<<<n_cols, 1024, 0, s>>>(cols, sums, h_dev, st, g, gscale);
-}
-
-void launch_reduce_rows(hipStream_t s, const double* part, const RowDesc* rows, int n_rows, double* out) {
-  if (n_rows > 0) k_reduce_rows<<<n_rows, kThreads, 0, s>>>(part, rows, out);
+void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows) {
+  if (n_rows > 0) k_reduce_rows<<<n_rows, kThreads, 0, s>>>(rows);
 }
 
 }  // namespace kde

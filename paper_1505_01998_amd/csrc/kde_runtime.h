@@ -1,0 +1,196 @@
+// kde_runtime.h -- host-side structures shared by the runtime and the server
+// of the bandwidth-selection library.  Internal; the ABI is kde_bw.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kde_bw.h"
+#include "kde_internal.h"
+
+namespace kde {
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+};
+
+// Work items of one column for one pass: blocks of the i < j triangle,
+// longest first.
+struct ColItems {
+  std::vector<int> row, jb, je;
+  std::vector<double> pairs;
+};
+
+struct UnitCost {
+  double pairs;  // algorithmic i < j pairs of the unit's item
+  double evals;  // pair-term evaluations of the unit
+};
+
+// Host plan of one column: its work decomposition (which depends only on n,
+// the grid size and the context options, never on other columns) and the
+// byte layout of its device block.
+struct ColPlan {
+  int n = 0;
+  int f64 = 0;
+  bool plugin = false, lscv = false;
+  int stages = 0;  // 0 when no plug-in
+  int hc = 16;
+  int n_h = 0, n_chunks = 0;
+  int grid_kind = 0;
+  double grid_lo = 0.0, grid_hi = 0.0;
+  std::vector<double> grid_h;  // explicit grid
+  ColItems psi_items, lscv_items;
+  // device block layout (byte offsets); raw holds the samples of a host column
+  bool want_x64 = false;
+  bool raw_in_block = false;
+  size_t raw_bytes = 0, off_raw = 0;
+  size_t off_x32 = 0, off_x64 = 0, off_stat = 0, off_nf = 0, off_psi_part = 0, off_psi_sums = 0, off_hin = 0,
+         off_h = 0, off_c32 = 0, off_c64 = 0, off_part = 0, off_sums = 0, off_g = 0, off_gs = 0, bytes = 0;
+};
+
+// Everything one pass of the executor launches, in order: moments, the
+// plug-in stages, the LSCV passes.  Column ids index `cols`.
+struct Upload {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+
+struct IterPlan {
+  std::vector<Upload> uploads;  // host-to-device copies issued before the launches
+  std::vector<ColDesc> cols;
+  std::vector<int> ids_stats;
+  std::vector<int> ids_begin[3], ids_finish[3];
+  std::vector<Unit> psi_units[3];
+  std::vector<UnitCost> psi_cost[3];
+  std::vector<RowDesc> psi_rows[3];
+  std::vector<Unit> psi_cond_units[3];  // FP64 re-run (mixed form), of columns finishing the stage
+  std::vector<UnitCost> psi_cond_cost[3];
+  std::vector<int> ids_plugin_final;
+  std::vector<int> ids_lscv_prep;
+  std::vector<Unit> lscv_units;
+  std::vector<UnitCost> lscv_cost;
+  std::vector<RowDesc> lscv_rows;
+  std::vector<int> ids_lscv_final;
+  int max_stat_blocks = 1;
+  void clear();
+};
+
+struct Server;
+struct ServerDeleter {
+  void operator()(Server* s) const;  // kde_server.hip
+};
+bool server_running(const Server* s);
+
+}  // namespace kde
+
+struct kde_ctx {
+  int device = 0;
+  kde_prec prec = KDE_PREC_MIXED;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // options
+  int opt_hc = 16;
+  int64_t opt_seg = -1;            // <0 automatic, 0 whole rows, >0 explicit
+  double opt_launch_evals = 4e12;  // pair-term evaluations per launch
+  double opt_fp64_kappa = 1e3;
+  double opt_serve_iter_evals = 4e11;  // server: pair-term evaluations per iteration
+  // device workspace of synchronous jobs
+  kde::DevBuf<char> stage;   // host columns copied in
+  kde::DevBuf<char> blocks;  // per-column device blocks, packed
+  kde::DevBuf<kde::DevState> st;
+  kde::DevBuf<char> blob;    // column table, id lists, units, rows of one executor pass
+  // pinned host staging
+  kde::DevState* h_st = nullptr;
+  size_t h_st_cap = 0;
+  double* h_out = nullptr;
+  size_t h_out_cap = 0;
+  char* h_blob = nullptr;
+  size_t h_blob_cap = 0;
+  // plan of the current synchronous job (kept alive until its copies finish)
+  std::vector<kde::ColPlan> plans;
+  std::vector<int> plan_req;  // request index of each planned column
+  kde::IterPlan iter;
+  // timing
+  bool timing = false;
+  int64_t t_launches[2] = {0, 0};
+  double t_ms[2] = {0, 0};
+  double t_evals[2] = {0, 0};
+  struct Pending {
+    hipEvent_t a, b;
+    int family;
+    double evals;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
+  // server (null when not serving)
+  std::unique_ptr<kde::Server, kde::ServerDeleter> server;
+};
+
+namespace kde {
+
+constexpr int kFamLscv = 0, kFamPsi = 1;
+
+kde_status fail(kde_ctx* c, kde_status st, const std::string& msg);
+kde_status status_of(int st);
+std::string check_column(const kde_column& x);
+std::string check_grid(const kde_grid& g);
+// Fills the work decomposition and block layout of one request's column.
+std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p);
+// Points a descriptor at a column block; raw is the caller's device column
+// (ignored when the plan keeps the samples in the block); st is its state.
+void bind_column(const ColPlan& p, char* block, const void* raw, DevState* st, ColDesc& d);
+// Appends a column's whole work (moments, every plug-in stage, the LSCV pass)
+// to an executor plan; host_raw / host grid are uploaded into the block.
+void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int id, const void* host_raw,
+                     IterPlan& it);
+// Pieces used by the server to schedule a column's work over several passes.
+void psi_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost);
+void lscv_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost);
+void psi_rows_of(const ColPlan& p, const ColDesc& d, std::vector<RowDesc>& rows);
+void lscv_rows_of(const ColPlan& p, const ColDesc& d, std::vector<RowDesc>& rows);
+void init_state(const ColPlan& p, double fp64_kappa, DevState& h);
+// Resets r (keeping its g/gscale pointers): h's NaN, k_lscv -1, status st.
+void init_result(kde_result& r, kde_status st);
+// Copies a finished column's scalar results (status, h's, plug-in info) into r.
+void fill_result(const ColPlan& p, const DevState& h, kde_result& r);
+// Enqueues one executor pass on the context's stream (no synchronisation).
+kde_status execute(kde_ctx* c, IterPlan& it);
+kde_status sync_and_check(kde_ctx* c);
+kde_status ensure_pinned_bytes(kde_ctx* c, char*& p, size_t& cap, size_t bytes);
+
+// Grows a device buffer to hold at least `count` elements (contents are lost).
+template <typename T>
+kde_status ensure(kde_ctx* c, DevBuf<T>& b, size_t count) {
+  if (b.cap >= count) return KDE_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  const size_t want = count < 256 ? 256 : count;
+  hipError_t e = hipMalloc((void**)&b.p, want * sizeof(T));
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(c, KDE_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+  }
+  b.cap = want;
+  return KDE_OK;
+}
+
+}  // namespace kde
+
+#define KDE_HIP_TRY(ctx, expr)                                                                                \
+  do {                                                                                                        \
+    hipError_t e_ = (expr);                                                                                   \
+    if (e_ != hipSuccess)                                                                                     \
+      return ::kde::fail((ctx), KDE_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_));             \
+  } while (0)

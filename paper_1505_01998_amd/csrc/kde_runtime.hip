@@ -1,13 +1,15 @@
 // kde_runtime.hip -- host runtime and C ABI of the bandwidth-selection library.
 //
-// Every call is a job over a set of columns (one for the single-column
-// selectors, many for kde_batch).  A job is a chain of kernels on one stream:
-// moments for all columns (FP64, two passes), the device-side scalar steps of
-// the selectors, the pair kernels over work units that mix columns (split into
-// launches of bounded work), fixed-order FP64 segmented reductions and the
-// finalize kernels; one round of device-to-host copies returns the results.
-// No step of the method runs on the host: the host checks arguments and plans
-// the work units.
+// Every call is a job over a set of columns: one for the single-column
+// selectors, many for kde_batch, the resident requests of a server iteration.
+// Each column gets a device block (working copies of its samples, partial
+// sums, grid, results) described by a ColDesc of absolute pointers, and its
+// own work decomposition, which depends only on its n, its grid size and the
+// context options.  The executor enqueues one pass: moments, the plug-in
+// stages, the LSCV pass, each as launches whose work units mix the columns
+// (largest first, split into launches of bounded work), then fixed-order
+// FP64 segmented reductions and the finalize kernels.  No step of the method
+// runs on the host: the host checks arguments and plans the work units.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,139 +21,40 @@
 
 #include "kde_bw.h"
 #include "kde_internal.h"
+#include "kde_runtime.h"
 
 using kde::ColDesc;
+using kde::ColItems;
+using kde::ColPlan;
 using kde::DevState;
+using kde::IterPlan;
 using kde::RowDesc;
 using kde::Unit;
+using kde::UnitCost;
 
-namespace {
-
-struct Pending {
-  hipEvent_t a, b;
-  int family;
-  double evals;
-};
-
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t cap = 0;
-};
-
-// Work items of one column for one pass: blocks of the i < j triangle.
-struct ColItems {
-  std::vector<int> row, jb, je;
-  std::vector<double> pairs;
-};
-
-// One column of a job as the host plans it.
-struct JobCol {
-  int req;            // index of the request it came from
-  const void* data;   // caller's samples (host or device)
-  int on_device;
-  int n;
-  int f64;
-  bool plugin, lscv;
-  int stages;
-  kde_grid grid;
-  ColDesc d;          // device descriptor (raw pointer filled at run time)
-  ColItems lscv_items, psi_items;
-};
-
-struct UnitCost {
-  double pairs;   // algorithmic i<j pairs of the unit's item
-  double evals;   // pair-term evaluations of the unit
-};
-
-}  // namespace
-
-struct kde_ctx {
-  int device = 0;
-  kde_prec prec = KDE_PREC_MIXED;
-  hipStream_t own = nullptr;
-  hipStream_t stream = nullptr;
-  std::string err;
-  // options
-  int opt_hc = 16;
-  int64_t opt_seg = -1;            // <0 automatic, 0 whole rows, >0 explicit
-  double opt_launch_evals = 4e12;  // pair-term evaluations per launch
-  double opt_fp64_kappa = 1e3;
-  // device workspace
-  DevBuf<char> stage;
-  DevBuf<float> x32;
-  DevBuf<double> x64;
-  DevBuf<double> part;
-  DevBuf<int> part_nf;
-  DevBuf<double> stat_part;
-  DevBuf<double> psi_sums, lscv_sums;
-  DevBuf<double> hin, hdev, c64, g, gs;
-  DevBuf<float> c32;
-  DevBuf<ColDesc> cols;
-  DevBuf<Unit> units;
-  DevBuf<RowDesc> rows;
-  DevBuf<DevState> st;
-  // pinned host staging
-  DevState* h_st = nullptr;
-  size_t h_st_cap = 0;
-  double* h_out = nullptr;
-  size_t h_out_cap = 0;
-  // host-side plan of the current job (kept alive until the job's copies finish)
-  std::vector<JobCol> jcols;
-  std::vector<ColDesc> h_cols;
-  std::vector<Unit> h_units;       // psi units, then LSCV units
-  std::vector<UnitCost> h_cost;
-  std::vector<RowDesc> h_rows;     // psi rows, then LSCV rows
-  std::vector<double> h_hin;
-  size_t n_psi_units = 0, n_lscv_units = 0, n_psi_rows = 0, n_lscv_rows = 0;
-  // timing
-  bool timing = false;
-  int64_t t_launches[2] = {0, 0};
-  double t_ms[2] = {0, 0};
-  double t_evals[2] = {0, 0};
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> ev_pool;
-};
-
-namespace {
-
-constexpr int kFamLscv = 0, kFamPsi = 1;
+namespace kde {
 
 kde_status fail(kde_ctx* c, kde_status st, const std::string& msg) {
   c->err = msg;
   return st;
 }
 
-#define HIP_TRY(ctx, expr)                                                                                    \
-  do {                                                                                                        \
-    hipError_t e_ = (expr);                                                                                   \
-    if (e_ != hipSuccess) return fail((ctx), KDE_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
-  } while (0)
-
-template <typename T>
-kde_status ensure(kde_ctx* c, DevBuf<T>& b, size_t count) {
-  if (b.cap >= count) return KDE_OK;
-  if (b.p) (void)hipFree(b.p);
-  b.p = nullptr;
-  b.cap = 0;
-  size_t want = std::max<size_t>(count, 256);
-  hipError_t e = hipMalloc((void**)&b.p, want * sizeof(T));
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return fail(c, KDE_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+kde_status status_of(int st) {
+  switch (st) {
+    case kStOk: return KDE_OK;
+    case kStInval: return KDE_E_INVAL;
+    case kStDegenerate: return KDE_E_DEGENERATE;
+    default: return KDE_E_DEVICE;
   }
-  b.cap = want;
-  return KDE_OK;
 }
 
-template <typename T>
-kde_status ensure_pinned(kde_ctx* c, T*& p, size_t& cap, size_t count) {
-  if (cap >= count) return KDE_OK;
+kde_status ensure_pinned_bytes(kde_ctx* c, char*& p, size_t& cap, size_t bytes) {
+  if (cap >= bytes) return KDE_OK;
   if (p) (void)hipHostFree(p);
   p = nullptr;
   cap = 0;
-  size_t want = std::max<size_t>(count, 64);
-  if (hipHostMalloc((void**)&p, want * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+  const size_t want = std::max<size_t>(bytes, 4096);
+  if (hipHostMalloc((void**)&p, want, hipHostMallocDefault) != hipSuccess) {
     p = nullptr;
     return fail(c, KDE_E_NOMEM, "pinned host allocation failed");
   }
@@ -159,67 +62,26 @@ kde_status ensure_pinned(kde_ctx* c, T*& p, size_t& cap, size_t count) {
   return KDE_OK;
 }
 
-kde_status status_of(int st) {
-  switch (st) {
-    case kde::kStOk: return KDE_OK;
-    case kde::kStInval: return KDE_E_INVAL;
-    case kde::kStDegenerate: return KDE_E_DEGENERATE;
-    default: return KDE_E_DEVICE;
+void IterPlan::clear() {
+  uploads.clear();
+  cols.clear();
+  ids_stats.clear();
+  for (int s = 0; s < 3; ++s) {
+    ids_begin[s].clear();
+    ids_finish[s].clear();
+    psi_units[s].clear();
+    psi_cost[s].clear();
+    psi_rows[s].clear();
+    psi_cond_units[s].clear();
+    psi_cond_cost[s].clear();
   }
-}
-
-kde_status map_status(kde_ctx* c, int st) {
-  switch (st) {
-    case kde::kStOk: return KDE_OK;
-    case kde::kStInval: return fail(c, KDE_E_INVAL, "sample column holds a non-finite value");
-    case kde::kStDegenerate:
-      return fail(c, KDE_E_DEGENERATE,
-                  "degenerate sample: zero spread, or a functional estimate with the wrong sign");
-    default: return fail(c, KDE_E_DEVICE, "unknown device status");
-  }
-}
-
-// ---- timing
-kde_status timed_begin(kde_ctx* c, Pending& p) {
-  if (!c->timing) return KDE_OK;
-  for (hipEvent_t* e : {&p.a, &p.b}) {
-    if (!c->ev_pool.empty()) {
-      *e = c->ev_pool.back();
-      c->ev_pool.pop_back();
-    } else {
-      HIP_TRY(c, hipEventCreate(e));
-    }
-  }
-  HIP_TRY(c, hipEventRecord(p.a, c->stream));
-  return KDE_OK;
-}
-
-kde_status timed_end(kde_ctx* c, Pending& p) {
-  if (!c->timing) return KDE_OK;
-  HIP_TRY(c, hipEventRecord(p.b, c->stream));
-  c->pending.push_back(p);
-  return KDE_OK;
-}
-
-// Called after the stream has been synchronised.
-kde_status collect_timing(kde_ctx* c) {
-  for (Pending& p : c->pending) {
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, p.a, p.b));
-    c->t_launches[p.family] += 1;
-    c->t_ms[p.family] += ms;
-    c->t_evals[p.family] += p.evals;
-    c->ev_pool.push_back(p.a);
-    c->ev_pool.push_back(p.b);
-  }
-  c->pending.clear();
-  return KDE_OK;
-}
-
-kde_status sync_and_check(kde_ctx* c) {
-  HIP_TRY(c, hipGetLastError());
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  return collect_timing(c);
+  ids_plugin_final.clear();
+  ids_lscv_prep.clear();
+  lscv_units.clear();
+  lscv_cost.clear();
+  lscv_rows.clear();
+  ids_lscv_final.clear();
+  max_stat_blocks = 1;
 }
 
 // ---- argument checks
@@ -247,10 +109,12 @@ std::string check_grid(const kde_grid& g) {
   return "";
 }
 
+namespace {
+
 // ---- work items
 double item_pairs(int64_t n, int64_t row, int64_t jb, int64_t je) {
-  const int64_t i0 = row * kde::kBI;
-  const int64_t i1 = std::min<int64_t>(n, i0 + kde::kBI);
+  const int64_t i0 = row * kBI;
+  const int64_t i1 = std::min<int64_t>(n, i0 + kBI);
   je = std::min<int64_t>(je, n);
   double p = 0.0;
   for (int64_t i = i0; i < i1; ++i) {
@@ -265,10 +129,10 @@ double item_pairs(int64_t n, int64_t row, int64_t jb, int64_t je) {
 void make_items(int64_t n, int64_t seg, ColItems& out) {
   std::vector<int> row, jb, je;
   std::vector<double> pr;
-  const int64_t rows = (n + kde::kBI - 1) / kde::kBI;
+  const int64_t rows = (n + kBI - 1) / kBI;
   for (int64_t r = 0; r < rows; ++r) {
-    const int64_t row0 = r * kde::kBI;
-    const int64_t len = ((n - row0) + kde::kBJ - 1) / kde::kBJ * kde::kBJ;
+    const int64_t row0 = r * kBI;
+    const int64_t len = ((n - row0) + kBJ - 1) / kBJ * kBJ;
     const int64_t step = seg > 0 ? seg : len;
     for (int64_t b = row0; b < row0 + len; b += step) {
       const int64_t e = std::min(b + step, row0 + len);
@@ -295,183 +159,244 @@ void make_items(int64_t n, int64_t seg, ColItems& out) {
   }
 }
 
-// Item length for a pass whose blocks each evaluate `hc` terms per pair.  It
-// depends only on n and the context options, never on the rest of a batch.
+// Item length for a pass whose blocks each evaluate `hc` terms per pair.
 int64_t pick_seg(const kde_ctx* c, int64_t n, int hc) {
-  if (c->opt_seg >= 0) return c->opt_seg == 0 ? 0 : (c->opt_seg + kde::kBJ - 1) / kde::kBJ * kde::kBJ;
+  if (c->opt_seg >= 0) return c->opt_seg == 0 ? 0 : (c->opt_seg + kBJ - 1) / kBJ * kBJ;
   // Aim for ~8192 blocks per launch so each launch fills the chip many times.
   const double per_block_pairs = c->opt_launch_evals / 8192.0 / (double)hc;
-  int64_t seg = (int64_t)(per_block_pairs / kde::kBI);
-  seg = std::max<int64_t>(kde::kBJ, seg / kde::kBJ * kde::kBJ);
+  int64_t seg = (int64_t)(per_block_pairs / kBI);
+  seg = std::max<int64_t>(kBJ, seg / kBJ * kBJ);
   if (seg >= n) return 0;
   return seg;
 }
 
-int lscv_hc(const kde_ctx* c) { return c->prec == KDE_PREC_FP64 ? 8 : c->opt_hc; }
-
-// Plans a job from the requests: columns, offsets, work units and reduction
-// rows.  Requests with bad arguments get status INVAL in `st` and no column.
-void plan_job(kde_ctx* c, const kde_request* reqs, int32_t n_req, std::vector<kde_status>& st,
-              std::vector<std::string>& msg) {
-  c->jcols.clear();
-  c->h_cols.clear();
-  c->h_units.clear();
-  c->h_cost.clear();
-  c->h_rows.clear();
-  c->h_hin.clear();
-  const int hc = lscv_hc(c);
-  st.assign(n_req, KDE_OK);
-  msg.assign(n_req, "");
-  int64_t x_off = 0, c_off = 0, part_off = 0;
-  for (int32_t k = 0; k < n_req; ++k) {
-    const kde_request& r = reqs[k];
-    std::string e = check_column(r.x);
-    const bool plugin = (r.methods & KDE_METHOD_PLUGIN) != 0;
-    const bool lscv = (r.methods & KDE_METHOD_LSCV) != 0;
-    if (e.empty() && plugin && r.stages != 2 && r.stages != 3) e = "stages must be 2 or 3";
-    if (e.empty() && lscv) e = check_grid(r.grid);
-    if (!e.empty()) {
-      st[k] = KDE_E_INVAL;
-      msg[k] = e;
-      continue;
-    }
-    JobCol jc;
-    jc.req = k;
-    jc.data = r.x.data;
-    jc.on_device = r.x.on_device;
-    jc.n = (int)r.x.n;
-    jc.f64 = r.x.dtype == KDE_F64;
-    jc.plugin = plugin;
-    jc.lscv = lscv;
-    jc.stages = plugin ? r.stages : 2;
-    jc.grid = r.grid;
-    std::memset(&jc.d, 0, sizeof(jc.d));
-    jc.d.n = jc.n;
-    jc.d.raw_f64 = jc.f64;
-    jc.d.x_off = x_off;
-    x_off += ((int64_t)jc.n + kde::kPad + 63) / 64 * 64;
-    if (plugin) {
-      make_items(jc.n, pick_seg(c, jc.n, 1), jc.psi_items);
-      jc.d.n_items_psi = (int)jc.psi_items.pairs.size();
-      jc.d.psi_part_off = part_off;
-      part_off += 2 * (int64_t)jc.d.n_items_psi;
-    }
-    if (lscv) {
-      make_items(jc.n, pick_seg(c, jc.n, hc), jc.lscv_items);
-      jc.d.n_h = r.grid.n_h;
-      jc.d.n_chunks = (r.grid.n_h + hc - 1) / hc;
-      jc.d.n_items = (int)jc.lscv_items.pairs.size();
-      jc.d.c_off = c_off;
-      c_off += (int64_t)jc.d.n_chunks * hc;
-      jc.d.part_off = part_off;
-      part_off += 2 * (int64_t)r.grid.n_h * jc.d.n_items;
-      jc.d.grid_kind = (int)r.grid.kind;
-      jc.d.grid_lo = r.grid.lo;
-      jc.d.grid_hi = r.grid.hi;
-    }
-    c->jcols.push_back(std::move(jc));
-  }
-  const int n_cols = (int)c->jcols.size();
-  // explicit grids, at each column's c_off
-  c->h_hin.assign((size_t)std::max<int64_t>(c_off, 1), 0.0);
-  for (const JobCol& jc : c->jcols)
-    if (jc.lscv && jc.grid.kind == KDE_GRID_EXPLICIT)
-      std::memcpy(c->h_hin.data() + jc.d.c_off, jc.grid.h, sizeof(double) * jc.grid.n_h);
-  struct Tmp {
-    Unit u;
-    UnitCost cost;
-  };
-  // psi units of all columns, largest first
-  std::vector<Tmp> tmp;
-  for (int col = 0; col < n_cols; ++col) {
-    const JobCol& jc = c->jcols[col];
-    if (!jc.plugin) continue;
-    for (size_t it = 0; it < jc.psi_items.pairs.size(); ++it) {
-      Tmp t;
-      t.u = Unit{col, jc.psi_items.row[it], jc.psi_items.jb[it], jc.psi_items.je[it], (int)it, 0};
-      t.cost = UnitCost{jc.psi_items.pairs[it], jc.psi_items.pairs[it]};
-      tmp.push_back(t);
-    }
-  }
-  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost.pairs > b.cost.pairs; });
-  for (const Tmp& t : tmp) {
-    c->h_units.push_back(t.u);
-    c->h_cost.push_back(t.cost);
-  }
-  c->n_psi_units = tmp.size();
-  // LSCV units: item-major, chunks inner, largest items first
-  tmp.clear();
-  for (int col = 0; col < n_cols; ++col) {
-    const JobCol& jc = c->jcols[col];
-    if (!jc.lscv) continue;
-    for (size_t it = 0; it < jc.lscv_items.pairs.size(); ++it)
-      for (int ch = 0; ch < jc.d.n_chunks; ++ch) {
-        Tmp t;
-        t.u = Unit{col, jc.lscv_items.row[it], jc.lscv_items.jb[it], jc.lscv_items.je[it], (int)it, ch};
-        const int valid = std::min(hc, jc.d.n_h - ch * hc);
-        t.cost = UnitCost{jc.lscv_items.pairs[it], jc.lscv_items.pairs[it] * valid};
-        tmp.push_back(t);
-      }
-  }
-  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost.pairs > b.cost.pairs; });
-  for (const Tmp& t : tmp) {
-    c->h_units.push_back(t.u);
-    c->h_cost.push_back(t.cost);
-  }
-  c->n_lscv_units = tmp.size();
-  // reduction rows
-  for (int col = 0; col < n_cols; ++col) {
-    const JobCol& jc = c->jcols[col];
-    if (!jc.plugin) continue;
-    for (int w = 0; w < 2; ++w)
-      c->h_rows.push_back(RowDesc{jc.d.psi_part_off + (int64_t)w * jc.d.n_items_psi, 2 * (int64_t)col + w,
-                                  jc.d.n_items_psi, 0});
-  }
-  c->n_psi_rows = c->h_rows.size();
-  for (int col = 0; col < n_cols; ++col) {
-    const JobCol& jc = c->jcols[col];
-    if (!jc.lscv) continue;
-    for (int r = 0; r < 2 * jc.d.n_h; ++r)
-      c->h_rows.push_back(RowDesc{jc.d.part_off + (int64_t)r * jc.d.n_items, 2 * jc.d.c_off + r, jc.d.n_items, 0});
-  }
-  c->n_lscv_rows = c->h_rows.size() - c->n_psi_rows;
+size_t take(size_t& at, size_t bytes) {
+  const size_t o = at;
+  at += (bytes + 255) / 256 * 256;
+  return o;
 }
 
-int64_t job_part_size(const kde_ctx* c) {
-  int64_t m = 0;
-  for (const JobCol& jc : c->jcols) {
-    if (jc.plugin) m = std::max(m, jc.d.psi_part_off + 2 * (int64_t)jc.d.n_items_psi);
-    if (jc.lscv) m = std::max(m, jc.d.part_off + 2 * (int64_t)jc.d.n_h * jc.d.n_items);
+}  // namespace
+
+std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
+  std::string e = check_column(r.x);
+  p = ColPlan();
+  p.plugin = (r.methods & KDE_METHOD_PLUGIN) != 0;
+  p.lscv = (r.methods & KDE_METHOD_LSCV) != 0;
+  if (e.empty() && p.plugin && r.stages != 2 && r.stages != 3) e = "stages must be 2 or 3";
+  if (e.empty() && p.lscv) e = check_grid(r.grid);
+  if (!e.empty()) return e;
+  const bool all64 = c->prec == KDE_PREC_FP64;
+  p.n = (int)r.x.n;
+  p.f64 = r.x.dtype == KDE_F64;
+  p.stages = p.plugin ? r.stages : 0;
+  p.hc = all64 ? 8 : c->opt_hc;
+  if (p.plugin) make_items(p.n, pick_seg(c, p.n, 1), p.psi_items);
+  if (p.lscv) {
+    p.n_h = r.grid.n_h;
+    p.n_chunks = (p.n_h + p.hc - 1) / p.hc;
+    p.grid_kind = (int)r.grid.kind;
+    p.grid_lo = r.grid.lo;
+    p.grid_hi = r.grid.hi;
+    if (r.grid.kind == KDE_GRID_EXPLICIT) p.grid_h.assign(r.grid.h, r.grid.h + p.n_h);
+    make_items(p.n, pick_seg(c, p.n, p.hc), p.lscv_items);
   }
-  return m;
+  p.want_x64 = all64 || (p.plugin && c->opt_fp64_kappa > 0.0);
+  p.raw_in_block = !r.x.on_device;
+  p.raw_bytes = (size_t)p.n * (p.f64 ? 8 : 4);
+  size_t at = 0;
+  const size_t xn = (size_t)p.n + kPad;
+  if (p.raw_in_block) p.off_raw = take(at, p.raw_bytes);
+  p.off_x32 = take(at, 4 * xn);
+  if (p.want_x64) p.off_x64 = take(at, 8 * xn);
+  p.off_stat = take(at, 8 * kStatBlocks);
+  p.off_nf = take(at, 4 * kStatBlocks);
+  if (p.plugin) {
+    p.off_psi_part = take(at, 16 * p.psi_items.pairs.size());
+    p.off_psi_sums = take(at, 16);
+  }
+  if (p.lscv) {
+    const size_t m = (size_t)p.n_chunks * p.hc;
+    p.off_hin = take(at, 8 * (size_t)p.n_h);
+    p.off_h = take(at, 8 * m);
+    p.off_c32 = take(at, 4 * m);
+    p.off_c64 = take(at, 8 * m);
+    p.off_part = take(at, 16 * (size_t)p.n_h * p.lscv_items.pairs.size());
+    p.off_sums = take(at, 16 * (size_t)p.n_h);
+    p.off_g = take(at, 8 * (size_t)p.n_h);
+    p.off_gs = take(at, 8 * (size_t)p.n_h);
+  }
+  p.bytes = at;
+  return "";
 }
 
-int64_t job_x_size(const kde_ctx* c) {
-  int64_t m = 0;
-  for (const JobCol& jc : c->jcols) m = std::max(m, jc.d.x_off + (int64_t)jc.n + kde::kPad);
-  return m;
+void bind_column(const ColPlan& p, char* b, const void* raw, DevState* st, ColDesc& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.raw = p.raw_in_block ? (const void*)(b + p.off_raw) : raw;
+  d.x32 = (float*)(b + p.off_x32);
+  d.x64 = p.want_x64 ? (double*)(b + p.off_x64) : nullptr;
+  d.stat = (double*)(b + p.off_stat);
+  d.stat_nf = (int*)(b + p.off_nf);
+  if (p.plugin) {
+    d.psi_part = (double*)(b + p.off_psi_part);
+    d.psi_sums = (double*)(b + p.off_psi_sums);
+  }
+  if (p.lscv) {
+    d.h_in = (const double*)(b + p.off_hin);
+    d.h = (double*)(b + p.off_h);
+    d.c32 = (float*)(b + p.off_c32);
+    d.c64 = (double*)(b + p.off_c64);
+    d.part = (double*)(b + p.off_part);
+    d.sums = (double*)(b + p.off_sums);
+    d.g = (double*)(b + p.off_g);
+    d.gs = (double*)(b + p.off_gs);
+  }
+  d.st = st;
+  d.n = p.n;
+  d.raw_f64 = p.f64;
+  d.n_h = p.lscv ? p.n_h : 0;
+  d.n_chunks = p.n_chunks;
+  d.n_items = (int)p.lscv_items.pairs.size();
+  d.n_items_psi = (int)p.psi_items.pairs.size();
+  d.grid_kind = p.grid_kind;
+  d.grid_lo = p.grid_lo;
+  d.grid_hi = p.grid_hi;
 }
 
-int64_t job_c_size(const kde_ctx* c, int hc) {
-  int64_t m = 0;
-  for (const JobCol& jc : c->jcols)
-    if (jc.lscv) m = std::max(m, jc.d.c_off + (int64_t)jc.d.n_chunks * hc);
-  return m;
+void init_state(const ColPlan& p, double fp64_kappa, DevState& h) {
+  std::memset(&h, 0, sizeof(h));
+  const double nan = std::nan("");
+  h.stages = p.stages;
+  for (int q = 0; q < 3; ++q) {
+    h.g[q] = h.psi[q] = h.kappa[q] = nan;
+    h.prec_used[q] = -1;
+  }
+  h.h_plugin = h.h_best = h.margin = nan;
+  h.k_best = -1;
+  h.fp64_kappa = fp64_kappa;
 }
 
-// Launch ranges over units [u0, u1) of one pass whose summed evaluations stay
-// within budget (at least 2048 blocks per launch when the pass has them, so a
-// launch fills the chip).  FP64 terms cost about five times the FP32 ones.
+void psi_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost) {
+  for (size_t it = 0; it < p.psi_items.pairs.size(); ++it) {
+    u.push_back(Unit{id, p.psi_items.row[it], p.psi_items.jb[it], p.psi_items.je[it], (int)it, 0});
+    cost.push_back(UnitCost{p.psi_items.pairs[it], p.psi_items.pairs[it]});
+  }
+}
+
+void lscv_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost) {
+  for (size_t it = 0; it < p.lscv_items.pairs.size(); ++it)
+    for (int ch = 0; ch < p.n_chunks; ++ch) {
+      u.push_back(Unit{id, p.lscv_items.row[it], p.lscv_items.jb[it], p.lscv_items.je[it], (int)it, ch});
+      const int valid = std::min(p.hc, p.n_h - ch * p.hc);
+      cost.push_back(UnitCost{p.lscv_items.pairs[it], p.lscv_items.pairs[it] * valid});
+    }
+}
+
+void psi_rows_of(const ColPlan& p, const ColDesc& d, std::vector<RowDesc>& rows) {
+  const int m = (int)p.psi_items.pairs.size();
+  for (int w = 0; w < 2; ++w) rows.push_back(RowDesc{d.psi_part + (size_t)w * m, d.psi_sums + w, m, 0});
+}
+
+void lscv_rows_of(const ColPlan& p, const ColDesc& d, std::vector<RowDesc>& rows) {
+  const int m = (int)p.lscv_items.pairs.size();
+  for (int r = 0; r < 2 * p.n_h; ++r) rows.push_back(RowDesc{d.part + (size_t)r * m, d.sums + r, m, 0});
+}
+
+void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int id, const void* host_raw,
+                     IterPlan& it) {
+  if ((int)it.cols.size() <= id) it.cols.resize(id + 1);
+  it.cols[id] = d;
+  if (p.raw_in_block) it.uploads.push_back(Upload{(void*)d.raw, host_raw, p.raw_bytes});
+  it.ids_stats.push_back(id);
+  it.max_stat_blocks = std::max(it.max_stat_blocks, std::min(kStatBlocks, (p.n + 2047) / 2048));
+  const bool cond = c->prec != KDE_PREC_FP64 && c->opt_fp64_kappa > 0.0;
+  if (p.plugin) {
+    for (int s = (p.stages == 3 ? 0 : 1); s < 3; ++s) {
+      it.ids_begin[s].push_back(id);
+      psi_units_of(p, id, it.psi_units[s], it.psi_cost[s]);
+      psi_rows_of(p, d, it.psi_rows[s]);
+      it.ids_finish[s].push_back(id);
+      if (cond) psi_units_of(p, id, it.psi_cond_units[s], it.psi_cond_cost[s]);
+    }
+    it.ids_plugin_final.push_back(id);
+  }
+  if (p.lscv) {
+    if (p.grid_kind == KDE_GRID_EXPLICIT)
+      it.uploads.push_back(Upload{(void*)d.h_in, p.grid_h.data(), sizeof(double) * p.n_h});
+    it.ids_lscv_prep.push_back(id);
+    lscv_units_of(p, id, it.lscv_units, it.lscv_cost);
+    lscv_rows_of(p, d, it.lscv_rows);
+    it.ids_lscv_final.push_back(id);
+  }
+}
+
+namespace {
+
+// ---- timing
+kde_status timed_begin(kde_ctx* c, kde_ctx::Pending& p) {
+  if (!c->timing) return KDE_OK;
+  for (hipEvent_t* e : {&p.a, &p.b}) {
+    if (!c->ev_pool.empty()) {
+      *e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+    } else {
+      KDE_HIP_TRY(c, hipEventCreate(e));
+    }
+  }
+  KDE_HIP_TRY(c, hipEventRecord(p.a, c->stream));
+  return KDE_OK;
+}
+
+kde_status timed_end(kde_ctx* c, kde_ctx::Pending& p) {
+  if (!c->timing) return KDE_OK;
+  KDE_HIP_TRY(c, hipEventRecord(p.b, c->stream));
+  c->pending.push_back(p);
+  return KDE_OK;
+}
+
+kde_status collect_timing(kde_ctx* c) {
+  for (kde_ctx::Pending& p : c->pending) {
+    float ms = 0.f;
+    KDE_HIP_TRY(c, hipEventElapsedTime(&ms, p.a, p.b));
+    c->t_launches[p.family] += 1;
+    c->t_ms[p.family] += ms;
+    c->t_evals[p.family] += p.evals;
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return KDE_OK;
+}
+
+// Sorts units largest first (the order blocks are dispatched in); results do
+// not depend on it, since every unit writes its own partial-sum slot.
+void sort_units(std::vector<Unit>& u, std::vector<UnitCost>& cost) {
+  std::vector<size_t> o(u.size());
+  for (size_t k = 0; k < o.size(); ++k) o[k] = k;
+  std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) { return cost[a].pairs > cost[b].pairs; });
+  std::vector<Unit> u2(u.size());
+  std::vector<UnitCost> c2(u.size());
+  for (size_t k = 0; k < o.size(); ++k) {
+    u2[k] = u[o[k]];
+    c2[k] = cost[o[k]];
+  }
+  u.swap(u2);
+  cost.swap(c2);
+}
+
+// Launch ranges over units [0, n) whose summed evaluations stay within
+// budget, with at least 2048 blocks per launch when the list has them, so a
+// launch fills the chip.  FP64 terms cost about five times the FP32 ones.
 template <typename F>
-kde_status for_each_launch(kde_ctx* c, size_t first, size_t count, bool f64, F&& launch) {
+kde_status for_each_launch(const kde_ctx* c, const std::vector<UnitCost>& cost, bool f64, F&& launch) {
   const double budget = f64 ? c->opt_launch_evals / 5.0 : c->opt_launch_evals;
-  size_t u0 = first;
-  const size_t end = first + count;
+  size_t u0 = 0;
+  const size_t end = cost.size();
   while (u0 < end) {
-    double acc = c->h_cost[u0].evals;
+    double acc = cost[u0].evals;
     size_t u1 = u0 + 1;
-    while (u1 < end && (acc + c->h_cost[u1].evals <= budget || u1 - u0 < 2048)) {
-      acc += c->h_cost[u1].evals;
+    while (u1 < end && (acc + cost[u1].evals <= budget || u1 - u0 < 2048)) {
+      acc += cost[u1].evals;
       ++u1;
     }
     kde_status s = launch((int)u0, (int)(u1 - u0), acc);
@@ -481,146 +406,195 @@ kde_status for_each_launch(kde_ctx* c, size_t first, size_t count, bool f64, F&&
   return KDE_OK;
 }
 
-kde_status run_psi_stage(kde_ctx* c, int n_cols, int stage, bool f64, bool conditional) {
-  const int r = 8 - 2 * stage;
-  kde_status s = for_each_launch(c, 0, c->n_psi_units, f64, [&](int u0, int cnt, double evals) -> kde_status {
-    // A conditional pass may exit at once on the device, so it is not timed.
-    Pending pd{nullptr, nullptr, kFamPsi, evals};
-    kde_status s2 = conditional ? KDE_OK : timed_begin(c, pd);
+// Packs the host arrays of a pass into one pinned blob and copies it to the
+// device in one transfer; returns device addresses of each array.
+struct Blob {
+  std::vector<std::pair<const void*, size_t>> parts;
+  std::vector<size_t> offs;
+  size_t bytes = 0;
+  size_t add(const void* p, size_t n) {
+    const size_t o = bytes;
+    parts.push_back({p, n});
+    offs.push_back(o);
+    bytes += (n + 255) / 256 * 256;
+    return o;
+  }
+};
+
+}  // namespace
+
+kde_status sync_and_check(kde_ctx* c) {
+  KDE_HIP_TRY(c, hipGetLastError());
+  KDE_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return collect_timing(c);
+}
+
+kde_status execute(kde_ctx* c, IterPlan& it) {
+  kde_status s;
+  const bool all64 = c->prec == KDE_PREC_FP64;
+  for (int q = 0; q < 3; ++q) {
+    sort_units(it.psi_units[q], it.psi_cost[q]);
+    sort_units(it.psi_cond_units[q], it.psi_cond_cost[q]);
+  }
+  sort_units(it.lscv_units, it.lscv_cost);
+  // one blob: column table, id lists, units, rows
+  Blob b;
+  auto vbytes = [](const auto& v) { return v.size() * sizeof(v[0]); };
+  const size_t o_cols = b.add(it.cols.data(), vbytes(it.cols));
+  const size_t o_stats = b.add(it.ids_stats.data(), vbytes(it.ids_stats));
+  size_t o_begin[3], o_finish[3], o_pu[3], o_pr[3], o_pc[3];
+  for (int q = 0; q < 3; ++q) {
+    o_begin[q] = b.add(it.ids_begin[q].data(), vbytes(it.ids_begin[q]));
+    o_finish[q] = b.add(it.ids_finish[q].data(), vbytes(it.ids_finish[q]));
+    o_pu[q] = b.add(it.psi_units[q].data(), vbytes(it.psi_units[q]));
+    o_pr[q] = b.add(it.psi_rows[q].data(), vbytes(it.psi_rows[q]));
+    o_pc[q] = b.add(it.psi_cond_units[q].data(), vbytes(it.psi_cond_units[q]));
+  }
+  const size_t o_pf = b.add(it.ids_plugin_final.data(), vbytes(it.ids_plugin_final));
+  const size_t o_lp = b.add(it.ids_lscv_prep.data(), vbytes(it.ids_lscv_prep));
+  const size_t o_lu = b.add(it.lscv_units.data(), vbytes(it.lscv_units));
+  const size_t o_lr = b.add(it.lscv_rows.data(), vbytes(it.lscv_rows));
+  const size_t o_lf = b.add(it.ids_lscv_final.data(), vbytes(it.ids_lscv_final));
+  if ((s = ensure_pinned_bytes(c, c->h_blob, c->h_blob_cap, b.bytes + 256))) return s;
+  if ((s = ensure(c, c->blob, b.bytes + 256))) return s;
+  for (size_t k = 0; k < b.parts.size(); ++k)
+    if (b.parts[k].second) std::memcpy(c->h_blob + b.offs[k], b.parts[k].first, b.parts[k].second);
+  for (const kde::Upload& u : it.uploads)
+    if (u.bytes) KDE_HIP_TRY(c, hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->h_blob, b.bytes, hipMemcpyHostToDevice, c->stream));
+  char* d = c->blob.p;
+  const ColDesc* cols = (const ColDesc*)(d + o_cols);
+  auto ids = [&](size_t o) { return (const int*)(d + o); };
+  hipStream_t st = c->stream;
+  // moments
+  kde::launch_stats(st, cols, ids(o_stats), (int)it.ids_stats.size(), it.max_stat_blocks);
+  // plug-in stages
+  for (int q = 0; q < 3; ++q) {
+    if (it.ids_begin[q].empty() && it.psi_units[q].empty() && it.ids_finish[q].empty()) continue;
+    const int r = 8 - 2 * q;
+    kde::launch_psi_begin(st, cols, ids(o_begin[q]), (int)it.ids_begin[q].size(), q);
+    const Unit* pu = (const Unit*)(d + o_pu[q]);
+    s = for_each_launch(c, it.psi_cost[q], all64, [&](int u0, int cnt, double evals) -> kde_status {
+      kde_ctx::Pending pd{nullptr, nullptr, kde::kFamPsi, evals};
+      kde_status s2 = timed_begin(c, pd);
+      if (s2) return s2;
+      kde::launch_psi_units(st, r, all64 ? 1 : 0, 0, cols, pu, u0, cnt);
+      return timed_end(c, pd);
+    });
+    if (s) return s;
+    kde::launch_reduce_rows(st, (const RowDesc*)(d + o_pr[q]), (int)it.psi_rows[q].size());
+    kde::launch_psi_finish(st, cols, ids(o_finish[q]), (int)it.ids_finish[q].size(), q, all64 ? 1 : 0, 0);
+    if (!all64 && !it.psi_cond_units[q].empty()) {
+      // FP64 re-run of the columns whose stage is badly conditioned; blocks of
+      // other columns exit at once, so these launches are not timed.
+      const Unit* pc = (const Unit*)(d + o_pc[q]);
+      s = for_each_launch(c, it.psi_cond_cost[q], true, [&](int u0, int cnt, double) -> kde_status {
+        kde::launch_psi_units(st, r, 1, 1, cols, pc, u0, cnt);
+        return KDE_OK;
+      });
+      if (s) return s;
+      kde::launch_reduce_rows(st, (const RowDesc*)(d + o_pr[q]), (int)it.psi_rows[q].size());
+      kde::launch_psi_finish(st, cols, ids(o_finish[q]), (int)it.ids_finish[q].size(), q, 1, 1);
+    }
+  }
+  kde::launch_plugin_final(st, cols, ids(o_pf), (int)it.ids_plugin_final.size());
+  // LSCV
+  const int hc = all64 ? 8 : c->opt_hc;
+  kde::launch_lscv_prep(st, cols, ids(o_lp), (int)it.ids_lscv_prep.size(), hc);
+  const Unit* lu = (const Unit*)(d + o_lu);
+  s = for_each_launch(c, it.lscv_cost, all64, [&](int u0, int cnt, double evals) -> kde_status {
+    kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
+    kde_status s2 = timed_begin(c, pd);
     if (s2) return s2;
-    kde::launch_psi_units(c->stream, r, f64 ? 1 : 0, conditional ? 1 : 0, c->x32.p, c->x64.p, c->cols.p,
-                          c->units.p, u0, cnt, c->part.p, c->st.p);
-    return conditional ? KDE_OK : timed_end(c, pd);
+    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, cols, lu, u0, cnt);
+    return timed_end(c, pd);
   });
   if (s) return s;
-  kde::launch_reduce_rows(c->stream, c->part.p, c->rows.p, (int)c->n_psi_rows, c->psi_sums.p);
-  kde::launch_psi_finish(c->stream, n_cols, c->cols.p, c->st.p, stage, c->psi_sums.p, f64 ? 1 : 0,
-                         conditional ? 1 : 0);
-  HIP_TRY(c, hipGetLastError());
+  kde::launch_reduce_rows(st, (const RowDesc*)(d + o_lr), (int)it.lscv_rows.size());
+  kde::launch_lscv_finalize(st, cols, ids(o_lf), (int)it.ids_lscv_final.size());
+  KDE_HIP_TRY(c, hipGetLastError());
   return KDE_OK;
 }
 
-// Enqueues the whole job planned by plan_job.  Results stay on the device
-// except the per-column states, whose copy back is enqueued last.
-kde_status run_job(kde_ctx* c) {
+}  // namespace kde
+
+namespace {
+
+using kde::fail;
+
+kde_status map_status(kde_ctx* c, int st) {
+  switch (st) {
+    case kde::kStOk: return KDE_OK;
+    case kde::kStInval: return fail(c, KDE_E_INVAL, "sample column holds a non-finite value");
+    case kde::kStDegenerate:
+      return fail(c, KDE_E_DEGENERATE,
+                  "degenerate sample: zero spread, or a functional estimate with the wrong sign");
+    default: return fail(c, KDE_E_DEVICE, "unknown device status");
+  }
+}
+
+kde_status busy(kde_ctx* c) {
+  return fail(c, KDE_E_BUSY, "a server is running on this context; use kde_submit/kde_poll/kde_wait");
+}
+
+bool serving(const kde_ctx* c) { return c->server && kde::server_running(c->server.get()); }
+
+// Plans and enqueues a synchronous job over n_req requests; per-request
+// argument errors land in st/msg.  The states' copy back is enqueued last.
+kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std::vector<kde_status>& st,
+                        std::vector<std::string>& msg) {
   kde_status s;
-  const int n_cols = (int)c->jcols.size();
+  st.assign(n_req, KDE_OK);
+  msg.assign(n_req, "");
+  c->plans.clear();
+  c->plan_req.clear();
+  for (int32_t k = 0; k < n_req; ++k) {
+    kde::ColPlan p;
+    std::string e = kde::plan_column(c, reqs[k], p);
+    if (!e.empty()) {
+      st[k] = KDE_E_INVAL;
+      msg[k] = e;
+      continue;
+    }
+    c->plans.push_back(std::move(p));
+    c->plan_req.push_back(k);
+  }
+  const int n_cols = (int)c->plans.size();
   if (n_cols == 0) return KDE_OK;
-  const bool all64 = c->prec == KDE_PREC_FP64;
-  const int hc = lscv_hc(c);
-  bool any_plugin = false, any_lscv = false;
-  int max_stages = 2;
-  for (const JobCol& jc : c->jcols) {
-    any_plugin |= jc.plugin;
-    any_lscv |= jc.lscv;
-    if (jc.plugin) max_stages = std::max(max_stages, jc.stages);
-  }
-  const bool want_x64 = all64 || (any_plugin && c->opt_fp64_kappa > 0.0);
-  // stage host columns on the device
-  size_t stage_bytes = 0;
-  for (const JobCol& jc : c->jcols)
-    if (!jc.on_device) stage_bytes += ((size_t)jc.n * (jc.f64 ? 8 : 4) + 255) / 256 * 256;
-  if ((s = ensure(c, c->stage, std::max<size_t>(stage_bytes, 1)))) return s;
-  size_t so = 0;
-  for (JobCol& jc : c->jcols) {
-    if (jc.on_device) {
-      jc.d.raw = jc.data;
-    } else {
-      const size_t bytes = (size_t)jc.n * (jc.f64 ? 8 : 4);
-      HIP_TRY(c, hipMemcpyAsync(c->stage.p + so, jc.data, bytes, hipMemcpyHostToDevice, c->stream));
-      jc.d.raw = c->stage.p + so;
-      so += (bytes + 255) / 256 * 256;
-    }
-  }
-  c->h_cols.resize(n_cols);
-  for (int k = 0; k < n_cols; ++k) c->h_cols[k] = c->jcols[k].d;
-  // buffers
-  const int64_t xs = job_x_size(c), cs = std::max<int64_t>(job_c_size(c, hc), 1);
-  if ((s = ensure(c, c->x32, (size_t)xs))) return s;
-  if (want_x64 && (s = ensure(c, c->x64, (size_t)xs))) return s;
-  if ((s = ensure(c, c->stat_part, (size_t)n_cols * kde::kStatBlocks))) return s;
-  if ((s = ensure(c, c->part_nf, (size_t)n_cols * kde::kStatBlocks))) return s;
-  if ((s = ensure(c, c->part, (size_t)std::max<int64_t>(job_part_size(c), 1)))) return s;
-  if ((s = ensure(c, c->psi_sums, (size_t)2 * n_cols))) return s;
-  if ((s = ensure(c, c->lscv_sums, (size_t)2 * cs))) return s;
-  for (auto* b : {&c->hin, &c->hdev, &c->c64, &c->g, &c->gs})
-    if ((s = ensure(c, *b, (size_t)cs))) return s;
-  if ((s = ensure(c, c->c32, (size_t)cs))) return s;
-  if ((s = ensure(c, c->cols, (size_t)n_cols))) return s;
-  if ((s = ensure(c, c->units, std::max<size_t>(c->h_units.size(), 1)))) return s;
-  if ((s = ensure(c, c->rows, std::max<size_t>(c->h_rows.size(), 1)))) return s;
-  if ((s = ensure(c, c->st, (size_t)n_cols))) return s;
-  if ((s = ensure_pinned(c, c->h_st, c->h_st_cap, (size_t)n_cols))) return s;
-  // initial per-column state
+  size_t total = 0;
+  std::vector<size_t> at(n_cols);
   for (int k = 0; k < n_cols; ++k) {
-    DevState& h = c->h_st[k];
-    std::memset(&h, 0, sizeof(h));
-    const double nan = std::nan("");
-    h.stages = c->jcols[k].plugin ? c->jcols[k].stages : 0;
-    for (int q = 0; q < 3; ++q) {
-      h.g[q] = h.psi[q] = h.kappa[q] = nan;
-      h.prec_used[q] = -1;
-    }
-    h.h_plugin = h.h_best = h.margin = nan;
-    h.k_best = -1;
-    h.fp64_kappa = c->opt_fp64_kappa;
+    at[k] = total;
+    total += (c->plans[k].bytes + 255) / 256 * 256;
   }
-  HIP_TRY(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(DevState) * n_cols, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->cols.p, c->h_cols.data(), sizeof(ColDesc) * n_cols, hipMemcpyHostToDevice,
-                            c->stream));
-  if (!c->h_units.empty())
-    HIP_TRY(c, hipMemcpyAsync(c->units.p, c->h_units.data(), sizeof(Unit) * c->h_units.size(),
-                              hipMemcpyHostToDevice, c->stream));
-  if (!c->h_rows.empty())
-    HIP_TRY(c, hipMemcpyAsync(c->rows.p, c->h_rows.data(), sizeof(RowDesc) * c->h_rows.size(),
-                              hipMemcpyHostToDevice, c->stream));
-  // moments of every column
-  int max_blocks = 1;
-  for (const JobCol& jc : c->jcols)
-    max_blocks = std::max(max_blocks, std::min(kde::kStatBlocks, (jc.n + 2047) / 2048));
-  kde::launch_stats(c->stream, n_cols, max_blocks, c->cols.p, c->stat_part.p, c->part_nf.p, c->x32.p,
-                    want_x64 ? c->x64.p : nullptr, c->st.p);
-  HIP_TRY(c, hipGetLastError());
-  // plug-in stages (columns without the plug-in have no psi units; their
-  // scalar steps run harmlessly and are not reported)
-  if (any_plugin) {
-    for (int stage = (max_stages == 3 ? 0 : 1); stage < 3; ++stage) {
-      kde::launch_psi_begin(c->stream, n_cols, c->st.p, stage);
-      if ((s = run_psi_stage(c, n_cols, stage, all64, false))) return s;
-      if (!all64 && c->opt_fp64_kappa > 0.0 && (s = run_psi_stage(c, n_cols, stage, true, true))) return s;
-    }
-    kde::launch_plugin_final(c->stream, n_cols, c->st.p);
+  if ((s = kde::ensure(c, c->blocks, total))) return s;
+  if ((s = kde::ensure(c, c->st, (size_t)n_cols))) return s;
+  char* hs = reinterpret_cast<char*>(c->h_st);
+  if ((s = kde::ensure_pinned_bytes(c, hs, c->h_st_cap, sizeof(DevState) * n_cols))) return s;
+  c->h_st = reinterpret_cast<DevState*>(hs);
+  kde::IterPlan& it = c->iter;
+  it.clear();
+  for (int k = 0; k < n_cols; ++k) {
+    const kde::ColPlan& p = c->plans[k];
+    const kde_request& r = reqs[c->plan_req[k]];
+    ColDesc d;
+    kde::bind_column(p, c->blocks.p + at[k], r.x.data, c->st.p + k, d);
+    kde::add_full_column(c, p, d, k, r.x.data, it);
+    kde::init_state(p, c->opt_fp64_kappa, c->h_st[k]);
   }
-  // LSCV
-  if (any_lscv) {
-    HIP_TRY(c, hipMemcpyAsync(c->hin.p, c->h_hin.data(), sizeof(double) * c->h_hin.size(), hipMemcpyHostToDevice,
-                              c->stream));
-    kde::launch_lscv_prep(c->stream, n_cols, hc, c->cols.p, c->hin.p, c->st.p, c->hdev.p, c->c32.p, c->c64.p);
-    s = for_each_launch(c, c->n_psi_units, c->n_lscv_units, all64,
-                        [&](int u0, int cnt, double evals) -> kde_status {
-                          Pending pd{nullptr, nullptr, kFamLscv, evals};
-                          kde_status s2 = timed_begin(c, pd);
-                          if (s2) return s2;
-                          kde::launch_lscv_units(c->stream, hc, all64 ? 1 : 0, c->x32.p, c->x64.p, c->cols.p,
-                                                 c->units.p, u0, cnt, c->c32.p, c->c64.p, c->part.p, c->st.p);
-                          return timed_end(c, pd);
-                        });
-    if (s) return s;
-    kde::launch_reduce_rows(c->stream, c->part.p, c->rows.p + c->n_psi_rows, (int)c->n_lscv_rows, c->lscv_sums.p);
-    kde::launch_lscv_finalize(c->stream, n_cols, c->cols.p, c->lscv_sums.p, c->hdev.p, c->st.p, c->g.p, c->gs.p);
-  }
-  HIP_TRY(c, hipGetLastError());
-  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(DevState) * n_cols, hipMemcpyDeviceToHost, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(DevState) * n_cols, hipMemcpyHostToDevice, c->stream));
+  if ((s = kde::execute(c, it))) return s;
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(DevState) * n_cols, hipMemcpyDeviceToHost, c->stream));
   return KDE_OK;
 }
 
-// Single-column helpers ------------------------------------------------------
 kde_status run_single(kde_ctx* c, const kde_request& r) {
   std::vector<kde_status> st;
   std::vector<std::string> msg;
-  plan_job(c, &r, 1, st, msg);
+  kde_status s = run_requests(c, &r, 1, st, msg);
+  if (s) return s;
   if (st[0] != KDE_OK) return fail(c, st[0], msg[0]);
-  return run_job(c);
+  return KDE_OK;
 }
 
 kde_request make_req(kde_column x, unsigned methods, int stages, const double* h_grid, int32_t n_h) {
@@ -653,7 +627,47 @@ void fill_plugin_info(const DevState& h, int stages, kde_plugin_info* info) {
   info->h = h.h_plugin;
 }
 
+kde_status ensure_out(kde_ctx* c, size_t doubles) {
+  char* p = reinterpret_cast<char*>(c->h_out);
+  size_t cap = c->h_out_cap * sizeof(double);
+  kde_status s = kde::ensure_pinned_bytes(c, p, cap, doubles * sizeof(double));
+  c->h_out = reinterpret_cast<double*>(p);
+  c->h_out_cap = cap / sizeof(double);
+  return s;
+}
+
 }  // namespace
+
+// exported for the server (kde_server.hip)
+namespace kde {
+void init_result(kde_result& r, kde_status st) {
+  double* g_keep = r.g_out;
+  double* gs_keep = r.gscale_out;
+  std::memset(&r, 0, sizeof(r));
+  r.g_out = g_keep;
+  r.gscale_out = gs_keep;
+  r.status = st;
+  const double nan = std::nan("");
+  r.sigma = r.h_rot = r.h_plugin = r.h_lscv = nan;
+  r.k_lscv = -1;
+}
+
+void fill_result(const ColPlan& p, const DevState& h, kde_result& r) {
+  r.status = status_of(h.status);
+  if (r.status == KDE_OK && p.plugin) r.status = status_of(h.pstatus);
+  r.sigma = h.sigma;
+  r.h_rot = h.h_rot;
+  if (p.plugin) {
+    fill_plugin_info(h, p.stages, &r.plugin);
+    r.h_plugin = h.h_plugin;
+  }
+  if (p.lscv) {
+    r.h_lscv = h.h_best;
+    r.k_lscv = h.k_best;
+    r.at_edge = h.at_edge;
+  }
+}
+}  // namespace kde
 
 // ======================================================================== C ABI
 extern "C" {
@@ -678,31 +692,22 @@ kde_status kde_ctx_create(int device, kde_prec prec, kde_ctx** out) {
   return KDE_OK;
 }
 
+kde_status kde_server_stop(kde_ctx* c);
+
 void kde_ctx_destroy(kde_ctx* c) {
   if (!c) return;
+  if (c->server) (void)kde_server_stop(c);
+  c->server.reset();
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   (void)hipFree(c->stage.p);
-  (void)hipFree(c->x32.p);
-  (void)hipFree(c->x64.p);
-  (void)hipFree(c->part.p);
-  (void)hipFree(c->part_nf.p);
-  (void)hipFree(c->stat_part.p);
-  (void)hipFree(c->psi_sums.p);
-  (void)hipFree(c->lscv_sums.p);
-  (void)hipFree(c->hin.p);
-  (void)hipFree(c->hdev.p);
-  (void)hipFree(c->c64.p);
-  (void)hipFree(c->c32.p);
-  (void)hipFree(c->g.p);
-  (void)hipFree(c->gs.p);
-  (void)hipFree(c->cols.p);
-  (void)hipFree(c->units.p);
-  (void)hipFree(c->rows.p);
+  (void)hipFree(c->blocks.p);
   (void)hipFree(c->st.p);
+  (void)hipFree(c->blob.p);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_out) (void)hipHostFree(c->h_out);
-  for (Pending& p : c->pending) {
+  if (c->h_blob) (void)hipHostFree(c->h_blob);
+  for (kde_ctx::Pending& p : c->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
@@ -718,12 +723,14 @@ const char* kde_last_error(const kde_ctx* c) {
 
 kde_status kde_ctx_set_stream(kde_ctx* c, void* hip_stream) {
   if (!c) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   c->stream = hip_stream ? (hipStream_t)hip_stream : c->own;
   return KDE_OK;
 }
 
 kde_status kde_ctx_set_precision(kde_ctx* c, kde_prec prec) {
   if (!c) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (prec != KDE_PREC_MIXED && prec != KDE_PREC_FP64) return fail(c, KDE_E_INVAL, "unknown precision");
   c->prec = prec;
   return KDE_OK;
@@ -731,6 +738,7 @@ kde_status kde_ctx_set_precision(kde_ctx* c, kde_prec prec) {
 
 kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
   if (!c || !key) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   const std::string k(key);
   if (k == "lscv_hc") {
     if (value < 0) value = 16;
@@ -742,6 +750,8 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_launch_evals = value <= 0 ? 4e12 : (double)value;
   } else if (k == "fp64_kappa") {
     c->opt_fp64_kappa = value < 0 ? 1e3 : (double)value;
+  } else if (k == "serve_iter_evals") {
+    c->opt_serve_iter_evals = value <= 0 ? 4e11 : (double)value;
   } else {
     return fail(c, KDE_E_INVAL, "unknown option " + k);
   }
@@ -750,6 +760,7 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
 
 kde_status kde_ctx_set_timing(kde_ctx* c, int enable) {
   if (!c) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   c->timing = enable != 0;
   for (int f = 0; f < 2; ++f) {
     c->t_launches[f] = 0;
@@ -763,9 +774,9 @@ kde_status kde_ctx_kernel_time(kde_ctx* c, const char* family, int64_t* launches
   if (!c || !family) return KDE_E_INVAL;
   int f;
   if (!std::strcmp(family, "lscv_pairs"))
-    f = kFamLscv;
+    f = kde::kFamLscv;
   else if (!std::strcmp(family, "psi_pairs"))
-    f = kFamPsi;
+    f = kde::kFamPsi;
   else
     return fail(c, KDE_E_INVAL, "unknown kernel family");
   if (launches) *launches = c->t_launches[f];
@@ -776,10 +787,11 @@ kde_status kde_ctx_kernel_time(kde_ctx* c, const char* family, int64_t* launches
 
 kde_status kde_bw_rot(kde_ctx* c, kde_column x, double* h_out) {
   if (!c || !h_out) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if ((s = run_single(c, make_req(x, KDE_METHOD_ROT, 2, nullptr, 0)))) return s;
-  if ((s = sync_and_check(c))) return s;
+  if ((s = kde::sync_and_check(c))) return s;
   if ((s = map_status(c, c->h_st[0].status))) return s;
   *h_out = c->h_st[0].h_rot;
   return KDE_OK;
@@ -787,10 +799,11 @@ kde_status kde_bw_rot(kde_ctx* c, kde_column x, double* h_out) {
 
 kde_status kde_bw_plugin(kde_ctx* c, kde_column x, int stages, double* h_out, kde_plugin_info* info) {
   if (!c || !h_out) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if ((s = run_single(c, make_req(x, KDE_METHOD_PLUGIN, stages, nullptr, 0)))) return s;
-  if ((s = sync_and_check(c))) return s;
+  if ((s = kde::sync_and_check(c))) return s;
   const DevState& h = c->h_st[0];
   if (info) fill_plugin_info(h, stages, info);
   if ((s = map_status(c, h.status))) return s;
@@ -802,17 +815,18 @@ kde_status kde_bw_plugin(kde_ctx* c, kde_column x, int stages, double* h_out, kd
 kde_status kde_lscv_curve(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* g_out,
                           double* gscale_out, double* grid_out) {
   if (!c || !g_out) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if (!h_grid && n_h <= 0) n_h = 150;
   if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
-  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, (size_t)3 * n_h))) return s;
-  const int64_t o = c->jcols[0].d.c_off;
-  HIP_TRY(c, hipMemcpyAsync(c->h_out, c->g.p + o, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->h_out + n_h, c->gs.p + o, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->h_out + 2 * (size_t)n_h, c->hdev.p + o, sizeof(double) * n_h, hipMemcpyDeviceToHost,
-                            c->stream));
-  if ((s = sync_and_check(c))) return s;
+  if ((s = ensure_out(c, (size_t)3 * n_h))) return s;
+  const ColDesc& d = c->iter.cols[0];
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out, d.g, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + n_h, d.gs, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + 2 * (size_t)n_h, d.h, sizeof(double) * n_h, hipMemcpyDeviceToHost,
+                                c->stream));
+  if ((s = kde::sync_and_check(c))) return s;
   if ((s = map_status(c, c->h_st[0].status))) return s;
   std::memcpy(g_out, c->h_out, sizeof(double) * n_h);
   if (gscale_out) std::memcpy(gscale_out, c->h_out + n_h, sizeof(double) * n_h);
@@ -823,13 +837,14 @@ kde_status kde_lscv_curve(kde_ctx* c, kde_column x, const double* h_grid, int32_
 kde_status kde_lscv_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* s1_out,
                          double* s2_out) {
   if (!c || !h_grid || !s1_out || !s2_out) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
-  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, (size_t)2 * n_h))) return s;
-  HIP_TRY(c, hipMemcpyAsync(c->h_out, c->lscv_sums.p + 2 * c->jcols[0].d.c_off, sizeof(double) * 2 * n_h,
-                            hipMemcpyDeviceToHost, c->stream));
-  if ((s = sync_and_check(c))) return s;
+  if ((s = ensure_out(c, (size_t)2 * n_h))) return s;
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out, c->iter.cols[0].sums, sizeof(double) * 2 * n_h, hipMemcpyDeviceToHost,
+                                c->stream));
+  if ((s = kde::sync_and_check(c))) return s;
   if ((s = map_status(c, c->h_st[0].status))) return s;
   for (int32_t k = 0; k < n_h; ++k) {
     s1_out[k] = c->h_out[2 * k];
@@ -841,12 +856,14 @@ kde_status kde_lscv_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t
 kde_status kde_lscv_item_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, const int32_t* sel,
                               int32_t n_sel, int32_t* n_items_out, int32_t* ranges_out, double* sums_out) {
   if (!c || !h_grid || !n_items_out || n_sel < 0) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (n_sel > 0 && (!sel || !ranges_out || !sums_out)) return fail(c, KDE_E_INVAL, "NULL selection buffers");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
-  const JobCol& jc = c->jcols[0];
-  const int32_t n_items = jc.d.n_items;
+  const kde::ColPlan& p = c->plans[0];
+  const ColDesc& d = c->iter.cols[0];
+  const int32_t n_items = d.n_items;
   std::vector<int32_t> idx((size_t)n_sel);
   for (int32_t k = 0; k < n_sel; ++k) {
     idx[k] = sel[k] < 0 ? n_items + sel[k] : sel[k];
@@ -855,19 +872,19 @@ kde_status kde_lscv_item_sums(kde_ctx* c, kde_column x, const double* h_grid, in
       return fail(c, KDE_E_INVAL, "item index out of range");
     }
   }
-  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, (size_t)2 * n_h * (n_sel > 0 ? n_sel : 1)))) return s;
+  if ((s = ensure_out(c, (size_t)2 * n_h * (n_sel > 0 ? n_sel : 1)))) return s;
   // the column's partials are laid out [2*n_h][n_items]: one strided column per selected item
   for (int32_t k = 0; k < n_sel; ++k)
-    HIP_TRY(c, hipMemcpy2DAsync(c->h_out + (size_t)k * 2 * n_h, sizeof(double), c->part.p + jc.d.part_off + idx[k],
-                                sizeof(double) * (size_t)n_items, sizeof(double), (size_t)2 * n_h,
-                                hipMemcpyDeviceToHost, c->stream));
-  if ((s = sync_and_check(c))) return s;
+    KDE_HIP_TRY(c, hipMemcpy2DAsync(c->h_out + (size_t)k * 2 * n_h, sizeof(double), d.part + idx[k],
+                                    sizeof(double) * (size_t)n_items, sizeof(double), (size_t)2 * n_h,
+                                    hipMemcpyDeviceToHost, c->stream));
+  if ((s = kde::sync_and_check(c))) return s;
   if ((s = map_status(c, c->h_st[0].status))) return s;
   *n_items_out = n_items;
   for (int32_t k = 0; k < n_sel; ++k) {
-    ranges_out[3 * k] = jc.lscv_items.row[idx[k]] * kde::kBI;
-    ranges_out[3 * k + 1] = jc.lscv_items.jb[idx[k]];
-    ranges_out[3 * k + 2] = jc.lscv_items.je[idx[k]];
+    ranges_out[3 * k] = p.lscv_items.row[idx[k]] * kde::kBI;
+    ranges_out[3 * k + 1] = p.lscv_items.jb[idx[k]];
+    ranges_out[3 * k + 2] = p.lscv_items.je[idx[k]];
     std::memcpy(sums_out + (size_t)k * 2 * n_h, c->h_out + (size_t)k * 2 * n_h, sizeof(double) * 2 * n_h);
   }
   return KDE_OK;
@@ -876,11 +893,12 @@ kde_status kde_lscv_item_sums(kde_ctx* c, kde_column x, const double* h_grid, in
 kde_status kde_bw_lscv(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* h_out, int32_t* k_out,
                        int* at_edge) {
   if (!c || !h_out) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde_status s;
   if (!h_grid && n_h <= 0) n_h = 150;
   if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
-  if ((s = sync_and_check(c))) return s;
+  if ((s = kde::sync_and_check(c))) return s;
   if ((s = map_status(c, c->h_st[0].status))) return s;
   *h_out = c->h_st[0].h_best;
   if (k_out) *k_out = c->h_st[0].k_best;
@@ -890,61 +908,40 @@ kde_status kde_bw_lscv(kde_ctx* c, kde_column x, const double* h_grid, int32_t n
 
 kde_status kde_batch(kde_ctx* c, const kde_request* reqs, int32_t n_req, kde_result* out) {
   if (!c || n_req < 0 || (n_req > 0 && (!reqs || !out))) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
   if (n_req > KDE_MAX_BATCH) return fail(c, KDE_E_INVAL, "more than KDE_MAX_BATCH requests");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   std::vector<kde_status> st;
   std::vector<std::string> msg;
-  plan_job(c, reqs, n_req, st, msg);
   kde_status s;
-  if ((s = run_job(c))) return s;
+  if ((s = run_requests(c, reqs, n_req, st, msg))) return s;
+  const int n_cols = (int)c->plans.size();
   // g / gscale of LSCV requests into pinned staging, then to the caller
   size_t total = 0;
-  for (const JobCol& jc : c->jcols)
-    if (jc.lscv) total += 2 * (size_t)jc.d.n_h;
-  if ((s = ensure_pinned(c, c->h_out, c->h_out_cap, std::max<size_t>(total, 1)))) return s;
+  for (const kde::ColPlan& p : c->plans)
+    if (p.lscv) total += 2 * (size_t)p.n_h;
+  if ((s = ensure_out(c, std::max<size_t>(total, 1)))) return s;
   size_t o = 0;
-  std::vector<size_t> at(c->jcols.size(), 0);
-  for (size_t k = 0; k < c->jcols.size(); ++k) {
-    const JobCol& jc = c->jcols[k];
-    if (!jc.lscv) continue;
+  std::vector<size_t> at(n_cols, 0);
+  for (int k = 0; k < n_cols; ++k) {
+    const kde::ColPlan& p = c->plans[k];
+    if (!p.lscv) continue;
+    const ColDesc& d = c->iter.cols[k];
     at[k] = o;
-    HIP_TRY(c, hipMemcpyAsync(c->h_out + o, c->g.p + jc.d.c_off, sizeof(double) * jc.d.n_h, hipMemcpyDeviceToHost,
-                              c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->h_out + o + jc.d.n_h, c->gs.p + jc.d.c_off, sizeof(double) * jc.d.n_h,
-                              hipMemcpyDeviceToHost, c->stream));
-    o += 2 * (size_t)jc.d.n_h;
+    KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + o, d.g, sizeof(double) * p.n_h, hipMemcpyDeviceToHost, c->stream));
+    KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + o + p.n_h, d.gs, sizeof(double) * p.n_h, hipMemcpyDeviceToHost,
+                                  c->stream));
+    o += 2 * (size_t)p.n_h;
   }
-  if ((s = sync_and_check(c))) return s;
-  const double nan = std::nan("");
-  for (int32_t k = 0; k < n_req; ++k) {
-    kde_result& r = out[k];
-    double* g_keep = r.g_out;
-    double* gs_keep = r.gscale_out;
-    std::memset(&r, 0, sizeof(r));
-    r.g_out = g_keep;
-    r.gscale_out = gs_keep;
-    r.status = st[k];
-    r.sigma = r.h_rot = r.h_plugin = r.h_lscv = nan;
-    r.k_lscv = -1;
-  }
-  for (size_t k = 0; k < c->jcols.size(); ++k) {
-    const JobCol& jc = c->jcols[k];
-    const DevState& h = c->h_st[k];
-    kde_result& r = out[jc.req];
-    r.status = status_of(h.status);
-    if (r.status == KDE_OK && jc.plugin) r.status = status_of(h.pstatus);
-    r.sigma = h.sigma;
-    r.h_rot = h.h_rot;
-    if (jc.plugin) {
-      fill_plugin_info(h, jc.stages, &r.plugin);
-      r.h_plugin = h.h_plugin;
-    }
-    if (jc.lscv) {
-      r.h_lscv = h.h_best;
-      r.k_lscv = h.k_best;
-      r.at_edge = h.at_edge;
-      if (r.g_out) std::memcpy(r.g_out, c->h_out + at[k], sizeof(double) * jc.d.n_h);
-      if (r.gscale_out) std::memcpy(r.gscale_out, c->h_out + at[k] + jc.d.n_h, sizeof(double) * jc.d.n_h);
+  if ((s = kde::sync_and_check(c))) return s;
+  for (int32_t k = 0; k < n_req; ++k) kde::init_result(out[k], st[k]);
+  for (int k = 0; k < n_cols; ++k) {
+    const kde::ColPlan& p = c->plans[k];
+    kde_result& r = out[c->plan_req[k]];
+    kde::fill_result(p, c->h_st[k], r);
+    if (p.lscv) {
+      if (r.g_out) std::memcpy(r.g_out, c->h_out + at[k], sizeof(double) * p.n_h);
+      if (r.gscale_out) std::memcpy(r.gscale_out, c->h_out + at[k] + p.n_h, sizeof(double) * p.n_h);
     }
   }
   return KDE_OK;

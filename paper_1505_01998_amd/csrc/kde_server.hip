@@ -1,0 +1,407 @@
+// kde_server.hip -- continuous-batching server for bandwidth-selection requests.
+//
+// One scheduler thread per context.  Clients submit requests (copied on
+// submit), which wait in a FIFO queue until admission: a free slot and room
+// in the HBM budget for the request's device block.  Admitted requests stay
+// resident.  Each scheduler iteration builds one executor pass over all
+// resident requests: the moments of newly admitted ones, then plug-in stage
+// units and LSCV units taken request by request, smallest remaining work
+// first, until the iteration's evaluation budget is used; a stage whose last
+// units are in the pass is finished in it, and requests whose work is all
+// done are finalised and copied back.  Requests arriving while an iteration
+// runs join the next one, so their work overlaps with the requests already
+// on the device.  Every request keeps the work decomposition and reduction
+// order it has alone, so its results are bitwise those of kde_batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "kde_runtime.h"
+
+namespace kde {
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct SrvReq {
+  uint64_t ticket = 0;
+  kde_request req;
+  std::vector<char> host_x;  // copy of host samples
+  void* dev_x = nullptr;     // copy of device samples
+  ColPlan plan;
+  char* block = nullptr;
+  int slot = -1;
+  bool stats_done = false, plugin_done = false, prep_done = false, lscv_done = false;
+  int stage = 0;
+  size_t psi_next = 0, lscv_next = 0;
+  std::vector<Unit> psi_u, lscv_u;
+  std::vector<UnitCost> psi_c, lscv_c;
+  double remaining = 0.0;
+  bool finishing = false, done = false;
+  kde_result res;
+  std::vector<double> g, gs;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct Server {
+  kde_ctx* c = nullptr;
+  uint64_t budget = 0;
+  int max_slots = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<SrvReq>> queue;
+  std::vector<std::shared_ptr<SrvReq>> active;
+  std::unordered_map<uint64_t, std::shared_ptr<SrvReq>> all;
+  std::vector<int> free_slots;
+  uint64_t next_ticket = 1;
+  uint64_t used = 0;
+  bool running = false, stopping = false;
+  std::thread th;
+  DevBuf<DevState> st;
+  DevState* h_st = nullptr;
+  IterPlan it;
+  void loop();
+};
+
+namespace {
+
+void finish_with(Server& s, const std::shared_ptr<SrvReq>& r, kde_status st) {
+  r->res.status = st;
+  r->t_done = now_s();
+  r->res.t_queue_s = (r->t_admit > 0 ? r->t_admit : r->t_done) - r->t_submit;
+  r->res.t_service_s = r->t_admit > 0 ? r->t_done - r->t_admit : 0.0;
+  r->done = true;
+  (void)s;
+}
+
+// Adds units [next, end) of one list to the pass while the budget lasts; at
+// least one unit when `force`.
+void take_units(const std::vector<Unit>& u, const std::vector<UnitCost>& cu, size_t& next, double& budget,
+                bool force, std::vector<Unit>& out, std::vector<UnitCost>& out_c, double& remaining) {
+  while (next < u.size() && (budget > 0.0 || force)) {
+    out.push_back(u[next]);
+    out_c.push_back(cu[next]);
+    budget -= cu[next].evals;
+    remaining -= cu[next].evals;
+    ++next;
+    force = false;
+  }
+}
+
+}  // namespace
+
+void Server::loop() {
+  kde_ctx* ctx = c;
+  (void)hipSetDevice(ctx->device);
+  const bool cond = ctx->prec != KDE_PREC_FP64 && ctx->opt_fp64_kappa > 0.0;
+  for (;;) {
+    std::vector<std::shared_ptr<SrvReq>> admitted;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        // admission: FIFO, slots and HBM budget
+        while (!queue.empty() && !free_slots.empty()) {
+          std::shared_ptr<SrvReq> r = queue.front();
+          const uint64_t fp = r->plan.bytes;
+          if (fp > budget) {
+            queue.pop_front();
+            finish_with(*this, r, KDE_E_NOMEM);
+            cv_done.notify_all();
+            continue;
+          }
+          if (used + fp > budget) break;
+          queue.pop_front();
+          r->slot = free_slots.back();
+          free_slots.pop_back();
+          used += fp;
+          admitted.push_back(r);
+        }
+        if (!admitted.empty() || !active.empty()) break;
+        if (stopping) return;
+        cv_work.wait_for(lk, std::chrono::milliseconds(50));
+      }
+    }
+    // device blocks and initial state of newly admitted requests
+    for (auto& r : admitted) {
+      r->t_admit = now_s();
+      if (hipMalloc((void**)&r->block, r->plan.bytes) != hipSuccess) {
+        r->block = nullptr;
+        std::lock_guard<std::mutex> lk(mu);
+        used -= r->plan.bytes;
+        free_slots.push_back(r->slot);
+        finish_with(*this, r, KDE_E_NOMEM);
+        cv_done.notify_all();
+        continue;
+      }
+      init_state(r->plan, ctx->opt_fp64_kappa, h_st[r->slot]);
+      (void)hipMemcpyAsync(st.p + r->slot, h_st + r->slot, sizeof(DevState), hipMemcpyHostToDevice, ctx->stream);
+      psi_units_of(r->plan, r->slot, r->psi_u, r->psi_c);
+      lscv_units_of(r->plan, r->slot, r->lscv_u, r->lscv_c);
+      r->stage = r->plan.stages == 3 ? 0 : 1;
+      r->remaining = 0.0;
+      for (const UnitCost& u : r->psi_c) r->remaining += u.evals * (3 - r->stage);
+      for (const UnitCost& u : r->lscv_c) r->remaining += u.evals;
+      active.push_back(r);
+    }
+    if (active.empty()) continue;
+    // one executor pass over the resident requests, smallest remaining first
+    it.clear();
+    it.cols.assign(max_slots, ColDesc());
+    std::sort(active.begin(), active.end(),
+              [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
+                return a->remaining < b->remaining || (a->remaining == b->remaining && a->ticket < b->ticket);
+              });
+    double left = ctx->opt_serve_iter_evals;
+    bool first = true;
+    for (auto& r : active) {
+      ColPlan& p = r->plan;
+      ColDesc d;
+      bind_column(p, r->block, r->dev_x, st.p + r->slot, d);
+      it.cols[r->slot] = d;
+      if (!r->stats_done) {
+        if (p.raw_in_block) it.uploads.push_back(Upload{(void*)d.raw, r->host_x.data(), p.raw_bytes});
+        if (p.lscv && p.grid_kind == KDE_GRID_EXPLICIT)
+          it.uploads.push_back(Upload{(void*)d.h_in, p.grid_h.data(), sizeof(double) * p.n_h});
+        it.ids_stats.push_back(r->slot);
+        it.max_stat_blocks = std::max(it.max_stat_blocks, std::min(kStatBlocks, (p.n + 2047) / 2048));
+        r->stats_done = true;
+      }
+      if (p.plugin && !r->plugin_done) {
+        while (r->stage < 3) {
+          const int s = r->stage;
+          if (r->psi_next == 0) it.ids_begin[s].push_back(r->slot);
+          take_units(r->psi_u, r->psi_c, r->psi_next, left, first, it.psi_units[s], it.psi_cost[s], r->remaining);
+          first = false;
+          if (r->psi_next < r->psi_u.size()) break;
+          it.ids_finish[s].push_back(r->slot);
+          psi_rows_of(p, d, it.psi_rows[s]);
+          if (cond) psi_units_of(p, r->slot, it.psi_cond_units[s], it.psi_cond_cost[s]);
+          r->stage++;
+          r->psi_next = 0;
+          if (left <= 0.0) break;
+        }
+        if (r->stage == 3) {
+          it.ids_plugin_final.push_back(r->slot);
+          r->plugin_done = true;
+        }
+      }
+      if (p.lscv && !r->lscv_done) {
+        if (!r->prep_done) {
+          it.ids_lscv_prep.push_back(r->slot);
+          r->prep_done = true;
+        }
+        take_units(r->lscv_u, r->lscv_c, r->lscv_next, left, first, it.lscv_units, it.lscv_cost, r->remaining);
+        first = false;
+        if (r->lscv_next == r->lscv_u.size()) {
+          lscv_rows_of(p, d, it.lscv_rows);
+          it.ids_lscv_final.push_back(r->slot);
+          r->lscv_done = true;
+        }
+      }
+      r->finishing = (!p.plugin || r->plugin_done) && (!p.lscv || r->lscv_done);
+    }
+    kde_status s = execute(ctx, it);
+    for (auto& r : active) {
+      if (!r->finishing || s != KDE_OK) continue;
+      if (hipMemcpyAsync(h_st + r->slot, st.p + r->slot, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream) !=
+          hipSuccess)
+        s = KDE_E_DEVICE;
+      if (r->plan.lscv) {
+        r->g.assign(r->plan.n_h, 0.0);
+        r->gs.assign(r->plan.n_h, 0.0);
+        const ColDesc& d = it.cols[r->slot];
+        if (hipMemcpyAsync(r->g.data(), d.g, sizeof(double) * r->plan.n_h, hipMemcpyDeviceToHost, ctx->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(r->gs.data(), d.gs, sizeof(double) * r->plan.n_h, hipMemcpyDeviceToHost, ctx->stream) !=
+                hipSuccess)
+          s = KDE_E_DEVICE;
+      }
+    }
+    if (s == KDE_OK) s = sync_and_check(ctx);
+    std::lock_guard<std::mutex> lk(mu);
+    std::vector<std::shared_ptr<SrvReq>> keep;
+    for (auto& r : active) {
+      if (s != KDE_OK || r->finishing) {
+        if (s == KDE_OK) {
+          fill_result(r->plan, h_st[r->slot], r->res);
+          finish_with(*this, r, r->res.status);
+        } else {
+          finish_with(*this, r, KDE_E_DEVICE);
+        }
+        (void)hipFree(r->block);
+        r->block = nullptr;
+        used -= r->plan.bytes;
+        free_slots.push_back(r->slot);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    active.swap(keep);
+    cv_done.notify_all();
+  }
+}
+
+void ServerDeleter::operator()(Server* s) const {
+  if (!s) return;
+  for (auto& kv : s->all)
+    if (kv.second->dev_x) (void)hipFree(kv.second->dev_x);
+  (void)hipFree(s->st.p);
+  if (s->h_st) (void)hipHostFree(s->h_st);
+  delete s;
+}
+
+bool server_running(const Server* s) { return s && s->running; }
+
+}  // namespace kde
+
+namespace {
+
+using kde::fail;
+using kde::Server;
+using kde::SrvReq;
+
+kde_status collect(kde_ctx* c, Server& s, uint64_t ticket, kde_result* out, std::unique_lock<std::mutex>& lk,
+                   double timeout_s) {
+  auto itr = s.all.find(ticket);
+  if (itr == s.all.end()) return fail(c, KDE_E_INVAL, "unknown ticket");
+  std::shared_ptr<SrvReq> r = itr->second;
+  if (!r->done) {
+    if (timeout_s == 0.0) return KDE_E_BUSY;
+    auto pred = [&] { return r->done; };
+    if (timeout_s < 0)
+      s.cv_done.wait(lk, pred);
+    else if (!s.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
+      return KDE_E_BUSY;
+  }
+  if (out) {
+    double* g = out->g_out;
+    double* gs = out->gscale_out;
+    *out = r->res;
+    out->g_out = g;
+    out->gscale_out = gs;
+    if (g && !r->g.empty()) std::memcpy(g, r->g.data(), sizeof(double) * r->g.size());
+    if (gs && !r->gs.empty()) std::memcpy(gs, r->gs.data(), sizeof(double) * r->gs.size());
+  }
+  if (r->dev_x) (void)hipFree(r->dev_x);
+  r->dev_x = nullptr;
+  s.all.erase(itr);
+  return KDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kde_status kde_server_start(kde_ctx* c, uint64_t hbm_budget_bytes, int32_t max_slots) {
+  if (!c) return KDE_E_INVAL;
+  if (c->server && c->server->running) return fail(c, KDE_E_BUSY, "a server is already running");
+  if (max_slots < 1 || max_slots > KDE_MAX_BATCH || hbm_budget_bytes == 0)
+    return fail(c, KDE_E_INVAL, "max_slots must be in [1, KDE_MAX_BATCH] and the budget > 0");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  c->server.reset();
+  std::unique_ptr<Server, kde::ServerDeleter> s(new Server());
+  s->c = c;
+  s->budget = hbm_budget_bytes;
+  s->max_slots = max_slots;
+  kde_status st;
+  if ((st = kde::ensure(c, s->st, (size_t)max_slots))) return st;
+  if (hipHostMalloc((void**)&s->h_st, sizeof(kde::DevState) * max_slots, hipHostMallocDefault) != hipSuccess) {
+    s->h_st = nullptr;
+    return fail(c, KDE_E_NOMEM, "pinned host allocation failed");
+  }
+  for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->running = true;
+  Server* raw = s.get();
+  c->server = std::move(s);
+  raw->th = std::thread([raw] { raw->loop(); });
+  return KDE_OK;
+}
+
+kde_status kde_submit(kde_ctx* c, const kde_request* req, uint64_t* ticket) {
+  if (!c || !req || !ticket) return KDE_E_INVAL;
+  Server* s = c->server.get();
+  if (!s || !s->running) return fail(c, KDE_E_INVAL, "no server is running on this context");
+  auto r = std::make_shared<SrvReq>();
+  r->req = *req;
+  // the plan copies an explicit grid; the samples are copied below
+  std::string e;
+  {
+    // plan_column reads only the options, which cannot change while serving
+    e = kde::plan_column(c, *req, r->plan);
+  }
+  if (!e.empty()) return fail(c, KDE_E_INVAL, e);
+  const size_t bytes = r->plan.raw_bytes;
+  if (req->x.on_device) {
+    if (hipMalloc(&r->dev_x, bytes) != hipSuccess) return fail(c, KDE_E_NOMEM, "device copy of the column failed");
+    if (hipMemcpy(r->dev_x, req->x.data, bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+      (void)hipFree(r->dev_x);
+      return fail(c, KDE_E_DEVICE, "device copy of the column failed");
+    }
+  } else {
+    r->host_x.assign((const char*)req->x.data, (const char*)req->x.data + bytes);
+  }
+  r->req.x.data = req->x.on_device ? r->dev_x : (const void*)r->host_x.data();
+  r->req.grid.h = r->plan.grid_h.empty() ? nullptr : r->plan.grid_h.data();
+  r->res.g_out = r->res.gscale_out = nullptr;
+  kde::init_result(r->res, KDE_OK);
+  r->t_submit = kde::now_s();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) {
+    if (r->dev_x) (void)hipFree(r->dev_x);
+    return fail(c, KDE_E_CANCELLED, "server is stopping");
+  }
+  r->ticket = s->next_ticket++;
+  s->queue.push_back(r);
+  s->all[r->ticket] = r;
+  *ticket = r->ticket;
+  s->cv_work.notify_one();
+  return KDE_OK;
+}
+
+kde_status kde_poll(kde_ctx* c, uint64_t ticket, kde_result* out) {
+  if (!c) return KDE_E_INVAL;
+  Server* s = c->server.get();
+  if (!s) return fail(c, KDE_E_INVAL, "no server on this context");
+  std::unique_lock<std::mutex> lk(s->mu);
+  return collect(c, *s, ticket, out, lk, 0.0);
+}
+
+kde_status kde_wait(kde_ctx* c, uint64_t ticket, kde_result* out, double timeout_s) {
+  if (!c) return KDE_E_INVAL;
+  Server* s = c->server.get();
+  if (!s) return fail(c, KDE_E_INVAL, "no server on this context");
+  std::unique_lock<std::mutex> lk(s->mu);
+  return collect(c, *s, ticket, out, lk, timeout_s);
+}
+
+kde_status kde_server_stop(kde_ctx* c) {
+  if (!c) return KDE_E_INVAL;
+  Server* s = c->server.get();
+  if (!s || !s->running) return KDE_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    while (!s->queue.empty()) {
+      std::shared_ptr<SrvReq> r = s->queue.front();
+      s->queue.pop_front();
+      kde::finish_with(*s, r, KDE_E_CANCELLED);
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+  }
+  s->th.join();
+  s->running = false;
+  return KDE_OK;
+}
+
+}  // extern "C"
