@@ -92,12 +92,170 @@ def cpu_baseline(w, x, budget_s: float):
     }
 
 
+def _requests_of(kde, cols, grid=None, stages=None):
+    A = kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV
+    return [kde.Request(x, A, stages or workloads.BATCH_STAGES, grid or workloads.BATCH_GRID) for x in cols]
+
+
+def batch_bench(args):
+    """512 uneven columns as one kde_batch job vs one call per column."""
+    import torch
+
+    import paper_1505_01998_amd as kde
+
+    specs = workloads.batch_columns()
+    cols = [torch.from_numpy(s.column()).to("cuda:0") for s in specs]
+    torch.cuda.synchronize()
+    reqs = _requests_of(kde, cols)
+    n_h = workloads.BATCH_GRID[3]
+    evals = sum(s.n * (s.n - 1) / 2 * (n_h + workloads.BATCH_STAGES) for s in specs)
+    ctx = kde.Context(0, args.precision)
+    for i in range(args.warmup):
+        log(f"warmup {i + 1}/{args.warmup}")
+        ctx.batch(reqs)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = ctx.batch(reqs)
+        log(f"batched step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    launches, ms, evals_k = ctx.kernel_time("lscv_pairs")
+    assert all(r.status == kde.KDE_OK for r in out)
+    t0 = time.perf_counter()
+    for k, r in enumerate(reqs):
+        ctx.batch([r])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"plain per-column calls done in {t_plain:.1f} s")
+    ctx.close()
+    achieved = evals_k / (ms * 1e-3)
+    return {
+        "metric": "pair-kernel evals/s (batched 512 uneven columns)",
+        "value": evals / t_batch,
+        "unit": "pair-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "batch-512", "columns": len(specs), "n_range": [1000, 200000], "n_h": n_h,
+                   "plugin_stages": workloads.BATCH_STAGES, "precision": args.precision},
+        "columns_per_s": len(specs) / t_batch,
+        "plain": {"columns_per_s": len(specs) / t_plain, "value": evals / t_plain, "seconds": t_plain},
+        "speedup_vs_plain": t_plain / t_batch,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": LSCV_PEAK / 1e12, "unit": "Teval/s",
+                     "frac": achieved / LSCV_PEAK, "traffic": None, "kernel": "k_lscv_units_f32",
+                     "launches": launches, "avg_launch_ms": ms / max(launches, 1)},
+    }
+
+
+def served_bench(args):
+    """Served form (continuous batching) vs plain per-request calls on the same
+    request stream: first at the stream's own arrival times, then load-matched
+    at 0.7 x the plain form's measured capacity."""
+    import threading
+
+    import paper_1505_01998_amd as kde
+
+    n_lo, n_hi = (2e3, 2e6) if args.workload == "served" else (2e3, 6e4)
+    stream = workloads.served_stream(args.requests, rate=args.rate, n_lo=n_lo, n_hi=n_hi)
+    cols = [a.spec.column() for a in stream]
+    reqs = _requests_of(kde, cols)
+    n_h = workloads.BATCH_GRID[3]
+    evals = sum(a.spec.n * (a.spec.n - 1) / 2 * (n_h + workloads.BATCH_STAGES) for a in stream)
+    log(f"{len(reqs)} requests, {evals:.3e} pair-evals, arrivals over {stream[-1].t:.2f} s")
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v), q))
+
+    def run_plain(ctx, times):
+        lat, t_start = [], time.perf_counter()
+        for r, t in zip(reqs, times):
+            now = time.perf_counter() - t_start
+            if now < t:
+                time.sleep(t - now)
+            res = ctx.batch([r])[0]
+            assert res.status == kde.KDE_OK
+            lat.append(time.perf_counter() - t_start - t)
+            if len(lat) % max(1, len(reqs) // 8) == 0:
+                log(f"  plain: {len(lat)}/{len(reqs)} done")
+        span = time.perf_counter() - t_start - times[0]
+        return lat, span
+
+    def run_served(ctx, times):
+        ctx.server_start(args.hbm_budget_gb << 30, args.slots)
+        tickets = [None] * len(reqs)
+        t_start = time.perf_counter()
+
+        def feeder():
+            for k, (r, t) in enumerate(zip(reqs, times)):
+                now = time.perf_counter() - t_start
+                if now < t:
+                    time.sleep(t - now)
+                tickets[k] = ctx.submit(r)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        lat, done_at = [], []
+        for k in range(len(reqs)):
+            while tickets[k] is None:
+                time.sleep(0.0005)
+            res = ctx.wait(tickets[k])
+            assert res.status == kde.KDE_OK, res.status
+            lat.append(res.t_queue_s + res.t_service_s)
+            done_at.append(time.perf_counter() - t_start)
+            if len(lat) % max(1, len(reqs) // 8) == 0:
+                log(f"  served: {len(lat)}/{len(reqs)} collected")
+        th.join()
+        ctx.server_stop()
+        return lat, max(done_at) - times[0]
+
+    def summary(lat, span):
+        return {"req_per_s": len(lat) / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "mean_s": float(np.mean(lat)),
+                "makespan_s": span}
+
+    out = {}
+    ctx = kde.Context(0, args.precision)
+    ctx.batch(reqs[:1])  # warm-up: code objects, allocations
+    arrivals = [a.t for a in stream]
+    log("plain at the stream's arrival times")
+    out["plain"] = summary(*run_plain(ctx, arrivals))
+    log("served at the stream's arrival times")
+    out["served"] = summary(*run_served(ctx, arrivals))
+    cap = out["plain"]["req_per_s"]
+    scale = args.rate / (0.7 * cap)
+    matched = [t * scale for t in arrivals]
+    log(f"load-matched: rate {0.7 * cap:.3f} req/s")
+    out["plain_load_matched"] = summary(*run_plain(ctx, matched))
+    out["served_load_matched"] = summary(*run_served(ctx, matched))
+    ctx.close()
+    return {
+        "metric": "served req/s + p99 latency vs plain",
+        "value": out["served"]["req_per_s"],
+        "unit": "req/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": out["served"]["makespan_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "requests": len(reqs), "rate_req_s": args.rate,
+                   "n_range": [n_lo, n_hi], "n_h": n_h, "plugin_stages": workloads.BATCH_STAGES,
+                   "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "pair_evals": evals,
+                   "load_matched_rate_req_s": 0.7 * cap},
+        **out,
+        "speedup_req_s": out["served"]["req_per_s"] / out["plain"]["req_per_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lognormal-1m", choices=workloads.WORKLOADS)
+    ap.add_argument("--workload", default="lognormal-1m",
+                    choices=workloads.WORKLOADS + ("batch-512", "served", "served-small"))
+    ap.add_argument("--requests", type=int, default=32, help="served: requests taken from the stream")
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrival rate of the stream (req/s)")
+    ap.add_argument("--hbm-budget-gb", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--hc", type=int, default=-1, help="bandwidths per LSCV pass (8, 16, 32; -1 = default)")
@@ -119,6 +277,13 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; the path is not sharded across GPUs",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "batch-512":
+        print(json.dumps(batch_bench(args)), flush=True)
+        return
+    if args.workload in ("served", "served-small"):
+        print(json.dumps(served_bench(args)), flush=True)
+        return
 
     import torch
 

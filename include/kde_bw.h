@@ -111,7 +111,9 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *   "launch_evals" pair-term evaluations per kernel launch (launch splitting)
  *   "fp64_kappa"   mixed precision: kappa above which a plug-in stage is re-run
  *                  in FP64 (0 = never)
- *   "serve_iter_evals" server: pair-term evaluations per scheduler iteration
+ *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
+ *                  iteration (an iteration also holds at least six rounds of
+ *                  1024 blocks of its largest work unit)
  * Unknown keys give KDE_E_INVAL. */
 kde_status kde_ctx_set_option(kde_ctx* ctx, const char* key, int64_t value);
 
@@ -233,7 +235,7 @@ kde_status kde_batch(kde_ctx* ctx, const kde_request* reqs, int32_t n_req, kde_r
  * stay resident on the device (samples, partial sums, state) until done.
  * Continuous batching: every scheduler iteration launches, in shared
  * launches, the next work units of every resident request, smallest
- * remaining work first, within serve_iter_evals pair-term evaluations;
+ * remaining work first, within the iteration's evaluation budget;
  * requests admitted while others run join the next iteration.  Each result
  * is bitwise identical to the same request run alone through kde_batch. */
 kde_status kde_server_start(kde_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots);

@@ -104,7 +104,7 @@ struct kde_ctx {
   int64_t opt_seg = -1;            // <0 automatic, 0 whole rows, >0 explicit
   double opt_launch_evals = 4e12;  // pair-term evaluations per launch
   double opt_fp64_kappa = 1e3;
-  double opt_serve_iter_evals = 4e11;  // server: pair-term evaluations per iteration
+  double opt_serve_iter_evals = 1e12;  // server: pair-term evaluations per iteration (minimum)
   // device workspace of synchronous jobs
   kde::DevBuf<char> stage;   // host columns copied in
   kde::DevBuf<char> blocks;  // per-column device blocks, packed

@@ -751,7 +751,7 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
   } else if (k == "fp64_kappa") {
     c->opt_fp64_kappa = value < 0 ? 1e3 : (double)value;
   } else if (k == "serve_iter_evals") {
-    c->opt_serve_iter_evals = value <= 0 ? 4e11 : (double)value;
+    c->opt_serve_iter_evals = value <= 0 ? 1e12 : (double)value;
   } else {
     return fail(c, KDE_E_INVAL, "unknown option " + k);
   }

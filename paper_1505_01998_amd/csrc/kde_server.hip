@@ -161,7 +161,17 @@ void Server::loop() {
               [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
                 return a->remaining < b->remaining || (a->remaining == b->remaining && a->ticket < b->ticket);
               });
-    double left = ctx->opt_serve_iter_evals;
+    // An iteration is one launch per pass, so it must hold several waves of its
+    // largest units or the launch tail idles the chip: at least 6 rounds of
+    // 1024 resident blocks of the largest unit any resident request has next.
+    double max_unit = 0.0;
+    for (auto& r : active) {
+      if (r->plan.plugin && !r->plugin_done && r->psi_next < r->psi_c.size())
+        max_unit = std::max(max_unit, r->psi_c[r->psi_next].evals);
+      if (r->plan.lscv && !r->lscv_done && r->lscv_next < r->lscv_c.size())
+        max_unit = std::max(max_unit, r->lscv_c[r->lscv_next].evals);
+    }
+    double left = std::max(ctx->opt_serve_iter_evals, 6.0 * 1024.0 * max_unit);
     bool first = true;
     for (auto& r : active) {
       ColPlan& p = r->plan;

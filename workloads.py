@@ -120,6 +120,26 @@ def batch_columns(count: int = 512, seed: int = 1998004, n_lo: float = 1e3, n_hi
     return [ColumnSpec(BATCH_FAMILIES[int(f)], int(n), int(k.generate_state(1)[0])) for n, f, k in zip(ns, fam, kids)]
 
 
+@dataclass
+class Arrival:
+    t: float
+    spec: ColumnSpec
+
+
+def served_stream(count: int, seed: int = 1998005, rate: float = 200.0, n_lo: float = 2e3, n_hi: float = 2e6):
+    """The first `count` requests of the served workload: Poisson arrivals at
+    `rate` per second, n log-uniform in [n_lo, n_hi], family uniform over the
+    four batch families; each request draws from its own child seed."""
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate, count)
+    ns = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count))).astype(np.int64)
+    fam = rng.integers(0, len(BATCH_FAMILIES), count)
+    kids = np.random.SeedSequence(seed).spawn(count)
+    t = np.cumsum(gaps)
+    return [Arrival(float(t[k]), ColumnSpec(BATCH_FAMILIES[int(fam[k])], int(ns[k]), int(kids[k].generate_state(1)[0])))
+            for k in range(count)]
+
+
 # Batched and served requests: plug-in with three stages and LSCV over 128
 # points log-spaced over h_rot * [1/64, 4] (the optimum of skewed and
 # multimodal columns lies well below h_rot).
