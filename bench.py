@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--hc", type=int, default=-1, help="bandwidths per LSCV pass (8, 16, 32; -1 = default)")
     ap.add_argument("--seg", type=int, default=-1, help="j-range per work item (-1 = automatic, 0 = whole rows)")
+    ap.add_argument("--mfma", type=int, default=-1, help="LSCV arguments on the matrix cores (1/0; -1 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -301,6 +302,8 @@ def main():
         ctx.set_option("lscv_hc", args.hc)
     if args.seg >= 0:
         ctx.set_option("seg", args.seg)
+    if args.mfma >= 0:
+        ctx.set_option("lscv_mfma", args.mfma)
 
     def step():
         h_pi, info = ctx.bw_plugin(xd, w.stages)

@@ -111,6 +111,9 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *   "launch_evals" pair-term evaluations per kernel launch (launch splitting)
  *   "fp64_kappa"   mixed precision: kappa above which a plug-in stage is re-run
  *                  in FP64 (0 = never)
+ *   "lscv_mfma"    1: form the LSCV exponent arguments on the matrix cores
+ *                  (mixed precision with lscv_hc 16; results identical in
+ *                  value to rounding, not bitwise, to the vector-ALU kernel)
  *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
  *                  iteration (an iteration also holds at least six rounds of
  *                  1024 blocks of its largest work unit)

@@ -20,6 +20,8 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results straight into VGPRs (no AGPR round trip before exp2)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=true",
     "-Wno-unused-result",
 ]
 

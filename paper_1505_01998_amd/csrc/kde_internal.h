@@ -113,7 +113,9 @@ void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, in
 // Pair kernels act on units[u0 .. u0 + n_units).
 void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColDesc* cols, const Unit* units, int u0,
                       int n_units);
-void launch_lscv_units(hipStream_t s, int hc, int f64, const ColDesc* cols, const Unit* units, int u0, int n_units);
+// mfma: use the matrix-core variant (FP32, 16 bandwidths per unit only).
+void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, const ColDesc* cols, const Unit* units, int u0,
+                       int n_units);
 void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows);
 
 }  // namespace kde

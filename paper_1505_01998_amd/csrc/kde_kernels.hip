@@ -647,6 +647,135 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f64(const ColDesc* __re
   }
 }
 
+// ---- LSCV pair kernel with the exponent arguments formed on the matrix cores.
+// The argument of every (pair, h) term is D^2 * c_h: an outer product of the
+// pair distances and the chunk's coefficients.  v_mfma_f32_32x32x2f32 forms
+// it for 32 samples i x 2 samples j x 16 bandwidths at once (A[row][k] =
+// D^2(i_row, j_k), B[k][col] = c[col % 16] if k = col / 16 else 0), so the
+// vector ALU only evaluates exp2 and accumulates.  Lane l ends up owning
+// bandwidth h = l % 16 for rows 8(r/4) + 4(l/32) + r%4 of the output block.
+// Groups of 16 j whose pairs are all valid (j > i, i < n, j < n) run without
+// masks; the others replace the argument of an invalid pair by -inf.
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr float kBigF = 3.0e38f;
+
+template <bool MASK>
+__device__ __forceinline__ void mfma_consume(const v16f& da, const v16f& db, int j0, int jsel, int k, int ibase,
+                                             int n, float (&s1)[4], float (&s2)[4]) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float ya = da[r], yb = db[r];
+    if (MASK) {
+      const int row = 8 * (r >> 2) + 4 * k + (r & 3);
+      const int j = j0 + jsel;
+      const int ia = ibase + row, ib = ibase + 32 + row;
+      ya = (j > ia && ia < n && j < n) ? ya : -kInfF;
+      yb = (j > ib && ib < n && j < n) ? yb : -kInfF;
+    }
+    const float ea = __builtin_amdgcn_exp2f(ya);
+    const float eb = __builtin_amdgcn_exp2f(yb);
+    s1[r & 3] += ea;
+    s2[r & 3] = __builtin_fmaf(ea, ea, s2[r & 3]);
+    s1[r & 3] += eb;
+    s2[r & 3] = __builtin_fmaf(eb, eb, s2[r & 3]);
+  }
+}
+
+// 8 pairs (j, j+1) of one group of 16 j; the matrix-core products of the next
+// pair are issued before the exponentials of the current one.
+template <bool MASK>
+__device__ __forceinline__ void mfma_group(const float4* __restrict__ tile, int jl, int jg, float xa, float xb,
+                                           int ibase, int n, float bop, int lane, float (&s1)[4], float (&s2)[4]) {
+  const int k = lane >> 5;
+  const int jsel = (lane & 31) >> 4;
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float xj[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = tile[(jl >> 2) + q];
+    xj[2 * q] = k ? v.y : v.x;
+    xj[2 * q + 1] = k ? v.w : v.z;
+  }
+  float ta = xa - xj[0], tb = xb - xj[0];
+  v16f da = __builtin_amdgcn_mfma_f32_32x32x2f32(fminf(ta * ta, kBigF), bop, zero, 0, 0, 0);
+  v16f db = __builtin_amdgcn_mfma_f32_32x32x2f32(fminf(tb * tb, kBigF), bop, zero, 0, 0, 0);
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    v16f na, nb;
+    if (p < 7) {
+      ta = xa - xj[p + 1];
+      tb = xb - xj[p + 1];
+      na = __builtin_amdgcn_mfma_f32_32x32x2f32(fminf(ta * ta, kBigF), bop, zero, 0, 0, 0);
+      nb = __builtin_amdgcn_mfma_f32_32x32x2f32(fminf(tb * tb, kBigF), bop, zero, 0, 0, 0);
+    }
+    mfma_consume<MASK>(da, db, jg + 2 * p, jsel, k, ibase, n, s1, s2);
+    if (p < 7) {
+      da = na;
+      db = nb;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lscv_units_mfma(const ColDesc* __restrict__ cols,
+                                                              const Unit* __restrict__ units, int u0) {
+  constexpr int HC = 16;
+  const Unit u = units[u0 + blockIdx.x];
+  const ColDesc c = cols[u.col];
+  if (c.st->status != kStOk) return;
+  const float* x = c.x32;
+  const int n = c.n;
+  __shared__ float4 tile[kBJ / 4];
+  __shared__ double red[4][HC][2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row0 = u.row * kBI;
+  const int wave_i0 = row0 + wave * 64;
+  // A-operand rows: lane l holds samples i = wave_i0 + (l % 32) and i + 32
+  const int ia = wave_i0 + (lane & 31), ib = ia + 32;
+  const float xa = (ia < n) ? x[ia] : 0.f;
+  const float xb = (ib < n) ? x[ib] : 0.f;
+  // B operand: k = lane / 32, col = lane % 32
+  const int kb = lane >> 5, colb = lane & 31;
+  const float bop = (kb == (colb >> 4)) ? c.c32[u.chunk * HC + (colb & 15)] : 0.f;
+  float a1 = 0.f, c1 = 0.f, a2 = 0.f, c2 = 0.f;
+  const bool rows_full = wave_i0 + 64 <= n;
+  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
+    __syncthreads();
+    for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
+    __syncthreads();
+    const int te = t0 + kBJ;
+    for (int js = max(t0, wave_i0); js < te; js += 16) {
+      float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
+      const bool clean = rows_full && js >= wave_i0 + 64 && js + 16 <= n;
+      if (clean)
+        mfma_group<false>(tile, js - t0, js, xa, xb, wave_i0, n, bop, lane, s1, s2);
+      else
+        mfma_group<true>(tile, js - t0, js, xa, xb, wave_i0, n, bop, lane, s1, s2);
+      kahan_add(a1, c1, (s1[0] + s1[1]) + (s1[2] + s1[3]));
+      kahan_add(a2, c2, (s2[0] + s2[1]) + (s2[2] + s2[3]));
+    }
+  }
+  // lanes l, l^16, l^32, l^48 hold the same bandwidth
+  double v1 = (double)a1 - (double)c1, v2 = (double)a2 - (double)c2;
+  v1 += __shfl_xor(v1, 16, 64);
+  v2 += __shfl_xor(v2, 16, 64);
+  v1 += __shfl_xor(v1, 32, 64);
+  v2 += __shfl_xor(v2, 32, 64);
+  if (lane < HC) {
+    red[wave][lane][0] = v1;
+    red[wave][lane][1] = v2;
+  }
+  __syncthreads();
+  if (tid < 2 * HC) {
+    const int hk = tid >> 1, w = tid & 1;
+    const int h = u.chunk * HC + hk;
+    if (h < c.n_h) {
+      const double v = ((red[0][hk][w] + red[1][hk][w]) + red[2][hk][w]) + red[3][hk][w];
+      c.part[(int64_t)(2 * h + w) * c.n_items + u.item] = v;
+    }
+  }
+}
+
 // Block per column.  g(h) = h^-1 [2 n^-2 ((4pi)^-1/2 S1 - 2 (2pi)^-1/2 S2) + n^-1 (4pi)^-1/2];
 // gscale with +.  Grid argmin with ties to the lowest index.
 __global__ __launch_bounds__(1024) void k_lscv_finalize(const ColDesc* __restrict__ cols,
@@ -779,8 +908,13 @@ void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColD
   }
 }
 
-void launch_lscv_units(hipStream_t s, int hc, int f64, const ColDesc* cols, const Unit* units, int u0, int n_units) {
+void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, const ColDesc* cols, const Unit* units, int u0,
+                       int n_units) {
   if (n_units <= 0) return;
+  if (mfma && !f64 && hc == 16) {
+    k_lscv_units_mfma<<<n_units, kThreads, 0, s>>>(cols, units, u0);
+    return;
+  }
   if (f64) {
     switch (hc) {
       case 4: k_lscv_units_f64<4><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;

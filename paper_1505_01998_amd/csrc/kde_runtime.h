@@ -104,6 +104,7 @@ struct kde_ctx {
   int64_t opt_seg = -1;            // <0 automatic, 0 whole rows, >0 explicit
   double opt_launch_evals = 4e12;  // pair-term evaluations per launch
   double opt_fp64_kappa = 1e3;
+  int opt_mfma = 0;                // LSCV exponent arguments on the matrix cores (FP32, lscv_hc 16)
   double opt_serve_iter_evals = 1e12;  // server: pair-term evaluations per iteration (minimum)
   // device workspace of synchronous jobs
   kde::DevBuf<char> stage;   // host columns copied in

@@ -506,7 +506,7 @@ kde_status execute(kde_ctx* c, IterPlan& it) {
     kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
     kde_status s2 = timed_begin(c, pd);
     if (s2) return s2;
-    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, cols, lu, u0, cnt);
+    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->opt_mfma, cols, lu, u0, cnt);
     return timed_end(c, pd);
   });
   if (s) return s;
@@ -750,6 +750,8 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_launch_evals = value <= 0 ? 4e12 : (double)value;
   } else if (k == "fp64_kappa") {
     c->opt_fp64_kappa = value < 0 ? 1e3 : (double)value;
+  } else if (k == "lscv_mfma") {
+    c->opt_mfma = value < 0 ? 0 : (value != 0);
   } else if (k == "serve_iter_evals") {
     c->opt_serve_iter_evals = value <= 0 ? 1e12 : (double)value;
   } else {

@@ -153,6 +153,25 @@ def test_lscv_tile_configs_agree(kde, hc, seg):
     check_curve(g, gs, oc, TOL, f"hc={hc} seg={seg}")
 
 
+@pytest.mark.parametrize("family,n", [("mixture", 4099), ("lognormal", 10007), ("bimodal", 65), ("normal", 2),
+                                      ("uniform", 300)])
+def test_lscv_matrix_core_variant(kde, family, n):
+    """The LSCV kernel that forms exponent arguments on the matrix cores meets
+    the same bar (including the masked diagonal, ragged tails and n_h not a
+    multiple of the 16-bandwidth chunk)."""
+    x = workloads.draw(family, n, 70 + n, np.float32)
+    grid = np.geomspace(0.004, 3.0, 41)
+    oc = oracle.lscv_curve(x, grid)
+    with kde.Context(0) as c:
+        c.set_option("lscv_mfma", 1)
+        g, gs, _ = c.lscv_curve(x, grid)
+        s1, s2 = c.lscv_sums(x, grid)
+    check_curve(g, gs, oc, TOL, f"mfma {family} {n}")
+    atol = n * (n - 1) / 2 * 2.0**-126
+    assert np.allclose(s1, oc.s1, rtol=TOL, atol=atol)
+    assert np.allclose(s2, oc.s2, rtol=TOL, atol=atol)
+
+
 def test_lscv_fp64_form(ctx64):
     x = workloads.draw("lognormal", 3333, 12, np.float32)
     grid = np.geomspace(0.003, 2.0, 19)
