@@ -45,19 +45,22 @@ LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 # source they were taken on; reported as null once that source changes.
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
-    "kernels_sha256": "15e425ddff1f835919f6ed65dfd1992272f796e9c7fbe7784d404a3687a72d85",
-    "fetch_bytes": 1.5053e7,
-    "write_bytes": 3.2968e6,
+    "kernel": "k_lscv_units_f32<16>",
+    "kernels_sha256": "10e198d8553feb354de702a945fa753029cf324f9a3206769963cb0612d9ee33",
+    "fetch_bytes": 1.6406e7,
+    "write_bytes": 3.3004e6,
 }
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    passes, or None when the workload, the kernel or its source has changed."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1505_01998_amd", "csrc", "kde_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     t = MEASURED_TRAFFIC
-    if sha != t["kernels_sha256"] or workload != t["workload"]:
+    if sha != t["kernels_sha256"] or workload != t["workload"] or kernel != t["kernel"]:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
 
@@ -328,6 +331,13 @@ def main():
     ms_step = dt * 1e3 / args.steps
     value = evals_step / (ms_step * 1e-3)
     achieved = evals_k / (ms * 1e-3)
+    hc = args.hc if args.hc > 0 else 16
+    if args.precision != "mixed":
+        kernel = "k_lscv_units_f64<8>"
+    elif args.mfma > 0:
+        kernel = "k_lscv_units_mfma"
+    else:
+        kernel = f"k_lscv_units_f32<{hc}>"
     out = {
         "metric": "pair-kernel evals/s (LSCV+plug-in, n=1M)",
         "value": value,
@@ -349,9 +359,9 @@ def main():
             "peak": LSCV_PEAK / 1e12,
             "unit": "Teval/s",
             "frac": achieved / LSCV_PEAK,
-            "traffic": measured_traffic(w.name),
+            "traffic": measured_traffic(w.name, kernel),
             "traffic_unit": "bytes per launch",
-            "kernel": "k_lscv_pairs_f32" if args.precision == "mixed" else "k_lscv_pairs_f64",
+            "kernel": kernel,
             "launches": launches,
             "avg_launch_ms": ms / max(launches, 1),
             "evals_per_launch": evals_k / max(launches, 1),
