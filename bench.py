@@ -65,6 +65,60 @@ def measured_traffic(workload: str, kernel: str):
     return t["fetch_bytes"] + t["write_bytes"]
 
 
+GOLDEN = {"lognormal-1m": os.path.join(ROOT, "tests", "golden", "lognormal_1m_oracle.json")}
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def accuracy(kde, xd, w, h_pi, info, g, gs):
+    """Error of the mixed form (outside the timed region): against the
+    all-FP64 GPU form on the same column (the whole plug-in chain and g(h) at
+    both grid ends, two interior indices and the chosen index +-2), and against
+    the FP64 oracle's stored full-size values where they exist."""
+    m = w.grid.size
+    k = int(np.argmin(g))
+    idx = sorted({0, m // 8, m // 2, m - 1, *[j for j in range(k - 2, k + 3) if 0 <= j < m]})
+    log(f"accuracy: FP64 GPU form, plug-in and g(h) at {len(idx)} grid points")
+    with kde.Context(0, "fp64") as c64:
+        t = time.perf_counter()
+        h64, info64 = c64.bw_plugin(xd, w.stages)
+        g64, gs64, _ = c64.lscv_curve(xd, w.grid[idx])
+        t64 = time.perf_counter() - t
+    win = [j for j in range(k - 2, k + 3) if 0 <= j < m]
+    g64_win = [g64[idx.index(j)] for j in win]
+    stages = range(3 - w.stages, 3)
+    out = {
+        "vs_fp64_gpu": {
+            "psi_order": [8, 6, 4][3 - w.stages:],
+            "psi_rel": [_rel(info.psi[s], info64.psi[s]) for s in stages],
+            "h_plugin_rel": _rel(h_pi, h64),
+            "g_indices": idx,
+            "g_err_over_gscale_max": max(abs(g[j] - g64[a]) / gs64[a] for a, j in enumerate(idx)),
+            "argmin_in_window_same": win[int(np.argmin(g64_win))] == k,
+            "fp64_seconds": t64,
+        },
+        "vs_oracle": None,
+    }
+    path = GOLDEN.get(w.name)
+    if path and os.path.exists(path):
+        ref = json.load(open(path))
+        o = {}
+        if "plugin" in ref:
+            o["psi_rel"] = [_rel(info.psi[s], ref["plugin"]["psi"][s]) for s in stages]
+            o["h_plugin_rel"] = _rel(h_pi, ref["plugin"]["h"])
+            o["fp64_gpu_psi_rel"] = [_rel(info64.psi[s], ref["plugin"]["psi"][s]) for s in stages]
+        pts = {int(j): v for j, v in ref.get("lscv", {}).items() if int(j) in idx}
+        if pts:
+            o["g_indices"] = sorted(pts)
+            o["g_err_over_gscale_max"] = max(abs(g[j] - v["g"]) / v["gscale"] for j, v in pts.items())
+            o["fp64_gpu_g_err_over_gscale_max"] = max(abs(g64[idx.index(j)] - v["g"]) / v["gscale"]
+                                                      for j, v in pts.items())
+        out["vs_oracle"] = o
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -100,6 +154,31 @@ def _requests_of(kde, cols, grid=None, stages=None):
     return [kde.Request(x, A, stages or workloads.BATCH_STAGES, grid or workloads.BATCH_GRID) for x in cols]
 
 
+def _apply_options(ctx, args):
+    if args.hc > 0:
+        ctx.set_option("lscv_hc", args.hc)
+    if args.seg >= 0:
+        ctx.set_option("seg", args.seg)
+    if args.mfma >= 0:
+        ctx.set_option("lscv_mfma", args.mfma)
+    if args.autotune >= 0:
+        ctx.set_option("autotune", args.autotune)
+    if args.graph >= 0:
+        ctx.set_option("graph", args.graph)
+
+
+def _lscv_kernel(ctx, args, n, n_h):
+    """Name of the LSCV kernel the runs used (the autotuner's cached choice for
+    the job's largest column when tuning is on)."""
+    if args.precision != "mixed":
+        return "k_lscv_units_f64<8>"
+    if args.autotune > 0:
+        return f"k_lscv_units_f32<{ctx.autotune(n, n_h)[0]}>"
+    if args.mfma > 0:
+        return "k_lscv_units_mfma"
+    return f"k_lscv_units_f32<{args.hc if args.hc > 0 else 16}>"
+
+
 def batch_bench(args):
     """512 uneven columns as one kde_batch job vs one call per column."""
     import torch
@@ -113,6 +192,7 @@ def batch_bench(args):
     n_h = workloads.BATCH_GRID[3]
     evals = sum(s.n * (s.n - 1) / 2 * (n_h + workloads.BATCH_STAGES) for s in specs)
     ctx = kde.Context(0, args.precision)
+    _apply_options(ctx, args)
     for i in range(args.warmup):
         log(f"warmup {i + 1}/{args.warmup}")
         ctx.batch(reqs)
@@ -132,6 +212,7 @@ def batch_bench(args):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     log(f"plain per-column calls done in {t_plain:.1f} s")
+    kernel = _lscv_kernel(ctx, args, max(s.n for s in specs), n_h)
     ctx.close()
     achieved = evals_k / (ms * 1e-3)
     return {
@@ -142,12 +223,13 @@ def batch_bench(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": "batch-512", "columns": len(specs), "n_range": [1000, 200000], "n_h": n_h,
-                   "plugin_stages": workloads.BATCH_STAGES, "precision": args.precision},
+                   "plugin_stages": workloads.BATCH_STAGES, "precision": args.precision,
+                   "autotune": args.autotune > 0},
         "columns_per_s": len(specs) / t_batch,
         "plain": {"columns_per_s": len(specs) / t_plain, "value": evals / t_plain, "seconds": t_plain},
         "speedup_vs_plain": t_plain / t_batch,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": LSCV_PEAK / 1e12, "unit": "Teval/s",
-                     "frac": achieved / LSCV_PEAK, "traffic": None, "kernel": "k_lscv_units_f32",
+                     "frac": achieved / LSCV_PEAK, "traffic": None, "kernel": kernel,
                      "launches": launches, "avg_launch_ms": ms / max(launches, 1)},
     }
 
@@ -219,6 +301,7 @@ def served_bench(args):
 
     out = {}
     ctx = kde.Context(0, args.precision)
+    _apply_options(ctx, args)
     ctx.batch(reqs[:1])  # warm-up: code objects, allocations
     arrivals = [a.t for a in stream]
     log("plain at the stream's arrival times")
@@ -261,9 +344,15 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--accuracy", type=int, default=1,
+                    help="compare the mixed form with the all-FP64 GPU form after the timed steps (1/0)")
     ap.add_argument("--hc", type=int, default=-1, help="bandwidths per LSCV pass (8, 16, 32; -1 = default)")
     ap.add_argument("--seg", type=int, default=-1, help="j-range per work item (-1 = automatic, 0 = whole rows)")
     ap.add_argument("--mfma", type=int, default=-1, help="LSCV arguments on the matrix cores (1/0; -1 = default)")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="replay captured HIP graphs of repeated jobs (1/0; -1 = default, off)")
+    ap.add_argument("--autotune", type=int, default=-1,
+                    help="pick the LSCV variant with the tile autotuner (1/0; -1 = default, off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -301,43 +390,43 @@ def main():
     xd = torch.from_numpy(x).to("cuda:0")
     torch.cuda.synchronize()
     ctx = kde.Context(0, args.precision)
-    if args.hc > 0:
-        ctx.set_option("lscv_hc", args.hc)
-    if args.seg >= 0:
-        ctx.set_option("seg", args.seg)
-    if args.mfma >= 0:
-        ctx.set_option("lscv_mfma", args.mfma)
+    _apply_options(ctx, args)
 
     def step():
         h_pi, info = ctx.bw_plugin(xd, w.stages)
         g, gs, _ = ctx.lscv_curve(xd, w.grid)
-        return h_pi, info, g
+        return h_pi, info, g, gs
 
     for i in range(args.warmup):
         log(f"warmup step {i + 1}/{args.warmup}")
         step()
-    ctx.set_timing(True)
+    # kernel timing brackets every launch with events, which the graph option
+    # does not capture; with graphs the kernels are timed on one extra
+    # (eager) step after the timed region
+    use_graph = args.graph > 0
+    if not use_graph:
+        ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        h_pi, info, g = step()
-        log(f"timed step {i + 1}/{args.steps} done")
+        h_pi, info, g, gs = step()
+        if args.steps <= 20 or (i + 1) % 50 == 0:
+            log(f"timed step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    graph_stats = ctx.graph_stats()
+    if use_graph:
+        ctx.set_timing(True)
+        step()
+        torch.cuda.synchronize()
     launches, ms, evals_k = ctx.kernel_time("lscv_pairs")
     p_launches, p_ms, p_evals = ctx.kernel_time("psi_pairs")
+    kernel = _lscv_kernel(ctx, args, n, n_h)
     ctx.close()
 
     ms_step = dt * 1e3 / args.steps
     value = evals_step / (ms_step * 1e-3)
     achieved = evals_k / (ms * 1e-3)
-    hc = args.hc if args.hc > 0 else 16
-    if args.precision != "mixed":
-        kernel = "k_lscv_units_f64<8>"
-    elif args.mfma > 0:
-        kernel = "k_lscv_units_mfma"
-    else:
-        kernel = f"k_lscv_units_f32<{hc}>"
     out = {
         "metric": "pair-kernel evals/s (LSCV+plug-in, n=1M)",
         "value": value,
@@ -352,7 +441,8 @@ def main():
         "dtype": "f32" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "family": w.family, "n": n, "n_h": n_h, "plugin_stages": w.stages,
-                   "precision": args.precision, "input_dtype": str(np.dtype(w.dtype))},
+                   "precision": args.precision, "input_dtype": str(np.dtype(w.dtype)), "autotune": args.autotune > 0,
+                   "graph": use_graph, "graph_captures_replays": list(graph_stats)},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -370,6 +460,8 @@ def main():
         "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals},
         "result": {"h_plugin": h_pi, "h_lscv": float(w.grid[int(np.argmin(g))]), "k_lscv": int(np.argmin(g))},
     }
+    if args.accuracy and args.precision == "mixed":
+        out["accuracy"] = accuracy(kde, xd, w, h_pi, info, g, gs)
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, x, args.cpu_budget)
     print(json.dumps(out), flush=True)

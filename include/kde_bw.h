@@ -117,8 +117,49 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
  *                  iteration (an iteration also holds at least six rounds of
  *                  1024 blocks of its largest work unit)
+ *   "autotune"     1: synchronous calls and kde_batch run the LSCV pass with
+ *                  the bandwidths per block that kde_autotune measured fastest
+ *                  for the job's largest LSCV column (tuning that shape on
+ *                  first use when the job holds at least 1e13 pair-term
+ *                  evaluations; smaller jobs use a cached decision or
+ *                  lscv_hc).  Results are bitwise those of any lscv_hc.
+ *   "graph"        1: the kernel launches of a synchronous call or kde_batch
+ *                  are captured into a HIP graph; a later call with the same
+ *                  signature (per request: validity, n, dtype, host/device,
+ *                  methods, stages, grid kind and size, log-grid range; the
+ *                  options) replays it instead of planning and launching
+ *                  again.  Samples, grid values and device column addresses
+ *                  are copied in around the graph, so a replay computes on the
+ *                  new inputs; results are bitwise those without the option.
+ *                  Up to 8 graphs are kept per context (least recently used
+ *                  replaced); a graph whose device buffers were reallocated
+ *                  by a larger job is captured again.  Inactive while timing
+ *                  is on or when the context runs on the null stream.
  * Unknown keys give KDE_E_INVAL. */
 kde_status kde_ctx_set_option(kde_ctx* ctx, const char* key, int64_t value);
+
+/* Counters of the "graph" option since the context was created: jobs whose
+ * launches were captured into a new graph, and jobs that replayed one. */
+kde_status kde_ctx_graph_stats(kde_ctx* ctx, int64_t* captures, int64_t* replays);
+
+/* Tile autotuner of the LSCV pair pass (eq. LSCV-gh over a grid, every h
+ * from one pair distance as in Section 4.5).  Times the vector-ALU kernel
+ * with 8, 16 and 32 bandwidths per block on trial launches shaped like a
+ * column of n samples with an n_h-point grid (the planner's longest work
+ * items, about 0.05 s of work each, on an all-zero column in buffers of the
+ * context) and caches the fastest per shape (quarter octave of n, n_h) in the
+ * context; the default 16 is kept unless another is 2% faster.  The variant
+ * never changes a result: items and summation order do not depend on it.
+ * out->hc receives the choice, out->evals_per_s the measured rates (pair-term
+ * evaluations per second for 8, 16, 32).  A cached shape returns at once.
+ * KDE_E_INVAL for n outside [2, KDE_MAX_N], n_h outside [1, KDE_MAX_NH] or a
+ * context in FP64 precision; KDE_E_BUSY while a server runs. */
+typedef struct {
+  int32_t hc;
+  int32_t pad0;
+  double evals_per_s[3];
+} kde_tune_info;
+kde_status kde_autotune(kde_ctx* ctx, int64_t n, int32_t n_h, kde_tune_info* out);
 
 /* Kernel timing.  While enabled, every launch of the pair kernels is bracketed
  * by HIP events on the stream it runs on.  kde_ctx_kernel_time reports, for

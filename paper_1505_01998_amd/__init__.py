@@ -45,7 +45,8 @@ EXPORTS = (
     "kde_ctx_create", "kde_ctx_destroy", "kde_last_error", "kde_ctx_set_stream", "kde_ctx_set_precision",
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
-    "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop",
+    "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
+    "kde_ctx_graph_stats",
 )
 
 
@@ -71,6 +72,10 @@ class kde_plugin_info(ctypes.Structure):
         ("precision_used", ctypes.c_int * 3),
         ("h", ctypes.c_double),
     ]
+
+
+class kde_tune_info(ctypes.Structure):
+    _fields_ = [("hc", ctypes.c_int32), ("pad0", ctypes.c_int32), ("evals_per_s", ctypes.c_double * 3)]
 
 
 class kde_grid(ctypes.Structure):
@@ -139,6 +144,8 @@ def _load():
     lib.kde_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result)]
     lib.kde_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result), ctypes.c_double]
     lib.kde_server_stop.argtypes = [P]
+    lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
+    lib.kde_ctx_graph_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     for name in EXPORTS:
         if name not in ("kde_ctx_destroy", "kde_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -227,6 +234,23 @@ def kde_ctx_kernel_time(ctx, family: str):
     ev = ctypes.c_double()
     _check(ctx, lib.kde_ctx_kernel_time(ctx, family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ev)))
     return n.value, ms.value, ev.value
+
+
+def kde_ctx_graph_stats(ctx):
+    """(captures, replays) of the graph option."""
+    a = ctypes.c_int64()
+    b = ctypes.c_int64()
+    _check(ctx, lib.kde_ctx_graph_stats(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def kde_autotune(ctx, n: int, n_h: int):
+    """(hc, {8: rate, 16: rate, 32: rate}) -- the LSCV variant the tile autotuner
+    picks for a column of n samples and an n_h-point grid, with the measured
+    pair-term evaluations per second of each."""
+    t = kde_tune_info()
+    _check(ctx, lib.kde_autotune(ctx, int(n), int(n_h), ctypes.byref(t)))
+    return t.hc, {8: t.evals_per_s[0], 16: t.evals_per_s[1], 32: t.evals_per_s[2]}
 
 
 def kde_bw_rot(ctx, x) -> float:
@@ -477,6 +501,12 @@ class Context:
 
     def bw_plugin(self, x, stages=2):
         return kde_bw_plugin(self.ctx, x, stages)
+
+    def autotune(self, n, n_h):
+        return kde_autotune(self.ctx, n, n_h)
+
+    def graph_stats(self):
+        return kde_ctx_graph_stats(self.ctx)
 
     def lscv_curve(self, x, h_grid=None, n_h=0):
         return kde_lscv_curve(self.ctx, x, h_grid, n_h)

@@ -6,6 +6,7 @@
 
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -85,6 +86,43 @@ struct IterPlan {
   void clear();
 };
 
+// Byte offsets of one executor pass's arrays in the device blob.
+struct PassLayout {
+  size_t o_cols = 0, o_stats = 0, o_pf = 0, o_lp = 0, o_lu = 0, o_lr = 0, o_lf = 0, bytes = 0;
+  size_t o_begin[3] = {0, 0, 0}, o_finish[3] = {0, 0, 0}, o_pu[3] = {0, 0, 0}, o_pr[3] = {0, 0, 0},
+         o_pc[3] = {0, 0, 0};
+};
+
+// Executable graph of a synchronous job (graph option): the job's kernel
+// launches, captured once and replayed for later jobs of the same signature
+// (request shapes, methods, grids and options).  Only launches are in the
+// graph; inputs, the blob and the states are copied around it, so a replay
+// sees new samples, grid values and device column addresses.  Jobs run one
+// at a time on the context's stream, so graphs of different jobs share the
+// context's device buffers.
+struct JobGraph {
+  std::string sig;
+  uint64_t last_use = 0;
+  hipGraphExec_t exec = nullptr;
+  const void* blocks = nullptr;  // device buffers the graph's kernels address
+  const void* st = nullptr;
+  const void* blob = nullptr;
+  std::vector<ColPlan> plans;
+  std::vector<int> plan_req;
+  std::vector<ColDesc> cols;
+  std::vector<char> blob_host;  // packed blob of the captured pass
+  PassLayout L;
+  void reset();
+};
+
+constexpr size_t kMaxGraphs = 8;
+
+// Variant of the LSCV pass chosen by the tile autotuner for one shape.
+struct TuneChoice {
+  int hc = 16;                 // bandwidths per block (8, 16, 32)
+  double rate[3] = {0, 0, 0};  // measured evals/s of hc 8, 16, 32
+};
+
 struct Server;
 struct ServerDeleter {
   void operator()(Server* s) const;  // kde_server.hip
@@ -106,6 +144,17 @@ struct kde_ctx {
   double opt_fp64_kappa = 1e3;
   int opt_mfma = 0;                // LSCV exponent arguments on the matrix cores (FP32, lscv_hc 16)
   double opt_serve_iter_evals = 1e12;  // server: pair-term evaluations per iteration (minimum)
+  int opt_autotune = 0;            // synchronous jobs pick the LSCV variant with the tile autotuner
+  int opt_graph = 0;               // synchronous jobs replay a captured graph of their launches
+  std::vector<kde::JobGraph> graphs;  // at most kde::kMaxGraphs, least recently used replaced
+  uint64_t graph_clock = 0;
+  int64_t graph_captures = 0, graph_replays = 0;
+  // LSCV variant of the current job (from the options, or the autotuner)
+  int job_hc = 16;
+  int job_mfma = 0;
+  // autotuner: decisions per shape (quarter-octave bucket of n, n_h) and its trial buffer
+  std::map<std::pair<int, int>, kde::TuneChoice> tune_cache;
+  kde::DevBuf<char> tune_buf;
   // device workspace of synchronous jobs
   kde::DevBuf<char> stage;   // host columns copied in
   kde::DevBuf<char> blocks;  // per-column device blocks, packed
@@ -146,6 +195,21 @@ kde_status fail(kde_ctx* c, kde_status st, const std::string& msg);
 kde_status status_of(int st);
 std::string check_column(const kde_column& x);
 std::string check_grid(const kde_grid& g);
+// Argument check of one request (column, stages, grid); "" when valid.
+std::string check_request(const kde_request& r);
+// Bandwidths per block that LSCV work items are sized for, whatever variant runs.
+constexpr int kSegRefHC = 16;
+// Work items of a column of n samples for items of `seg` samples (0: whole rows).
+void make_items(int64_t n, int64_t seg, ColItems& out);
+// Item length of a pass whose blocks evaluate `hc` terms per pair.
+int64_t pick_seg(const kde_ctx* c, int64_t n, int hc);
+// Sets c->job_hc / job_mfma for a synchronous job over these requests: the
+// options, or with the autotune option the tuned vector-ALU variant of the
+// job's largest LSCV column (tuning that shape first when the job is large).
+kde_status select_variant(kde_ctx* c, const kde_request* reqs, int32_t n_req);
+// Times the LSCV variants on a column of n samples and an n_h-point grid (or
+// returns the cached decision for that shape).
+kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out);
 // Fills the work decomposition and block layout of one request's column.
 std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p);
 // Points a descriptor at a column block; raw is the caller's device column
@@ -165,7 +229,13 @@ void init_state(const ColPlan& p, double fp64_kappa, DevState& h);
 void init_result(kde_result& r, kde_status st);
 // Copies a finished column's scalar results (status, h's, plug-in info) into r.
 void fill_result(const ColPlan& p, const DevState& h, kde_result& r);
-// Enqueues one executor pass on the context's stream (no synchronisation).
+// Enqueues one executor pass on the context's stream (no synchronisation):
+// pack_pass sorts the units and packs the blob in pinned memory,
+// upload_pass copies inputs and the blob, launch_pass enqueues the kernels
+// (launches only, so it can be captured into a graph).
+kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L);
+kde_status upload_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
+kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status execute(kde_ctx* c, IterPlan& it);
 kde_status sync_and_check(kde_ctx* c);
 kde_status ensure_pinned_bytes(kde_ctx* c, char*& p, size_t& cap, size_t bytes);

@@ -109,8 +109,6 @@ std::string check_grid(const kde_grid& g) {
   return "";
 }
 
-namespace {
-
 // ---- work items
 double item_pairs(int64_t n, int64_t row, int64_t jb, int64_t je) {
   const int64_t i0 = row * kBI;
@@ -160,6 +158,9 @@ void make_items(int64_t n, int64_t seg, ColItems& out) {
 }
 
 // Item length for a pass whose blocks each evaluate `hc` terms per pair.
+// The LSCV pass sizes its items for kSegRefHC bandwidths per block whatever
+// variant runs, so the items, and with them every sum's order, do not depend
+// on the variant.
 int64_t pick_seg(const kde_ctx* c, int64_t n, int hc) {
   if (c->opt_seg >= 0) return c->opt_seg == 0 ? 0 : (c->opt_seg + kBJ - 1) / kBJ * kBJ;
   // Aim for ~8192 blocks per launch so each launch fills the chip many times.
@@ -170,6 +171,8 @@ int64_t pick_seg(const kde_ctx* c, int64_t n, int hc) {
   return seg;
 }
 
+namespace {
+
 size_t take(size_t& at, size_t bytes) {
   const size_t o = at;
   at += (bytes + 255) / 256 * 256;
@@ -178,19 +181,24 @@ size_t take(size_t& at, size_t bytes) {
 
 }  // namespace
 
-std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
+std::string check_request(const kde_request& r) {
   std::string e = check_column(r.x);
+  if (e.empty() && (r.methods & KDE_METHOD_PLUGIN) && r.stages != 2 && r.stages != 3) e = "stages must be 2 or 3";
+  if (e.empty() && (r.methods & KDE_METHOD_LSCV)) e = check_grid(r.grid);
+  return e;
+}
+
+std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
+  std::string e = check_request(r);
   p = ColPlan();
   p.plugin = (r.methods & KDE_METHOD_PLUGIN) != 0;
   p.lscv = (r.methods & KDE_METHOD_LSCV) != 0;
-  if (e.empty() && p.plugin && r.stages != 2 && r.stages != 3) e = "stages must be 2 or 3";
-  if (e.empty() && p.lscv) e = check_grid(r.grid);
   if (!e.empty()) return e;
   const bool all64 = c->prec == KDE_PREC_FP64;
   p.n = (int)r.x.n;
   p.f64 = r.x.dtype == KDE_F64;
   p.stages = p.plugin ? r.stages : 0;
-  p.hc = all64 ? 8 : c->opt_hc;
+  p.hc = all64 ? 8 : c->job_hc;
   if (p.plugin) make_items(p.n, pick_seg(c, p.n, 1), p.psi_items);
   if (p.lscv) {
     p.n_h = r.grid.n_h;
@@ -199,7 +207,7 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
     p.grid_lo = r.grid.lo;
     p.grid_hi = r.grid.hi;
     if (r.grid.kind == KDE_GRID_EXPLICIT) p.grid_h.assign(r.grid.h, r.grid.h + p.n_h);
-    make_items(p.n, pick_seg(c, p.n, p.hc), p.lscv_items);
+    make_items(p.n, pick_seg(c, p.n, kSegRefHC), p.lscv_items);
   }
   p.want_x64 = all64 || (p.plugin && c->opt_fp64_kappa > 0.0);
   p.raw_in_block = !r.x.on_device;
@@ -429,9 +437,8 @@ kde_status sync_and_check(kde_ctx* c) {
   return collect_timing(c);
 }
 
-kde_status execute(kde_ctx* c, IterPlan& it) {
+kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
   kde_status s;
-  const bool all64 = c->prec == KDE_PREC_FP64;
   for (int q = 0; q < 3; ++q) {
     sort_units(it.psi_units[q], it.psi_cost[q]);
     sort_units(it.psi_cond_units[q], it.psi_cond_cost[q]);
@@ -440,40 +447,50 @@ kde_status execute(kde_ctx* c, IterPlan& it) {
   // one blob: column table, id lists, units, rows
   Blob b;
   auto vbytes = [](const auto& v) { return v.size() * sizeof(v[0]); };
-  const size_t o_cols = b.add(it.cols.data(), vbytes(it.cols));
-  const size_t o_stats = b.add(it.ids_stats.data(), vbytes(it.ids_stats));
-  size_t o_begin[3], o_finish[3], o_pu[3], o_pr[3], o_pc[3];
+  L.o_cols = b.add(it.cols.data(), vbytes(it.cols));
+  L.o_stats = b.add(it.ids_stats.data(), vbytes(it.ids_stats));
   for (int q = 0; q < 3; ++q) {
-    o_begin[q] = b.add(it.ids_begin[q].data(), vbytes(it.ids_begin[q]));
-    o_finish[q] = b.add(it.ids_finish[q].data(), vbytes(it.ids_finish[q]));
-    o_pu[q] = b.add(it.psi_units[q].data(), vbytes(it.psi_units[q]));
-    o_pr[q] = b.add(it.psi_rows[q].data(), vbytes(it.psi_rows[q]));
-    o_pc[q] = b.add(it.psi_cond_units[q].data(), vbytes(it.psi_cond_units[q]));
+    L.o_begin[q] = b.add(it.ids_begin[q].data(), vbytes(it.ids_begin[q]));
+    L.o_finish[q] = b.add(it.ids_finish[q].data(), vbytes(it.ids_finish[q]));
+    L.o_pu[q] = b.add(it.psi_units[q].data(), vbytes(it.psi_units[q]));
+    L.o_pr[q] = b.add(it.psi_rows[q].data(), vbytes(it.psi_rows[q]));
+    L.o_pc[q] = b.add(it.psi_cond_units[q].data(), vbytes(it.psi_cond_units[q]));
   }
-  const size_t o_pf = b.add(it.ids_plugin_final.data(), vbytes(it.ids_plugin_final));
-  const size_t o_lp = b.add(it.ids_lscv_prep.data(), vbytes(it.ids_lscv_prep));
-  const size_t o_lu = b.add(it.lscv_units.data(), vbytes(it.lscv_units));
-  const size_t o_lr = b.add(it.lscv_rows.data(), vbytes(it.lscv_rows));
-  const size_t o_lf = b.add(it.ids_lscv_final.data(), vbytes(it.ids_lscv_final));
+  L.o_pf = b.add(it.ids_plugin_final.data(), vbytes(it.ids_plugin_final));
+  L.o_lp = b.add(it.ids_lscv_prep.data(), vbytes(it.ids_lscv_prep));
+  L.o_lu = b.add(it.lscv_units.data(), vbytes(it.lscv_units));
+  L.o_lr = b.add(it.lscv_rows.data(), vbytes(it.lscv_rows));
+  L.o_lf = b.add(it.ids_lscv_final.data(), vbytes(it.ids_lscv_final));
+  L.bytes = b.bytes;
   if ((s = ensure_pinned_bytes(c, c->h_blob, c->h_blob_cap, b.bytes + 256))) return s;
   if ((s = ensure(c, c->blob, b.bytes + 256))) return s;
   for (size_t k = 0; k < b.parts.size(); ++k)
     if (b.parts[k].second) std::memcpy(c->h_blob + b.offs[k], b.parts[k].first, b.parts[k].second);
+  return KDE_OK;
+}
+
+kde_status upload_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
   for (const kde::Upload& u : it.uploads)
     if (u.bytes) KDE_HIP_TRY(c, hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, c->stream));
-  KDE_HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->h_blob, b.bytes, hipMemcpyHostToDevice, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->h_blob, L.bytes, hipMemcpyHostToDevice, c->stream));
+  return KDE_OK;
+}
+
+kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
+  kde_status s;
+  const bool all64 = c->prec == KDE_PREC_FP64;
   char* d = c->blob.p;
-  const ColDesc* cols = (const ColDesc*)(d + o_cols);
+  const ColDesc* cols = (const ColDesc*)(d + L.o_cols);
   auto ids = [&](size_t o) { return (const int*)(d + o); };
   hipStream_t st = c->stream;
   // moments
-  kde::launch_stats(st, cols, ids(o_stats), (int)it.ids_stats.size(), it.max_stat_blocks);
+  kde::launch_stats(st, cols, ids(L.o_stats), (int)it.ids_stats.size(), it.max_stat_blocks);
   // plug-in stages
   for (int q = 0; q < 3; ++q) {
     if (it.ids_begin[q].empty() && it.psi_units[q].empty() && it.ids_finish[q].empty()) continue;
     const int r = 8 - 2 * q;
-    kde::launch_psi_begin(st, cols, ids(o_begin[q]), (int)it.ids_begin[q].size(), q);
-    const Unit* pu = (const Unit*)(d + o_pu[q]);
+    kde::launch_psi_begin(st, cols, ids(L.o_begin[q]), (int)it.ids_begin[q].size(), q);
+    const Unit* pu = (const Unit*)(d + L.o_pu[q]);
     s = for_each_launch(c, it.psi_cost[q], all64, [&](int u0, int cnt, double evals) -> kde_status {
       kde_ctx::Pending pd{nullptr, nullptr, kde::kFamPsi, evals};
       kde_status s2 = timed_begin(c, pd);
@@ -482,38 +499,57 @@ kde_status execute(kde_ctx* c, IterPlan& it) {
       return timed_end(c, pd);
     });
     if (s) return s;
-    kde::launch_reduce_rows(st, (const RowDesc*)(d + o_pr[q]), (int)it.psi_rows[q].size());
-    kde::launch_psi_finish(st, cols, ids(o_finish[q]), (int)it.ids_finish[q].size(), q, all64 ? 1 : 0, 0);
+    kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_pr[q]), (int)it.psi_rows[q].size());
+    kde::launch_psi_finish(st, cols, ids(L.o_finish[q]), (int)it.ids_finish[q].size(), q, all64 ? 1 : 0, 0);
     if (!all64 && !it.psi_cond_units[q].empty()) {
       // FP64 re-run of the columns whose stage is badly conditioned; blocks of
       // other columns exit at once, so these launches are not timed.
-      const Unit* pc = (const Unit*)(d + o_pc[q]);
+      const Unit* pc = (const Unit*)(d + L.o_pc[q]);
       s = for_each_launch(c, it.psi_cond_cost[q], true, [&](int u0, int cnt, double) -> kde_status {
         kde::launch_psi_units(st, r, 1, 1, cols, pc, u0, cnt);
         return KDE_OK;
       });
       if (s) return s;
-      kde::launch_reduce_rows(st, (const RowDesc*)(d + o_pr[q]), (int)it.psi_rows[q].size());
-      kde::launch_psi_finish(st, cols, ids(o_finish[q]), (int)it.ids_finish[q].size(), q, 1, 1);
+      kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_pr[q]), (int)it.psi_rows[q].size());
+      kde::launch_psi_finish(st, cols, ids(L.o_finish[q]), (int)it.ids_finish[q].size(), q, 1, 1);
     }
   }
-  kde::launch_plugin_final(st, cols, ids(o_pf), (int)it.ids_plugin_final.size());
+  kde::launch_plugin_final(st, cols, ids(L.o_pf), (int)it.ids_plugin_final.size());
   // LSCV
-  const int hc = all64 ? 8 : c->opt_hc;
-  kde::launch_lscv_prep(st, cols, ids(o_lp), (int)it.ids_lscv_prep.size(), hc);
-  const Unit* lu = (const Unit*)(d + o_lu);
+  const int hc = all64 ? 8 : c->job_hc;
+  kde::launch_lscv_prep(st, cols, ids(L.o_lp), (int)it.ids_lscv_prep.size(), hc);
+  const Unit* lu = (const Unit*)(d + L.o_lu);
   s = for_each_launch(c, it.lscv_cost, all64, [&](int u0, int cnt, double evals) -> kde_status {
     kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
     kde_status s2 = timed_begin(c, pd);
     if (s2) return s2;
-    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->opt_mfma, cols, lu, u0, cnt);
+    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->job_mfma, cols, lu, u0, cnt);
     return timed_end(c, pd);
   });
   if (s) return s;
-  kde::launch_reduce_rows(st, (const RowDesc*)(d + o_lr), (int)it.lscv_rows.size());
-  kde::launch_lscv_finalize(st, cols, ids(o_lf), (int)it.ids_lscv_final.size());
+  kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_lr), (int)it.lscv_rows.size());
+  kde::launch_lscv_finalize(st, cols, ids(L.o_lf), (int)it.ids_lscv_final.size());
   KDE_HIP_TRY(c, hipGetLastError());
   return KDE_OK;
+}
+
+kde_status execute(kde_ctx* c, IterPlan& it) {
+  PassLayout L;
+  kde_status s;
+  if ((s = pack_pass(c, it, L))) return s;
+  if ((s = upload_pass(c, it, L))) return s;
+  return launch_pass(c, it, L);
+}
+
+void JobGraph::reset() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  exec = nullptr;
+  last_use = 0;
+  sig.clear();
+  plans.clear();
+  plan_req.clear();
+  cols.clear();
+  blob_host.clear();
 }
 
 }  // namespace kde
@@ -539,13 +575,147 @@ kde_status busy(kde_ctx* c) {
 
 bool serving(const kde_ctx* c) { return c->server && kde::server_running(c->server.get()); }
 
+// ---- graph replay of repeated jobs
+// Everything a job's kernel launches depend on besides the device buffers:
+// the options, and per request its validity, shape, methods and grid kind.
+std::string job_signature(const kde_ctx* c, const kde_request* reqs, int32_t n_req,
+                          const std::vector<kde_status>& st) {
+  std::string sig;
+  auto put = [&](const auto& v) { sig.append(reinterpret_cast<const char*>(&v), sizeof(v)); };
+  put(n_req);
+  put(c->prec);
+  put(c->job_hc);
+  put(c->job_mfma);
+  put(c->opt_seg);
+  put(c->opt_launch_evals);
+  put(c->opt_fp64_kappa);
+  for (int32_t k = 0; k < n_req; ++k) {
+    const kde_request& r = reqs[k];
+    const int ok = st[k] == KDE_OK;
+    put(ok);
+    if (!ok) continue;
+    put(r.x.n);
+    put(r.x.dtype);
+    put(r.x.on_device);
+    put(r.methods);
+    if (r.methods & KDE_METHOD_PLUGIN) put(r.stages);
+    if (r.methods & KDE_METHOD_LSCV) {
+      put(r.grid.kind);
+      put(r.grid.n_h);
+      if (r.grid.kind == KDE_GRID_LOG_ROT) {
+        put(r.grid.lo);
+        put(r.grid.hi);
+      }
+    }
+  }
+  return sig;
+}
+
+// Replays the cached graph for a job of the same signature: new samples,
+// grids and device column addresses go in through the copies around it.
+kde_status replay_job(kde_ctx* c, kde::JobGraph& g, const kde_request* reqs) {
+  g.last_use = ++c->graph_clock;
+  kde_status s;
+  c->plans = g.plans;
+  c->plan_req = g.plan_req;
+  c->iter.clear();
+  c->iter.cols = g.cols;
+  const int n_cols = (int)c->plans.size();
+  char* hs = reinterpret_cast<char*>(c->h_st);
+  if ((s = kde::ensure_pinned_bytes(c, hs, c->h_st_cap, sizeof(DevState) * n_cols))) return s;
+  c->h_st = reinterpret_cast<DevState*>(hs);
+  if ((s = kde::ensure_pinned_bytes(c, c->h_blob, c->h_blob_cap, g.blob_host.size()))) return s;
+  std::memcpy(c->h_blob, g.blob_host.data(), g.blob_host.size());
+  for (int k = 0; k < n_cols; ++k) {
+    kde::ColPlan& p = c->plans[k];
+    const kde_request& r = reqs[c->plan_req[k]];
+    ColDesc& d = c->iter.cols[k];
+    if (p.raw_in_block)
+      KDE_HIP_TRY(c, hipMemcpyAsync((void*)d.raw, r.x.data, p.raw_bytes, hipMemcpyHostToDevice, c->stream));
+    else
+      d.raw = r.x.data;
+    if (p.lscv && p.grid_kind == KDE_GRID_EXPLICIT) {
+      p.grid_h.assign(r.grid.h, r.grid.h + p.n_h);
+      KDE_HIP_TRY(c, hipMemcpyAsync((void*)d.h_in, p.grid_h.data(), sizeof(double) * p.n_h, hipMemcpyHostToDevice,
+                                    c->stream));
+    }
+    kde::init_state(p, c->opt_fp64_kappa, c->h_st[k]);
+  }
+  std::memcpy(c->h_blob + g.L.o_cols, c->iter.cols.data(), sizeof(ColDesc) * n_cols);
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(DevState) * n_cols, hipMemcpyHostToDevice, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->blob.p, c->h_blob, g.L.bytes, hipMemcpyHostToDevice, c->stream));
+  KDE_HIP_TRY(c, hipGraphLaunch(g.exec, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(DevState) * n_cols, hipMemcpyDeviceToHost, c->stream));
+  ++c->graph_replays;
+  return KDE_OK;
+}
+
+// Enqueues a planned pass with its launches captured into a graph, keeps the
+// graph for later jobs of the same signature and launches it.
+kde_status capture_job(kde_ctx* c, std::string sig) {
+  kde_status s;
+  if (c->graphs.size() < kde::kMaxGraphs) c->graphs.emplace_back();
+  kde::JobGraph* lru = &c->graphs[0];
+  for (kde::JobGraph& x : c->graphs)
+    if (x.last_use < lru->last_use) lru = &x;
+  kde::JobGraph& g = *lru;
+  g.reset();
+  g.last_use = ++c->graph_clock;
+  kde::PassLayout L;
+  if ((s = kde::pack_pass(c, c->iter, L))) return s;
+  if ((s = kde::upload_pass(c, c->iter, L))) return s;
+  KDE_HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  const kde_status ls = kde::launch_pass(c, c->iter, L);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+  if (ls || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ls) return ls;
+    return fail(c, KDE_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(c, KDE_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+  g.exec = exec;
+  g.sig = std::move(sig);
+  g.blocks = c->blocks.p;
+  g.st = c->st.p;
+  g.blob = c->blob.p;
+  g.plans = c->plans;
+  g.plan_req = c->plan_req;
+  g.cols = c->iter.cols;
+  g.blob_host.assign(c->h_blob, c->h_blob + L.bytes);
+  g.L = L;
+  KDE_HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+  ++c->graph_captures;
+  return KDE_OK;
+}
+
 // Plans and enqueues a synchronous job over n_req requests; per-request
 // argument errors land in st/msg.  The states' copy back is enqueued last.
+// With the graph option (and timing off, on a non-null stream) the job's
+// launches come from a graph: replayed when a kept graph has the job's
+// signature and the device buffers did not move, captured otherwise.
 kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std::vector<kde_status>& st,
                         std::vector<std::string>& msg) {
   kde_status s;
   st.assign(n_req, KDE_OK);
   msg.assign(n_req, "");
+  if ((s = kde::select_variant(c, reqs, n_req))) return s;
+  const bool use_graph = c->opt_graph && !c->timing && c->stream != nullptr;
+  std::string sig;
+  if (use_graph) {
+    for (int32_t k = 0; k < n_req; ++k) {
+      msg[k] = kde::check_request(reqs[k]);
+      if (!msg[k].empty()) st[k] = KDE_E_INVAL;
+    }
+    sig = job_signature(c, reqs, n_req, st);
+    for (kde::JobGraph& g : c->graphs)
+      if (g.exec && g.sig == sig && g.blocks == c->blocks.p && g.st == c->st.p && g.blob == c->blob.p &&
+          !g.plans.empty())
+        return replay_job(c, g, reqs);
+  }
   c->plans.clear();
   c->plan_req.clear();
   for (int32_t k = 0; k < n_req; ++k) {
@@ -583,7 +753,11 @@ kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std:
     kde::init_state(p, c->opt_fp64_kappa, c->h_st[k]);
   }
   KDE_HIP_TRY(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(DevState) * n_cols, hipMemcpyHostToDevice, c->stream));
-  if ((s = kde::execute(c, it))) return s;
+  if (use_graph)
+    s = capture_job(c, std::move(sig));
+  else
+    s = kde::execute(c, it);
+  if (s) return s;
   KDE_HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(DevState) * n_cols, hipMemcpyDeviceToHost, c->stream));
   return KDE_OK;
 }
@@ -704,6 +878,8 @@ void kde_ctx_destroy(kde_ctx* c) {
   (void)hipFree(c->blocks.p);
   (void)hipFree(c->st.p);
   (void)hipFree(c->blob.p);
+  (void)hipFree(c->tune_buf.p);
+  for (kde::JobGraph& g : c->graphs) g.reset();
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_out) (void)hipHostFree(c->h_out);
   if (c->h_blob) (void)hipHostFree(c->h_blob);
@@ -752,11 +928,22 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_fp64_kappa = value < 0 ? 1e3 : (double)value;
   } else if (k == "lscv_mfma") {
     c->opt_mfma = value < 0 ? 0 : (value != 0);
+  } else if (k == "graph") {
+    c->opt_graph = value < 0 ? 0 : (value != 0);
+  } else if (k == "autotune") {
+    c->opt_autotune = value < 0 ? 0 : (value != 0);
   } else if (k == "serve_iter_evals") {
     c->opt_serve_iter_evals = value <= 0 ? 1e12 : (double)value;
   } else {
     return fail(c, KDE_E_INVAL, "unknown option " + k);
   }
+  return KDE_OK;
+}
+
+kde_status kde_ctx_graph_stats(kde_ctx* c, int64_t* captures, int64_t* replays) {
+  if (!c || !captures || !replays) return KDE_E_INVAL;
+  *captures = c->graph_captures;
+  *replays = c->graph_replays;
   return KDE_OK;
 }
 

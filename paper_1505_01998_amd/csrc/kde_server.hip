@@ -319,6 +319,10 @@ kde_status kde_server_start(kde_ctx* c, uint64_t hbm_budget_bytes, int32_t max_s
     return fail(c, KDE_E_INVAL, "max_slots must be in [1, KDE_MAX_BATCH] and the budget > 0");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   c->server.reset();
+  // served requests run the LSCV variant the options name (the variant does
+  // not change any result, only the speed)
+  c->job_hc = c->opt_hc;
+  c->job_mfma = c->opt_mfma;
   std::unique_ptr<Server, kde::ServerDeleter> s(new Server());
   s->c = c;
   s->budget = hbm_budget_bytes;

@@ -1,0 +1,188 @@
+// kde_tune.hip -- tile autotuner for the LSCV pair pass.
+//
+// The LSCV pass (Section 4.4.2, every grid h of eq. LSCV-gh from one pair
+// distance, Section 4.5) has three vector-ALU kernel variants: 8, 16 or 32
+// bandwidths per block.  They trade register pressure (waves per SIMD)
+// against how far the pair distance is amortised, and waste different amounts
+// of work on the padded last chunk of a grid.  Work items are sized
+// independently of the variant and every (item, h) sum is accumulated in the
+// same order by all of them, so the variant changes the speed and never a
+// result.  (The matrix-core form folds shorter runs, so its sums differ in
+// rounding; it stays an explicit option and is not a candidate.)
+//
+// The tuner measures each variant's steady-state rate: launches of B and 2B
+// identical units (a row of 256 samples against a j-range as long as the
+// column's, capped at 8192) are timed and the difference is divided into the
+// extra work, which cancels launch overhead and the partly filled last round
+// of blocks.  Pair terms cost the same whatever the sample values, so the
+// trial column is all zeros.  The rate is then scaled by the share of the
+// variant's bandwidth slots that the grid fills (a 100-point grid fills 100
+// of 104 slots at 8 per block, 112 at 16, 128 at 32).  Decisions are cached
+// per context by shape (quarter octave of n, grid size).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kde_runtime.h"
+
+namespace kde {
+
+namespace {
+
+constexpr int kTrialUnits = 4096;          // B: 4096 and 8192 units per variant (16 and 32 per CU)
+constexpr int kTrialMaxJ = 8192;            // j-range of a trial unit (samples)
+constexpr double kTuneMinJobEvals = 1e13;  // jobs smaller than this use the cached or default variant
+constexpr double kSwitchGain = 1.02;       // a variant replaces the default only when this much faster
+
+constexpr int kVariants[3] = {8, 16, 32};  // bandwidths per block
+
+std::pair<int, int> shape_key(int64_t n, int n_h) {
+  return {(int)std::floor(4.0 * std::log2((double)std::max<int64_t>(n, 2))), n_h};
+}
+
+}  // namespace
+
+kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
+  if (n < 2 || n > KDE_MAX_N || n_h < 1 || n_h > KDE_MAX_NH) return fail(c, KDE_E_INVAL, "bad tuning shape");
+  const auto key = shape_key(n, n_h);
+  auto hit = c->tune_cache.find(key);
+  if (hit != c->tune_cache.end()) {
+    out = hit->second;
+    return KDE_OK;
+  }
+  // trial column: L zero samples (+ padding), one row against j in [0, L)
+  const int L = (int)std::min<int64_t>(((n + kBJ - 1) / kBJ) * kBJ, kTrialMaxJ);
+  const int B2 = 2 * kTrialUnits;
+  const size_t xn = (size_t)L + kPad;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = at;
+    at += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_x = take(4 * xn), o_c = take(4 * 32), o_part = take(16 * 32 * (size_t)B2),
+               o_st = take(sizeof(DevState)), o_col = take(sizeof(ColDesc)), o_units = take(sizeof(Unit) * B2);
+  kde_status s;
+  if ((s = ensure(c, c->tune_buf, at))) return s;
+  char* b = c->tune_buf.p;
+  // zero samples and state (status OK); coefficients -1, so masked pairs
+  // (infinite distance) give exp2(-inf) = 0 as in a real pass
+  KDE_HIP_TRY(c, hipMemsetAsync(b, 0, o_units, c->stream));
+  KDE_HIP_TRY(c, hipMemsetD32Async((hipDeviceptr_t)(b + o_c), 0xBF800000u, 32, c->stream));
+  // every unit writes its own partial slots (item = unit index)
+  std::vector<Unit> u(B2);
+  for (int k = 0; k < B2; ++k) u[k] = Unit{0, 0, 0, L, k, 0};
+  KDE_HIP_TRY(c, hipMemcpyAsync(b + o_units, u.data(), sizeof(Unit) * B2, hipMemcpyHostToDevice, c->stream));
+  const ColDesc* cols = (const ColDesc*)(b + o_col);
+  const Unit* dev_units = (const Unit*)(b + o_units);
+  hipEvent_t ev[3];
+  int made = 0;
+  hipError_t he = hipSuccess;
+  for (; made < 3 && he == hipSuccess; ++made) he = hipEventCreate(&ev[made]);
+  if (he != hipSuccess) --made;
+  TuneChoice r;
+  for (int v = 0; v < 3 && he == hipSuccess; ++v) {
+    const int hc = kVariants[v];
+    ColDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.x32 = (float*)(b + o_x);
+    d.c32 = (float*)(b + o_c);
+    d.part = (double*)(b + o_part);
+    d.st = (DevState*)(b + o_st);
+    d.n = L;
+    d.n_h = hc;
+    d.n_items = B2;
+    // synchronous, as `d` is reused for the next variant
+    he = hipMemcpyAsync(b + o_col, &d, sizeof(d), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    // warm-up, then B units and 2B units back to back
+    if (he == hipSuccess) {
+      launch_lscv_units(c->stream, hc, 0, 0, cols, dev_units, 0, kTrialUnits);
+      he = hipEventRecord(ev[0], c->stream);
+    }
+    if (he == hipSuccess) {
+      launch_lscv_units(c->stream, hc, 0, 0, cols, dev_units, 0, kTrialUnits);
+      he = hipEventRecord(ev[1], c->stream);
+    }
+    if (he == hipSuccess) {
+      launch_lscv_units(c->stream, hc, 0, 0, cols, dev_units, 0, B2);
+      he = hipEventRecord(ev[2], c->stream);
+    }
+    if (he == hipSuccess) he = hipGetLastError();
+    if (he == hipSuccess) he = hipEventSynchronize(ev[2]);
+    float t1 = 0.f, t2 = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&t1, ev[0], ev[1]);
+    if (he == hipSuccess) he = hipEventElapsedTime(&t2, ev[1], ev[2]);
+    const double slots = 256.0 * L * hc * kTrialUnits;  // (pair, h) slots of the extra B units
+    const double fill = (double)n_h / (double)(((n_h + hc - 1) / hc) * hc);
+    r.rate[v] = (t2 > t1) ? slots / ((t2 - t1) * 1e-3) * fill : 0.0;
+  }
+  for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+  if (he != hipSuccess) return fail(c, KDE_E_DEVICE, std::string("autotune trial: ") + hipGetErrorString(he));
+  int best = 1;  // the default variant, 16 bandwidths per block
+  for (int v = 0; v < 3; ++v)
+    if (r.rate[v] > r.rate[best] * kSwitchGain) best = v;
+  r.hc = kVariants[best];
+  c->tune_cache[key] = r;
+  out = r;
+  return KDE_OK;
+}
+
+kde_status select_variant(kde_ctx* c, const kde_request* reqs, int32_t n_req) {
+  c->job_hc = c->opt_hc;
+  c->job_mfma = c->opt_mfma;
+  if (!c->opt_autotune || c->prec == KDE_PREC_FP64) return KDE_OK;
+  // the job's largest LSCV column decides; malformed requests are skipped
+  // here and rejected by the planner
+  int64_t n_best = 0;
+  int nh_best = 0;
+  double w_best = 0.0, total = 0.0;
+  for (int32_t k = 0; k < n_req; ++k) {
+    const kde_request& r = reqs[k];
+    if (!(r.methods & KDE_METHOD_LSCV) || r.x.n < 2 || r.x.n > KDE_MAX_N || r.grid.n_h < 1 ||
+        r.grid.n_h > KDE_MAX_NH)
+      continue;
+    const double w = 0.5 * (double)r.x.n * (double)(r.x.n - 1) * r.grid.n_h;
+    total += w;
+    if (w > w_best) {
+      w_best = w;
+      n_best = r.x.n;
+      nh_best = r.grid.n_h;
+    }
+  }
+  if (n_best == 0) return KDE_OK;
+  auto hit = c->tune_cache.find(shape_key(n_best, nh_best));
+  TuneChoice t;
+  if (hit != c->tune_cache.end()) {
+    t = hit->second;
+  } else if (total >= kTuneMinJobEvals) {
+    kde_status s = tune_shape(c, n_best, nh_best, t);
+    if (s) return s;
+  } else {
+    return KDE_OK;
+  }
+  c->job_hc = t.hc;
+  c->job_mfma = 0;
+  return KDE_OK;
+}
+
+}  // namespace kde
+
+extern "C" kde_status kde_autotune(kde_ctx* c, int64_t n, int32_t n_h, kde_tune_info* out) {
+  if (!c) return KDE_E_INVAL;
+  if (c->server && kde::server_running(c->server.get()))
+    return kde::fail(c, KDE_E_BUSY, "a server is running on this context");
+  if (c->prec == KDE_PREC_FP64) return kde::fail(c, KDE_E_INVAL, "the autotuner covers the mixed-precision form");
+  if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  kde::TuneChoice t;
+  kde_status s = kde::tune_shape(c, n, n_h, t);
+  if (s) return s;
+  if (out) {
+    out->hc = t.hc;
+    for (int v = 0; v < 3; ++v) out->evals_per_s[v] = t.rate[v];
+  }
+  return KDE_OK;
+}

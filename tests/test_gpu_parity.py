@@ -13,7 +13,9 @@ Tolerances (mixed precision):
     <= 2 max|dg| (reported).
 FP64 form: 1e-10 on the same quantities.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -294,3 +296,42 @@ def test_lscv_lognormal_1m_sampled_items(kde):
         m = o1 > 1e-20
         worst = max(worst, float(np.max(np.abs(g1[m] - o1[m]) / o1[m])))
     print(f"lognormal-1m sampled items: max rel err {worst:.3e} over {len(sel)} items x {hk.size} h")
+
+
+GOLDEN_1M = os.path.join(os.path.dirname(__file__), "golden", "lognormal_1m_oracle.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_1M),
+                    reason="full-size oracle values not written (tests/golden/make_lognormal_1m.py)")
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_lognormal_1m_full_size_oracle_values(kde, precision):
+    """The bench column at full size (n = 1,000,000) against the FP64 oracle's
+    stored values: the whole three-stage plug-in chain and g(h) at the stored
+    grid indices.  The FP64 form's tolerance is 1e-10 times the stage's
+    condition number for psi (a sum of terms of both signs) and 1e-10 of
+    gscale for g."""
+    ref = json.load(open(GOLDEN_1M))
+    w = workloads.workload("lognormal-1m")
+    x = w.column()
+    with kde.Context(0, precision) as c:
+        h, info = c.bw_plugin(x, 3)
+        idx = sorted(int(k) for k in ref.get("lscv", {}))
+        if idx:
+            g, gs, _ = c.lscv_curve(x, w.grid[idx])
+    p = ref["plugin"]
+    for s in range(3):
+        tol = TOL if precision == "mixed" else TOL64 * max(1.0, p["kappa"][s])
+        assert info.psi[s] == pytest.approx(p["psi"][s], rel=tol), s
+        assert info.g[s] == pytest.approx(p["g"][s], rel=tol), s
+    tol = TOL if precision == "mixed" else TOL64 * max(p["kappa"])
+    assert h == pytest.approx(p["h"], rel=tol)
+    assert info.sigma == pytest.approx(p["sigma"], rel=1e-12)
+    worst = 0.0
+    for a, k in enumerate(idx):
+        v = ref["lscv"][str(k)]
+        err = abs(g[a] - v["g"]) / v["gscale"]
+        worst = max(worst, err)
+        assert err <= (TOL if precision == "mixed" else TOL64), (k, g[a], v["g"])
+    print(f"lognormal-1m full size ({precision}): psi rel "
+          f"{[abs(info.psi[s] - p['psi'][s]) / abs(p['psi'][s]) for s in range(3)]}, "
+          f"h rel {abs(h - p['h']) / p['h']:.2e}, max |dg|/gscale {worst:.2e} over {len(idx)} h")

@@ -1,0 +1,89 @@
+"""The tile autotuner of the LSCV pass: every variant it chooses between gives
+bitwise the same sums, its decision is cached per shape, and a context that
+tunes returns the same results as one that does not."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kde():
+    import paper_1505_01998_amd as kde
+
+    return kde
+
+
+def test_variants_bitwise_equal(kde):
+    x = workloads.draw("gamma", 20011, 17, np.float32)
+    grid = np.geomspace(0.01, 3.0, 100)  # not a multiple of 8, 16 or 32: padded last chunks
+    out = {}
+    with kde.Context(0) as c:
+        for hc in (8, 16, 32):
+            c.set_option("lscv_hc", hc)
+            out[hc] = c.lscv_sums(x, grid)
+    for hc in (8, 32):
+        assert np.array_equal(out[hc][0], out[16][0]) and np.array_equal(out[hc][1], out[16][1]), hc
+    o = oracle.lscv_curve(x, grid)
+    assert np.allclose(out[16][0], o.s1, rtol=1e-5) and np.allclose(out[16][1], o.s2, rtol=1e-5)
+
+
+def test_autotune_choice_and_cache(kde):
+    with kde.Context(0) as c:
+        t0 = time.perf_counter()
+        hc, rates = c.autotune(200_000, 128)
+        t1 = time.perf_counter()
+        hc2, rates2 = c.autotune(200_000, 128)
+        t2 = time.perf_counter()
+        # same quarter octave of n: the cached decision
+        hc3, rates3 = c.autotune(205_000, 128)
+    print(f"autotune n=2e5 n_h=128: hc={hc} rates={ {k: f'{v:.3e}' for k, v in rates.items()} } "
+          f"first {t1 - t0:.3f} s, cached {t2 - t1:.6f} s")
+    assert hc in (8, 16, 32)
+    assert all(v > 1e11 for v in rates.values())
+    # the default is kept unless another variant is 2% faster
+    assert rates[hc] >= rates[16]
+    if hc != 16:
+        assert rates[hc] > 1.02 * rates[16]
+    assert (hc2, rates2) == (hc, rates) and (hc3, rates3) == (hc, rates)
+    assert t2 - t1 < 0.05
+
+
+def test_autotune_errors(kde):
+    with kde.Context(0) as c:
+        for n, nh in ((1, 10), (1000, 0), (1000, 70000)):
+            with pytest.raises(kde.KdeError) as e:
+                c.autotune(n, nh)
+            assert e.value.status == kde.KDE_E_INVAL
+    with kde.Context(0, "fp64") as c:
+        with pytest.raises(kde.KdeError) as e:
+            c.autotune(1000, 10)
+        assert e.value.status == kde.KDE_E_INVAL
+
+
+def test_autotuned_jobs_equal_default(kde):
+    """A job large enough to be tuned (>= 1e13 pair-term evaluations) and a
+    small one: the tuning context's results are bitwise the default's."""
+    big = workloads.draw("bimodal", 400_000, 5, np.float32)
+    grid = np.geomspace(0.002, 1.0, 128)
+    small = [kde.Request(workloads.draw(f, 3000 + 7 * k, k, np.float32),
+                         kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, 3, workloads.BATCH_GRID)
+             for k, f in enumerate(workloads.BATCH_FAMILIES)]
+    with kde.Context(0) as tuned, kde.Context(0) as plain:
+        tuned.set_option("autotune", 1)
+        g_t, gs_t, _ = tuned.lscv_curve(big, grid)
+        g_p, gs_p, _ = plain.lscv_curve(big, grid)
+        r_t = tuned.batch(small)
+        r_p = plain.batch(small)
+        hc, _ = tuned.autotune(big.size, grid.size)  # cached by the first call
+    assert np.array_equal(g_t, g_p) and np.array_equal(gs_t, gs_p)
+    for a, b in zip(r_t, r_p):
+        assert a.status == b.status == kde.KDE_OK
+        assert a.h_lscv == b.h_lscv and a.h_plugin == b.h_plugin
+        assert np.array_equal(a.g, b.g)
+    assert hc in (8, 16, 32)
