@@ -43,10 +43,13 @@ LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 # WRITE_SIZE passes, each scaled by the ratio the same counter shows for a
 # plain 1 GiB copy (fetch x2.0, write x1.0).  Valid only for the kernel
 # source they were taken on; reported as null once that source changes.
+# The kernels and the planner that sizes their work units (and so the
+# partial-sum writes per launch) decide the traffic.
+TRAFFIC_SOURCES = ("kde_kernels.hip", "kde_runtime.hip")
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32<16>",
-    "kernels_sha256": "10e198d8553feb354de702a945fa753029cf324f9a3206769963cb0612d9ee33",
+    "sources_sha256": "stale",
     "fetch_bytes": 1.6406e7,
     "write_bytes": 3.3004e6,
 }
@@ -57,10 +60,12 @@ def measured_traffic(workload: str, kernel: str):
     passes, or None when the workload, the kernel or its source has changed."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_1505_01998_amd", "csrc", "kde_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1505_01998_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()
     t = MEASURED_TRAFFIC
-    if sha != t["kernels_sha256"] or workload != t["workload"] or kernel != t["kernel"]:
+    if sha != t["sources_sha256"] or workload != t["workload"] or kernel != t["kernel"]:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
 
@@ -75,18 +80,18 @@ def _rel(a, b):
 def accuracy(kde, xd, w, h_pi, info, g, gs):
     """Error of the mixed form (outside the timed region): against the
     all-FP64 GPU form on the same column (the whole plug-in chain and g(h) at
-    both grid ends, two interior indices and the chosen index +-2), and against
+    both grid ends, two interior indices and the chosen index +-6), and against
     the FP64 oracle's stored full-size values where they exist."""
     m = w.grid.size
     k = int(np.argmin(g))
-    idx = sorted({0, m // 8, m // 2, m - 1, *[j for j in range(k - 2, k + 3) if 0 <= j < m]})
+    win = [j for j in range(k - 6, k + 7) if 0 <= j < m]
+    idx = sorted({0, m // 8, m // 2, m - 1, *win})
     log(f"accuracy: FP64 GPU form, plug-in and g(h) at {len(idx)} grid points")
     with kde.Context(0, "fp64") as c64:
         t = time.perf_counter()
         h64, info64 = c64.bw_plugin(xd, w.stages)
         g64, gs64, _ = c64.lscv_curve(xd, w.grid[idx])
         t64 = time.perf_counter() - t
-    win = [j for j in range(k - 2, k + 3) if 0 <= j < m]
     g64_win = [g64[idx.index(j)] for j in win]
     stages = range(3 - w.stages, 3)
     out = {
@@ -97,6 +102,9 @@ def accuracy(kde, xd, w, h_pi, info, g, gs):
             "g_indices": idx,
             "g_err_over_gscale_max": max(abs(g[j] - g64[a]) / gs64[a] for a, j in enumerate(idx)),
             "argmin_in_window_same": win[int(np.argmin(g64_win))] == k,
+            "window": win,
+            "window_g_minus_min_over_gscale": [(g[j] - g[k]) / gs[k] for j in win],
+            "window_fp64_g_minus_min_over_gscale": [(v - min(g64_win)) / gs64[idx.index(k)] for v in g64_win],
             "fp64_seconds": t64,
         },
         "vs_oracle": None,

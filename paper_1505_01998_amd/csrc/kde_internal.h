@@ -109,7 +109,7 @@ void launch_psi_finish(hipStream_t s, const ColDesc* cols, const int* ids, int n
                        int conditional);
 void launch_plugin_final(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids);
 void launch_lscv_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int hc);
-void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids);
+void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int f64);
 // Pair kernels act on units[u0 .. u0 + n_units).
 void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColDesc* cols, const Unit* units, int u0,
                       int n_units);

@@ -778,8 +778,15 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_mfma(const ColDesc* __r
 
 // Block per column.  g(h) = h^-1 [2 n^-2 ((4pi)^-1/2 S1 - 2 (2pi)^-1/2 S2) + n^-1 (4pi)^-1/2];
 // gscale with +.  Grid argmin with ties to the lowest index.
+// g(h) of every grid point, argmin, edge flag and margin.  The mixed form's
+// pair sums are exact sums at the bandwidth whose FP32 exponent coefficient
+// c32 = -log2(e)/(4 h^2) is exactly representable; that bandwidth (within
+// 3e-8 of the grid value) also goes into the 1/h factor, so each g is a
+// consistent evaluation at a point next to the grid value rather than a
+// mixture of two bandwidths, and the per-point error does not jump from one
+// grid point to the next with the rounding of its coefficient.
 __global__ __launch_bounds__(1024) void k_lscv_finalize(const ColDesc* __restrict__ cols,
-                                                        const int* __restrict__ ids) {
+                                                        const int* __restrict__ ids, int f64) {
   const ColDesc c = cols[ids[blockIdx.x]];
   if (c.n_h <= 0) return;
   DevState& d = *c.st;
@@ -797,7 +804,12 @@ __global__ __launch_bounds__(1024) void k_lscv_finalize(const ColDesc* __restric
   double best = kInfD;
   int kbest = 0x7fffffff;
   for (int k = t; k < n_h; k += blockDim.x) {
-    const double s1 = sums[2 * k], s2 = sums[2 * k + 1], h = h_dev[k];
+    const double s1 = sums[2 * k], s2 = sums[2 * k + 1];
+    double h = h_dev[k];
+    if (!f64) {
+      const double cq = (double)c.c32[k];
+      if (cq < 0.0 && isfinite(cq)) h = sqrt(-kLog2E / (4.0 * cq));
+    }
     const double a = ckk * s1, b = ck * s2;
     const double gv = (2.0 / (n * n) * (a - 2.0 * b) + ckk / n) / h;
     g[k] = ok ? gv : NAN;
@@ -886,8 +898,8 @@ void launch_lscv_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_
   if (n_ids > 0) k_lscv_prep<<<n_ids, kThreads, 0, s>>>(cols, ids, hc);
 }
 
-void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids) {
-  if (n_ids > 0) k_lscv_finalize<<<n_ids, 1024, 0, s>>>(cols, ids);
+void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int f64) {
+  if (n_ids > 0) k_lscv_finalize<<<n_ids, 1024, 0, s>>>(cols, ids, f64);
 }
 
 void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColDesc* cols, const Unit* units, int u0,

@@ -163,8 +163,10 @@ void make_items(int64_t n, int64_t seg, ColItems& out) {
 // on the variant.
 int64_t pick_seg(const kde_ctx* c, int64_t n, int hc) {
   if (c->opt_seg >= 0) return c->opt_seg == 0 ? 0 : (c->opt_seg + kBJ - 1) / kBJ * kBJ;
-  // Aim for ~8192 blocks per launch so each launch fills the chip many times.
-  const double per_block_pairs = c->opt_launch_evals / 8192.0 / (double)hc;
+  // Aim for ~32768 blocks per launch: about 32 rounds of the ~1024 blocks the
+  // chip holds at once, so the partly filled last round of each launch (the
+  // launches of a pass run back to back, not overlapped) costs ~1-2%.
+  const double per_block_pairs = c->opt_launch_evals / 32768.0 / (double)hc;
   int64_t seg = (int64_t)(per_block_pairs / kBI);
   seg = std::max<int64_t>(kBJ, seg / kBJ * kBJ);
   if (seg >= n) return 0;
@@ -528,7 +530,7 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
   });
   if (s) return s;
   kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_lr), (int)it.lscv_rows.size());
-  kde::launch_lscv_finalize(st, cols, ids(L.o_lf), (int)it.ids_lscv_final.size());
+  kde::launch_lscv_finalize(st, cols, ids(L.o_lf), (int)it.ids_lscv_final.size(), all64 ? 1 : 0);
   KDE_HIP_TRY(c, hipGetLastError());
   return KDE_OK;
 }
