@@ -261,6 +261,27 @@ typedef struct {
   double t_queue_s, t_service_s; /* served requests: time queued, time admitted to done */
 } kde_result;
 
+/* Device memory one request needs in a job or a server slot (its column
+ * block: working copies of the samples, partial sums, grid, results), under
+ * the options of ctx, or the defaults (mixed precision) when ctx is NULL.
+ * Host-only: no device is touched, so it also runs without a GPU.  This is
+ * the size the server's admission compares with its HBM budget.
+ * KDE_E_INVAL for an invalid request (same checks as the calls that run it);
+ * KDE_E_BUSY while a server runs on ctx. */
+kde_status kde_request_footprint(const kde_ctx* ctx, const kde_request* req, uint64_t* bytes);
+
+/* Work items of the pair triangle i < j of a column of n samples, as the
+ * planner cuts it (Section 5.4 walks the same triangle in tiles): item k
+ * covers i in [row_begin[k], row_begin[k] + 256) and j in
+ * [j_begin[k], j_end[k]) with j > i, holds pairs[k] such pairs, and the items
+ * are ordered longest first.  seg: j-range per item as the "seg" option
+ * (0 = whole rows, > 0 rounded up to a multiple of 512, < 0 = automatic for
+ * the LSCV pass under the default launch size).  Writes min(cap, count) items
+ * and sets *n_items = count.  Host-only.  KDE_E_INVAL for n outside
+ * [2, KDE_MAX_N], cap < 0, or NULL arrays with cap > 0. */
+kde_status kde_plan_items(int64_t n, int64_t seg, int32_t cap, int32_t* n_items, int32_t* row_begin,
+                          int32_t* j_begin, int32_t* j_end, double* pairs);
+
 /* Run n_req (<= KDE_MAX_BATCH) requests as one job.  Per-request argument errors and degenerate
  * samples are reported in out[k].status (the other requests still run); a
  * degenerate plug-in chain does not stop the LSCV pass of the same request

@@ -46,7 +46,7 @@ EXPORTS = (
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
-    "kde_ctx_graph_stats",
+    "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items",
 )
 
 
@@ -146,6 +146,9 @@ def _load():
     lib.kde_server_stop.argtypes = [P]
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
     lib.kde_ctx_graph_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    lib.kde_request_footprint.argtypes = [P, ctypes.POINTER(kde_request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.kde_plan_items.argtypes = [I64, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                   ctypes.POINTER(I32), PD]
     for name in EXPORTS:
         if name not in ("kde_ctx_destroy", "kde_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -234,6 +237,34 @@ def kde_ctx_kernel_time(ctx, family: str):
     ev = ctypes.c_double()
     _check(ctx, lib.kde_ctx_kernel_time(ctx, family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ev)))
     return n.value, ms.value, ev.value
+
+
+def kde_plan_items(n: int, seg: int = -1):
+    """Work items of the i < j triangle of n samples: arrays (row_begin, j_begin, j_end, pairs), longest first."""
+    m = ctypes.c_int32()
+    st = lib.kde_plan_items(int(n), int(seg), 0, ctypes.byref(m), None, None, None, None)
+    if st != KDE_OK:
+        raise KdeError(st, "kde_plan_items: invalid arguments")
+    k = m.value
+    i0, jb, je = (np.empty(k, np.int32) for _ in range(3))
+    pr = np.empty(k, np.float64)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    st = lib.kde_plan_items(int(n), int(seg), k, ctypes.byref(m), i0.ctypes.data_as(P32), jb.ctypes.data_as(P32),
+                            je.ctypes.data_as(P32), _pd(pr))
+    if st != KDE_OK:
+        raise KdeError(st, "kde_plan_items failed")
+    return i0, jb, je, pr
+
+
+def kde_request_footprint(req, ctx=None) -> int:
+    """Device bytes a Request needs (its column block), under ctx's options or the defaults."""
+    r, keep, _ = _make_request(req)
+    b = ctypes.c_uint64()
+    st = lib.kde_request_footprint(ctx, ctypes.byref(r), ctypes.byref(b))
+    del keep
+    if st != KDE_OK:
+        raise KdeError(st, "kde_request_footprint: invalid request" if st == KDE_E_INVAL else "busy")
+    return b.value
 
 
 def kde_ctx_graph_stats(ctx):
@@ -507,6 +538,9 @@ class Context:
 
     def graph_stats(self):
         return kde_ctx_graph_stats(self.ctx)
+
+    def footprint(self, req):
+        return kde_request_footprint(req, self.ctx)
 
     def lscv_curve(self, x, h_grid=None, n_h=0):
         return kde_lscv_curve(self.ctx, x, h_grid, n_h)

@@ -942,6 +942,44 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
   return KDE_OK;
 }
 
+kde_status kde_request_footprint(const kde_ctx* c, const kde_request* r, uint64_t* bytes) {
+  if (!r || !bytes) return KDE_E_INVAL;
+  if (c && serving(c)) return KDE_E_BUSY;
+  // the planner reads only the options: a context-free copy of them
+  kde_ctx o;
+  if (c) {
+    o.prec = c->prec;
+    o.opt_hc = c->opt_hc;
+    o.opt_seg = c->opt_seg;
+    o.opt_launch_evals = c->opt_launch_evals;
+    o.opt_fp64_kappa = c->opt_fp64_kappa;
+  }
+  o.job_hc = o.opt_hc;
+  kde::ColPlan p;
+  if (!kde::plan_column(&o, *r, p).empty()) return KDE_E_INVAL;
+  *bytes = (uint64_t)((p.bytes + 255) / 256 * 256);
+  return KDE_OK;
+}
+
+kde_status kde_plan_items(int64_t n, int64_t seg, int32_t cap, int32_t* n_items, int32_t* row_begin, int32_t* j_begin,
+                          int32_t* j_end, double* pairs) {
+  if (n < 2 || n > KDE_MAX_N || cap < 0 || !n_items) return KDE_E_INVAL;
+  if (cap > 0 && (!row_begin || !j_begin || !j_end || !pairs)) return KDE_E_INVAL;
+  kde_ctx o;
+  o.opt_seg = seg < 0 ? -1 : seg;
+  kde::ColItems it;
+  kde::make_items(n, kde::pick_seg(&o, n, kde::kSegRefHC), it);
+  const int32_t m = (int32_t)it.pairs.size();
+  *n_items = m;
+  for (int32_t k = 0; k < std::min(m, cap); ++k) {
+    row_begin[k] = it.row[k] * kde::kBI;
+    j_begin[k] = it.jb[k];
+    j_end[k] = it.je[k];
+    pairs[k] = it.pairs[k];
+  }
+  return KDE_OK;
+}
+
 kde_status kde_ctx_graph_stats(kde_ctx* c, int64_t* captures, int64_t* replays) {
   if (!c || !captures || !replays) return KDE_E_INVAL;
   *captures = c->graph_captures;

@@ -335,3 +335,52 @@ def test_lognormal_1m_full_size_oracle_values(kde, precision):
     print(f"lognormal-1m full size ({precision}): psi rel "
           f"{[abs(info.psi[s] - p['psi'][s]) / abs(p['psi'][s]) for s in range(3)]}, "
           f"h rel {abs(h - p['h']) / p['h']:.2e}, max |dg|/gscale {worst:.2e} over {len(idx)} h")
+
+
+@pytest.mark.parametrize("family,n", [("bimodal", 4099), ("lognormal", 20011)])
+def test_invariances_on_the_gpu(kde, ctx, family, n):
+    """Shift, reflection and permutation leave sigma, psi_r and g(h) unchanged;
+    scaling by a multiplies h_rot and h_PI by |a|, psi_r at the scaled pilot by
+    |a|^-(r+1), and g_{ax}(|a| h) = g_x(h) / |a| (Section 4.4 definitions
+    depend on the samples only through X_i - X_j).  Within the mixed form's
+    tolerance; the power-of-two scale and shift keep the FP32 inputs exact."""
+    x = workloads.draw(family, n, 77, np.float64)
+    grid = np.geomspace(0.02, 2.0, 48)
+    rng = np.random.Generator(np.random.PCG64(5))
+    h0, i0 = ctx.bw_plugin(x, 3)
+    g0, gs0, _ = ctx.lscv_curve(x, grid)
+    for y in (x + 4.0, -x, x[rng.permutation(n)]):
+        h1, i1 = ctx.bw_plugin(y, 3)
+        g1, _, _ = ctx.lscv_curve(y, grid)
+        assert i1.sigma == pytest.approx(i0.sigma, rel=1e-12)
+        assert h1 == pytest.approx(h0, rel=TOL)
+        for s in range(3):
+            assert i1.psi[s] == pytest.approx(i0.psi[s], rel=TOL)
+        assert np.all(np.abs(g1 - g0) <= TOL * gs0)
+    a = -2.0
+    h2, i2 = ctx.bw_plugin(a * x, 3)
+    g2, _, _ = ctx.lscv_curve(a * x, abs(a) * grid)
+    assert i2.h_rot == pytest.approx(abs(a) * i0.h_rot, rel=1e-12)
+    assert h2 == pytest.approx(abs(a) * h0, rel=TOL)
+    for s, r in enumerate((8, 6, 4)):
+        assert i2.psi[s] == pytest.approx(i0.psi[s] * abs(a) ** -(r + 1), rel=TOL)
+    assert np.all(np.abs(g2 - g0 / abs(a)) <= TOL * gs0 / abs(a))
+    assert int(np.argmin(g2)) == int(np.argmin(g0))
+
+
+def test_lognormal_1m_argmin_mixed_equals_fp64(kde):
+    """The bench column at full size: the mixed form's chosen grid index over
+    all 512 h is the all-FP64 form's argmin over the chosen index +-6, and the
+    two forms agree on that window to far below the tolerance."""
+    w = workloads.workload("lognormal-1m")
+    x = w.column()
+    with kde.Context(0) as c:
+        g, gs, _ = c.lscv_curve(x, w.grid)
+    k = int(np.argmin(g))
+    win = np.arange(max(0, k - 6), min(w.grid.size, k + 7))
+    with kde.Context(0, "fp64") as c64:
+        g64, gs64, _ = c64.lscv_curve(x, w.grid[win])
+    assert win[int(np.argmin(g64))] == k
+    err = np.abs(g[win] - g64) / gs64
+    print(f"lognormal-1m: k = {k}, max |g_mixed - g_fp64| / gscale on k+-6: {err.max():.2e}")
+    assert err.max() <= TOL

@@ -142,3 +142,20 @@ def test_stop_cancels_queued_and_sync_calls_are_refused(kde):
     assert kde.KDE_E_CANCELLED in st
     with pytest.raises(kde.KdeError):
         srv.poll(ts[0])  # collected (and the context is closed)
+
+
+def test_admission_uses_the_request_footprint(kde):
+    """A request whose footprint equals the budget is served; one byte less
+    and it completes with KDE_E_NOMEM."""
+    r = kde.Request(workloads.draw("gamma", 5000, 11, np.float32), kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, 3,
+                    workloads.BATCH_GRID)
+    with kde.Context(0) as srv:
+        fp = srv.footprint(r)
+        assert fp == kde.kde_request_footprint(r)  # default options
+        srv.server_start(fp, 1)
+        ok = srv.wait(srv.submit(r), timeout_s=60)
+        srv.server_stop()
+        srv.server_start(fp - 1, 1)
+        no = srv.wait(srv.submit(r), timeout_s=60)
+        srv.server_stop()
+    assert ok.status == kde.KDE_OK and no.status == kde.KDE_E_NOMEM
