@@ -271,15 +271,17 @@ typedef struct {
 kde_status kde_request_footprint(const kde_ctx* ctx, const kde_request* req, uint64_t* bytes);
 
 /* Work items of the pair triangle i < j of a column of n samples, as the
- * planner cuts it (Section 5.4 walks the same triangle in tiles): item k
- * covers i in [row_begin[k], row_begin[k] + 256) and j in
+ * planner cuts it for the LSCV pass over an n_h-point grid (n_h > 0) or for a
+ * plug-in stage (n_h = 0); Section 5.4 walks the same triangle in tiles.
+ * Item k covers i in [row_begin[k], row_begin[k] + 256) and j in
  * [j_begin[k], j_end[k]) with j > i, holds pairs[k] such pairs, and the items
  * are ordered longest first.  seg: j-range per item as the "seg" option
- * (0 = whole rows, > 0 rounded up to a multiple of 512, < 0 = automatic for
- * the LSCV pass under the default launch size).  Writes min(cap, count) items
- * and sets *n_items = count.  Host-only.  KDE_E_INVAL for n outside
- * [2, KDE_MAX_N], cap < 0, or NULL arrays with cap > 0. */
-kde_status kde_plan_items(int64_t n, int64_t seg, int32_t cap, int32_t* n_items, int32_t* row_begin,
+ * (0 = whole rows, > 0 rounded up to a multiple of 512, < 0 = automatic under
+ * the default launch size, lengthened when the pass would exceed 2^24 work
+ * units).  Writes min(cap, count) items and sets *n_items = count.
+ * Host-only.  KDE_E_INVAL for n outside [2, KDE_MAX_N], n_h outside
+ * [0, KDE_MAX_NH], cap < 0, or NULL arrays with cap > 0. */
+kde_status kde_plan_items(int64_t n, int32_t n_h, int64_t seg, int32_t cap, int32_t* n_items, int32_t* row_begin,
                           int32_t* j_begin, int32_t* j_end, double* pairs);
 
 /* Run n_req (<= KDE_MAX_BATCH) requests as one job.  Per-request argument errors and degenerate

@@ -147,8 +147,8 @@ def _load():
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
     lib.kde_ctx_graph_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.kde_request_footprint.argtypes = [P, ctypes.POINTER(kde_request), ctypes.POINTER(ctypes.c_uint64)]
-    lib.kde_plan_items.argtypes = [I64, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
-                                   ctypes.POINTER(I32), PD]
+    lib.kde_plan_items.argtypes = [I64, I32, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                   ctypes.POINTER(I32), ctypes.POINTER(I32), PD]
     for name in EXPORTS:
         if name not in ("kde_ctx_destroy", "kde_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -239,18 +239,20 @@ def kde_ctx_kernel_time(ctx, family: str):
     return n.value, ms.value, ev.value
 
 
-def kde_plan_items(n: int, seg: int = -1):
-    """Work items of the i < j triangle of n samples: arrays (row_begin, j_begin, j_end, pairs), longest first."""
+def kde_plan_items(n: int, n_h: int = 128, seg: int = -1):
+    """Work items of the i < j triangle of n samples for the LSCV pass over n_h
+    bandwidths (n_h = 0: a plug-in stage): arrays (row_begin, j_begin, j_end,
+    pairs), longest first."""
     m = ctypes.c_int32()
-    st = lib.kde_plan_items(int(n), int(seg), 0, ctypes.byref(m), None, None, None, None)
+    st = lib.kde_plan_items(int(n), int(n_h), int(seg), 0, ctypes.byref(m), None, None, None, None)
     if st != KDE_OK:
         raise KdeError(st, "kde_plan_items: invalid arguments")
     k = m.value
     i0, jb, je = (np.empty(k, np.int32) for _ in range(3))
     pr = np.empty(k, np.float64)
     P32 = ctypes.POINTER(ctypes.c_int32)
-    st = lib.kde_plan_items(int(n), int(seg), k, ctypes.byref(m), i0.ctypes.data_as(P32), jb.ctypes.data_as(P32),
-                            je.ctypes.data_as(P32), _pd(pr))
+    st = lib.kde_plan_items(int(n), int(n_h), int(seg), k, ctypes.byref(m), i0.ctypes.data_as(P32),
+                            jb.ctypes.data_as(P32), je.ctypes.data_as(P32), _pd(pr))
     if st != KDE_OK:
         raise KdeError(st, "kde_plan_items failed")
     return i0, jb, je, pr

@@ -203,6 +203,10 @@ constexpr int kSegRefHC = 16;
 void make_items(int64_t n, int64_t seg, ColItems& out);
 // Item length of a pass whose blocks evaluate `hc` terms per pair.
 int64_t pick_seg(const kde_ctx* c, int64_t n, int hc);
+// Units a pass may hold before the planner lengthens its items.
+constexpr double kMaxUnits = 16777216.0;
+// pick_seg, lengthened while items x chunks would exceed kMaxUnits.
+int64_t capped_seg(const kde_ctx* c, int64_t n, int hc, double chunks);
 // Sets c->job_hc / job_mfma for a synchronous job over these requests: the
 // options, or with the autotune option the tuned vector-ALU variant of the
 // job's largest LSCV column (tuning that shape first when the job is large).

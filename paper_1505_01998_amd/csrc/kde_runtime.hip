@@ -173,6 +173,19 @@ int64_t pick_seg(const kde_ctx* c, int64_t n, int hc) {
   return seg;
 }
 
+// Item length of a pass with `chunks` units per item: pick_seg's length,
+// doubled while the pass would hold more than kMaxUnits units, which bounds
+// the planner's host memory (24 bytes a unit) for very large columns; at the
+// sizes of the workloads (n <= 2e6) the cap is far away.
+int64_t capped_seg(const kde_ctx* c, int64_t n, int hc, double chunks) {
+  int64_t seg = pick_seg(c, n, hc);
+  if (c->opt_seg >= 0 || seg == 0) return seg;
+  const double rows = (double)((n + kBI - 1) / kBI);
+  const double row_samples = 0.5 * (double)n * (double)n / kBI;  // sum of the rows' j-spans
+  while (seg < n && (row_samples / (double)seg + rows) * chunks > kMaxUnits) seg *= 2;
+  return seg >= n ? 0 : seg;
+}
+
 namespace {
 
 size_t take(size_t& at, size_t bytes) {
@@ -201,7 +214,7 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
   p.f64 = r.x.dtype == KDE_F64;
   p.stages = p.plugin ? r.stages : 0;
   p.hc = all64 ? 8 : c->job_hc;
-  if (p.plugin) make_items(p.n, pick_seg(c, p.n, 1), p.psi_items);
+  if (p.plugin) make_items(p.n, capped_seg(c, p.n, 1, 1.0), p.psi_items);
   if (p.lscv) {
     p.n_h = r.grid.n_h;
     p.n_chunks = (p.n_h + p.hc - 1) / p.hc;
@@ -209,7 +222,7 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
     p.grid_lo = r.grid.lo;
     p.grid_hi = r.grid.hi;
     if (r.grid.kind == KDE_GRID_EXPLICIT) p.grid_h.assign(r.grid.h, r.grid.h + p.n_h);
-    make_items(p.n, pick_seg(c, p.n, kSegRefHC), p.lscv_items);
+    make_items(p.n, capped_seg(c, p.n, kSegRefHC, (double)((p.n_h + kSegRefHC - 1) / kSegRefHC)), p.lscv_items);
   }
   p.want_x64 = all64 || (p.plugin && c->opt_fp64_kappa > 0.0);
   p.raw_in_block = !r.x.on_device;
@@ -961,14 +974,18 @@ kde_status kde_request_footprint(const kde_ctx* c, const kde_request* r, uint64_
   return KDE_OK;
 }
 
-kde_status kde_plan_items(int64_t n, int64_t seg, int32_t cap, int32_t* n_items, int32_t* row_begin, int32_t* j_begin,
-                          int32_t* j_end, double* pairs) {
-  if (n < 2 || n > KDE_MAX_N || cap < 0 || !n_items) return KDE_E_INVAL;
+kde_status kde_plan_items(int64_t n, int32_t n_h, int64_t seg, int32_t cap, int32_t* n_items, int32_t* row_begin,
+                          int32_t* j_begin, int32_t* j_end, double* pairs) {
+  if (n < 2 || n > KDE_MAX_N || n_h < 0 || n_h > KDE_MAX_NH || cap < 0 || !n_items) return KDE_E_INVAL;
   if (cap > 0 && (!row_begin || !j_begin || !j_end || !pairs)) return KDE_E_INVAL;
   kde_ctx o;
   o.opt_seg = seg < 0 ? -1 : seg;
   kde::ColItems it;
-  kde::make_items(n, kde::pick_seg(&o, n, kde::kSegRefHC), it);
+  if (n_h > 0)
+    kde::make_items(n, kde::capped_seg(&o, n, kde::kSegRefHC, (double)((n_h + kde::kSegRefHC - 1) / kde::kSegRefHC)),
+                    it);
+  else
+    kde::make_items(n, kde::capped_seg(&o, n, 1, 1.0), it);
   const int32_t m = (int32_t)it.pairs.size();
   *n_items = m;
   for (int32_t k = 0; k < std::min(m, cap); ++k) {

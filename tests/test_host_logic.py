@@ -8,8 +8,8 @@ import pytest
 import paper_1505_01998_amd as kde
 
 
-def _covered(n, seg):
-    i0, jb, je, pr = kde.kde_plan_items(n, seg)
+def _covered(n, seg, n_h=128):
+    i0, jb, je, pr = kde.kde_plan_items(n, n_h, seg)
     count = np.zeros((n, n), np.int32)
     for a, b, e, p in zip(i0, jb, je, pr):
         assert a % 256 == 0 and (b - a) % 512 == 0 and (e - a) % 512 == 0 and b < e
@@ -26,16 +26,17 @@ def _covered(n, seg):
 
 @pytest.mark.parametrize("n", [2, 3, 255, 256, 257, 511, 512, 513, 1000, 3001])
 @pytest.mark.parametrize("seg", [-1, 0, 512, 700, 1536])
-def test_items_cover_the_triangle_exactly_once(n, seg):
-    count, pr = _covered(n, seg)
+@pytest.mark.parametrize("n_h", [0, 128])
+def test_items_cover_the_triangle_exactly_once(n, seg, n_h):
+    count, pr = _covered(n, seg, n_h)
     iu = np.triu_indices(n, 1)
     assert np.all(count[iu] == 1)
     assert count.sum() == n * (n - 1) // 2 == pr.sum()
 
 
-@pytest.mark.parametrize("n", [1_000_000, 2_000_000, 123_457])
-def test_items_at_full_size(n):
-    i0, jb, je, pr = kde.kde_plan_items(n, -1)
+@pytest.mark.parametrize("n,n_h", [(1_000_000, 512), (2_000_000, 128), (123_457, 256), (1_000_000, 0)])
+def test_items_at_full_size(n, n_h):
+    i0, jb, je, pr = kde.kde_plan_items(n, n_h, -1)
     assert pr.sum() == n * (n - 1) / 2
     assert np.all(pr > 0) and np.all(np.diff(pr) <= 0)
     assert i0.max() < n and jb.min() >= 0
@@ -49,10 +50,22 @@ def test_items_at_full_size(n):
 
 
 def test_plan_items_errors():
-    for n in (1, 0, -5, (1 << 30) + 1):
+    for n, n_h in ((1, 10), (0, 10), (-5, 10), ((1 << 30) + 1, 10), (1000, -1), (1000, 65537)):
         with pytest.raises(kde.KdeError) as e:
-            kde.kde_plan_items(n)
+            kde.kde_plan_items(n, n_h)
         assert e.value.status == kde.KDE_E_INVAL
+
+
+def test_unit_count_is_bounded_for_very_large_columns():
+    """The automatic cut lengthens items so that a pass holds at most 2^24
+    units (items x 16-bandwidth chunks); at the workloads' sizes it does not
+    act (the n = 1e6 cut is the launch-size rule's)."""
+    m = kde.kde_plan_items(20_000_000, 512)[0].size
+    assert m * 32 <= 1 << 24
+    assert kde.kde_plan_items(20_000_000, 0)[0].size <= 1 << 24
+    a = kde.kde_plan_items(1_000_000, 512)[2]
+    b = kde.kde_plan_items(1_000_000, 16)[2]
+    assert np.array_equal(a, b)
 
 
 def test_footprint_grows_with_the_request():
@@ -68,7 +81,7 @@ def test_footprint_grows_with_the_request():
     assert fp(10_000, dtype=np.float64) > fp(10_000)
     # at least the padded FP32 copy and the FP64 partial slab of the LSCV pass
     n, n_h = 1_000_000, 128
-    items = kde.kde_plan_items(n)[0].size
+    items = kde.kde_plan_items(n, n_h)[0].size
     assert fp(n) >= 4 * (n + 768) + 16 * n_h * items
     assert fp(n) % 256 == 0
 
