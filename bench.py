@@ -50,9 +50,9 @@ PLANNER_BEGIN, PLANNER_END = "// ---- work items", "size_t take("
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32<16>",
-    "sources_sha256": "3e48efe43e230428c1b1ceeb9cdc15d0967f38397dc21b0b3bba192f0b00bfe7",
-    "fetch_bytes": 2.6870e7,
-    "write_bytes": 8.5995e6,
+    "sources_sha256": "8d01c9aa1c8a66ca097728eb10053796ddd1429fd8508ef526a962578d57d886",
+    "fetch_bytes": 2.6886e7,
+    "write_bytes": 8.5991e6,
 }
 
 
