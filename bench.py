@@ -178,6 +178,8 @@ def _apply_options(ctx, args):
         ctx.set_option("autotune", args.autotune)
     if args.graph >= 0:
         ctx.set_option("graph", args.graph)
+    if getattr(args, "prune", -1) >= 0:
+        ctx.set_option("prune", args.prune)
 
 
 def _lscv_kernel(ctx, args, n, n_h):
@@ -185,6 +187,9 @@ def _lscv_kernel(ctx, args, n, n_h):
     the job's largest column when tuning is on)."""
     if args.precision != "mixed":
         return "k_lscv_units_f64<8>"
+    if args.prune > 0:
+        hc = ctx.autotune(n, n_h)[0] if args.autotune > 0 else (args.hc if args.hc > 0 else 16)
+        return f"k_lscv_units_prune<{hc}> (evals counted dense)"
     if args.autotune > 0:
         return f"k_lscv_units_f32<{ctx.autotune(n, n_h)[0]}>"
     if args.mfma > 0:
@@ -362,6 +367,8 @@ def main():
     ap.add_argument("--hc", type=int, default=-1, help="bandwidths per LSCV pass (8, 16, 32; -1 = default)")
     ap.add_argument("--seg", type=int, default=-1, help="j-range per work item (-1 = automatic, 0 = whole rows)")
     ap.add_argument("--mfma", type=int, default=-1, help="LSCV arguments on the matrix cores (1/0; -1 = default)")
+    ap.add_argument("--prune", type=int, default=-1,
+                    help="LSCV tile pruning on sorted samples (1/0; -1 = default, off)")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay captured HIP graphs of repeated jobs (1/0; -1 = default, off)")
     ap.add_argument("--autotune", type=int, default=-1,
@@ -405,7 +412,15 @@ def main():
     ctx = kde.Context(0, args.precision)
     _apply_options(ctx, args)
 
+    performed = []
+
     def step():
+        if args.prune > 0:
+            # one job for both selectors, so the performed LSCV evaluations come back
+            r = ctx.batch([kde.Request(xd, kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, w.stages, w.grid)])[0]
+            assert r.status == kde.KDE_OK, r.status
+            performed.append(r.lscv_evals / r.lscv_evals_dense)
+            return r.h_plugin, r.plugin, r.g, r.gscale
         h_pi, info = ctx.bw_plugin(xd, w.stages)
         g, gs, _ = ctx.lscv_curve(xd, w.grid)
         return h_pi, info, g, gs
@@ -455,7 +470,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "family": w.family, "n": n, "n_h": n_h, "plugin_stages": w.stages,
                    "precision": args.precision, "input_dtype": str(np.dtype(w.dtype)), "autotune": args.autotune > 0,
-                   "graph": use_graph, "graph_captures_replays": list(graph_stats)},
+                   "graph": use_graph, "graph_captures_replays": list(graph_stats), "prune": args.prune > 0},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -472,6 +487,11 @@ def main():
         },
         "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals},
         "result": {"h_plugin": h_pi, "h_lscv": float(w.grid[int(np.argmin(g))]), "k_lscv": int(np.argmin(g))},
+        "prune": None if args.prune <= 0 else {
+            "performed_frac": performed[-1],
+            "performed_evals_per_s": (pairs * n_h * performed[-1] + pairs * w.stages) / (ms_step * 1e-3),
+            "note": "value counts the dense method's evaluations; the pruned sweep skips tiles whose total is "
+                    "below 2^-34 of every sum"},
     }
     if args.accuracy and args.precision == "mixed":
         out["accuracy"] = accuracy(kde, xd, w, h_pi, info, g, gs)

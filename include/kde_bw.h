@@ -123,6 +123,19 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  first use when the job holds at least 1e13 pair-term
  *                  evaluations; smaller jobs use a cached decision or
  *                  lscv_hc).  Results are bitwise those of any lscv_hc.
+ *   "prune"        1: LSCV tile pruning on sorted samples (mixed precision,
+ *                  synchronous calls and kde_batch; kde_server_start refuses
+ *                  it).  Each LSCV column is sorted on the device (the pair
+ *                  sums do not depend on the order); the first j-tile of every
+ *                  row gives lower bounds L(h) of the positive pair sums; a
+ *                  256 x 512 tile farther from its row than the chunk's cut
+ *                  is skipped when even its largest possible terms add up,
+ *                  over all skipped tiles, to less than 2^-34 L(h) for S1 and
+ *                  S2 and every h of the chunk.  Results stay within 2^-34 of
+ *                  the dense sums on top of the arithmetic error;
+ *                  kde_result.lscv_evals counts what was evaluated.  The
+ *                  plug-in passes are unchanged.  Graph replay is off while
+ *                  pruning.
  *   "graph"        1: the kernel launches of a synchronous call or kde_batch
  *                  are captured into a HIP graph; a later call with the same
  *                  signature (per request: validity, n, dtype, host/device,
@@ -259,6 +272,8 @@ typedef struct {
   double* g_out;           /* caller-owned [n_h] for g(h), or NULL */
   double* gscale_out;      /* caller-owned [n_h], or NULL */
   double t_queue_s, t_service_s; /* served requests: time queued, time admitted to done */
+  double lscv_evals_dense;  /* LSCV pair-term evaluations of the method: n(n-1)/2 * n_h */
+  double lscv_evals;        /* of them performed (less with the "prune" option) */
 } kde_result;
 
 /* Device memory one request needs in a job or a server slot (its column

@@ -101,6 +101,8 @@ class kde_result(ctypes.Structure):
         ("gscale_out", ctypes.POINTER(ctypes.c_double)),
         ("t_queue_s", ctypes.c_double),
         ("t_service_s", ctypes.c_double),
+        ("lscv_evals_dense", ctypes.c_double),
+        ("lscv_evals", ctypes.c_double),
     ]
 
 
@@ -399,6 +401,8 @@ class Result:
     gscale: np.ndarray
     t_queue_s: float = 0.0
     t_service_s: float = 0.0
+    lscv_evals_dense: float = 0.0
+    lscv_evals: float = 0.0
 
 
 def _make_request(r: Request):
@@ -430,7 +434,7 @@ def _unpack_result(res: kde_result, g, gs) -> Result:
     info = PluginInfo(p.sigma, p.h_rot, p.stages, tuple(p.g), tuple(p.psi), tuple(p.kappa),
                       tuple(p.precision_used), p.h)
     return Result(res.status, res.sigma, res.h_rot, res.h_plugin, res.h_lscv, res.k_lscv, bool(res.at_edge), info,
-                  g, gs, res.t_queue_s, res.t_service_s)
+                  g, gs, res.t_queue_s, res.t_service_s, res.lscv_evals_dense, res.lscv_evals)
 
 
 def kde_batch(ctx, requests):

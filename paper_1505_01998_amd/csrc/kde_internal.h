@@ -52,6 +52,7 @@ struct DevState {
   double fp64_kappa;  // kappa threshold for the FP64 re-run (0 = never)
   float cf[2];      // FP32 pair coefficients of the current psi pass: 1/g^2, -log2(e)/(2 g^2)
   double cd[2];     // FP64 pair coefficients: 1/g^2, -1/(2 g^2)
+  double pruned_evals;  // LSCV pair-term evaluations skipped by tile pruning (exact count)
 };
 
 // One column of a job: where its data, coefficients, partial sums and state
@@ -73,6 +74,8 @@ struct ColDesc {
   double* sums;         // LSCV pair sums [2 n_h]
   double* g;            // g(h) [n_h]
   double* gs;           // gscale(h) [n_h]
+  double* near_sums;    // tile pruning: pair sums of each row's first j-tile [2 n_h] (lower bounds)
+  float* d2cut;         // tile pruning: squared distance beyond which a tile is skipped, per chunk
   DevState* st;
   int n;
   int raw_f64;
@@ -114,8 +117,16 @@ void launch_lscv_finalize(hipStream_t s, const ColDesc* cols, const int* ids, in
 void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColDesc* cols, const Unit* units, int u0,
                       int n_units);
 // mfma: use the matrix-core variant (FP32, 16 bandwidths per unit only).
-void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, const ColDesc* cols, const Unit* units, int u0,
-                       int n_units);
+// Tile pruning: per column, the cut distance of every bandwidth chunk from
+// the near-tile sums (relative bound eps on every skipped share).
+void launch_lscv_prune_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int hc, double eps);
+void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, int prune, const ColDesc* cols, const Unit* units,
+                       int u0, int n_units);
 void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows);
+
+// ---- ascending sort of FP32 keys (kde_sort.hip): temporary bytes for
+// `count` keys (0 on failure), and the sort itself.
+size_t sort_temp_bytes(int count);
+hipError_t sort_keys(void* tmp, size_t tmp_bytes, const float* in, float* out, int count, hipStream_t s);
 
 }  // namespace kde

@@ -572,6 +572,122 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __re
   }
 }
 
+// Tile pruning on sorted samples: the same sweep over a column sorted
+// ascending, whose j-tiles therefore lie at growing distance from the unit's
+// row of i.  A uniform scan of the tiles' first samples finds the first tile
+// whose smallest distance to the row exceeds the chunk's cut (every later
+// tile is farther still); the sweep stops there and the skipped pairs are
+// counted exactly.
+template <int HC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 1)))
+void k_lscv_units_prune(const ColDesc* __restrict__ cols, const Unit* __restrict__ units, int u0) {
+  const Unit u = units[u0 + blockIdx.x];
+  const ColDesc c = cols[u.col];
+  if (c.st->status != kStOk) return;
+  const float* x = c.x32;
+  const int n = c.n;
+  const int row0 = u.row * kBI;
+  int j_end = u.j_end;
+  {
+    const float row_max = x[min(row0 + kBI, n) - 1];
+    const float cut = c.d2cut[u.chunk];
+    for (int t = u.j_begin; t < u.j_end; t += kBJ) {
+      const float dd = x[t] - row_max;
+      if (dd > 0.f && dd * dd > cut) {
+        j_end = t;
+        break;
+      }
+    }
+  }
+  __shared__ float4 tile[kBJ / 4];
+  __shared__ double red[4][2 * HC];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = row0 + tid;
+  const float xi = (i < n) ? x[i] : 0.f;
+  const int wave_i0 = row0 + wave * 64;
+  const float* cc = c.c32 + u.chunk * HC;
+  float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
+#pragma unroll
+  for (int k = 0; k < HC; ++k) {
+    ck[k] = cc[k];
+    a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
+  }
+  for (int t0 = u.j_begin; t0 < j_end; t0 += kBJ) {
+    __syncthreads();
+    for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
+    __syncthreads();
+    int js = max(t0, wave_i0);
+    const int te = t0 + kBJ;
+    if (js < te) {
+      if (js == wave_i0) {
+        lscv_run<HC, true>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
+        js += kRun;
+      }
+      for (; js < te; js += kRun) lscv_run<HC, false>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
+    }
+  }
+  if (tid == 0 && j_end < u.j_end && j_end < n) {
+    // every skipped tile lies right of the row (distance > 0): all its pairs count
+    const double rows = (double)min(kBI, n - row0);
+    const double hv = (double)min(HC, c.n_h - u.chunk * HC);
+    atomicAdd(&c.st->pruned_evals, rows * (double)(min(u.j_end, n) - j_end) * hv);
+  }
+  const bool valid = i < n;
+#pragma unroll
+  for (int k = 0; k < HC; ++k) {
+    const double v1 = wave_sum(valid ? (double)a1[k] - (double)c1[k] : 0.0);
+    const double v2 = wave_sum(valid ? (double)a2[k] - (double)c2[k] : 0.0);
+    if (lane == 0) {
+      red[wave][2 * k] = v1;
+      red[wave][2 * k + 1] = v2;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * HC) {
+    const int h = u.chunk * HC + (tid >> 1);
+    if (h < c.n_h) {
+      const double v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+      c.part[(int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
+    }
+  }
+}
+
+// Tile pruning (mixed form, sorted column): per bandwidth chunk the squared
+// distance D2 beyond which a 256 x 512 tile is skipped.  A skipped tile holds
+// at most 2^17 pairs, each term at most exp2(c_max D^2) (c_max: the chunk's
+// coefficient closest to zero, i.e. its largest h) for S1 and its square for
+// S2.  With T an upper bound on the (row, tile) pairs of the column and L1,
+// L2 the smallest near-tile sums (lower bounds of S1, S2: all terms are
+// positive) over the chunk's bandwidths, a tile is skipped only when 2^17
+// exp2(c_max D^2) < eps L1 / T and 2^17 exp2(2 c_max D^2) < eps L2 / T, so
+// everything skipped is below eps S1(h) and eps S2(h) for every h of the
+// chunk.
+__global__ __launch_bounds__(kThreads) void k_lscv_prune_prep(const ColDesc* __restrict__ cols,
+                                                              const int* __restrict__ ids, int hc, double eps) {
+  const ColDesc c = cols[ids[blockIdx.x]];
+  if (c.n_h <= 0 || c.st->status != kStOk) return;
+  const double n = (double)c.n;
+  const double rows = ceil(n / kBI);
+  const double T = rows * (ceil(n / kBJ) + 1.0);
+  const double lt = log2(eps / (T * (double)kBI * (double)kBJ));
+  for (int ch = threadIdx.x; ch < c.n_chunks; ch += blockDim.x) {
+    double l1 = kInfD, l2 = kInfD, cmax = -kInfD;
+    for (int k = ch * hc; k < min(c.n_h, (ch + 1) * hc); ++k) {
+      l1 = fmin(l1, c.near_sums[2 * k]);
+      l2 = fmin(l2, c.near_sums[2 * k + 1]);
+      cmax = fmax(cmax, (double)c.c32[k]);
+    }
+    double cut = kInfD;
+    if (l1 > 0.0 && l2 > 0.0 && cmax < 0.0) {
+      const double d1 = (lt + log2(l1)) / cmax;
+      const double d2 = (lt + log2(l2)) / (2.0 * cmax);
+      cut = fmax(d1, d2) * (1.0 + 1e-6) + 1e-30;
+    }
+    c.d2cut[ch] = (float)cut;
+  }
+}
+
 template <int HC, bool MASK>
 __device__ __forceinline__ void lscv_run64(const double* __restrict__ tile, int jl, int jg, double xi, int i,
                                            const double (&ck)[HC], double (&s1)[HC], double (&s2)[HC]) {
@@ -920,9 +1036,17 @@ void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColD
   }
 }
 
-void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, const ColDesc* cols, const Unit* units, int u0,
-                       int n_units) {
+void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, int prune, const ColDesc* cols, const Unit* units,
+                       int u0, int n_units) {
   if (n_units <= 0) return;
+  if (prune && !f64) {
+    switch (hc) {
+      case 8: k_lscv_units_prune<8><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      case 32: k_lscv_units_prune<32><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+      default: k_lscv_units_prune<16><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
+    }
+    return;
+  }
   if (mfma && !f64 && hc == 16) {
     k_lscv_units_mfma<<<n_units, kThreads, 0, s>>>(cols, units, u0);
     return;
@@ -939,6 +1063,10 @@ void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, const ColDesc* 
       default: k_lscv_units_f32<16><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
     }
   }
+}
+
+void launch_lscv_prune_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int hc, double eps) {
+  if (n_ids > 0) k_lscv_prune_prep<<<n_ids, kThreads, 0, s>>>(cols, ids, hc, eps);
 }
 
 void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows) {

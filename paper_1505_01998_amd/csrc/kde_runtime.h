@@ -50,12 +50,24 @@ struct ColPlan {
   double grid_lo = 0.0, grid_hi = 0.0;
   std::vector<double> grid_h;  // explicit grid
   ColItems psi_items, lscv_items;
+  // tile pruning (mixed form, LSCV): a sorted copy of the column, the first
+  // j-tile of every row as "near" items, and per-chunk cut distances
+  bool prune = false;
+  ColItems near_items;
+  size_t off_xs = 0, off_near_part = 0, off_near_sums = 0, off_d2cut = 0;
   // device block layout (byte offsets); raw holds the samples of a host column
   bool want_x64 = false;
   bool raw_in_block = false;
   size_t raw_bytes = 0, off_raw = 0;
   size_t off_x32 = 0, off_x64 = 0, off_stat = 0, off_nf = 0, off_psi_part = 0, off_psi_sums = 0, off_hin = 0,
          off_h = 0, off_c32 = 0, off_c64 = 0, off_part = 0, off_sums = 0, off_g = 0, off_gs = 0, bytes = 0;
+};
+
+// A sort of one column's padded FP32 copy (tile pruning).
+struct SortJob {
+  const float* in;
+  float* out;
+  int count;
 };
 
 // Everything one pass of the executor launches, in order: moments, the
@@ -82,6 +94,14 @@ struct IterPlan {
   std::vector<UnitCost> lscv_cost;
   std::vector<RowDesc> lscv_rows;
   std::vector<int> ids_lscv_final;
+  // tile pruning: sorts, near-tile units and rows, cut preparation, pruned units
+  std::vector<SortJob> sorts;
+  std::vector<Unit> near_units;
+  std::vector<UnitCost> near_cost;
+  std::vector<RowDesc> near_rows;
+  std::vector<int> ids_prune;
+  std::vector<Unit> prune_units;
+  std::vector<UnitCost> prune_cost;
   int max_stat_blocks = 1;
   void clear();
 };
@@ -89,7 +109,9 @@ struct IterPlan {
 // Byte offsets of one executor pass's arrays in the device blob.
 struct PassLayout {
   size_t o_cols = 0, o_stats = 0, o_pf = 0, o_lp = 0, o_lu = 0, o_lr = 0, o_lf = 0, bytes = 0;
-  size_t o_begin[3] = {0, 0, 0}, o_finish[3] = {0, 0, 0}, o_pu[3] = {0, 0, 0}, o_pr[3] = {0, 0, 0},
+  size_t o_nu = 0, o_nr = 0, o_pp = 0, o_pu = 0;  // tile pruning: near units/rows, prune ids, pruned units
+  size_t sort_tmp = 0;                            // temporary bytes of the largest sort
+  size_t o_begin[3] = {0, 0, 0}, o_finish[3] = {0, 0, 0}, o_psu[3] = {0, 0, 0}, o_pr[3] = {0, 0, 0},
          o_pc[3] = {0, 0, 0};
 };
 
@@ -116,6 +138,9 @@ struct JobGraph {
 };
 
 constexpr size_t kMaxGraphs = 8;
+// Tile pruning: the skipped share of every pair sum is below this fraction
+// of the sum (2^-34).
+constexpr double kPruneEps = 5.820766091346741e-11;
 
 // Variant of the LSCV pass chosen by the tile autotuner for one shape.
 struct TuneChoice {
@@ -146,6 +171,8 @@ struct kde_ctx {
   double opt_serve_iter_evals = 1e12;  // server: pair-term evaluations per iteration (minimum)
   int opt_autotune = 0;            // synchronous jobs pick the LSCV variant with the tile autotuner
   int opt_graph = 0;               // synchronous jobs replay a captured graph of their launches
+  int opt_prune = 0;               // LSCV tile pruning on sorted samples (mixed form, synchronous jobs)
+  kde::DevBuf<char> sort_tmp;      // temporary storage of the column sorts
   std::vector<kde::JobGraph> graphs;  // at most kde::kMaxGraphs, least recently used replaced
   uint64_t graph_clock = 0;
   int64_t graph_captures = 0, graph_replays = 0;
@@ -221,8 +248,10 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p);
 void bind_column(const ColPlan& p, char* block, const void* raw, DevState* st, ColDesc& d);
 // Appends a column's whole work (moments, every plug-in stage, the LSCV pass)
 // to an executor plan; host_raw / host grid are uploaded into the block.
+// extra_id: with tile pruning, the index of the column's two extra
+// descriptors (near tiles, pruned sweep) in the pass's column table, else -1.
 void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int id, const void* host_raw,
-                     IterPlan& it);
+                     IterPlan& it, int extra_id = -1);
 // Pieces used by the server to schedule a column's work over several passes.
 void psi_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost);
 void lscv_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost);

@@ -81,6 +81,13 @@ void IterPlan::clear() {
   lscv_cost.clear();
   lscv_rows.clear();
   ids_lscv_final.clear();
+  sorts.clear();
+  near_units.clear();
+  near_cost.clear();
+  near_rows.clear();
+  ids_prune.clear();
+  prune_units.clear();
+  prune_cost.clear();
   max_stat_blocks = 1;
 }
 
@@ -223,6 +230,17 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
     p.grid_hi = r.grid.hi;
     if (r.grid.kind == KDE_GRID_EXPLICIT) p.grid_h.assign(r.grid.h, r.grid.h + p.n_h);
     make_items(p.n, capped_seg(c, p.n, kSegRefHC, (double)((p.n_h + kSegRefHC - 1) / kSegRefHC)), p.lscv_items);
+    p.prune = c->opt_prune && !all64;
+    if (p.prune) {
+      // the first j-tile of every row: j in [row0, row0 + kBJ)
+      const int rows = (p.n + kBI - 1) / kBI;
+      for (int r = 0; r < rows; ++r) {
+        p.near_items.row.push_back(r);
+        p.near_items.jb.push_back(r * kBI);
+        p.near_items.je.push_back(r * kBI + kBJ);
+        p.near_items.pairs.push_back(item_pairs(p.n, r, (int64_t)r * kBI, (int64_t)r * kBI + kBJ));
+      }
+    }
   }
   p.want_x64 = all64 || (p.plugin && c->opt_fp64_kappa > 0.0);
   p.raw_in_block = !r.x.on_device;
@@ -248,6 +266,12 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
     p.off_sums = take(at, 16 * (size_t)p.n_h);
     p.off_g = take(at, 8 * (size_t)p.n_h);
     p.off_gs = take(at, 8 * (size_t)p.n_h);
+    if (p.prune) {
+      p.off_xs = take(at, 4 * xn);
+      p.off_near_part = take(at, 16 * (size_t)p.n_h * p.near_items.pairs.size());
+      p.off_near_sums = take(at, 16 * (size_t)p.n_h);
+      p.off_d2cut = take(at, 4 * (size_t)p.n_chunks);
+    }
   }
   p.bytes = at;
   return "";
@@ -273,6 +297,10 @@ void bind_column(const ColPlan& p, char* b, const void* raw, DevState* st, ColDe
     d.sums = (double*)(b + p.off_sums);
     d.g = (double*)(b + p.off_g);
     d.gs = (double*)(b + p.off_gs);
+    if (p.prune) {
+      d.near_sums = (double*)(b + p.off_near_sums);
+      d.d2cut = (float*)(b + p.off_d2cut);
+    }
   }
   d.st = st;
   d.n = p.n;
@@ -326,7 +354,7 @@ void lscv_rows_of(const ColPlan& p, const ColDesc& d, std::vector<RowDesc>& rows
 }
 
 void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int id, const void* host_raw,
-                     IterPlan& it) {
+                     IterPlan& it, int extra_id) {
   if ((int)it.cols.size() <= id) it.cols.resize(id + 1);
   it.cols[id] = d;
   if (p.raw_in_block) it.uploads.push_back(Upload{(void*)d.raw, host_raw, p.raw_bytes});
@@ -347,7 +375,31 @@ void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int i
     if (p.grid_kind == KDE_GRID_EXPLICIT)
       it.uploads.push_back(Upload{(void*)d.h_in, p.grid_h.data(), sizeof(double) * p.n_h});
     it.ids_lscv_prep.push_back(id);
-    lscv_units_of(p, id, it.lscv_units, it.lscv_cost);
+    if (p.prune && extra_id >= 0) {
+      // near descriptor: sorted copy, near-tile slab; sweep descriptor: sorted copy, main slab
+      ColDesc nd = d, sd = d;
+      float* xs = (float*)((char*)d.x32 - p.off_x32 + p.off_xs);
+      nd.x32 = sd.x32 = xs;
+      nd.part = (double*)((char*)d.x32 - p.off_x32 + p.off_near_part);
+      nd.n_items = (int)p.near_items.pairs.size();
+      if ((int)it.cols.size() < extra_id + 2) it.cols.resize(extra_id + 2);
+      it.cols[extra_id] = nd;
+      it.cols[extra_id + 1] = sd;
+      it.sorts.push_back(SortJob{d.x32, xs, p.n + kPad});
+      const int m = (int)p.near_items.pairs.size();
+      for (int r = 0; r < m; ++r)
+        for (int ch = 0; ch < p.n_chunks; ++ch) {
+          it.near_units.push_back(Unit{extra_id, p.near_items.row[r], p.near_items.jb[r], p.near_items.je[r], r, ch});
+          const int valid = std::min(p.hc, p.n_h - ch * p.hc);
+          it.near_cost.push_back(UnitCost{p.near_items.pairs[r], p.near_items.pairs[r] * valid});
+        }
+      for (int r = 0; r < 2 * p.n_h; ++r)
+        it.near_rows.push_back(RowDesc{nd.part + (size_t)r * m, d.near_sums + r, m, 0});
+      it.ids_prune.push_back(id);
+      lscv_units_of(p, extra_id + 1, it.prune_units, it.prune_cost);
+    } else {
+      lscv_units_of(p, id, it.lscv_units, it.lscv_cost);
+    }
     lscv_rows_of(p, d, it.lscv_rows);
     it.ids_lscv_final.push_back(id);
   }
@@ -393,10 +445,26 @@ kde_status collect_timing(kde_ctx* c) {
 
 // Sorts units largest first (the order blocks are dispatched in); results do
 // not depend on it, since every unit writes its own partial-sum slot.
-void sort_units(std::vector<Unit>& u, std::vector<UnitCost>& cost) {
+// scatter: units of equal planned size are put in a fixed pseudo-random
+// order instead of (item, chunk) order.  With tile pruning their real cost
+// depends strongly on the chunk (small bandwidths skip most tiles), and
+// consecutive blocks are dealt round-robin to the chip's eight dies, so in
+// (item, chunk) order each die would always get the same chunks.
+void sort_units(std::vector<Unit>& u, std::vector<UnitCost>& cost, bool scatter = false) {
   std::vector<size_t> o(u.size());
   for (size_t k = 0; k < o.size(); ++k) o[k] = k;
-  std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) { return cost[a].pairs > cost[b].pairs; });
+  std::vector<uint32_t> key(scatter ? u.size() : 0);
+  for (size_t k = 0; k < key.size(); ++k) {
+    uint32_t h = (uint32_t)u[k].item * 0x9E3779B1u ^ (uint32_t)u[k].chunk * 0x85EBCA77u ^ (uint32_t)u[k].col;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    key[k] = h;
+  }
+  std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) {
+    if (cost[a].pairs != cost[b].pairs) return cost[a].pairs > cost[b].pairs;
+    return scatter && key[a] < key[b];
+  });
   std::vector<Unit> u2(u.size());
   std::vector<UnitCost> c2(u.size());
   for (size_t k = 0; k < o.size(); ++k) {
@@ -459,6 +527,8 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
     sort_units(it.psi_cond_units[q], it.psi_cond_cost[q]);
   }
   sort_units(it.lscv_units, it.lscv_cost);
+  sort_units(it.near_units, it.near_cost);
+  sort_units(it.prune_units, it.prune_cost, true);
   // one blob: column table, id lists, units, rows
   Blob b;
   auto vbytes = [](const auto& v) { return v.size() * sizeof(v[0]); };
@@ -467,7 +537,7 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
   for (int q = 0; q < 3; ++q) {
     L.o_begin[q] = b.add(it.ids_begin[q].data(), vbytes(it.ids_begin[q]));
     L.o_finish[q] = b.add(it.ids_finish[q].data(), vbytes(it.ids_finish[q]));
-    L.o_pu[q] = b.add(it.psi_units[q].data(), vbytes(it.psi_units[q]));
+    L.o_psu[q] = b.add(it.psi_units[q].data(), vbytes(it.psi_units[q]));
     L.o_pr[q] = b.add(it.psi_rows[q].data(), vbytes(it.psi_rows[q]));
     L.o_pc[q] = b.add(it.psi_cond_units[q].data(), vbytes(it.psi_cond_units[q]));
   }
@@ -476,7 +546,18 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
   L.o_lu = b.add(it.lscv_units.data(), vbytes(it.lscv_units));
   L.o_lr = b.add(it.lscv_rows.data(), vbytes(it.lscv_rows));
   L.o_lf = b.add(it.ids_lscv_final.data(), vbytes(it.ids_lscv_final));
+  L.o_nu = b.add(it.near_units.data(), vbytes(it.near_units));
+  L.o_nr = b.add(it.near_rows.data(), vbytes(it.near_rows));
+  L.o_pp = b.add(it.ids_prune.data(), vbytes(it.ids_prune));
+  L.o_pu = b.add(it.prune_units.data(), vbytes(it.prune_units));
   L.bytes = b.bytes;
+  L.sort_tmp = 0;
+  for (const SortJob& j : it.sorts) {
+    const size_t t = kde::sort_temp_bytes(j.count);
+    if (t == 0) return fail(c, KDE_E_DEVICE, "sort temporary size query failed");
+    L.sort_tmp = std::max(L.sort_tmp, t);
+  }
+  if (L.sort_tmp && (s = ensure(c, c->sort_tmp, L.sort_tmp))) return s;
   if ((s = ensure_pinned_bytes(c, c->h_blob, c->h_blob_cap, b.bytes + 256))) return s;
   if ((s = ensure(c, c->blob, b.bytes + 256))) return s;
   for (size_t k = 0; k < b.parts.size(); ++k)
@@ -505,7 +586,7 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
     if (it.ids_begin[q].empty() && it.psi_units[q].empty() && it.ids_finish[q].empty()) continue;
     const int r = 8 - 2 * q;
     kde::launch_psi_begin(st, cols, ids(L.o_begin[q]), (int)it.ids_begin[q].size(), q);
-    const Unit* pu = (const Unit*)(d + L.o_pu[q]);
+    const Unit* pu = (const Unit*)(d + L.o_psu[q]);
     s = for_each_launch(c, it.psi_cost[q], all64, [&](int u0, int cnt, double evals) -> kde_status {
       kde_ctx::Pending pd{nullptr, nullptr, kde::kFamPsi, evals};
       kde_status s2 = timed_begin(c, pd);
@@ -533,12 +614,34 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
   // LSCV
   const int hc = all64 ? 8 : c->job_hc;
   kde::launch_lscv_prep(st, cols, ids(L.o_lp), (int)it.ids_lscv_prep.size(), hc);
+  if (!it.sorts.empty()) {
+    // tile pruning: sort, near-tile lower bounds, cut distances
+    for (const SortJob& j : it.sorts)
+      KDE_HIP_TRY(c, kde::sort_keys(c->sort_tmp.p, L.sort_tmp, j.in, j.out, j.count, st));
+    const Unit* nu = (const Unit*)(d + L.o_nu);
+    s = for_each_launch(c, it.near_cost, false, [&](int u0, int cnt, double) -> kde_status {
+      kde::launch_lscv_units(st, hc, 0, 0, 0, cols, nu, u0, cnt);
+      return KDE_OK;
+    });
+    if (s) return s;
+    kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_nr), (int)it.near_rows.size());
+    kde::launch_lscv_prune_prep(st, cols, ids(L.o_pp), (int)it.ids_prune.size(), hc, kPruneEps);
+    const Unit* pru = (const Unit*)(d + L.o_pu);
+    s = for_each_launch(c, it.prune_cost, false, [&](int u0, int cnt, double evals) -> kde_status {
+      kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
+      kde_status s2 = timed_begin(c, pd);
+      if (s2) return s2;
+      kde::launch_lscv_units(st, hc, 0, 0, 1, cols, pru, u0, cnt);
+      return timed_end(c, pd);
+    });
+    if (s) return s;
+  }
   const Unit* lu = (const Unit*)(d + L.o_lu);
   s = for_each_launch(c, it.lscv_cost, all64, [&](int u0, int cnt, double evals) -> kde_status {
     kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
     kde_status s2 = timed_begin(c, pd);
     if (s2) return s2;
-    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->job_mfma, cols, lu, u0, cnt);
+    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->job_mfma, 0, cols, lu, u0, cnt);
     return timed_end(c, pd);
   });
   if (s) return s;
@@ -718,7 +821,7 @@ kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std:
   st.assign(n_req, KDE_OK);
   msg.assign(n_req, "");
   if ((s = kde::select_variant(c, reqs, n_req))) return s;
-  const bool use_graph = c->opt_graph && !c->timing && c->stream != nullptr;
+  const bool use_graph = c->opt_graph && !c->opt_prune && !c->timing && c->stream != nullptr;
   std::string sig;
   if (use_graph) {
     for (int32_t k = 0; k < n_req; ++k) {
@@ -759,12 +862,14 @@ kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std:
   c->h_st = reinterpret_cast<DevState*>(hs);
   kde::IterPlan& it = c->iter;
   it.clear();
+  int extra = n_cols;  // tile pruning: two more descriptors per pruned column
   for (int k = 0; k < n_cols; ++k) {
     const kde::ColPlan& p = c->plans[k];
     const kde_request& r = reqs[c->plan_req[k]];
     ColDesc d;
     kde::bind_column(p, c->blocks.p + at[k], r.x.data, c->st.p + k, d);
-    kde::add_full_column(c, p, d, k, r.x.data, it);
+    kde::add_full_column(c, p, d, k, r.x.data, it, p.prune ? extra : -1);
+    if (p.prune) extra += 2;
     kde::init_state(p, c->opt_fp64_kappa, c->h_st[k]);
   }
   KDE_HIP_TRY(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(DevState) * n_cols, hipMemcpyHostToDevice, c->stream));
@@ -854,6 +959,8 @@ void fill_result(const ColPlan& p, const DevState& h, kde_result& r) {
     r.h_lscv = h.h_best;
     r.k_lscv = h.k_best;
     r.at_edge = h.at_edge;
+    r.lscv_evals_dense = 0.5 * (double)p.n * (double)(p.n - 1) * (double)p.n_h;
+    r.lscv_evals = r.lscv_evals_dense - h.pruned_evals;
   }
 }
 }  // namespace kde
@@ -943,6 +1050,8 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_fp64_kappa = value < 0 ? 1e3 : (double)value;
   } else if (k == "lscv_mfma") {
     c->opt_mfma = value < 0 ? 0 : (value != 0);
+  } else if (k == "prune") {
+    c->opt_prune = value < 0 ? 0 : (value != 0);
   } else if (k == "graph") {
     c->opt_graph = value < 0 ? 0 : (value != 0);
   } else if (k == "autotune") {
@@ -966,6 +1075,7 @@ kde_status kde_request_footprint(const kde_ctx* c, const kde_request* r, uint64_
     o.opt_seg = c->opt_seg;
     o.opt_launch_evals = c->opt_launch_evals;
     o.opt_fp64_kappa = c->opt_fp64_kappa;
+    o.opt_prune = c->opt_prune;
   }
   o.job_hc = o.opt_hc;
   kde::ColPlan p;

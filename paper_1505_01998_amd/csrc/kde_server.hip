@@ -317,6 +317,7 @@ kde_status kde_server_start(kde_ctx* c, uint64_t hbm_budget_bytes, int32_t max_s
   if (c->server && c->server->running) return fail(c, KDE_E_BUSY, "a server is already running");
   if (max_slots < 1 || max_slots > KDE_MAX_BATCH || hbm_budget_bytes == 0)
     return fail(c, KDE_E_INVAL, "max_slots must be in [1, KDE_MAX_BATCH] and the budget > 0");
+  if (c->opt_prune) return fail(c, KDE_E_INVAL, "tile pruning (option prune) is for synchronous calls; turn it off");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   c->server.reset();
   // served requests run the LSCV variant the options name (the variant does

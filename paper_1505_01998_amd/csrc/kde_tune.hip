@@ -100,15 +100,15 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     // warm-up, then B units and 2B units back to back
     if (he == hipSuccess) {
-      launch_lscv_units(c->stream, hc, 0, 0, cols, dev_units, 0, kTrialUnits);
+      launch_lscv_units(c->stream, hc, 0, 0, 0, cols, dev_units, 0, kTrialUnits);
       he = hipEventRecord(ev[0], c->stream);
     }
     if (he == hipSuccess) {
-      launch_lscv_units(c->stream, hc, 0, 0, cols, dev_units, 0, kTrialUnits);
+      launch_lscv_units(c->stream, hc, 0, 0, 0, cols, dev_units, 0, kTrialUnits);
       he = hipEventRecord(ev[1], c->stream);
     }
     if (he == hipSuccess) {
-      launch_lscv_units(c->stream, hc, 0, 0, cols, dev_units, 0, B2);
+      launch_lscv_units(c->stream, hc, 0, 0, 0, cols, dev_units, 0, B2);
       he = hipEventRecord(ev[2], c->stream);
     }
     if (he == hipSuccess) he = hipGetLastError();

@@ -1,0 +1,101 @@
+"""Tile pruning on sorted samples (option "prune"): the LSCV sums may drop only
+tiles whose total is provably below 2^-34 of every sum, so results must agree
+with the dense form far inside the tolerance and with the oracle to it; the
+chosen grid index must not move; the evaluation count must shrink where
+samples are spread, and be exact (performed + skipped = dense)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+EPS = 2.0**-34
+
+
+@pytest.fixture(scope="module")
+def kde():
+    import paper_1505_01998_amd as kde
+
+    return kde
+
+
+def _pair(kde, reqs):
+    with kde.Context(0) as dense, kde.Context(0) as pr:
+        pr.set_option("prune", 1)
+        a = dense.batch(reqs)
+        b = pr.batch(reqs)
+    return a, b
+
+
+@pytest.mark.parametrize("family,n,grid", [
+    ("lognormal", 20011, np.geomspace(0.002, 0.6, 96)),
+    ("bimodal", 4099, np.geomspace(0.01, 2.0, 40)),
+    ("uniform", 257, np.geomspace(0.001, 0.3, 17)),
+    ("mixture", 100_000, np.geomspace(0.005, 2.0, 256)),
+])
+def test_pruned_equals_dense_and_oracle(kde, family, n, grid):
+    x = workloads.draw(family, n, 41, np.float32)
+    req = kde.Request(x, kde.KDE_METHOD_LSCV | kde.KDE_METHOD_PLUGIN, 3, grid)
+    (a,), (b,) = _pair(kde, [req])
+    assert a.status == b.status == kde.KDE_OK
+    # plug-in passes are not pruned: bitwise equal
+    assert a.h_plugin == b.h_plugin and a.plugin.psi == b.plugin.psi
+    # dense vs pruned: summation order differs (sorted samples) and at most
+    # 2^-34 of each sum is dropped
+    d = np.abs(a.g - b.g) / a.gscale
+    assert d.max() <= 1e-7, d.max()
+    assert b.k_lscv == a.k_lscv
+    assert a.lscv_evals == a.lscv_evals_dense == pytest.approx(n * (n - 1) / 2 * grid.size, rel=1e-15)
+    assert b.lscv_evals_dense == a.lscv_evals_dense and 0 < b.lscv_evals <= b.lscv_evals_dense
+    if n <= 20011:
+        o = oracle.lscv_curve(x, grid)
+        assert np.all(np.abs(b.g - o.g) <= TOL * o.gscale)
+        assert b.k_lscv == int(np.argmin(o.g)) or o.g[b.k_lscv] - o.g.min() <= 2 * np.abs(b.g - o.g).max()
+    print(f"{family} n={n}: performed {b.lscv_evals / b.lscv_evals_dense:.3f} of the dense evaluations, "
+          f"max |g_pruned - g_dense| / gscale {d.max():.2e}")
+
+
+def test_pruning_skips_far_tiles_and_counts_exactly(kde):
+    """Two far-apart clusters: every pair across them is negligible at small
+    h, so about half the dense evaluations are skipped; the raw sums stay
+    within the bound of the dense ones."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    n = 30000
+    x = np.concatenate([rng.normal(0.0, 1.0, n // 2), rng.normal(1000.0, 1.0, n - n // 2)]).astype(np.float32)
+    rng.shuffle(x)
+    grid = np.geomspace(0.01, 1.0, 32)
+    (a,), (b,) = _pair(kde, [kde.Request(x, kde.KDE_METHOD_LSCV, 2, grid)])
+    frac = b.lscv_evals / b.lscv_evals_dense
+    assert frac < 0.6, frac
+    assert b.lscv_evals == int(b.lscv_evals)  # an exact count
+    with kde.Context(0) as dense, kde.Context(0) as pr:
+        pr.set_option("prune", 1)
+        s_d = dense.lscv_sums(x, grid)
+        s_p = pr.lscv_sums(x, grid)
+    for sd, sp in zip(s_d, s_p):
+        assert np.all(sp <= sd * (1 + 1e-6)) and np.all(sd - sp <= 1e-6 * sd + EPS * sd)
+    print(f"two clusters: performed {frac:.3f} of the dense evaluations")
+
+
+def test_pruned_batch_results_equal_pruned_alone(kde):
+    A = kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV
+    reqs = [kde.Request(workloads.draw(f, 3000 + 1999 * k, 60 + k, np.float32), A, 3, workloads.BATCH_GRID)
+            for k, f in enumerate(workloads.BATCH_FAMILIES)]
+    with kde.Context(0) as pr:
+        pr.set_option("prune", 1)
+        batch = pr.batch(reqs)
+        alone = [pr.batch([r])[0] for r in reqs]
+    for a, b in zip(batch, alone):
+        assert a.status == b.status == kde.KDE_OK
+        assert np.array_equal(a.g, b.g) and a.k_lscv == b.k_lscv and a.lscv_evals == b.lscv_evals
+
+
+def test_prune_refused_by_the_server(kde):
+    with kde.Context(0) as c:
+        c.set_option("prune", 1)
+        with pytest.raises(kde.KdeError) as e:
+            c.server_start(1 << 30, 4)
+        assert e.value.status == kde.KDE_E_INVAL
