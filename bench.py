@@ -50,9 +50,9 @@ PLANNER_BEGIN, PLANNER_END = "// ---- work items", "size_t take("
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32<16>",
-    "sources_sha256": "8d01c9aa1c8a66ca097728eb10053796ddd1429fd8508ef526a962578d57d886",
-    "fetch_bytes": 2.6886e7,
-    "write_bytes": 8.5991e6,
+    "sources_sha256": "d560f63435d99aeb8de4eadc1bf570b3b27fa81e8821190b0ff20064a0636267",
+    "fetch_bytes": 2.6885e7,
+    "write_bytes": 8.5992e6,
 }
 
 
