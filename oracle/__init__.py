@@ -90,6 +90,7 @@ def _load():
     lib.orc_lscv_block_sums.argtypes = [PD, L, L, L, L, L, PD, I, PD, PD]
     lib.orc_argmin.argtypes = [PD, I, PI, PI, PD]
     lib.orc_lscv.argtypes = [PD, L, PD, I, PD, PI, PI]
+    lib.orc_lscv_min.argtypes = [PD, L, D, D, D, I, PD, PD, PI, PD, PD]
     _lib = lib
     return lib
 
@@ -246,3 +247,14 @@ def bw_lscv(x, grid):
     _check(_load().orc_lscv(_p(a), a.size, _p(gr), gr.size, ctypes.byref(h), ctypes.byref(k), ctypes.byref(e)),
            "lscv")
     return h.value, k.value, bool(e.value)
+
+
+def lscv_min(x, lo: float, hi: float, tol: float = 1e-4, points: int = 16):
+    """(h, g, steps, (a, b)) -- LSCV bandwidth by the log-spaced k-section search
+    over [lo, hi] (Section 4.4.2's alternative to the brute-force grid)."""
+    a = _col(x)
+    h, g, a0, b0 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = ctypes.c_int()
+    _check(_load().orc_lscv_min(_p(a), a.size, float(lo), float(hi), float(tol), int(points), ctypes.byref(h),
+                                ctypes.byref(g), ctypes.byref(st), ctypes.byref(a0), ctypes.byref(b0)), "lscv_min")
+    return h.value, g.value, st.value, (a0.value, b0.value)

@@ -380,3 +380,52 @@ int orc_lscv(const double* x, long n, const double* grid, int n_h, double* h_out
   free(g);
   return st;
 }
+
+/* LSCV bandwidth by search (Section 4.4.2 names a golden-ratio type search as
+ * the alternative to the brute-force grid).  Each step evaluates g(h) at m
+ * points spaced evenly in log h over the bracket [a, b], ends included, takes
+ * the smallest (lowest index on ties) and narrows the bracket to its two
+ * neighbours, until b/a - 1 <= tol.  Returns the best point of the last step,
+ * its g, the steps taken and the last bracket. */
+int orc_lscv_min(const double* x, long n, double lo, double hi, double tol, int m, double* h_out, double* g_out,
+                 int* steps_out, double* a_out, double* b_out) {
+  if (!(lo > 0.0) || !(hi > lo) || !isfinite(hi) || !(tol > 0.0) || m < 4) return ORC_INVAL;
+  double* grid = (double*)malloc(sizeof(double) * (size_t)m);
+  double* g = (double*)malloc(sizeof(double) * (size_t)m);
+  if (!grid || !g) {
+    free(grid);
+    free(g);
+    return ORC_NOMEM;
+  }
+  double a = lo, b = hi, hb = 0.0, gb = 0.0;
+  int steps = 0, st = ORC_OK;
+  for (; steps < 200; ++steps) {
+    for (int j = 0; j < m; ++j) grid[j] = a * pow(b / a, (double)j / (double)(m - 1));
+    grid[m - 1] = b;
+    int ascending = 1;
+    for (int j = 1; j < m; ++j) ascending = ascending && grid[j] > grid[j - 1];
+    if (!ascending) break;
+    st = orc_lscv_curve(x, n, grid, m, g, NULL, NULL, NULL);
+    if (st) break;
+    int k;
+    orc_argmin(g, m, &k, NULL, NULL);
+    hb = grid[k];
+    gb = g[k];
+    if (b / a - 1.0 <= tol) {
+      ++steps;
+      break;
+    }
+    const double na = grid[k > 0 ? k - 1 : 0], nb = grid[k < m - 1 ? k + 1 : m - 1];
+    a = na;
+    b = nb;
+  }
+  free(grid);
+  free(g);
+  if (st) return st;
+  *h_out = hb;
+  if (g_out) *g_out = gb;
+  if (steps_out) *steps_out = steps;
+  if (a_out) *a_out = a;
+  if (b_out) *b_out = b;
+  return ORC_OK;
+}

@@ -328,3 +328,45 @@ def test_error_paths():
     # duplicates are allowed: the pair contributes exp(0) = 1
     c = oracle.lscv_curve([1.0, 1.0], [0.5])
     assert c.s1[0] == 1.0 and c.s2[0] == 1.0
+
+
+def test_lscv_search_matches_a_library_minimiser():
+    """The k-section search (Section 4.4.2's alternative to the grid) lands on
+    the minimiser scipy's bounded Brent method finds for the same g(h) in
+    log h, near the same local minimum; for an interior minimum its step count
+    follows from the bracket shrinking by 2/(m - 1) in log h per step."""
+    from scipy.optimize import minimize_scalar
+
+    for fam, n, seed in (("normal", 400, 3), ("bimodal", 600, 8), ("lognormal", 500, 2)):
+        x = workloads.draw(fam, n, seed, np.float64)
+        lo, hi, tol, m = 0.01, 3.0, 1e-7, 16
+        h, g, steps, (a, b) = oracle.lscv_min(x, lo, hi, tol, m)
+        assert a <= h <= b and b / a - 1 <= tol
+
+        def f(t):
+            return oracle.lscv_curve(x, np.array([np.exp(t)])).g[0]
+
+        # the same local minimum: Brent on a bracket of +-5% around the search's point
+        r = minimize_scalar(f, bounds=(np.log(h) - 0.05, np.log(h) + 0.05), method="bounded",
+                            options={"xatol": 1e-10})
+        assert np.exp(r.x) == pytest.approx(h, rel=1e-5), fam
+        assert g <= r.fun + 1e-12 * abs(r.fun), fam
+        assert g == pytest.approx(f(np.log(h)), rel=1e-14)
+        # and no coarse grid point over the whole range is lower
+        coarse = oracle.lscv_curve(x, np.geomspace(lo, hi, 200)).g
+        assert g <= coarse.min() + 1e-12 * abs(coarse.min()), fam
+        # interior minimum: steps = first j with (hi/lo)^((2/(m-1))^j) - 1 <= tol, plus one
+        w0, rr = np.log(hi / lo), 2.0 / (m - 1)
+        j = next(j for j in range(200) if np.expm1(w0 * rr**j) <= tol)
+        assert steps == j + 1, (fam, steps, j)
+
+
+def test_lscv_search_edge_and_errors():
+    x = workloads.draw("normal", 300, 5, np.float64)
+    # a range entirely above the optimum: g rises, the search closes on the lower end
+    h, g, steps, (a, b) = oracle.lscv_min(x, 2.0, 5.0, 1e-6, 8)
+    assert a == 2.0 and h == 2.0
+    for bad in ((0.0, 1.0, 1e-3, 8), (1.0, 0.5, 1e-3, 8), (0.1, 1.0, 0.0, 8), (0.1, 1.0, 1e-3, 3)):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.lscv_min(x, *bad)
+        assert e.value.code == oracle.INVAL
