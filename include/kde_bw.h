@@ -335,6 +335,28 @@ kde_status kde_wait(kde_ctx* ctx, uint64_t ticket, kde_result* out, double timeo
  * the context is destroyed or a new server starts. */
 kde_status kde_server_stop(kde_ctx* ctx);
 
+/* LSCV bandwidth by a search instead of a fixed grid: the alternative to the
+ * brute-force grid that Section 4.4.2 names (a golden-ratio type search).
+ * Each step evaluates g(h) of eq. (LSCV-gh) at `points` bandwidths spaced
+ * evenly in log h over the current bracket, ends included, in one pass of
+ * the pair kernel (one pair distance for all of them); the bracket becomes
+ * the two neighbours of the step's smallest g (ties to the lowest), so it
+ * shrinks by 2/(points - 1) in log h per step, until its width hi/lo - 1 is
+ * at most rel_tol.  h_out receives the bandwidth with the smallest g of the
+ * last step.  On a g with several local minima the first step's spacing
+ * decides which one is followed.  info (may be NULL) receives g there, the
+ * steps, the bandwidths evaluated and the last bracket.  KDE_E_INVAL unless
+ * 0 < h_lo < h_hi (finite), rel_tol > 0 and 4 <= points <= KDE_MAX_NH. */
+typedef struct {
+  double g;             /* g(h_out) */
+  int32_t iterations;   /* search steps (kernel passes) */
+  int32_t pad0;
+  int64_t evaluated;    /* bandwidths evaluated in all */
+  double bracket_lo, bracket_hi;
+} kde_lscv_min_info;
+kde_status kde_bw_lscv_min(kde_ctx* ctx, kde_column x, double h_lo, double h_hi, double rel_tol, int32_t points,
+                           double* h_out, kde_lscv_min_info* info);
+
 /* LSCV bandwidth: the grid point minimising g(h), eq. (LSCV-finalH); ties go
  * to the lowest index.  k_out (may be NULL) receives its index, at_edge (may
  * be NULL) 1 when it is the first or last grid point. */

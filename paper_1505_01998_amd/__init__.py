@@ -46,7 +46,7 @@ EXPORTS = (
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
-    "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items",
+    "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min",
 )
 
 
@@ -76,6 +76,11 @@ class kde_plugin_info(ctypes.Structure):
 
 class kde_tune_info(ctypes.Structure):
     _fields_ = [("hc", ctypes.c_int32), ("pad0", ctypes.c_int32), ("evals_per_s", ctypes.c_double * 3)]
+
+
+class kde_lscv_min_info(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("iterations", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("evaluated", ctypes.c_int64), ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double)]
 
 
 class kde_grid(ctypes.Structure):
@@ -116,7 +121,7 @@ def _load():
     except ImportError:
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_1505_01998_amd/build.py (hipcc, gfx950)")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     PD = ctypes.POINTER(ctypes.c_double)
@@ -147,6 +152,8 @@ def _load():
     lib.kde_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result), ctypes.c_double]
     lib.kde_server_stop.argtypes = [P]
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
+    lib.kde_bw_lscv_min.argtypes = [P, kde_column, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, PD,
+                                    ctypes.POINTER(kde_lscv_min_info)]
     lib.kde_ctx_graph_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.kde_request_footprint.argtypes = [P, ctypes.POINTER(kde_request), ctypes.POINTER(ctypes.c_uint64)]
     lib.kde_plan_items.argtypes = [I64, I32, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -269,6 +276,18 @@ def kde_request_footprint(req, ctx=None) -> int:
     if st != KDE_OK:
         raise KdeError(st, "kde_request_footprint: invalid request" if st == KDE_E_INVAL else "busy")
     return b.value
+
+
+def kde_bw_lscv_min(ctx, x, h_lo: float, h_hi: float, rel_tol: float = 1e-4, points: int = 16):
+    """(h, info dict) -- LSCV bandwidth by the log-spaced k-section search."""
+    col, keep = make_column(x)
+    h = ctypes.c_double()
+    info = kde_lscv_min_info()
+    _check(ctx, lib.kde_bw_lscv_min(ctx, col, float(h_lo), float(h_hi), float(rel_tol), int(points), ctypes.byref(h),
+                                    ctypes.byref(info)))
+    del keep
+    return h.value, {"g": info.g, "iterations": info.iterations, "evaluated": info.evaluated,
+                     "bracket": (info.bracket_lo, info.bracket_hi)}
 
 
 def kde_ctx_graph_stats(ctx):
@@ -544,6 +563,9 @@ class Context:
 
     def graph_stats(self):
         return kde_ctx_graph_stats(self.ctx)
+
+    def bw_lscv_min(self, x, h_lo, h_hi, rel_tol=1e-4, points=16):
+        return kde_bw_lscv_min(self.ctx, x, h_lo, h_hi, rel_tol, points)
 
     def footprint(self, req):
         return kde_request_footprint(req, self.ctx)

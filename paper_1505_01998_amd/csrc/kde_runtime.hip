@@ -1262,6 +1262,56 @@ kde_status kde_bw_lscv(kde_ctx* c, kde_column x, const double* h_grid, int32_t n
   return KDE_OK;
 }
 
+kde_status kde_bw_lscv_min(kde_ctx* c, kde_column x, double h_lo, double h_hi, double rel_tol, int32_t points,
+                           double* h_out, kde_lscv_min_info* info) {
+  if (!c || !h_out) return KDE_E_INVAL;
+  if (serving(c)) return busy(c);
+  if (!(h_lo > 0.0) || !(h_hi > h_lo) || !std::isfinite(h_hi) || !(rel_tol > 0.0) || points < 4 ||
+      points > KDE_MAX_NH)
+    return fail(c, KDE_E_INVAL, "need 0 < h_lo < h_hi finite, rel_tol > 0 and 4 <= points <= KDE_MAX_NH");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  kde_status s;
+  std::vector<double> grid((size_t)points), gval((size_t)points);
+  double a = h_lo, b = h_hi, best_h = 0.0, best_g = 0.0;
+  int it = 0;
+  int64_t evaluated = 0;
+  for (; it < 200; ++it) {
+    // points log-spaced over the bracket, ends included
+    for (int32_t j = 0; j < points; ++j) grid[j] = a * std::pow(b / a, (double)j / (double)(points - 1));
+    grid[points - 1] = b;
+    bool ascending = true;
+    for (int32_t j = 1; j < points; ++j) ascending = ascending && grid[j] > grid[j - 1];
+    if (!ascending) break;  // the bracket is below the FP64 resolution of h
+    if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, grid.data(), points)))) return s;
+    if ((s = ensure_out(c, (size_t)points))) return s;
+    KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out, c->iter.cols[0].g, sizeof(double) * points, hipMemcpyDeviceToHost,
+                                  c->stream));
+    if ((s = kde::sync_and_check(c))) return s;
+    if ((s = map_status(c, c->h_st[0].status))) return s;
+    std::memcpy(gval.data(), c->h_out, sizeof(double) * points);
+    evaluated += points;
+    const int k = c->h_st[0].k_best;
+    best_h = grid[k];
+    best_g = gval[k];
+    if (b / a - 1.0 <= rel_tol) {
+      ++it;
+      break;
+    }
+    const double na = grid[k > 0 ? k - 1 : 0], nb = grid[k < points - 1 ? k + 1 : points - 1];
+    a = na;
+    b = nb;
+  }
+  *h_out = best_h;
+  if (info) {
+    info->g = best_g;
+    info->iterations = it;
+    info->evaluated = evaluated;
+    info->bracket_lo = a;
+    info->bracket_hi = b;
+  }
+  return KDE_OK;
+}
+
 kde_status kde_batch(kde_ctx* c, const kde_request* reqs, int32_t n_req, kde_result* out) {
   if (!c || n_req < 0 || (n_req > 0 && (!reqs || !out))) return KDE_E_INVAL;
   if (serving(c)) return busy(c);
