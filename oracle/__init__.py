@@ -91,6 +91,8 @@ def _load():
     lib.orc_argmin.argtypes = [PD, I, PI, PI, PD]
     lib.orc_lscv.argtypes = [PD, L, PD, I, PD, PI, PI]
     lib.orc_lscv_min.argtypes = [PD, L, D, D, D, I, PD, PD, PI, PD, PD]
+    lib.orc_density.argtypes = [PD, L, D, PD, I, PD]
+    lib.orc_range_aggregates.argtypes = [PD, L, D, PD, PD, I, PD, PD]
     _lib = lib
     return lib
 
@@ -258,3 +260,25 @@ def lscv_min(x, lo: float, hi: float, tol: float = 1e-4, points: int = 16):
     _check(_load().orc_lscv_min(_p(a), a.size, float(lo), float(hi), float(tol), int(points), ctypes.byref(h),
                                 ctypes.byref(g), ctypes.byref(st), ctypes.byref(a0), ctypes.byref(b0)), "lscv_min")
     return h.value, g.value, st.value, (a0.value, b0.value)
+
+
+def density(x, h: float, points) -> np.ndarray:
+    """Density estimate at the points, eq. (kde-def), Gaussian kernel."""
+    a = _col(x)
+    p = _col(points)
+    out = np.empty(p.size, np.float64)
+    _check(_load().orc_density(_p(a), a.size, float(h), _p(p), p.size, _p(out)), "density")
+    return out
+
+
+def range_aggregates(x, h: float, lo, hi):
+    """(count, sum) over the ranges [lo[k], hi[k]]: n times the integrals of f
+    and x f over the range, eq. (count) and eq. (sum)."""
+    a = _col(x)
+    l = _col(lo)
+    u = _col(hi)
+    cnt = np.empty(l.size, np.float64)
+    sm = np.empty(l.size, np.float64)
+    _check(_load().orc_range_aggregates(_p(a), a.size, float(h), _p(l), _p(u), l.size, _p(cnt), _p(sm)),
+           "range_aggregates")
+    return cnt, sm

@@ -370,3 +370,69 @@ def test_lscv_search_edge_and_errors():
         with pytest.raises(oracle.OracleError) as e:
             oracle.lscv_min(x, *bad)
         assert e.value.code == oracle.INVAL
+
+
+TOY = np.array([0.0, 1.0, 1.1, 1.5, 1.9, 2.8, 2.9, 3.5])  # the 8-point example of Section 2
+
+
+def test_density_matches_a_library_kde_and_its_moments():
+    """f(p) = (n h)^-1 sum phi((p - X_i)/h): scipy's gaussian_kde with its
+    bandwidth factor set to h / sigma-hat is the same estimator; the estimate
+    integrates to 1, has the sample mean as its mean and (n-1)/n V + h^2 as
+    its variance (composite Simpson on a grid of step h/64)."""
+    from scipy import integrate
+    from scipy.stats import gaussian_kde
+
+    for x, h in ((TOY, 0.4), (workloads.draw("bimodal", 700, 4, np.float64), 0.3),
+                 (workloads.draw("lognormal", 500, 9, np.float64), 0.05)):
+        pts = np.linspace(x.min() - 1, x.max() + 1, 41)
+        f = oracle.density(x, h, pts)
+        ref = gaussian_kde(x, bw_method=h / np.std(x, ddof=1))(pts)
+        assert np.allclose(f, ref, rtol=1e-12, atol=1e-15)
+        t = np.arange(x.min() - 12 * h, x.max() + 12 * h, h / 64)
+        ft = oracle.density(x, h, t)
+        assert integrate.simpson(ft, x=t) == pytest.approx(1.0, abs=1e-9)
+        assert integrate.simpson(t * ft, x=t) == pytest.approx(x.mean(), rel=1e-9, abs=1e-9)
+        assert integrate.simpson((t - x.mean())**2 * ft, x=t) == pytest.approx(np.var(x) + h * h, rel=1e-8)
+    # two equal samples: the kernel itself
+    p = np.array([0.2, 1.5, 3.0])
+    assert oracle.density([1.5, 1.5], 0.7, p) == pytest.approx(
+        np.exp(-0.5 * ((p - 1.5) / 0.7)**2) / (0.7 * np.sqrt(2 * np.pi)), rel=1e-14)
+
+
+def test_range_aggregates_match_quadrature_and_a_library_kde():
+    """COUNT = n int f and SUM = n int x f over [a, b] (eq. (count), (sum)):
+    against scipy's gaussian_kde box integral and adaptive quadrature of the
+    oracle's own density; the whole line gives n and the sum of the samples."""
+    from scipy import integrate
+    from scipy.stats import gaussian_kde
+
+    x = workloads.draw("gamma", 600, 12, np.float64)
+    h = 0.25
+    lo = np.array([-np.inf, 0.5, 1.0, 2.0, 7.0, 3.0, -5.0])
+    hi = np.array([np.inf, 1.5, 1.0, 6.0, 30.0, 3.1, -1.0])
+    cnt, sm = oracle.range_aggregates(x, h, lo, hi)
+    kde = gaussian_kde(x, bw_method=h / np.std(x, ddof=1))
+    assert cnt[0] == pytest.approx(x.size, rel=1e-14) and sm[0] == pytest.approx(x.sum(), rel=1e-13)
+    assert cnt[2] == 0.0 and sm[2] == 0.0  # an empty range
+    for k in range(1, lo.size):
+        assert cnt[k] == pytest.approx(x.size * kde.integrate_box_1d(lo[k], hi[k]), rel=1e-10, abs=1e-12)
+        if hi[k] > lo[k]:
+            a_, b_ = max(lo[k], x.min() - 12 * h), min(hi[k], x.max() + 12 * h)
+            if b_ <= a_:
+                assert cnt[k] < 1e-20
+                continue
+            t = np.linspace(a_, b_, 2 * int((b_ - a_) / (h / 64)) + 3)
+            ft = oracle.density(x, h, t)
+            assert cnt[k] == pytest.approx(x.size * integrate.simpson(ft, x=t), rel=1e-8, abs=1e-9)
+            assert sm[k] == pytest.approx(x.size * integrate.simpson(t * ft, x=t), rel=1e-8, abs=1e-9)
+
+
+def test_consumer_error_paths():
+    for call in (lambda: oracle.density(TOY, 0.0, [1.0]), lambda: oracle.density(TOY, np.inf, [1.0]),
+                 lambda: oracle.density([1.0, np.nan], 0.5, [1.0]),
+                 lambda: oracle.range_aggregates(TOY, 0.5, [2.0], [1.0]),
+                 lambda: oracle.range_aggregates(TOY, 0.5, [np.nan], [1.0])):
+        with pytest.raises(oracle.OracleError) as e:
+            call()
+        assert e.value.code == oracle.INVAL
