@@ -41,6 +41,7 @@ extern "C" {
 #define KDE_MAX_N ((int64_t)1 << 30)
 #define KDE_MAX_NH 65536
 #define KDE_MAX_BATCH 65535
+#define KDE_MAX_QUERIES (1 << 24) /* query points or ranges per kde_density / kde_range_aggregates call */
 
 typedef enum {
   KDE_OK = 0,
@@ -334,6 +335,27 @@ kde_status kde_wait(kde_ctx* ctx, uint64_t ticket, kde_result* out, double timeo
  * stops the scheduler thread.  Results not yet collected stay pollable until
  * the context is destroyed or a new server starts. */
 kde_status kde_server_stop(kde_ctx* ctx);
+
+/* Density estimate at query points, eq. (kde-def) with d = 1 and the
+ * Gaussian kernel: f_out[k] = (n h)^-1 sum_i phi((points[k] - X_i) / h), for
+ * a bandwidth h chosen by the selectors.  Mixed form: FP32 terms in
+ * compensated 64-term runs, FP64 across pieces; FP64 form: FP64 terms.
+ * points[m] and f_out[m] are host arrays.  KDE_E_INVAL for a bad column,
+ * h <= 0 or not finite, m outside [1, KDE_MAX_QUERIES] or a non-finite point. */
+kde_status kde_density(kde_ctx* ctx, kde_column x, double h, const double* points, int32_t m, double* f_out);
+
+/* Approximate range aggregates from the estimate (Section 3.2, eq. (count)
+ * and eq. (sum)), for ranges [lo[k], hi[k]] of the column's values:
+ *   count_out[k] = n * int f = sum_i [Phi(beta_i) - Phi(alpha_i)],
+ *   sum_out[k]   = n * int x f = sum_i [X_i (Phi(beta_i) - Phi(alpha_i)) + h (phi(alpha_i) - phi(beta_i))],
+ *   avg_out[k]   = sum_out[k] / count_out[k]  (NaN when the count is 0),
+ * alpha_i = (lo - X_i)/h, beta_i = (hi - X_i)/h: the Gaussian kernel
+ * integrates in closed form, so no numerical quadrature is involved.  FP64,
+ * differences of Phi taken between tails (erfc).  Infinite ends are allowed.
+ * avg_out may be NULL.  KDE_E_INVAL for a bad column, h <= 0 or not finite,
+ * q outside [1, KDE_MAX_QUERIES], a NaN end or lo > hi. */
+kde_status kde_range_aggregates(kde_ctx* ctx, kde_column x, double h, const double* lo, const double* hi, int32_t q,
+                                double* count_out, double* sum_out, double* avg_out);
 
 /* LSCV bandwidth by a search instead of a fixed grid: the alternative to the
  * brute-force grid that Section 4.4.2 names (a golden-ratio type search).

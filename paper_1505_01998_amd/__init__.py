@@ -46,7 +46,8 @@ EXPORTS = (
     "kde_ctx_set_option", "kde_ctx_set_timing", "kde_ctx_kernel_time", "kde_bw_rot", "kde_bw_plugin",
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
-    "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min",
+    "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min", "kde_density",
+    "kde_range_aggregates",
 )
 
 
@@ -152,6 +153,8 @@ def _load():
     lib.kde_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result), ctypes.c_double]
     lib.kde_server_stop.argtypes = [P]
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
+    lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
+    lib.kde_range_aggregates.argtypes = [P, kde_column, ctypes.c_double, PD, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_min.argtypes = [P, kde_column, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, PD,
                                     ctypes.POINTER(kde_lscv_min_info)]
     lib.kde_ctx_graph_stats.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
@@ -276,6 +279,29 @@ def kde_request_footprint(req, ctx=None) -> int:
     if st != KDE_OK:
         raise KdeError(st, "kde_request_footprint: invalid request" if st == KDE_E_INVAL else "busy")
     return b.value
+
+
+def kde_density(ctx, x, h: float, points):
+    """Density estimate f(points) at bandwidth h."""
+    col, keep = make_column(x)
+    q = np.ascontiguousarray(np.asarray(points, np.float64).ravel())
+    out = np.empty(q.size, np.float64)
+    _check(ctx, lib.kde_density(ctx, col, float(h), _pd(q), int(q.size), _pd(out)))
+    del keep
+    return out
+
+
+def kde_range_aggregates(ctx, x, h: float, lo, hi):
+    """(count, sum, avg) arrays over the ranges [lo[k], hi[k]]."""
+    col, keep = make_column(x)
+    a = np.ascontiguousarray(np.asarray(lo, np.float64).ravel())
+    b = np.ascontiguousarray(np.asarray(hi, np.float64).ravel())
+    if a.size != b.size:
+        raise ValueError("lo and hi differ in length")
+    cnt, sm, av = (np.empty(a.size, np.float64) for _ in range(3))
+    _check(ctx, lib.kde_range_aggregates(ctx, col, float(h), _pd(a), _pd(b), int(a.size), _pd(cnt), _pd(sm), _pd(av)))
+    del keep
+    return cnt, sm, av
 
 
 def kde_bw_lscv_min(ctx, x, h_lo: float, h_hi: float, rel_tol: float = 1e-4, points: int = 16):
@@ -566,6 +592,12 @@ class Context:
 
     def bw_lscv_min(self, x, h_lo, h_hi, rel_tol=1e-4, points=16):
         return kde_bw_lscv_min(self.ctx, x, h_lo, h_hi, rel_tol, points)
+
+    def density(self, x, h, points):
+        return kde_density(self.ctx, x, h, points)
+
+    def range_aggregates(self, x, h, lo, hi):
+        return kde_range_aggregates(self.ctx, x, h, lo, hi)
 
     def footprint(self, req):
         return kde_request_footprint(req, self.ctx)

@@ -173,6 +173,7 @@ struct kde_ctx {
   int opt_graph = 0;               // synchronous jobs replay a captured graph of their launches
   int opt_prune = 0;               // LSCV tile pruning on sorted samples (mixed form, synchronous jobs)
   kde::DevBuf<char> sort_tmp;      // temporary storage of the column sorts
+  kde::DevBuf<char> qbuf;          // query points / ranges, partials and outputs of the consumers
   std::vector<kde::JobGraph> graphs;  // at most kde::kMaxGraphs, least recently used replaced
   uint64_t graph_clock = 0;
   int64_t graph_captures = 0, graph_replays = 0;
@@ -238,6 +239,11 @@ int64_t capped_seg(const kde_ctx* c, int64_t n, int hc, double chunks);
 // options, or with the autotune option the tuned vector-ALU variant of the
 // job's largest LSCV column (tuning that shape first when the job is large).
 kde_status select_variant(kde_ctx* c, const kde_request* reqs, int32_t n_req);
+// Stages one column on the device (validation, moments, the padded working
+// copies) with a rule-of-thumb job and returns the device address of its
+// descriptor, valid until the context's next job.  KDE_E_INVAL for a bad or
+// non-finite column; a column of zero spread is staged (its DevState says so).
+kde_status stage_column(kde_ctx* c, kde_column x, const ColDesc** dcol);
 // Times the LSCV variants on a column of n samples and an n_h-point grid (or
 // returns the cached decision for that shape).
 kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out);

@@ -908,6 +908,19 @@ kde_request make_req(kde_column x, unsigned methods, int stages, const double* h
   return r;
 }
 
+}  // namespace
+
+kde_status kde::stage_column(kde_ctx* c, kde_column x, const kde::ColDesc** dcol) {
+  kde_status s;
+  if ((s = run_single(c, make_req(x, KDE_METHOD_ROT, 2, nullptr, 0)))) return s;
+  if ((s = kde::sync_and_check(c))) return s;
+  if (c->h_st[0].status == kde::kStInval) return kde::fail(c, KDE_E_INVAL, "sample column holds a non-finite value");
+  *dcol = reinterpret_cast<const kde::ColDesc*>(c->blob.p);  // the pass's column table starts the blob
+  return KDE_OK;
+}
+
+namespace {
+
 void fill_plugin_info(const DevState& h, int stages, kde_plugin_info* info) {
   info->sigma = h.sigma;
   info->h_rot = h.h_rot;
@@ -1001,6 +1014,8 @@ void kde_ctx_destroy(kde_ctx* c) {
   (void)hipFree(c->st.p);
   (void)hipFree(c->blob.p);
   (void)hipFree(c->tune_buf.p);
+  (void)hipFree(c->sort_tmp.p);
+  (void)hipFree(c->qbuf.p);
   for (kde::JobGraph& g : c->graphs) g.reset();
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_out) (void)hipHostFree(c->h_out);
