@@ -92,6 +92,7 @@ def _load():
     lib.orc_lscv.argtypes = [PD, L, PD, I, PD, PI, PI]
     lib.orc_lscv_min.argtypes = [PD, L, D, D, D, I, PD, PD, PI, PD, PD]
     lib.orc_density.argtypes = [PD, L, D, PD, I, PD]
+    lib.orc_lscv_md_curve.argtypes = [PD, L, I, PD, I, PD, PD, PD, PD]
     lib.orc_range_aggregates.argtypes = [PD, L, D, PD, PD, I, PD, PD]
     _lib = lib
     return lib
@@ -282,3 +283,17 @@ def range_aggregates(x, h: float, lo, hi):
     _check(_load().orc_range_aggregates(_p(a), a.size, float(h), _p(l), _p(u), l.size, _p(cnt), _p(sm)),
            "range_aggregates")
     return cnt, sm
+
+
+def lscv_md_curve(x, grid) -> LscvCurve:
+    """LSCV_h for d-dimensional samples (rows of x, n x d), sphered by the
+    sample covariance: eq. (LSCV-gh) with S(v) of eq. (LSCV_MOD-Pv)."""
+    a = np.ascontiguousarray(np.asarray(x, np.float64))
+    if a.ndim == 1:
+        a = a[:, None]
+    n, d = a.shape
+    gr = _col(grid)
+    m = gr.size
+    g, gs, s1, s2 = (np.empty(m, dtype=np.float64) for _ in range(4))
+    _check(_load().orc_lscv_md_curve(_p(a.ravel()), n, d, _p(gr), m, _p(g), _p(gs), _p(s1), _p(s2)), "lscv_md_curve")
+    return LscvCurve(g, gs, s1, s2)

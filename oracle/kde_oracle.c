@@ -482,3 +482,137 @@ int orc_range_aggregates(const double* x, long n, double h, const double* lo, co
   }
   return ORC_OK;
 }
+
+/* ---- LSCV_h for d >= 1 (Section 4.4.2, the sphered form of eq. (LSCV-gh)):
+ * x is row-major n x d.  Sigma from eq. (LSCV-variance)/(LSCV-covariance)
+ * written two-pass (mean first), S(v) = v^T Sigma^-1 v of eq. (LSCV_MOD-Pv)
+ * evaluated as its double sum for every pair, and
+ *   g(h) = h^-d [2 n^-2 sum_{i<j} ((K*K)~(v) - 2 K~(v)) + n^-1 R(K)]
+ * with K~, (K*K)~ of eq. (LSCV_MOD-Kv2)/(LSCV_MOD-KKv) (two separate exp
+ * calls) and R(K) = (4 pi)^(-d/2) |Sigma|^(-1/2) (eq. LSCV_MULTI-rk with
+ * H = Sigma).  Sigma is factored by Cholesky; not positive definite (a pivot
+ * at most 1e-12 of its diagonal entry) -> DEGENERATE. */
+static int orc_cov_inverse(const double* x, long n, int d, double* inv, double* logdet) {
+  double* m = (double*)calloc((size_t)d, sizeof(double));
+  double* S = (double*)calloc((size_t)d * d, sizeof(double));
+  double* L = (double*)calloc((size_t)d * d, sizeof(double));
+  double* Li = (double*)calloc((size_t)d * d, sizeof(double));
+  int st = ORC_OK;
+  if (!m || !S || !L || !Li) {
+    st = ORC_NOMEM;
+    goto out;
+  }
+  for (int a = 0; a < d; ++a) {
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += x[i * d + a];
+    m[a] = s / (double)n;
+  }
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) {
+      double s = 0.0;
+      for (long i = 0; i < n; ++i) s += (x[i * d + a] - m[a]) * (x[i * d + b] - m[b]);
+      S[a * d + b] = S[b * d + a] = s / (double)(n - 1);
+    }
+  /* Cholesky S = L L^T */
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) {
+      double s = S[a * d + b];
+      for (int k = 0; k < b; ++k) s -= L[a * d + k] * L[b * d + k];
+      if (a == b) {
+        /* a pivot below 1e-12 of its diagonal entry: singular to working precision */
+        if (!(s > 1e-12 * S[a * d + a]) || !isfinite(s)) {
+          st = ORC_DEGENERATE;
+          goto out;
+        }
+        L[a * d + a] = sqrt(s);
+      } else {
+        L[a * d + b] = s / L[b * d + b];
+      }
+    }
+  *logdet = 0.0;
+  for (int a = 0; a < d; ++a) *logdet += 2.0 * log(L[a * d + a]);
+  /* L^-1 by forward substitution, then Sigma^-1 = L^-T L^-1 */
+  for (int c = 0; c < d; ++c)
+    for (int a = 0; a < d; ++a) {
+      double s = (a == c) ? 1.0 : 0.0;
+      for (int k = 0; k < a; ++k) s -= L[a * d + k] * Li[k * d + c];
+      Li[a * d + c] = s / L[a * d + a];
+    }
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += Li[k * d + a] * Li[k * d + b];
+      inv[a * d + b] = s;
+    }
+out:
+  free(m);
+  free(S);
+  free(L);
+  free(Li);
+  return st;
+}
+
+int orc_lscv_md_curve(const double* x, long n, int d, const double* grid, int n_h, double* g_out,
+                      double* gscale_out, double* s1_out, double* s2_out) {
+  if (n < 2 || d < 1 || n_h < 1) return ORC_INVAL;
+  for (long i = 0; i < n * d; ++i)
+    if (!isfinite(x[i])) return ORC_INVAL;
+  for (int k = 0; k < n_h; ++k)
+    if (!(grid[k] > 0.0) || !isfinite(grid[k]) || (k > 0 && !(grid[k] > grid[k - 1]))) return ORC_INVAL;
+  double* inv = (double*)malloc(sizeof(double) * (size_t)d * d);
+  double* rows1 = (double*)calloc((size_t)n * n_h, sizeof(double));
+  double* rows2 = (double*)calloc((size_t)n * n_h, sizeof(double));
+  double logdet = 0.0;
+  int st = ORC_OK;
+  if (!inv || !rows1 || !rows2) {
+    st = ORC_NOMEM;
+    goto done;
+  }
+  st = orc_cov_inverse(x, n, d, inv, &logdet);
+  if (st) goto done;
+#pragma omp parallel
+  {
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(dynamic, 16)
+    for (long i = 0; i < n; ++i)
+      for (long j = i + 1; j < n; ++j) {
+        for (int a = 0; a < d; ++a) v[a] = x[i * d + a] - x[j * d + a];
+        double S = 0.0;
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) S += v[a] * inv[a * d + b] * v[b];
+        for (int k = 0; k < n_h; ++k) {
+          const double h2 = grid[k] * grid[k];
+          rows1[i * n_h + k] += exp(-S / (4.0 * h2));
+          rows2[i * n_h + k] += exp(-S / (2.0 * h2));
+        }
+      }
+    free(v);
+  }
+  {
+    double* col = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!col) {
+      st = ORC_NOMEM;
+      goto done;
+    }
+    const double sq = exp(-0.5 * logdet);
+    const double A = pow(4.0 * ORC_PI, -0.5 * d) * sq, B = pow(2.0 * ORC_PI, -0.5 * d) * sq;
+    const double nn = (double)n;
+    for (int k = 0; k < n_h; ++k) {
+      for (long i = 0; i < n; ++i) col[i] = rows1[i * n_h + k];
+      const double s1 = neumaier_sum(col, n);
+      for (long i = 0; i < n; ++i) col[i] = rows2[i * n_h + k];
+      const double s2 = neumaier_sum(col, n);
+      const double hd = pow(grid[k], -(double)d);
+      g_out[k] = hd * (2.0 / (nn * nn) * (A * s1 - 2.0 * B * s2) + A / nn);
+      if (gscale_out) gscale_out[k] = hd * (2.0 / (nn * nn) * (A * s1 + 2.0 * B * s2) + A / nn);
+      if (s1_out) s1_out[k] = s1;
+      if (s2_out) s2_out[k] = s2;
+    }
+    free(col);
+  }
+done:
+  free(inv);
+  free(rows1);
+  free(rows2);
+  return st;
+}

@@ -436,3 +436,47 @@ def test_consumer_error_paths():
         with pytest.raises(oracle.OracleError) as e:
             call()
         assert e.value.code == oracle.INVAL
+
+
+def test_lscv_md_reduces_to_one_dimension_and_matches_brute_force():
+    """LSCV_h in d dimensions (eq. LSCV-gh with S(v) = v^T Sigma^-1 v): at
+    d = 1 the sphered objective equals the data-unit objective at sigma h
+    exactly; for d = 2, 3 the pair sums match a numpy all-pairs computation
+    whose inverse covariance comes from numpy.linalg."""
+    x = workloads.draw("bimodal", 500, 3, np.float64)
+    grid = np.geomspace(0.05, 1.5, 12)
+    md = oracle.lscv_md_curve(x[:, None], grid)
+    one = oracle.lscv_curve(x, np.std(x, ddof=1) * grid)
+    assert np.allclose(md.g, one.g, rtol=1e-12) and np.allclose(md.s1, one.s1, rtol=1e-12)
+    rng = np.random.Generator(np.random.PCG64(11))
+    for d in (2, 3):
+        n = 300
+        z = rng.standard_normal((n, d)) @ rng.standard_normal((d, d)) + rng.uniform(-2, 2, d)
+        inv = np.linalg.inv(np.cov(z, rowvar=False))
+        iu = np.triu_indices(n, 1)
+        v = z[:, None, :] - z[None, :, :]
+        S = np.einsum("ija,ab,ijb->ij", v, inv, v)[iu]
+        c = oracle.lscv_md_curve(z, grid)
+        for k, h in enumerate(grid):
+            assert c.s1[k] == pytest.approx(np.exp(-S / (4 * h * h)).sum(), rel=1e-11)
+            assert c.s2[k] == pytest.approx(np.exp(-S / (2 * h * h)).sum(), rel=1e-11)
+
+
+def test_lscv_md_affine_invariance_and_errors():
+    """The sphered objective is invariant in shape under x -> A x + b:
+    S(v) is unchanged and |Sigma|^-1/2 scales by 1/|det A|, so
+    g_{Ax+b}(h) = g_x(h) / |det A|; collinear samples have a singular Sigma."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    z = rng.standard_normal((250, 3)) * [1.0, 2.0, 0.5]
+    A = np.array([[2.0, 0.3, 0.0], [-0.5, 1.0, 0.7], [0.1, 0.0, -1.5]])
+    grid = np.geomspace(0.1, 2.0, 9)
+    g0 = oracle.lscv_md_curve(z, grid).g
+    g1 = oracle.lscv_md_curve(z @ A.T + [5.0, -3.0, 100.0], grid).g
+    assert np.allclose(g1, g0 / abs(np.linalg.det(A)), rtol=1e-9)
+    col = np.stack([z[:, 0], 2 * z[:, 0] + 1], axis=1)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.lscv_md_curve(col, grid)
+    assert e.value.code == oracle.DEGENERATE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.lscv_md_curve(z, grid[::-1])
+    assert e.value.code == oracle.INVAL
