@@ -42,6 +42,7 @@ extern "C" {
 #define KDE_MAX_NH 65536
 #define KDE_MAX_BATCH 65535
 #define KDE_MAX_QUERIES (1 << 24) /* query points or ranges per kde_density / kde_range_aggregates call */
+#define KDE_MAX_D 16 /* dimensions of a sample matrix (kde_lscv_md_curve) */
 
 typedef enum {
   KDE_OK = 0,
@@ -356,6 +357,35 @@ kde_status kde_density(kde_ctx* ctx, kde_column x, double h, const double* point
  * q outside [1, KDE_MAX_QUERIES], a NaN end or lo > hi. */
 kde_status kde_range_aggregates(kde_ctx* ctx, kde_column x, double h, const double* lo, const double* hi, int32_t q,
                                 double* count_out, double* sum_out, double* avg_out);
+
+/* A matrix of n d-dimensional samples, row-major (sample i occupies
+ * data[i*d .. i*d + d)), float32 or float64, host or device memory. */
+typedef struct {
+  const void* data;
+  int64_t n;
+  int32_t d;
+  kde_dtype dtype;
+  int on_device;
+} kde_matrix;
+
+/* LSCV_h for d-dimensional samples, Section 4.4.2: the sphered objective
+ *   g(h) = h^-d [2 n^-2 sum_{i<j} T~(X_i - X_j) + n^-1 R(K)],
+ * T~ = (K*K)~ - 2 K~ of eq. (LSCV_MOD-Kv2)/(LSCV_MOD-KKv) through
+ * S(v) = v^T Sigma^-1 v (eq. LSCV_MOD-Pv), Sigma the n-1 sample covariance,
+ * R(K) = (4 pi)^(-d/2) |Sigma|^(-1/2) (eq. LSCV_MULTI-rk with H = Sigma); h is
+ * in units of Sigma^(1/2).  S(v) is formed per pair from whitened samples
+ * (Y = L^-1 (X - mean), Sigma = L L^T) and reused for every h, never stored.
+ * h_grid == NULL: n_h points (150 if n_h <= 0) linear over [h0/4, 4 h0],
+ * h0 = (4/((d+2) n))^(1/(d+4)).  g_out[n_h]; gscale_out, grid_out may be
+ * NULL.  KDE_E_INVAL for a bad matrix (n < 2, d outside [1, KDE_MAX_D], a
+ * non-finite value) or grid; KDE_E_DEGENERATE when Sigma is singular (a
+ * Cholesky pivot at most 1e-12 of its diagonal entry). */
+kde_status kde_lscv_md_curve(kde_ctx* ctx, kde_matrix x, const double* h_grid, int32_t n_h, double* g_out,
+                             double* gscale_out, double* grid_out);
+/* The grid point minimising the d-dimensional g(h), eq. (LSCV-finalH); ties
+ * to the lowest index; k_out may be NULL. */
+kde_status kde_bw_lscv_md(kde_ctx* ctx, kde_matrix x, const double* h_grid, int32_t n_h, double* h_out,
+                          int32_t* k_out);
 
 /* LSCV bandwidth by a search instead of a fixed grid: the alternative to the
  * brute-force grid that Section 4.4.2 names (a golden-ratio type search).

@@ -47,7 +47,7 @@ EXPORTS = (
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
     "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min", "kde_density",
-    "kde_range_aggregates",
+    "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md",
 )
 
 
@@ -82,6 +82,11 @@ class kde_tune_info(ctypes.Structure):
 class kde_lscv_min_info(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("iterations", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("evaluated", ctypes.c_int64), ("bracket_lo", ctypes.c_double), ("bracket_hi", ctypes.c_double)]
+
+
+class kde_matrix(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("dtype", ctypes.c_int),
+                ("on_device", ctypes.c_int)]
 
 
 class kde_grid(ctypes.Structure):
@@ -154,6 +159,8 @@ def _load():
     lib.kde_server_stop.argtypes = [P]
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
     lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
+    lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
+    lib.kde_bw_lscv_md.argtypes = [P, kde_matrix, PD, I32, PD, ctypes.POINTER(I32)]
     lib.kde_range_aggregates.argtypes = [P, kde_column, ctypes.c_double, PD, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_min.argtypes = [P, kde_column, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, PD,
                                     ctypes.POINTER(kde_lscv_min_info)]
@@ -279,6 +286,46 @@ def kde_request_footprint(req, ctx=None) -> int:
     if st != KDE_OK:
         raise KdeError(st, "kde_request_footprint: invalid request" if st == KDE_E_INVAL else "busy")
     return b.value
+
+
+def make_matrix(x):
+    """(kde_matrix, keepalive) for an n x d numpy array or CUDA tensor (row-major)."""
+    if hasattr(x, "is_cuda") and x.is_cuda:
+        t = x.contiguous()
+        if t.dim() != 2:
+            raise ValueError("a sample matrix is n x d")
+        dt = {"torch.float32": KDE_F32, "torch.float64": KDE_F64}[str(t.dtype)]
+        return kde_matrix(t.data_ptr(), t.shape[0], t.shape[1], dt, 1), t
+    a = np.asarray(x)
+    if a.dtype not in (np.float32, np.float64):
+        a = a.astype(np.float64)
+    a = np.ascontiguousarray(a)
+    if a.ndim != 2:
+        raise ValueError("a sample matrix is n x d")
+    return kde_matrix(a.ctypes.data, a.shape[0], a.shape[1], KDE_F64 if a.dtype == np.float64 else KDE_F32, 0), a
+
+
+def kde_lscv_md_curve(ctx, x, h_grid=None, n_h: int = 0):
+    """(g, gscale, grid) of the d-dimensional LSCV_h objective."""
+    m, keep = make_matrix(x)
+    gr = None if h_grid is None else _grid(h_grid)
+    k = gr.size if gr is not None else (n_h if n_h > 0 else 150)
+    g, gs, grid = (np.empty(k, np.float64) for _ in range(3))
+    _check(ctx, lib.kde_lscv_md_curve(ctx, m, _pd(gr), int(k), _pd(g), _pd(gs), _pd(grid)))
+    del keep
+    return g, gs, grid
+
+
+def kde_bw_lscv_md(ctx, x, h_grid=None, n_h: int = 0):
+    """(h, k) -- the grid point minimising the d-dimensional g(h)."""
+    m, keep = make_matrix(x)
+    gr = None if h_grid is None else _grid(h_grid)
+    k = gr.size if gr is not None else int(n_h)
+    h = ctypes.c_double()
+    kk = ctypes.c_int32()
+    _check(ctx, lib.kde_bw_lscv_md(ctx, m, _pd(gr), int(k), ctypes.byref(h), ctypes.byref(kk)))
+    del keep
+    return h.value, kk.value
 
 
 def kde_density(ctx, x, h: float, points):
@@ -595,6 +642,12 @@ class Context:
 
     def density(self, x, h, points):
         return kde_density(self.ctx, x, h, points)
+
+    def lscv_md_curve(self, x, h_grid=None, n_h=0):
+        return kde_lscv_md_curve(self.ctx, x, h_grid, n_h)
+
+    def bw_lscv_md(self, x, h_grid=None, n_h=0):
+        return kde_bw_lscv_md(self.ctx, x, h_grid, n_h)
 
     def range_aggregates(self, x, h, lo, hi):
         return kde_range_aggregates(self.ctx, x, h, lo, hi)

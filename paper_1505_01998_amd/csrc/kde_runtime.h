@@ -174,6 +174,7 @@ struct kde_ctx {
   int opt_prune = 0;               // LSCV tile pruning on sorted samples (mixed form, synchronous jobs)
   kde::DevBuf<char> sort_tmp;      // temporary storage of the column sorts
   kde::DevBuf<char> qbuf;          // query points / ranges, partials and outputs of the consumers
+  kde::DevBuf<char> mdbuf;         // d-dimensional LSCV: samples, moments, whitened copy, partials
   std::vector<kde::JobGraph> graphs;  // at most kde::kMaxGraphs, least recently used replaced
   uint64_t graph_clock = 0;
   int64_t graph_captures = 0, graph_replays = 0;

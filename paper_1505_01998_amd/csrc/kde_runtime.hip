@@ -1016,6 +1016,7 @@ void kde_ctx_destroy(kde_ctx* c) {
   (void)hipFree(c->tune_buf.p);
   (void)hipFree(c->sort_tmp.p);
   (void)hipFree(c->qbuf.p);
+  (void)hipFree(c->mdbuf.p);
   for (kde::JobGraph& g : c->graphs) g.reset();
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_out) (void)hipHostFree(c->h_out);
