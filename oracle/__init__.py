@@ -93,6 +93,8 @@ def _load():
     lib.orc_lscv_min.argtypes = [PD, L, D, D, D, I, PD, PD, PI, PD, PD]
     lib.orc_density.argtypes = [PD, L, D, PD, I, PD]
     lib.orc_lscv_md_curve.argtypes = [PD, L, I, PD, I, PD, PD, PD, PD]
+    lib.orc_lscv_H.argtypes = [PD, L, I, PD, PD]
+    lib.orc_lscv_H_min.argtypes = [PD, L, I, D, D, I, PD, PD, PI]
     lib.orc_range_aggregates.argtypes = [PD, L, D, PD, PD, I, PD, PD]
     _lib = lib
     return lib
@@ -297,3 +299,29 @@ def lscv_md_curve(x, grid) -> LscvCurve:
     g, gs, s1, s2 = (np.empty(m, dtype=np.float64) for _ in range(4))
     _check(_load().orc_lscv_md_curve(_p(a.ravel()), n, d, _p(gr), m, _p(g), _p(gs), _p(s1), _p(s2)), "lscv_md_curve")
     return LscvCurve(g, gs, s1, s2)
+
+
+def lscv_H(x, H) -> float:
+    """LSCV_H objective g(H), eq. (LSCV_MULTI-gh), at a bandwidth matrix H."""
+    a = np.ascontiguousarray(np.asarray(x, np.float64))
+    if a.ndim == 1:
+        a = a[:, None]
+    n, d = a.shape
+    Hm = np.ascontiguousarray(np.asarray(H, np.float64).reshape(d, d))
+    g = ctypes.c_double()
+    _check(_load().orc_lscv_H(_p(a.ravel()), n, d, _p(Hm.ravel()), ctypes.byref(g)), "lscv_H")
+    return g.value
+
+
+def lscv_H_min(x, ftol: float = 1e-10, xtol: float = 1e-6, max_evals: int = 2000):
+    """(H, g, evaluations) -- Nelder-Mead over the Cholesky parametrisation of H."""
+    a = np.ascontiguousarray(np.asarray(x, np.float64))
+    if a.ndim == 1:
+        a = a[:, None]
+    n, d = a.shape
+    H = np.empty(d * d, np.float64)
+    g = ctypes.c_double()
+    ev = ctypes.c_int()
+    _check(_load().orc_lscv_H_min(_p(a.ravel()), n, d, float(ftol), float(xtol), int(max_evals), _p(H),
+                                  ctypes.byref(g), ctypes.byref(ev)), "lscv_H_min")
+    return H.reshape(d, d), g.value, ev.value

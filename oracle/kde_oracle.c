@@ -616,3 +616,236 @@ done:
   free(rows2);
   return st;
 }
+
+/* Cholesky factor of a symmetric positive definite d x d matrix A (row-major):
+ * L (lower, row-major), log|A| and A^-1.  A pivot at most 1e-12 of its
+ * diagonal entry counts as singular. */
+static int orc_spd(const double* A, int d, double* L, double* inv, double* logdet) {
+  for (int i = 0; i < d * d; ++i) L[i] = 0.0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) {
+      double s = A[a * d + b];
+      for (int k = 0; k < b; ++k) s -= L[a * d + k] * L[b * d + k];
+      if (a == b) {
+        if (!(s > 1e-12 * A[a * d + a]) || !isfinite(s)) return ORC_DEGENERATE;
+        L[a * d + a] = sqrt(s);
+      } else {
+        L[a * d + b] = s / L[b * d + b];
+      }
+    }
+  double ld = 0.0;
+  for (int a = 0; a < d; ++a) ld += 2.0 * log(L[a * d + a]);
+  *logdet = ld;
+  if (inv) {
+    double Li[16 * 16];
+    for (int c = 0; c < d; ++c)
+      for (int a = 0; a < d; ++a) {
+        double s = (a == c) ? 1.0 : 0.0;
+        for (int k = 0; k < a; ++k) s -= L[a * d + k] * Li[k * d + c];
+        Li[a * d + c] = s / L[a * d + a];
+      }
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) s += Li[k * d + a] * Li[k * d + b];
+        inv[a * d + b] = s;
+      }
+  }
+  return ORC_OK;
+}
+
+/* LSCV_H objective at a bandwidth matrix H (Section 4.4.3, eq. (LSCV_MULTI-gh)
+ * with (LSCV_MULTI-Kx), (LSCV_MULTI-KKx), (LSCV_MULTI-rk)):
+ *   g(H) = 2 n^-2 sum_{i<j} [(K*K)_H - 2 K_H](X_i - X_j) + n^-1 R(K),
+ * (K*K)_H(v) = (4 pi)^(-d/2) |H|^(-1/2) exp(-v^T H^-1 v / 4),
+ * K_H(v) = (2 pi)^(-d/2) |H|^(-1/2) exp(-v^T H^-1 v / 2),
+ * R(K) = 2^-d pi^(-d/2) |H|^(-1/2).  x row-major n x d, H row-major d x d,
+ * d <= 16.  H not positive definite -> DEGENERATE. */
+int orc_lscv_H(const double* x, long n, int d, const double* H, double* g_out) {
+  if (n < 2 || d < 1 || d > 16) return ORC_INVAL;
+  for (long i = 0; i < n * d; ++i)
+    if (!isfinite(x[i])) return ORC_INVAL;
+  double L[256], inv[256], logdet;
+  int st = orc_spd(H, d, L, inv, &logdet);
+  if (st) return st;
+  double* rows1 = (double*)calloc((size_t)n, sizeof(double));
+  double* rows2 = (double*)calloc((size_t)n, sizeof(double));
+  if (!rows1 || !rows2) {
+    free(rows1);
+    free(rows2);
+    return ORC_NOMEM;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < n; ++i) {
+    double v[16];
+    double r1 = 0.0, r2 = 0.0;
+    for (long j = i + 1; j < n; ++j) {
+      for (int a = 0; a < d; ++a) v[a] = x[i * d + a] - x[j * d + a];
+      double q = 0.0;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) q += v[a] * inv[a * d + b] * v[b];
+      r1 += exp(-q / 4.0);
+      r2 += exp(-q / 2.0);
+    }
+    rows1[i] = r1;
+    rows2[i] = r2;
+  }
+  const double s1 = neumaier_sum(rows1, n), s2 = neumaier_sum(rows2, n);
+  free(rows1);
+  free(rows2);
+  const double sq = exp(-0.5 * logdet), nn = (double)n;
+  const double A = pow(4.0 * ORC_PI, -0.5 * d) * sq, B = pow(2.0 * ORC_PI, -0.5 * d) * sq;
+  const double R = pow(2.0, -(double)d) * pow(ORC_PI, -0.5 * d) * sq;
+  *g_out = 2.0 / (nn * nn) * (A * s1 - 2.0 * B * s2) + R / nn;
+  return ORC_OK;
+}
+
+/* ---- Nelder-Mead over H (Section 4.4.3 names the method; the search space
+ * is kept to positive definite matrices by the parametrisation): theta holds
+ * the lower triangle of C, row by row, with the logarithm on the diagonal,
+ * H = C C^T.  Start: eq. (LSCV-H-start) read as the squared bandwidth
+ * H0 = s^2 Sigma, s = (4/(d+2))^(1/(d+4)) n^(-1/(d+4)).  Initial steps 0.25 on
+ * the log-diagonal and 0.25 sqrt(C_aa C_bb) off it.  Moves: reflection 1,
+ * expansion 2, contractions 1/2, shrink 1/2 towards the best vertex.  Stops
+ * when the spread of g over the simplex is at most ftol |g_best| and every
+ * vertex is within xtol of the best in every parameter, or after max_evals
+ * evaluations. */
+static void orc_theta_to_H(const double* th, int d, double* H) {
+  double C[256];
+  int p = 0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) C[a * d + b] = 0.0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) C[a * d + b] = (a == b) ? exp(th[p++]) : th[p++];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += C[a * d + k] * C[b * d + k];
+      H[a * d + b] = s;
+    }
+}
+
+int orc_lscv_H_min(const double* x, long n, int d, double ftol, double xtol, int max_evals, double* H_out,
+                   double* g_out, int* evals_out) {
+  if (n < 2 || d < 1 || d > 16 || !(ftol > 0.0) || !(xtol > 0.0) || max_evals < 1) return ORC_INVAL;
+  const int p = d * (d + 1) / 2;
+  double Sinv[256], L[256], logdet;
+  int st = orc_cov_inverse(x, n, d, Sinv, &logdet);
+  if (st) return st;
+  /* Sigma itself, for the start */
+  double S[256], Ls[256], dummy;
+  {
+    double* m = (double*)calloc((size_t)d, sizeof(double));
+    for (int a = 0; a < d; ++a) {
+      for (long i = 0; i < n; ++i) m[a] += x[i * d + a];
+      m[a] /= (double)n;
+    }
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double s = 0.0;
+        for (long i = 0; i < n; ++i) s += (x[i * d + a] - m[a]) * (x[i * d + b] - m[b]);
+        S[a * d + b] = s / (double)(n - 1);
+      }
+    free(m);
+  }
+  const double s = pow(4.0 / (d + 2.0), 1.0 / (d + 4.0)) * pow((double)n, -1.0 / (d + 4.0));
+  for (int i = 0; i < d * d; ++i) S[i] *= s * s;
+  st = orc_spd(S, d, Ls, NULL, &dummy);
+  if (st) return st;
+  (void)L;
+  double V[17 * 136], F[17], H[256];
+  int q = 0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) V[q++] = (a == b) ? log(Ls[a * d + a]) : Ls[a * d + b];
+  for (int k = 1; k <= p; ++k) {
+    for (int j = 0; j < p; ++j) V[k * p + j] = V[j];
+    int a = 0, b = 0, idx = 0;
+    for (a = 0; a < d; ++a) {
+      for (b = 0; b <= a; ++b, ++idx)
+        if (idx == k - 1) goto found;
+    }
+  found:
+    V[k * p + (k - 1)] += (a == b) ? 0.25 : 0.25 * sqrt(Ls[a * d + a] * Ls[b * d + b]);
+  }
+  int evals = 0;
+  for (int k = 0; k <= p; ++k) {
+    orc_theta_to_H(V + k * p, d, H);
+    if (orc_lscv_H(x, n, d, H, &F[k])) F[k] = INFINITY;
+    ++evals;
+  }
+  double c[136], r[136], e[136], t[136], fr, fe, ft;
+  for (;;) {
+    /* order: insertion sort by F (stable: ties keep their order) */
+    for (int i = 1; i <= p; ++i)
+      for (int j = i; j > 0 && F[j] < F[j - 1]; --j) {
+        double tf = F[j];
+        F[j] = F[j - 1];
+        F[j - 1] = tf;
+        for (int m2 = 0; m2 < p; ++m2) {
+          double tv = V[j * p + m2];
+          V[j * p + m2] = V[(j - 1) * p + m2];
+          V[(j - 1) * p + m2] = tv;
+        }
+      }
+    double xs = 0.0;
+    for (int i = 1; i <= p; ++i)
+      for (int j = 0; j < p; ++j) xs = fmax(xs, fabs(V[i * p + j] - V[j]));
+    if ((F[p] - F[0] <= ftol * fabs(F[0]) && xs <= xtol) || evals >= max_evals) break;
+    for (int j = 0; j < p; ++j) {
+      c[j] = 0.0;
+      for (int i = 0; i < p; ++i) c[j] += V[i * p + j];
+      c[j] /= (double)p;
+    }
+#define ORC_EVAL(vec, out)                         \
+  do {                                             \
+    orc_theta_to_H(vec, d, H);                     \
+    if (orc_lscv_H(x, n, d, H, &(out))) out = INFINITY; \
+    ++evals;                                       \
+  } while (0)
+    for (int j = 0; j < p; ++j) r[j] = c[j] + (c[j] - V[p * p + j]);
+    ORC_EVAL(r, fr);
+    int shrink = 0;
+    if (fr < F[0]) {
+      for (int j = 0; j < p; ++j) e[j] = c[j] + 2.0 * (c[j] - V[p * p + j]);
+      ORC_EVAL(e, fe);
+      if (fe < fr) {
+        for (int j = 0; j < p; ++j) V[p * p + j] = e[j];
+        F[p] = fe;
+      } else {
+        for (int j = 0; j < p; ++j) V[p * p + j] = r[j];
+        F[p] = fr;
+      }
+    } else if (fr < F[p - 1]) {
+      for (int j = 0; j < p; ++j) V[p * p + j] = r[j];
+      F[p] = fr;
+    } else if (fr < F[p]) {
+      for (int j = 0; j < p; ++j) t[j] = c[j] + 0.5 * (r[j] - c[j]);
+      ORC_EVAL(t, ft);
+      if (ft <= fr) {
+        for (int j = 0; j < p; ++j) V[p * p + j] = t[j];
+        F[p] = ft;
+      } else {
+        shrink = 1;
+      }
+    } else {
+      for (int j = 0; j < p; ++j) t[j] = c[j] + 0.5 * (V[p * p + j] - c[j]);
+      ORC_EVAL(t, ft);
+      if (ft < F[p]) {
+        for (int j = 0; j < p; ++j) V[p * p + j] = t[j];
+        F[p] = ft;
+      } else {
+        shrink = 1;
+      }
+    }
+    if (shrink)
+      for (int i = 1; i <= p; ++i) {
+        for (int j = 0; j < p; ++j) V[i * p + j] = V[j] + 0.5 * (V[i * p + j] - V[j]);
+        ORC_EVAL(V + i * p, F[i]);
+      }
+#undef ORC_EVAL
+  }
+  orc_theta_to_H(V, d, H_out);
+  if (g_out) *g_out = F[0];
+  if (evals_out) *evals_out = evals;
+  return ORC_OK;
+}

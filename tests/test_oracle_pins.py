@@ -480,3 +480,65 @@ def test_lscv_md_affine_invariance_and_errors():
     with pytest.raises(oracle.OracleError) as e:
         oracle.lscv_md_curve(z, grid[::-1])
     assert e.value.code == oracle.INVAL
+
+
+def test_lscv_H_reductions_brute_force_and_invariance():
+    """LSCV_H, eq. (LSCV_MULTI-gh): at H = h^2 Sigma it is the sphered LSCV_h
+    objective, at d = 1 the univariate one at h = sqrt(H); its pair sums match
+    numpy with a library inverse; g_{Ax}(A H A^T) = g_x(H) / |det A|."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    for d in (2, 3):
+        z = rng.standard_normal((300, d)) @ (rng.standard_normal((d, d)) + 2 * np.eye(d)).T
+        S = np.cov(z, rowvar=False)
+        for h in (0.2, 0.5, 1.1):
+            assert oracle.lscv_H(z, h * h * S) == pytest.approx(oracle.lscv_md_curve(z, [h]).g[0], rel=1e-12)
+        M = rng.standard_normal((d, d))
+        H = M @ M.T + 0.3 * np.eye(d)
+        inv = np.linalg.inv(H)
+        iu = np.triu_indices(z.shape[0], 1)
+        v = z[:, None, :] - z[None, :, :]
+        q = np.einsum("ija,ab,ijb->ij", v, inv, v)[iu]
+        n = z.shape[0]
+        sq = np.linalg.det(H) ** -0.5
+        g = (2 / n**2 * ((4 * np.pi) ** (-d / 2) * sq * np.exp(-q / 4).sum()
+                         - 2 * (2 * np.pi) ** (-d / 2) * sq * np.exp(-q / 2).sum())
+             + (2.0 ** -d) * np.pi ** (-d / 2) * sq / n)
+        assert oracle.lscv_H(z, H) == pytest.approx(g, rel=1e-11)
+        A = rng.standard_normal((d, d)) + 3 * np.eye(d)
+        assert oracle.lscv_H(z @ A.T + 7.0, A @ H @ A.T) == pytest.approx(
+            oracle.lscv_H(z, H) / abs(np.linalg.det(A)), rel=1e-10)
+    x = workloads.draw("mixture", 400, 5, np.float64)
+    for h in (0.1, 0.3):
+        assert oracle.lscv_H(x[:, None], [[h * h]]) == pytest.approx(oracle.lscv_curve(x, [h]).g[0], rel=1e-12)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.lscv_H(z, -np.eye(3))
+    assert e.value.code == oracle.DEGENERATE
+
+
+def test_lscv_H_nelder_mead_matches_scipy():
+    """The oracle's Nelder-Mead (Section 4.4.3) over H = C C^T, C lower
+    triangular with log-diagonal, lands where scipy's Nelder-Mead on the same
+    objective and start does, and a full H does at least as well as the best
+    H = h^2 Sigma of the LSCV_h family."""
+    from scipy.optimize import minimize
+
+    rng = np.random.Generator(np.random.PCG64(22))
+    z = rng.standard_normal((350, 2)) @ np.array([[1.0, 0.0], [0.8, 0.4]]).T
+    z[:120] = 0.5 * z[:120] + [2.5, 1.0]
+    H, g, evals = oracle.lscv_H_min(z, ftol=1e-12, xtol=1e-8, max_evals=4000)
+    assert evals < 4000
+    n, d = z.shape
+    s = (4 / (d + 2)) ** (1 / (d + 4)) * n ** (-1 / (d + 4))
+    C0 = np.linalg.cholesky(s * s * np.cov(z, rowvar=False))
+    th0 = np.array([np.log(C0[0, 0]), C0[1, 0], np.log(C0[1, 1])])
+
+    def f(th):
+        C = np.array([[np.exp(th[0]), 0.0], [th[1], np.exp(th[2])]])
+        return oracle.lscv_H(z, C @ C.T)
+
+    r = minimize(f, th0, method="Nelder-Mead", options={"xatol": 1e-9, "fatol": 1e-14, "maxfev": 5000})
+    Cr = np.array([[np.exp(r.x[0]), 0.0], [r.x[1], np.exp(r.x[2])]])
+    assert g == pytest.approx(r.fun, rel=1e-9)
+    assert np.allclose(H, Cr @ Cr.T, rtol=1e-4, atol=1e-7)
+    best_h = min(oracle.lscv_md_curve(z, np.geomspace(0.1, 2.0, 400)).g)
+    assert g <= best_h + 1e-12
