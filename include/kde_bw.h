@@ -43,6 +43,8 @@ extern "C" {
 #define KDE_MAX_BATCH 65535
 #define KDE_MAX_QUERIES (1 << 24) /* query points or ranges per kde_density / kde_range_aggregates call */
 #define KDE_MAX_D 16 /* dimensions of a sample matrix (kde_lscv_md_curve) */
+#define KDE_MAX_HD 4 /* dimensions of a sample matrix for LSCV_H (kde_lscv_H_eval, kde_bw_lscv_H) */
+#define KDE_MAX_H_EVAL 65536 /* bandwidth matrices per kde_lscv_H_eval call */
 
 typedef enum {
   KDE_OK = 0,
@@ -386,6 +388,53 @@ kde_status kde_lscv_md_curve(kde_ctx* ctx, kde_matrix x, const double* h_grid, i
  * to the lowest index; k_out may be NULL. */
 kde_status kde_bw_lscv_md(kde_ctx* ctx, kde_matrix x, const double* h_grid, int32_t n_h, double* h_out,
                           int32_t* k_out);
+
+/* LSCV_H, Section 4.4.3: the objective at full bandwidth matrices,
+ *   g(H) = 2 n^-2 sum_{i<j} [(K*K)_H - 2 K_H](X_i - X_j) + n^-1 R(K),
+ * eq. (LSCV_MULTI-gh) with (LSCV_MULTI-KKx), (LSCV_MULTI-Kx), (LSCV_MULTI-rk):
+ * (K*K)_H(v) = (4 pi)^(-d/2) |H|^(-1/2) exp(-v^T H^-1 v / 4),
+ * K_H(v) = (2 pi)^(-d/2) |H|^(-1/2) exp(-v^T H^-1 v / 2),
+ * R(K) = 2^-d pi^(-d/2) |H|^(-1/2); H in the units of the data (H = h^2 for
+ * d = 1).  H holds m row-major d x d matrices, only their lower triangles are
+ * read.  One pass of the pair kernel evaluates up to 64 matrices: each pair's
+ * whitened difference (Y = L^-1 (X - mean), Sigma = L L^T) gives the monomials
+ * of its quadratic form once for all of them.  g_out[m]; gscale_out (may be
+ * NULL) receives 2 n^-2 (A S1 + 2 B S2) + n^-1 R, the scale of the terms.
+ * A matrix that is not positive definite (a Cholesky pivot at most 1e-12 of
+ * its diagonal entry) gets g = +inf and scale 0.  The mixed form computes the
+ * quadratic form from FP32 coefficients and evaluates g exactly at the
+ * matrix those coefficients represent (within FP32 rounding of H).
+ * KDE_E_INVAL for a bad matrix (n < 2, d outside [1, KDE_MAX_HD], a
+ * non-finite value), a non-finite entry of H or m outside [1, KDE_MAX_H_EVAL];
+ * KDE_E_DEGENERATE when the sample covariance is singular. */
+kde_status kde_lscv_H_eval(kde_ctx* ctx, kde_matrix x, const double* H, int32_t m, double* g_out,
+                           double* gscale_out);
+
+typedef struct {
+  double g;          /* g(H_out) */
+  int32_t evals;     /* evaluations of g */
+  int32_t passes;    /* passes of the pair kernel (a batch of matrices each) */
+  int32_t converged; /* 1: both tolerances met; 0: stopped at max_evals */
+  int32_t pad0;
+} kde_lscv_H_info;
+/* The LSCV_H bandwidth matrix (Section 4.4.3): Nelder-Mead minimisation of
+ * g(H) over H = C C^T, C lower triangular with parameters theta = the lower
+ * triangle row by row, log C_aa in place of each diagonal entry, so every
+ * trial matrix is positive definite.  Start: the rule-of-thumb matrix of
+ * eq. (LSCV-H-start) taken as the squared bandwidth s^2 Sigma,
+ * s = (4/(d+2))^(1/(d+4)) n^(-1/(d+4)); initial steps 0.25 on each
+ * log-diagonal parameter and 0.25 sqrt(C_aa C_bb) on an off-diagonal one;
+ * reflection 1, expansion 2, contractions 1/2, shrink 1/2 towards the best
+ * vertex.  Stops when max g - min g over the simplex is at most ftol |min g|
+ * and every vertex lies within xtol of the best in every parameter, or after
+ * max_evals evaluations.  The p + 1 starting vertices, and the p vertices of
+ * a shrink, are evaluated in one pass each.  H_out receives the best vertex's
+ * matrix (row-major d x d); info may be NULL.  The mixed form's g carries
+ * relative noise of about 1e-9 and below between nearby matrices, so an ftol
+ * under that can run to max_evals.  Errors as kde_lscv_H_eval, and
+ * KDE_E_INVAL for ftol or xtol not > 0 or max_evals < 1. */
+kde_status kde_bw_lscv_H(kde_ctx* ctx, kde_matrix x, double ftol, double xtol, int32_t max_evals, double* H_out,
+                         kde_lscv_H_info* info);
 
 /* LSCV bandwidth by a search instead of a fixed grid: the alternative to the
  * brute-force grid that Section 4.4.2 names (a golden-ratio type search).

@@ -27,6 +27,9 @@ KDE_PREC_MIXED, KDE_PREC_FP64 = 0, 1
 KDE_MAX_N = 1 << 30
 KDE_MAX_NH = 65536
 KDE_MAX_BATCH = 65535
+KDE_MAX_D = 16
+KDE_MAX_HD = 4
+KDE_MAX_H_EVAL = 65536
 KDE_GRID_EXPLICIT, KDE_GRID_PAPER, KDE_GRID_LOG_ROT = 0, 1, 2
 KDE_METHOD_ROT, KDE_METHOD_PLUGIN, KDE_METHOD_LSCV = 1, 2, 4
 
@@ -47,7 +50,7 @@ EXPORTS = (
     "kde_lscv_curve", "kde_lscv_sums", "kde_lscv_item_sums", "kde_bw_lscv", "kde_batch",
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
     "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min", "kde_density",
-    "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md",
+    "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md", "kde_lscv_H_eval", "kde_bw_lscv_H",
 )
 
 
@@ -87,6 +90,11 @@ class kde_lscv_min_info(ctypes.Structure):
 class kde_matrix(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("dtype", ctypes.c_int),
                 ("on_device", ctypes.c_int)]
+
+
+class kde_lscv_H_info(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("evals", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("pad0", ctypes.c_int32)]
 
 
 class kde_grid(ctypes.Structure):
@@ -161,6 +169,9 @@ def _load():
     lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_md.argtypes = [P, kde_matrix, PD, I32, PD, ctypes.POINTER(I32)]
+    lib.kde_lscv_H_eval.argtypes = [P, kde_matrix, PD, I32, PD, PD]
+    lib.kde_bw_lscv_H.argtypes = [P, kde_matrix, ctypes.c_double, ctypes.c_double, I32, PD,
+                                  ctypes.POINTER(kde_lscv_H_info)]
     lib.kde_range_aggregates.argtypes = [P, kde_column, ctypes.c_double, PD, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_min.argtypes = [P, kde_column, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, PD,
                                     ctypes.POINTER(kde_lscv_min_info)]
@@ -326,6 +337,32 @@ def kde_bw_lscv_md(ctx, x, h_grid=None, n_h: int = 0):
     _check(ctx, lib.kde_bw_lscv_md(ctx, m, _pd(gr), int(k), ctypes.byref(h), ctypes.byref(kk)))
     del keep
     return h.value, kk.value
+
+
+def kde_lscv_H_eval(ctx, x, H):
+    """(g, gscale) of LSCV_H at bandwidth matrices H (m x d x d, or one d x d)."""
+    m, keep = make_matrix(x)
+    d = m.d
+    Hs = np.ascontiguousarray(np.asarray(H, np.float64))
+    if Hs.ndim == 2:
+        Hs = Hs[None]
+    if Hs.ndim != 3 or Hs.shape[1:] != (d, d):
+        raise ValueError("H must be m x d x d for d-dimensional samples")
+    k = Hs.shape[0]
+    g, gs = np.empty(k, np.float64), np.empty(k, np.float64)
+    _check(ctx, lib.kde_lscv_H_eval(ctx, m, _pd(Hs.ravel()), int(k), _pd(g), _pd(gs)))
+    del keep
+    return g, gs
+
+
+def kde_bw_lscv_H(ctx, x, ftol: float = 1e-10, xtol: float = 1e-6, max_evals: int = 2000):
+    """(H, info) -- the Nelder-Mead LSCV_H bandwidth matrix."""
+    m, keep = make_matrix(x)
+    H = np.empty(m.d * m.d, np.float64)
+    info = kde_lscv_H_info()
+    _check(ctx, lib.kde_bw_lscv_H(ctx, m, float(ftol), float(xtol), int(max_evals), _pd(H), ctypes.byref(info)))
+    del keep
+    return H.reshape(m.d, m.d), info
 
 
 def kde_density(ctx, x, h: float, points):
@@ -648,6 +685,12 @@ class Context:
 
     def bw_lscv_md(self, x, h_grid=None, n_h=0):
         return kde_bw_lscv_md(self.ctx, x, h_grid, n_h)
+
+    def lscv_H_eval(self, x, H):
+        return kde_lscv_H_eval(self.ctx, x, H)
+
+    def bw_lscv_H(self, x, ftol=1e-10, xtol=1e-6, max_evals=2000):
+        return kde_bw_lscv_H(self.ctx, x, ftol, xtol, max_evals)
 
     def range_aggregates(self, x, h, lo, hi):
         return kde_range_aggregates(self.ctx, x, h, lo, hi)

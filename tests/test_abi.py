@@ -10,7 +10,7 @@ HEADER = os.path.join(ROOT, "include", "kde_bw.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*(kde_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*(kde_[A-Za-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
