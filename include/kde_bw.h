@@ -43,7 +43,6 @@ extern "C" {
 #define KDE_MAX_BATCH 65535
 #define KDE_MAX_QUERIES (1 << 24) /* query points or ranges per kde_density / kde_range_aggregates call */
 #define KDE_MAX_D 16 /* dimensions of a sample matrix (kde_lscv_md_curve) */
-#define KDE_MAX_HD 4 /* dimensions of a sample matrix for LSCV_H (kde_lscv_H_eval, kde_bw_lscv_H) */
 #define KDE_MAX_H_EVAL 65536 /* bandwidth matrices per kde_lscv_H_eval call */
 
 typedef enum {
@@ -396,15 +395,18 @@ kde_status kde_bw_lscv_md(kde_ctx* ctx, kde_matrix x, const double* h_grid, int3
  * K_H(v) = (2 pi)^(-d/2) |H|^(-1/2) exp(-v^T H^-1 v / 2),
  * R(K) = 2^-d pi^(-d/2) |H|^(-1/2); H in the units of the data (H = h^2 for
  * d = 1).  H holds m row-major d x d matrices, only their lower triangles are
- * read.  One pass of the pair kernel evaluates up to 64 matrices: each pair's
- * whitened difference (Y = L^-1 (X - mean), Sigma = L L^T) gives the monomials
- * of its quadratic form once for all of them.  g_out[m]; gscale_out (may be
+ * read.  For d <= 4 one pass of the pair kernel evaluates up to 64 matrices:
+ * each pair's whitened difference (Y = L^-1 (X - mean), Sigma = L L^T) gives
+ * the monomials of its quadratic form once for all of them, four matrices a
+ * block.  For 4 < d <= 16 each matrix has a sweep of its own over samples
+ * whitened for it (Z = L_G^-1 Y, G = L^-1 H L^-T).  g_out[m]; gscale_out (may be
  * NULL) receives 2 n^-2 (A S1 + 2 B S2) + n^-1 R, the scale of the terms.
  * A matrix that is not positive definite (a Cholesky pivot at most 1e-12 of
- * its diagonal entry) gets g = +inf and scale 0.  The mixed form computes the
- * quadratic form from FP32 coefficients and evaluates g exactly at the
- * matrix those coefficients represent (within FP32 rounding of H).
- * KDE_E_INVAL for a bad matrix (n < 2, d outside [1, KDE_MAX_HD], a
+ * its diagonal entry) gets g = +inf and scale 0.  The mixed form (d <= 4)
+ * computes the quadratic form from FP32 coefficients and evaluates g exactly
+ * at the matrix those coefficients represent (within FP32 rounding of H);
+ * for d > 4 it rounds the re-whitened samples to FP32.
+ * KDE_E_INVAL for a bad matrix (n < 2, d outside [1, KDE_MAX_D], a
  * non-finite value), a non-finite entry of H or m outside [1, KDE_MAX_H_EVAL];
  * KDE_E_DEGENERATE when the sample covariance is singular. */
 kde_status kde_lscv_H_eval(kde_ctx* ctx, kde_matrix x, const double* H, int32_t m, double* g_out,

@@ -28,7 +28,6 @@ KDE_MAX_N = 1 << 30
 KDE_MAX_NH = 65536
 KDE_MAX_BATCH = 65535
 KDE_MAX_D = 16
-KDE_MAX_HD = 4
 KDE_MAX_H_EVAL = 65536
 KDE_GRID_EXPLICIT, KDE_GRID_PAPER, KDE_GRID_LOG_ROT = 0, 1, 2
 KDE_METHOD_ROT, KDE_METHOD_PLUGIN, KDE_METHOD_LSCV = 1, 2, 4

@@ -176,10 +176,12 @@ __global__ void k_md_factor(const double* part, int nblk, MdState* st) {
   st->h0 = pow(4.0 / ((d + 2.0) * (double)st->n), 1.0 / (d + 4.0));
 }
 
-// Y[a][i] = sum_b L^-1[a][b] (x_ib - mean_b), a < D (coordinates a >= d are 0);
-// padding: +inf in coordinate 0, 0 elsewhere
+// Y[a][i] = sum_b M[a][b] (x_ib - mean_b), a < D (coordinates a >= d are 0),
+// M lower triangular with row stride KDE_MAX_D (L^-1 for the sphered
+// samples); padding: +inf in coordinate 0, 0 elsewhere
 __global__ __launch_bounds__(kThreads) void k_md_whiten(const void* raw, int f64, int n, int D, int npad,
-                                                        const MdState* st, float* y32, double* y64) {
+                                                        const MdState* st, const double* M, float* y32,
+                                                        double* y64) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= npad) return;
   const int d = st->d;
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_md_whiten(const void* raw, int f64
       w = a == 0 ? (double)__builtin_inff() : 0.0;
     } else if (a < d) {
       w = 0.0;
-      for (int b = 0; b <= a; ++b) w += st->linv[a * KDE_MAX_D + b] * v[b];
+      for (int b = 0; b <= a; ++b) w += M[a * KDE_MAX_D + b] * v[b];
     } else {
       w = 0.0;
     }
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(1024) void k_md_finalize(MdState* st, const double*
   }
 }
 
-// ---- LSCV_H (Section 4.4.3): g(H) at bandwidth matrices H, 1 <= d <= 4.
+// ---- LSCV_H (Section 4.4.3): g(H) at bandwidth matrices H, batched for 1 <= d <= 4.
 // In whitened coordinates w = Y_i - Y_j the quadratic form of the pair is
 // v^T H^-1 v = w^T P w with P = G^-1, G = L^-1 H L^-T (Sigma = L L^T).  A pair's
 // monomials w_a w_b (a <= b < D) are formed once in registers and each matrix
@@ -557,6 +559,88 @@ __global__ void k_H_prep(const MdState* st, const double* H, int m, int D, int f
     o.logdet32 = f64 ? o.logdet64 : st->logdet - ldP32;
     o.valid = ok32 ? 1 : 0;
   }
+  out[k] = o;
+}
+
+// ---- LSCV_H for 4 < d <= 16: one matrix a sweep.  With G = L_G L_G^T the
+// quadratic form is |L_G^-1 w|^2, so the samples are whitened once more,
+// Z = M (X - mean) with M = L_G^-1 L^-1 (lower triangular), and the sphered
+// pair kernel runs on Z with the single coefficient -1/4 (S2 from e^2).
+// Both forms evaluate g at H itself; the mixed form rounds Z to FP32.
+__global__ void k_HT_prep(const MdState* st, const double* H, int m, HDesc* out, double* Mout) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int d = st->d;
+  double A[KDE_MAX_D][KDE_MAX_D], L[KDE_MAX_D][KDE_MAX_D], T[KDE_MAX_D][KDE_MAX_D];
+  double* M = Mout + (int64_t)k * KDE_MAX_D * KDE_MAX_D;
+  for (int q = 0; q < KDE_MAX_D * KDE_MAX_D; ++q) M[q] = 0.0;
+  HDesc o;
+  for (int q = 0; q < kMaxMono; ++q) {
+    o.c32[q] = 0.f;
+    o.c64[q] = 0.0;
+  }
+  o.valid = 0;
+  o.pad0 = 0;
+  o.logdet64 = o.logdet32 = 0.0;
+  const double* Hk = H + (int64_t)k * d * d;
+  // Cholesky of A with the library's pivot rule; returns log|A| or NaN
+  auto chol = [&](double& ld) {
+    ld = 0.0;
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b <= a; ++b) {
+        double s = A[a][b];
+        for (int c = 0; c < b; ++c) s -= L[a][c] * L[b][c];
+        if (a == b) {
+          if (!(s > 1e-12 * A[a][a]) || !isfinite(s)) return false;
+          L[a][a] = sqrt(s);
+          ld += 2.0 * log(L[a][a]);
+        } else {
+          L[a][b] = s / L[b][b];
+        }
+      }
+    return true;
+  };
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) A[a][b] = A[b][a] = Hk[a * d + b];
+  double ldH, ldG;
+  if (st->status != kStOk || !chol(ldH)) {
+    out[k] = o;
+    return;
+  }
+  for (int a = 0; a < d; ++a)  // T = L^-1 H
+    for (int b = 0; b < d; ++b) {
+      double s = 0.0;
+      for (int c = 0; c <= a; ++c) s += st->linv[a * KDE_MAX_D + c] * A[c][b];
+      T[a][b] = s;
+    }
+  for (int a = 0; a < d; ++a)  // G = T L^-T into A
+    for (int b = 0; b <= a; ++b) {
+      double s = 0.0;
+      for (int c = 0; c <= b; ++c) s += T[a][c] * st->linv[b * KDE_MAX_D + c];
+      A[a][b] = A[b][a] = s;
+    }
+  if (!chol(ldG)) {
+    out[k] = o;
+    return;
+  }
+  for (int c = 0; c < d; ++c)  // T = L_G^-1 (lower)
+    for (int a = 0; a < d; ++a) {
+      if (a < c) {
+        T[a][c] = 0.0;
+        continue;
+      }
+      double s = (a == c) ? 1.0 : 0.0;
+      for (int q = c; q < a; ++q) s -= L[a][q] * T[q][c];
+      T[a][c] = s / L[a][a];
+    }
+  for (int a = 0; a < d; ++a)  // M = L_G^-1 L^-1
+    for (int b = 0; b <= a; ++b) {
+      double s = 0.0;
+      for (int c = b; c <= a; ++c) s += T[a][c] * st->linv[c * KDE_MAX_D + b];
+      M[a * KDE_MAX_D + b] = s;
+    }
+  o.logdet64 = o.logdet32 = st->logdet + ldG;
+  o.valid = 1;
   out[k] = o;
 }
 
@@ -836,6 +920,16 @@ void launch_md(hipStream_t s, int D, bool f64, const float* y32, const double* y
 #undef KDE_MD_CASE
 }
 
+// the sphered pair kernel with a single coefficient (LSCV_H, 4 < d <= 16)
+void launch_md_one(hipStream_t s, int D, bool f64, const float* y32, const double* y64, int npad,
+                   const MdState* st, const float* c32, const double* c64, const Unit* units, int u0, int cnt,
+                   double* part, int n_items) {
+  if (D <= 8)
+    launch_md_units<8, 1>(s, f64, y32, y64, npad, st, c32, c64, units, u0, cnt, part, n_items, 1);
+  else
+    launch_md_units<16, 1>(s, f64, y32, y64, npad, st, c32, c64, units, u0, cnt, part, n_items, 1);
+}
+
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 // moments, covariance, Cholesky factor and whitened copy of the samples (the
@@ -847,7 +941,8 @@ void md_stage(hipStream_t st, const void* raw, bool raw_f64, int n, int d, int D
   k_md_mean<<<1, 64, 0, st>>>(ps, nf, nblk, n, d, dst);
   k_md_cov<<<nblk, kThreads, 0, st>>>(raw, fx, n, d, nblk, dst, pc);
   k_md_factor<<<1, 64, 0, st>>>(pc, nblk, dst);
-  k_md_whiten<<<(npad + kThreads - 1) / kThreads, kThreads, 0, st>>>(raw, fx, n, D, npad, dst, y32, y64);
+  k_md_whiten<<<(npad + kThreads - 1) / kThreads, kThreads, 0, st>>>(raw, fx, n, D, npad, dst, dst->linv, y32,
+                                                                     y64);
 }
 
 }  // namespace
@@ -961,12 +1056,17 @@ struct HRun {
   kde_ctx* c = nullptr;
   int n = 0, d = 0, D = 0, npad = 0, n_items = 0;
   bool f64 = false;
+  bool one = false;           // d > kMaxHD: one matrix a sweep on re-whitened samples
+  const void* raw = nullptr;  // the samples on the device
+  bool raw_f64 = false;
   std::vector<double> pairs;  // per item
   char* b = nullptr;
   size_t o_st = 0, o_y32 = 0, o_y64 = 0, o_hin = 0, o_hd = 0, o_part = 0, o_sums = 0, o_g = 0, o_gs = 0,
-         o_units = 0, o_rows = 0;
+         o_units = 0, o_rows = 0, o_hm = 0, o_coef = 0;
   MdState state{};
   int passes = 0;
+  float coef32 = 0.f;  // host sources of the coefficient copies (live until the stage's sync)
+  double coef64 = 0.0;
 };
 
 // Item length of an LSCV_H pass: about 8192 blocks for a single matrix
@@ -979,14 +1079,15 @@ int64_t h_seg(const kde_ctx* c, int64_t n) {
 }
 
 kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
-  if (!x.data || x.n < 2 || x.n > KDE_MAX_N || x.d < 1 || x.d > KDE_MAX_HD ||
+  if (!x.data || x.n < 2 || x.n > KDE_MAX_N || x.d < 1 || x.d > KDE_MAX_D ||
       (x.dtype != KDE_F32 && x.dtype != KDE_F64))
-    return fail(c, KDE_E_INVAL, "need a row-major n x d matrix, 2 <= n <= KDE_MAX_N, 1 <= d <= KDE_MAX_HD");
+    return fail(c, KDE_E_INVAL, "need a row-major n x d matrix, 2 <= n <= KDE_MAX_N, 1 <= d <= KDE_MAX_D");
   r.c = c;
   r.f64 = c->prec == KDE_PREC_FP64;
   r.n = (int)x.n;
   r.d = x.d;
   r.D = md_width(r.d);
+  r.one = r.d > kMaxHD;
   r.npad = r.n + kPad;
   const int n = r.n, d = r.d, D = r.D;
   const int esz = x.dtype == KDE_F64 ? 8 : 4;
@@ -1019,6 +1120,8 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   r.o_gs = take(8 * (size_t)kHPass);
   r.o_units = take(sizeof(Unit) * units.size());
   r.o_rows = take(sizeof(RowDesc) * 2 * (size_t)kHPass);
+  r.o_hm = r.one ? take(8 * (size_t)kHPass * KDE_MAX_D * KDE_MAX_D) : 0;
+  r.o_coef = take(16);
   kde_status s;
   if ((s = ensure(c, c->mdbuf, at))) return s;
   char* b = r.b = c->mdbuf.p;
@@ -1027,9 +1130,15 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   std::vector<RowDesc> rows;
   for (int q = 0; q < 2 * kHPass; ++q) rows.push_back(RowDesc{part + (size_t)q * r.n_items, sums + q, r.n_items, 0});
   hipStream_t st = c->stream;
-  const void* raw = x.on_device ? x.data : (const void*)(b + o_raw);
+  const void* raw = r.raw = x.on_device ? x.data : (const void*)(b + o_raw);
+  r.raw_f64 = x.dtype == KDE_F64;
   if (!x.on_device)
     KDE_HIP_TRY(c, hipMemcpyAsync(b + o_raw, x.data, (size_t)n * d * esz, hipMemcpyHostToDevice, st));
+  // the single coefficient of the one-matrix sweep: -log2(e)/4 (FP32), -1/4 (FP64)
+  r.coef32 = (float)(-kLog2ED * 0.25);
+  r.coef64 = -0.25;
+  KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_coef, &r.coef64, 8, hipMemcpyHostToDevice, st));
+  KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_coef + 8, &r.coef32, 4, hipMemcpyHostToDevice, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_rows, rows.data(), sizeof(RowDesc) * rows.size(), hipMemcpyHostToDevice, st));
   MdState* dst = (MdState*)(b + r.o_st);
@@ -1055,10 +1164,30 @@ kde_status h_pass(HRun& r, const double* H, int m, double* g, double* gs) {
   const HDesc* hd = (const HDesc*)(b + r.o_hd);
   double* part = (double*)(b + r.o_part);
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_hin, H, 8 * (size_t)m * r.d * r.d, hipMemcpyHostToDevice, st));
-  k_H_prep<<<1, kHPass, 0, st>>>(dst, (const double*)(b + r.o_hin), m, r.D, r.f64 ? 1 : 0, (HDesc*)(b + r.o_hd));
   // launches of at most launch_evals pair-term evaluations and at least 2048 blocks
   const double budget = r.f64 ? c->opt_launch_evals / 5.0 : c->opt_launch_evals;
-  const size_t total = (size_t)chunks * r.n_items;
+  if (r.one) {
+    const double* hm = (const double*)(b + r.o_hm);
+    k_HT_prep<<<1, kHPass, 0, st>>>(dst, (const double*)(b + r.o_hin), m, (HDesc*)(b + r.o_hd), (double*)hm);
+    float* z32 = r.f64 ? nullptr : (float*)(b + r.o_y32);
+    double* z64 = r.f64 ? (double*)(b + r.o_y64) : nullptr;
+    for (int k = 0; k < m; ++k) {
+      k_md_whiten<<<(r.npad + kThreads - 1) / kThreads, kThreads, 0, st>>>(
+          r.raw, r.raw_f64 ? 1 : 0, r.n, r.D, r.npad, dst, hm + (size_t)k * KDE_MAX_D * KDE_MAX_D, z32, z64);
+      for (size_t u0 = 0; u0 < (size_t)r.n_items;) {
+        double acc = r.pairs[u0];
+        size_t u1 = u0 + 1;
+        while (u1 < (size_t)r.n_items && (acc + r.pairs[u1] <= budget || u1 - u0 < 2048)) acc += r.pairs[u1++];
+        launch_md_one(st, r.D, r.f64, z32, z64, r.npad, dst, (const float*)(b + r.o_coef + 8),
+                      (const double*)(b + r.o_coef), (const Unit*)(b + r.o_units), (int)u0, (int)(u1 - u0),
+                      part + (size_t)2 * k * r.n_items, r.n_items);
+        u0 = u1;
+      }
+    }
+  } else {
+    k_H_prep<<<1, kHPass, 0, st>>>(dst, (const double*)(b + r.o_hin), m, r.D, r.f64 ? 1 : 0, (HDesc*)(b + r.o_hd));
+  }
+  const size_t total = r.one ? 0 : (size_t)chunks * r.n_items;
   for (size_t u0 = 0; u0 < total;) {
     double acc = r.pairs[u0 % r.n_items] * MH;
     size_t u1 = u0 + 1;
@@ -1090,7 +1219,7 @@ kde_status h_eval(HRun& r, const double* H, int m, double* g, double* gs) {
 // H = C C^T from theta: the lower triangle of C row by row, the logarithm of
 // each diagonal entry in place of the entry
 void theta_to_H(const double* th, int d, double* H) {
-  double C[kMaxHD][kMaxHD] = {};
+  double C[KDE_MAX_D][KDE_MAX_D] = {};
   int p = 0;
   for (int a = 0; a < d; ++a)
     for (int b = 0; b <= a; ++b, ++p) C[a][b] = (a == b) ? std::exp(th[p]) : th[p];
@@ -1115,7 +1244,7 @@ kde_status h_search(HRun& r, double ftol, double xtol, int max_evals, double* H_
   kde_ctx* c = r.c;
   // Cholesky factor of s^2 Sigma
   const double sc = std::pow(4.0 / (d + 2.0), 1.0 / (d + 4.0)) * std::pow((double)r.n, -1.0 / (d + 4.0));
-  double S[kMaxHD][kMaxHD], Ls[kMaxHD][kMaxHD] = {};
+  double S[KDE_MAX_D][KDE_MAX_D], Ls[KDE_MAX_D][KDE_MAX_D] = {};
   for (int a = 0; a < d; ++a)
     for (int b = 0; b < d; ++b) S[a][b] = r.state.sigma[a * KDE_MAX_D + b] * sc * sc;
   for (int a = 0; a < d; ++a)
@@ -1263,7 +1392,7 @@ kde_status kde_lscv_H_eval(kde_ctx* c, kde_matrix x, const double* H, int32_t m,
   if (!c || !g_out || !H) return KDE_E_INVAL;
   if (c->server && kde::server_running(c->server.get())) return kde::fail(c, KDE_E_BUSY, "a server is running");
   if (m < 1 || m > KDE_MAX_H_EVAL) return kde::fail(c, KDE_E_INVAL, "matrix count outside [1, KDE_MAX_H_EVAL]");
-  if (x.d >= 1 && x.d <= KDE_MAX_HD)
+  if (x.d >= 1 && x.d <= KDE_MAX_D)
     for (int64_t q = 0; q < (int64_t)m * x.d * x.d; ++q)
       if (!std::isfinite(H[q])) return kde::fail(c, KDE_E_INVAL, "bandwidth matrix holds a non-finite value");
   if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
