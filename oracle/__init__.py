@@ -95,6 +95,7 @@ def _load():
     lib.orc_lscv_md_curve.argtypes = [PD, L, I, PD, I, PD, PD, PD, PD]
     lib.orc_lscv_H.argtypes = [PD, L, I, PD, PD]
     lib.orc_lscv_H_min.argtypes = [PD, L, I, D, D, I, PD, PD, PI]
+    lib.orc_density_H.argtypes = [PD, L, I, PD, PD, I, PD]
     lib.orc_range_aggregates.argtypes = [PD, L, D, PD, PD, I, PD, PD]
     _lib = lib
     return lib
@@ -325,3 +326,98 @@ def lscv_H_min(x, ftol: float = 1e-10, xtol: float = 1e-6, max_evals: int = 2000
     _check(_load().orc_lscv_H_min(_p(a.ravel()), n, d, float(ftol), float(xtol), int(max_evals), _p(H),
                                   ctypes.byref(g), ctypes.byref(ev)), "lscv_H_min")
     return H.reshape(d, d), g.value, ev.value
+
+
+def density_H(x, H, points) -> np.ndarray:
+    """Density estimate with bandwidth matrix H at points (m x d), eq. (kde-def-H)."""
+    a = np.ascontiguousarray(np.asarray(x, np.float64))
+    if a.ndim == 1:
+        a = a[:, None]
+    n, d = a.shape
+    Hm = np.ascontiguousarray(np.asarray(H, np.float64).reshape(d, d))
+    p = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, d))
+    out = np.empty(p.shape[0], np.float64)
+    _check(_load().orc_density_H(_p(a.ravel()), n, d, _p(Hm.ravel()), _p(p.ravel()), p.shape[0], _p(out)),
+           "density_H")
+    return out
+
+
+def range_aggregates_2d(x, H, boxes):
+    """COUNT, SUM of the first and SUM of the second coordinate over boxes
+    [a, b] x [c, d] (rows of ``boxes``: a, b, c, d), eq. (count-sum-2D) with
+    the density estimate of eq. (kde-def-H), d = 2.
+
+    Per sample the kernel is a bivariate normal with mean X_i and covariance
+    H.  In its standardised coordinates U (first) and V (second), corr rho,
+    V given U = z is normal with mean rho z and deviation s = sqrt(1 - rho^2),
+    so over the standardised box [al1, be1] x [al2, be2]
+      P     = int_al1^be1 phi(z) B(z) dz,   B(z) = Phi(b'(z)) - Phi(a'(z)),
+      E[U]  = int_al1^be1 z phi(z) B(z) dz,
+      E[V]  = int_al1^be1 phi(z) (rho z B(z) + s (phi(a'(z)) - phi(b'(z)))) dz,
+    a'(z) = (al2 - rho z)/s, b'(z) = (be2 - rho z)/s, each integral taken by
+    adaptive quadrature (scipy's quad, relative tolerance 1e-12, absolute
+    1e-15 of the kernel's unit mass) with break points at 0 and where B
+    changes.  COUNT = sum_i P_i, SUM_x = sum_i (x_i P_i +
+    sqrt(H11) E[U]_i), SUM_y = sum_i (y_i P_i + sqrt(H22) E[V]_i).  Pure
+    Python per sample: for small n only."""
+    import warnings
+
+    from scipy import integrate
+    from scipy.special import ndtr
+
+    a = np.asarray(x, np.float64)
+    if a.ndim != 2 or a.shape[1] != 2 or a.shape[0] < 1 or not np.all(np.isfinite(a)):
+        raise OracleError(INVAL, "range_aggregates_2d")
+    Hm = np.asarray(H, np.float64).reshape(2, 2)
+    s1, s2 = np.sqrt(Hm[0, 0]), np.sqrt(Hm[1, 1])
+    if not (Hm[0, 0] > 0 and Hm[1, 1] > 0) or not np.all(np.isfinite(Hm)):
+        raise OracleError(DEGENERATE, "range_aggregates_2d")
+    rho = Hm[1, 0] / (s1 * s2)
+    if not (abs(rho) < 1.0 - 1e-12):
+        raise OracleError(DEGENERATE, "range_aggregates_2d")
+    s = np.sqrt((1.0 - rho) * (1.0 + rho))
+    bx = np.asarray(boxes, np.float64).reshape(-1, 4)
+    if np.any(np.isnan(bx)) or np.any(bx[:, 0] > bx[:, 1]) or np.any(bx[:, 2] > bx[:, 3]):
+        raise OracleError(INVAL, "range_aggregates_2d")
+    phi = lambda z: np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)  # noqa: E731
+    cnt, sx, sy = (np.zeros(bx.shape[0]) for _ in range(3))
+    for k, (lo1, hi1, lo2, hi2) in enumerate(bx):
+        if lo1 == hi1 or lo2 == hi2:
+            continue
+        for xi, yi in a:
+            al1, be1 = (lo1 - xi) / s1, (hi1 - xi) / s1
+            al2, be2 = (lo2 - yi) / s2, (hi2 - yi) / s2
+            z0, z1 = max(al1, -40.0), min(be1, 40.0)
+            if not z1 > z0:
+                continue
+
+            def B(z):
+                return ndtr((be2 - rho * z) / s) - ndtr((al2 - rho * z) / s)
+
+            def C(z):
+                ap, bp = (al2 - rho * z) / s, (be2 - rho * z) / s
+                pa = 0.0 if np.isinf(ap) else phi(ap)
+                pb = 0.0 if np.isinf(bp) else phi(bp)
+                return rho * z * B(z) + s * (pa - pb)
+
+            pts = []
+            if rho != 0.0:
+                w = s / abs(rho)
+                for c in (al2 / rho, be2 / rho):
+                    if np.isfinite(c):
+                        pts += [c + f * w for f in (-30, -10, -3, -1, 0, 1, 3, 10, 30)]
+            pts = sorted(p for p in pts + [0.0] if z0 < p < z1)
+            kw = dict(epsabs=1e-15, epsrel=1e-12, limit=400)
+            if pts:
+                kw["points"] = pts
+            with warnings.catch_warnings():
+                # integrals that vanish (E[U] over the whole line) cannot meet a
+                # relative tolerance; the absolute one still holds
+                warnings.simplefilter("ignore", integrate.IntegrationWarning)
+                P = integrate.quad(lambda z: phi(z) * B(z), z0, z1, **kw)[0]
+                EU = integrate.quad(lambda z: z * phi(z) * B(z), z0, z1, **kw)[0]
+                EV = integrate.quad(lambda z: phi(z) * C(z), z0, z1, **kw)[0]
+            cnt[k] += P
+            sx[k] += xi * P + s1 * EU
+            sy[k] += yi * P + s2 * EV
+    return cnt, sx, sy

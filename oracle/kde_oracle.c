@@ -849,3 +849,43 @@ int orc_lscv_H_min(const double* x, long n, int d, double ftol, double xtol, int
   if (evals_out) *evals_out = evals;
   return ORC_OK;
 }
+
+/* Density estimate with a bandwidth matrix at m points, eq. (kde-def-H) with
+ * K_H of eq. (K_H) and K of eq. (gaussian):
+ *   f(p) = n^-1 sum_i (2 pi)^(-d/2) |H|^(-1/2) exp(-(p - X_i)^T H^-1 (p - X_i) / 2).
+ * x row-major n x d, H row-major d x d (lower triangle read), pts row-major
+ * m x d.  H^-1 and |H| from its Cholesky factor; the quadratic form is the
+ * double sum per pair; each point's sum is Neumaier-compensated in sample
+ * order.  H not positive definite -> DEGENERATE. */
+int orc_density_H(const double* x, long n, int d, const double* H, const double* pts, int m, double* out) {
+  if (n < 1 || d < 1 || d > 16 || m < 1) return ORC_INVAL;
+  for (long i = 0; i < n * d; ++i)
+    if (!isfinite(x[i])) return ORC_INVAL;
+  for (long i = 0; i < (long)m * d; ++i)
+    if (!isfinite(pts[i])) return ORC_INVAL;
+  double Hs[256], L[256], inv[256], logdet;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b <= a; ++b) Hs[a * d + b] = Hs[b * d + a] = H[a * d + b];
+  for (int i = 0; i < d * d; ++i)
+    if (!isfinite(Hs[i])) return ORC_INVAL;
+  int st = orc_spd(Hs, d, L, inv, &logdet);
+  if (st) return st;
+  const double norm = pow(2.0 * ORC_PI, -0.5 * d) * exp(-0.5 * logdet) / (double)n;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int k = 0; k < m; ++k) {
+    double v[16];
+    double s = 0.0, c = 0.0;
+    for (long i = 0; i < n; ++i) {
+      for (int a = 0; a < d; ++a) v[a] = pts[(long)k * d + a] - x[i * d + a];
+      double q = 0.0;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) q += v[a] * inv[a * d + b] * v[b];
+      const double t = exp(-0.5 * q);
+      const double y = s + t;
+      c += (fabs(s) >= fabs(t)) ? (s - y) + t : (t - y) + s;
+      s = y;
+    }
+    out[k] = (s + c) * norm;
+  }
+  return ORC_OK;
+}

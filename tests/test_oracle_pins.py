@@ -542,3 +542,139 @@ def test_lscv_H_nelder_mead_matches_scipy():
     assert np.allclose(H, Cr @ Cr.T, rtol=1e-4, atol=1e-7)
     best_h = min(oracle.lscv_md_curve(z, np.geomspace(0.1, 2.0, 400)).g)
     assert g <= best_h + 1e-12
+
+
+def test_density_H_reductions_and_library_forms():
+    """Eq. (kde-def-H): at d = 1 it is the univariate estimate with h = sqrt(H);
+    with H = h^2 Sigma it is scipy's gaussian_kde with bandwidth factor h; a
+    single sample gives scipy's multivariate normal density; a diagonal H is a
+    product of univariate normal densities; an affine map of samples, point
+    and H divides f by |det A|."""
+    from scipy.stats import gaussian_kde, multivariate_normal, norm
+
+    rng = np.random.Generator(np.random.PCG64(31))
+    x1 = workloads.draw("bimodal", 300, 2, np.float64)
+    p1 = np.linspace(-4, 4, 17)
+    assert np.allclose(oracle.density_H(x1, [[0.09]], p1[:, None]), oracle.density(x1, 0.3, p1), rtol=1e-13)
+    for d in (2, 3):
+        z = rng.standard_normal((250, d)) @ (rng.standard_normal((d, d)) + 2 * np.eye(d)).T
+        pts = z[:9] + 0.3 * rng.standard_normal((9, d))
+        S = np.cov(z, rowvar=False)
+        for h in (0.2, 0.6):
+            ref = gaussian_kde(z.T, bw_method=h)(pts.T)
+            assert np.allclose(oracle.density_H(z, h * h * S, pts), ref, rtol=1e-11)
+        M = rng.standard_normal((d, d))
+        H = M @ M.T + 0.2 * np.eye(d)
+        assert oracle.density_H(z[:1], H, pts) == pytest.approx(multivariate_normal(z[0], H).pdf(pts), rel=1e-12)
+        hd = np.array([0.3, 0.7, 1.1][:d])
+        prod = np.mean(np.prod(norm.pdf(pts[:, None, :], loc=z[None, :, :], scale=hd), axis=2), axis=1)
+        assert np.allclose(oracle.density_H(z, np.diag(hd * hd), pts), prod, rtol=1e-12)
+        A = rng.standard_normal((d, d)) + 2 * np.eye(d)
+        fa = oracle.density_H(z @ A.T + 1.5, A @ H @ A.T, pts @ A.T + 1.5)
+        assert np.allclose(fa, oracle.density_H(z, H, pts) / abs(np.linalg.det(A)), rtol=1e-11)
+
+
+def test_density_H_integrates_to_one_with_the_sample_moments():
+    """d = 2 on a grid of step 1/40 over +-8 deviations: mass 1, mean the
+    sample mean, covariance (n-1)/n Sigma + H (composite Simpson)."""
+    from scipy import integrate
+
+    rng = np.random.Generator(np.random.PCG64(32))
+    z = rng.standard_normal((40, 2)) @ np.array([[1.0, 0.0], [0.6, 0.5]]).T
+    H = np.array([[0.09, 0.03], [0.03, 0.05]])
+    g0 = np.arange(z[:, 0].min() - 3, z[:, 0].max() + 3, 1 / 40)
+    g1 = np.arange(z[:, 1].min() - 3, z[:, 1].max() + 3, 1 / 40)
+    G0, G1 = np.meshgrid(g0, g1, indexing="ij")
+    f = oracle.density_H(z, H, np.stack([G0.ravel(), G1.ravel()], 1)).reshape(G0.shape)
+
+    def I2(v):
+        return integrate.simpson(integrate.simpson(v, x=g1, axis=1), x=g0)
+
+    assert I2(f) == pytest.approx(1.0, abs=1e-9)
+    m = z.mean(0)
+    assert I2(G0 * f) == pytest.approx(m[0], abs=1e-9) and I2(G1 * f) == pytest.approx(m[1], abs=1e-9)
+    C = np.cov(z, rowvar=False) * (z.shape[0] - 1) / z.shape[0] + H
+    assert I2((G0 - m[0]) * (G1 - m[1]) * f) == pytest.approx(C[0, 1], rel=1e-8)
+    assert I2((G0 - m[0]) ** 2 * f) == pytest.approx(C[0, 0], rel=1e-8)
+
+
+def test_range_aggregates_2d_against_closed_forms_and_libraries():
+    """Eq. (count-sum-2D) with the estimate of eq. (kde-def-H): the whole plane
+    gives n and the coordinate sums; a box over the whole second axis gives
+    the univariate aggregates of the first coordinate with h = sqrt(H11)
+    (the kernel's marginal), whatever the correlation; a diagonal H gives
+    products of univariate normal masses; COUNT matches scipy's rectangle
+    probability of the multivariate normal (Genz's algorithm); adjacent
+    boxes add up; and COUNT and SUM agree with 2-D Simpson integration of the
+    oracle's own density."""
+    from scipy import integrate
+    from scipy.special import ndtr
+    from scipy.stats import multivariate_normal
+
+    rng = np.random.Generator(np.random.PCG64(33))
+    z = rng.standard_normal((60, 2)) @ np.array([[1.0, 0.0], [0.7, 0.6]]).T
+    H = np.array([[0.16, 0.09], [0.09, 0.12]])
+    inf = np.inf
+    c, sx, sy = oracle.range_aggregates_2d(z, H, [[-inf, inf, -inf, inf]])
+    assert c[0] == pytest.approx(60, rel=1e-12)
+    assert sx[0] == pytest.approx(z[:, 0].sum(), abs=1e-11) and sy[0] == pytest.approx(z[:, 1].sum(), abs=1e-11)
+    lo, hi = np.array([-0.5, 0.2, 1.0]), np.array([0.8, 0.9, 4.0])
+    c, sx, _ = oracle.range_aggregates_2d(z, H, np.stack([lo, hi, np.full(3, -inf), np.full(3, inf)], 1))
+    c1, s1 = oracle.range_aggregates(z[:, 0], 0.4, lo, hi)
+    assert np.allclose(c, c1, rtol=1e-11, atol=1e-13) and np.allclose(sx, s1, rtol=1e-11, atol=1e-13)
+    boxes = np.array([[-1.0, 0.5, -0.3, 1.2], [0.0, 2.0, -2.0, 0.0], [-3.0, -1.0, 1.0, 3.0], [0.1, 0.1, 0.0, 1.0]])
+    D = np.diag([0.2, 0.05])
+    cd, sxd, syd = oracle.range_aggregates_2d(z, D, boxes)
+    sd = np.sqrt(np.diag(D))
+    for k, (a, b, cc, dd) in enumerate(boxes):
+        pa = ndtr((b - z[:, 0]) / sd[0]) - ndtr((a - z[:, 0]) / sd[0])
+        pb = ndtr((dd - z[:, 1]) / sd[1]) - ndtr((cc - z[:, 1]) / sd[1])
+        assert cd[k] == pytest.approx(np.sum(pa * pb), rel=1e-11, abs=1e-14)
+    cf, sxf, syf = oracle.range_aggregates_2d(z, H, boxes)
+    assert cf[3] == 0.0 and sxf[3] == 0.0  # an empty box
+    for k, (a, b, cc, dd) in enumerate(boxes[:3]):
+        ref = sum(multivariate_normal.cdf([b, dd], mean=p, cov=H, lower_limit=[a, cc], abseps=1e-12,
+                                          releps=1e-12, maxpts=10**6) for p in z)
+        assert cf[k] == pytest.approx(ref, rel=1e-9, abs=1e-10)
+    # additivity: [-1, 0.5] = [-1, 0] + [0, 0.5] in the first coordinate
+    parts = oracle.range_aggregates_2d(z, H, [[-1.0, 0.0, -0.3, 1.2], [0.0, 0.5, -0.3, 1.2]])
+    for whole, pr in zip((cf[0], sxf[0], syf[0]), parts):
+        assert whole == pytest.approx(pr.sum(), rel=1e-11, abs=1e-13)
+    # 2-D Simpson of the density over the first box
+    a, b, cc, dd = boxes[0]
+    g0, g1 = np.linspace(a, b, 241), np.linspace(cc, dd, 241)
+    G0, G1 = np.meshgrid(g0, g1, indexing="ij")
+    f = oracle.density_H(z, H, np.stack([G0.ravel(), G1.ravel()], 1)).reshape(G0.shape)
+
+    def I2(v):
+        return 60 * integrate.simpson(integrate.simpson(v, x=g1, axis=1), x=g0)
+
+    assert cf[0] == pytest.approx(I2(f), rel=1e-8)
+    assert sxf[0] == pytest.approx(I2(G0 * f), rel=1e-8, abs=1e-9)
+    assert syf[0] == pytest.approx(I2(G1 * f), rel=1e-8, abs=1e-9)
+
+
+def test_range_aggregates_2d_strong_correlation_and_errors():
+    """rho = 0.995: COUNT against scipy's rectangle probability; boxes along
+    and across the kernel's long axis.  Bad boxes and singular H fail."""
+    from scipy.stats import multivariate_normal
+
+    rng = np.random.Generator(np.random.PCG64(34))
+    z = rng.standard_normal((30, 2))
+    H = np.array([[0.04, 0.0398], [0.0398, 0.04]])
+    boxes = np.array([[-0.5, 0.5, -0.5, 0.5], [-0.2, 0.3, 0.25, 0.6], [1.0, 1.5, -1.5, -1.0]])
+    c, _, _ = oracle.range_aggregates_2d(z, H, boxes)
+    for k, (a, b, cc, dd) in enumerate(boxes):
+        ref = sum(multivariate_normal.cdf([b, dd], mean=p, cov=H, lower_limit=[a, cc], abseps=1e-12,
+                                          releps=1e-12, maxpts=10**6) for p in z)
+        assert c[k] == pytest.approx(ref, rel=1e-8, abs=1e-10)
+    for bad in ([[1.0, 0.0, 0.0, 1.0]], [[0.0, 1.0, np.nan, 1.0]]):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.range_aggregates_2d(z, H, bad)
+        assert e.value.code == oracle.INVAL
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.range_aggregates_2d(z, [[1.0, 1.0], [1.0, 1.0]], [[0, 1, 0, 1]])
+    assert e.value.code == oracle.DEGENERATE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.density_H(z, [[1.0, 2.0], [2.0, 1.0]], z[:2])
+    assert e.value.code == oracle.DEGENERATE
