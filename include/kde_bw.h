@@ -438,6 +438,40 @@ typedef struct {
 kde_status kde_bw_lscv_H(kde_ctx* ctx, kde_matrix x, double ftol, double xtol, int32_t max_evals, double* H_out,
                          kde_lscv_H_info* info);
 
+/* Density estimate with a bandwidth matrix at m query points, eq. (kde-def-H)
+ * with K_H of eq. (K_H) and the Gaussian K of eq. (gaussian):
+ *   f(p) = n^-1 sum_i (2 pi)^(-d/2) |H|^(-1/2) exp(-(p - X_i)^T H^-1 (p - X_i) / 2),
+ * 1 <= d <= KDE_MAX_D; H row-major d x d (lower triangle read), covering the
+ * three classes of eq. (3_classes_of_H) (h^2 I, diagonal, full; H = h^2
+ * Sigma for the sphered LSCV_h bandwidth).  points: host array, row-major
+ * m x d; f_out[m] host.  Samples and points are whitened by L_H^-1
+ * (H = L_H L_H^T) in FP64; the squared distance is FP64 in both forms, the
+ * mixed form takes its exponential in FP32.  KDE_E_INVAL for a bad matrix
+ * (n < 1, d outside [1, KDE_MAX_D], a non-finite value), a non-finite
+ * entry of H or point, or m outside [1, KDE_MAX_QUERIES]; KDE_E_DEGENERATE
+ * when H is not positive definite (a Cholesky pivot at most 1e-12 of its
+ * diagonal entry). */
+kde_status kde_density_H(kde_ctx* ctx, kde_matrix x, const double* H, const double* points, int32_t m,
+                         double* f_out);
+
+/* Approximate 2-D range aggregates from the estimate of eq. (kde-def-H),
+ * eq. (count-sum-2D): for boxes [a, b] x [c, d] (boxes: host array, q rows
+ * of a, b, c, d; infinite ends allowed)
+ *   count_out[k] = n * int int f,  sumx_out[k] = n * int int x f,
+ *   sumy_out[k] = n * int int y f,  avgx_out[k] = sumx / count,
+ *   avgy_out[k] = sumy / count (NaN when the count is 0; both may be NULL).
+ * Per sample the kernel is a bivariate normal with mean X_i and covariance
+ * H, so each term is a rectangle probability (four values of the bivariate
+ * normal CDF through Owen's T function, 20-point Gauss-Legendre) and a
+ * closed-form first moment; FP64, absolute error about 1e-16 of each
+ * sample's unit mass.  x must have d = 2; H row-major 2 x 2, lower triangle
+ * read.  KDE_E_INVAL for a bad matrix, a non-finite H, q outside
+ * [1, KDE_MAX_QUERIES], a NaN end or an end pair out of order;
+ * KDE_E_DEGENERATE when H is not positive definite. */
+kde_status kde_range_aggregates_2d(kde_ctx* ctx, kde_matrix x, const double* H, const double* boxes, int32_t q,
+                                   double* count_out, double* sumx_out, double* sumy_out, double* avgx_out,
+                                   double* avgy_out);
+
 /* LSCV bandwidth by a search instead of a fixed grid: the alternative to the
  * brute-force grid that Section 4.4.2 names (a golden-ratio type search).
  * Each step evaluates g(h) of eq. (LSCV-gh) at `points` bandwidths spaced

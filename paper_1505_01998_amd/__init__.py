@@ -50,6 +50,7 @@ EXPORTS = (
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
     "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min", "kde_density",
     "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md", "kde_lscv_H_eval", "kde_bw_lscv_H",
+    "kde_density_H", "kde_range_aggregates_2d",
 )
 
 
@@ -169,6 +170,8 @@ def _load():
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_md.argtypes = [P, kde_matrix, PD, I32, PD, ctypes.POINTER(I32)]
     lib.kde_lscv_H_eval.argtypes = [P, kde_matrix, PD, I32, PD, PD]
+    lib.kde_density_H.argtypes = [P, kde_matrix, PD, PD, I32, PD]
+    lib.kde_range_aggregates_2d.argtypes = [P, kde_matrix, PD, PD, I32, PD, PD, PD, PD, PD]
     lib.kde_bw_lscv_H.argtypes = [P, kde_matrix, ctypes.c_double, ctypes.c_double, I32, PD,
                                   ctypes.POINTER(kde_lscv_H_info)]
     lib.kde_range_aggregates.argtypes = [P, kde_column, ctypes.c_double, PD, PD, I32, PD, PD, PD]
@@ -352,6 +355,30 @@ def kde_lscv_H_eval(ctx, x, H):
     _check(ctx, lib.kde_lscv_H_eval(ctx, m, _pd(Hs.ravel()), int(k), _pd(g), _pd(gs)))
     del keep
     return g, gs
+
+
+def kde_density_H(ctx, x, H, points):
+    """Density estimate with bandwidth matrix H at points (m x d host array)."""
+    m, keep = make_matrix(x)
+    d = m.d
+    Hm = np.ascontiguousarray(np.asarray(H, np.float64).reshape(d, d))
+    p = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, d))
+    out = np.empty(p.shape[0], np.float64)
+    _check(ctx, lib.kde_density_H(ctx, m, _pd(Hm.ravel()), _pd(p.ravel()), int(p.shape[0]), _pd(out)))
+    del keep
+    return out
+
+
+def kde_range_aggregates_2d(ctx, x, H, boxes):
+    """(count, sum_x, sum_y, avg_x, avg_y) over boxes (rows a, b, c, d) for n x 2 samples."""
+    m, keep = make_matrix(x)
+    Hm = np.ascontiguousarray(np.asarray(H, np.float64).reshape(2, 2))
+    bx = np.ascontiguousarray(np.asarray(boxes, np.float64).reshape(-1, 4))
+    q = bx.shape[0]
+    outs = [np.empty(q, np.float64) for _ in range(5)]
+    _check(ctx, lib.kde_range_aggregates_2d(ctx, m, _pd(Hm.ravel()), _pd(bx.ravel()), int(q), *(_pd(o) for o in outs)))
+    del keep
+    return tuple(outs)
 
 
 def kde_bw_lscv_H(ctx, x, ftol: float = 1e-10, xtol: float = 1e-6, max_evals: int = 2000):
@@ -690,6 +717,12 @@ class Context:
 
     def bw_lscv_H(self, x, ftol=1e-10, xtol=1e-6, max_evals=2000):
         return kde_bw_lscv_H(self.ctx, x, ftol, xtol, max_evals)
+
+    def density_H(self, x, H, points):
+        return kde_density_H(self.ctx, x, H, points)
+
+    def range_aggregates_2d(self, x, H, boxes):
+        return kde_range_aggregates_2d(self.ctx, x, H, boxes)
 
     def range_aggregates(self, x, h, lo, hi):
         return kde_range_aggregates(self.ctx, x, h, lo, hi)

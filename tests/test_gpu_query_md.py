@@ -1,0 +1,177 @@
+"""The estimate's consumers for d-dimensional samples against the oracle: the
+density with a bandwidth matrix (kde_density_H, eq. kde-def-H) and 2-D range
+COUNT/SUM/AVG (kde_range_aggregates_2d, eq. count-sum-2D).  Density: FP64
+relative 1e-12, mixed 2e-5 (FP32 exponentials of FP64 exponents);
+aggregates (FP64 both sides): 1e-10 relative plus 1e-13 of a unit mass per
+sample, the oracle's quadrature tolerance and the device's rounding."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kde():
+    import paper_1505_01998_amd as kde
+
+    return kde
+
+
+def _sample(n, d, seed, dtype=np.float64):
+    """A two-component Gaussian mixture with correlated coordinates."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = rng.standard_normal((d, d)) + 2 * np.eye(d)
+    comp = rng.random(n) < 0.35
+    z = rng.standard_normal((n, d)) @ A.T
+    z[comp] = 0.4 * z[comp] + 3.0
+    return np.ascontiguousarray(z.astype(dtype))
+
+
+def _spd(d, seed, scale=0.1):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = rng.standard_normal((d, d))
+    return scale * (M @ M.T / d + 0.5 * np.eye(d))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 16])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_density_H_matches_oracle(kde, d, precision):
+    n = 3001 if d <= 8 else 1201
+    x = _sample(n, d, 60 + d, np.float32 if precision == "mixed" else np.float64)
+    H = _spd(d, 7 + d, 0.3)
+    rng = np.random.Generator(np.random.PCG64(d))
+    pts = x[rng.integers(0, n, 300)].astype(np.float64) + rng.standard_normal((300, d)) * 0.7
+    with kde.Context(0, precision) as c:
+        f = c.density_H(x, H, pts)
+    o = oracle.density_H(x, H, pts)
+    tol = 2e-5 if precision == "mixed" else 1e-12
+    err = np.abs(f - o) / o
+    assert err.max() <= tol, err.max()
+    print(f"d={d} {precision}: max relative error {err.max():.2e}")
+
+
+def test_density_H_reductions_device_input_and_errors(kde):
+    import torch
+
+    x1 = _sample(5000, 1, 3)[:, 0]
+    p1 = np.linspace(-6, 8, 57)
+    with kde.Context(0, "fp64") as c:
+        fH = c.density_H(x1[:, None], [[0.09]], p1[:, None])
+        f1 = c.density(x1, 0.3, p1)
+        assert np.allclose(fH, f1, rtol=1e-12)
+    x = _sample(2000, 3, 4, np.float32)
+    H = _spd(3, 2)
+    pts = x[:50].astype(np.float64) + 0.1
+    with kde.Context(0) as c:
+        f = c.density_H(x, H, pts)
+        fd = c.density_H(torch.from_numpy(x).to("cuda:0"), H, pts)
+        assert np.array_equal(f, fd)
+        Hu = H.copy()
+        Hu[0, 2] = 99.0  # only the lower triangle is read
+        assert np.array_equal(c.density_H(x, Hu, pts), f)
+        with pytest.raises(kde.KdeError) as e:
+            c.density_H(x, -H, pts)
+        assert e.value.status == kde.KDE_E_DEGENERATE
+        bad = pts.copy()
+        bad[3, 1] = np.inf
+        for args in ((x, H, bad), (_sample(100, 17, 1), np.eye(17), np.zeros((2, 17)))):
+            with pytest.raises(kde.KdeError) as e:
+                c.density_H(*args)
+            assert e.value.status == kde.KDE_E_INVAL
+        assert np.array_equal(c.density_H(x, H, pts), f)
+
+
+def _agg_close(g, o, n, scale):
+    """|dg| <= 1e-10 |o| + 1e-13 n scale."""
+    return np.all(np.abs(g - o) <= 1e-10 * np.abs(o) + 1e-13 * n * scale)
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.6, -0.85, 0.995])
+def test_range_aggregates_2d_matches_oracle(kde, rho):
+    n = 400
+    x = _sample(n, 2, 70, np.float64)
+    s1, s2 = 0.35, 0.5
+    H = np.array([[s1 * s1, rho * s1 * s2], [rho * s1 * s2, s2 * s2]])
+    inf = np.inf
+    boxes = np.array([[-1.0, 1.0, -1.0, 1.5], [0.5, 4.0, 2.0, 5.0], [-inf, 0.0, -inf, inf], [2.5, 3.5, -inf, 2.9],
+                      [-8.0, -6.0, -3.0, 3.0], [1.0, 1.0, 0.0, 2.0], [-inf, inf, -inf, inf], [3.0, 3.2, 2.9, 3.05]])
+    with kde.Context(0) as c:
+        cnt, sx, sy, ax, ay = c.range_aggregates_2d(x, H, boxes)
+    oc, osx, osy = oracle.range_aggregates_2d(x, H, boxes)
+    big = np.abs(x).max() + 1.0
+    assert _agg_close(cnt, oc, n, 1.0), np.abs(cnt - oc).max()
+    assert _agg_close(sx, osx, n, big) and _agg_close(sy, osy, n, big)
+    assert cnt[5] == 0.0 and sx[5] == 0.0 and np.isnan(ax[5])
+    assert cnt[6] == pytest.approx(n, rel=1e-13)
+    ok = cnt > 0
+    assert np.allclose(ax[ok], sx[ok] / cnt[ok], rtol=1e-15) and np.allclose(ay[ok], sy[ok] / cnt[ok], rtol=1e-15)
+    print(f"rho={rho}: max |dCOUNT| {np.abs(cnt - oc).max():.2e}, max |dSUM| "
+          f"{max(np.abs(sx - osx).max(), np.abs(sy - osy).max()):.2e}")
+
+
+def test_range_aggregates_2d_large_column_properties(kde):
+    """n = 1e6: the whole plane gives n and the coordinate sums; a box over
+    the whole second axis equals the univariate aggregates of the first
+    coordinate at h = sqrt(H11); adjacent boxes add up."""
+    import time
+
+    n = 1_000_000
+    x = _sample(n, 2, 71, np.float32)
+    H = np.array([[0.04, 0.018], [0.018, 0.03]])
+    inf = np.inf
+    lo, hi = np.array([-2.0, 0.0, 1.5]), np.array([0.0, 1.5, 6.0])
+    rng = np.random.Generator(np.random.PCG64(5))
+    rand = np.sort(rng.normal(0, 3, (58, 2)), axis=1)
+    rand2 = np.sort(rng.normal(0, 3, (58, 2)), axis=1)
+    boxes = np.concatenate([[[-inf, inf, -inf, inf]], np.stack([lo, hi, np.full(3, -inf), np.full(3, inf)], 1),
+                            [[-1.0, 0.5, -1.0, 2.0], [0.5, 2.0, -1.0, 2.0], [-1.0, 2.0, -1.0, 2.0]],
+                            np.concatenate([rand, rand2], 1)])
+    with kde.Context(0, "fp64") as c:
+        c.range_aggregates_2d(x[:1000], H, boxes[:2])
+        t = time.perf_counter()
+        cnt, sx, sy, _, _ = c.range_aggregates_2d(x, H, boxes)
+        dt = time.perf_counter() - t
+        c1, s1, _ = c.range_aggregates(x[:, 0].copy(), 0.2, lo, hi)
+    xd = x.astype(np.float64)
+    assert cnt[0] == pytest.approx(n, rel=1e-12)
+    assert sx[0] == pytest.approx(xd[:, 0].sum(), rel=1e-10, abs=1e-6)
+    assert sy[0] == pytest.approx(xd[:, 1].sum(), rel=1e-10, abs=1e-6)
+    assert np.allclose(cnt[1:4], c1, rtol=1e-10, atol=1e-7) and np.allclose(sx[1:4], s1, rtol=1e-10, atol=1e-7)
+    for v in (cnt, sx, sy):
+        assert v[6] == pytest.approx(v[4] + v[5], rel=1e-11, abs=1e-7)
+    print(f"n=1e6, {boxes.shape[0]} boxes: {dt * 1e3:.1f} ms")
+
+
+def test_range_aggregates_2d_errors(kde):
+    x = _sample(300, 2, 72)
+    H = np.array([[0.1, 0.02], [0.02, 0.1]])
+    with kde.Context(0) as c:
+        for boxes in ([[1.0, 0.0, 0.0, 1.0]], [[0.0, 1.0, np.nan, 1.0]], [[0.0, 1.0, 2.0, 1.0]]):
+            with pytest.raises(kde.KdeError) as e:
+                c.range_aggregates_2d(x, H, boxes)
+            assert e.value.status == kde.KDE_E_INVAL
+        with pytest.raises(kde.KdeError) as e:
+            c.range_aggregates_2d(_sample(300, 3, 1), H, [[0, 1, 0, 1]])
+        assert e.value.status == kde.KDE_E_INVAL
+        with pytest.raises(kde.KdeError) as e:
+            c.range_aggregates_2d(x, [[1.0, 1.0], [1.0, 1.0]], [[0, 1, 0, 1]])
+        assert e.value.status == kde.KDE_E_DEGENERATE
+        cnt = c.range_aggregates_2d(x, H, [[-np.inf, np.inf, -np.inf, np.inf]])[0]
+        assert cnt[0] == pytest.approx(300, rel=1e-13)
+
+
+def test_density_H_throughput(kde):
+    import time
+
+    x = _sample(100_000, 2, 73, np.float32)
+    H = _spd(2, 1, 0.05)
+    pts = np.random.Generator(np.random.PCG64(2)).normal(0, 2, (4096, 2))
+    with kde.Context(0) as c:
+        c.density_H(x, H, pts[:256])
+        t = time.perf_counter()
+        f = c.density_H(x, H, pts)
+        dt = time.perf_counter() - t
+    assert np.all(np.isfinite(f))
+    print(f"density_H d=2: n=1e5, 4096 points in {dt * 1e3:.2f} ms, {1e5 * 4096 / dt:.3e} pair terms/s")
