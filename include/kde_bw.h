@@ -120,6 +120,11 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
  *                  iteration (an iteration also holds at least six rounds of
  *                  1024 blocks of its largest work unit)
+ *   "serve_fail_ticket" server, failure handling: the request with this
+ *                  ticket (tickets count from 1 per server) is treated as if
+ *                  its pass had failed: it ends with KDE_E_DEVICE and frees
+ *                  its slot while the requests sharing its launches complete
+ *                  (0: off).  Forced from the host; every kernel runs as usual.
  *   "autotune"     1: synchronous calls and kde_batch run the LSCV pass with
  *                  the bandwidths per block that kde_autotune measured fastest
  *                  for the job's largest LSCV column (tuning that shape on
@@ -333,6 +338,13 @@ kde_status kde_submit(kde_ctx* ctx, const kde_request* req, uint64_t* ticket);
 kde_status kde_poll(kde_ctx* ctx, uint64_t ticket, kde_result* out);
 /* As kde_poll, blocking up to timeout_s seconds (< 0: no limit). */
 kde_status kde_wait(kde_ctx* ctx, uint64_t ticket, kde_result* out, double timeout_s);
+/* Cancels one request: a queued one leaves the queue at once, an admitted one
+ * leaves at the end of the scheduler iteration that is running (its slot and
+ * budget are released); either way its result, collected by kde_poll or
+ * kde_wait, has status KDE_E_CANCELLED.  A request that finishes in the
+ * running iteration, or has finished, keeps its result.  KDE_E_INVAL for an
+ * unknown (or already collected) ticket. */
+kde_status kde_cancel(kde_ctx* ctx, uint64_t ticket);
 /* Cancels queued requests (status KDE_E_CANCELLED), finishes admitted ones,
  * stops the scheduler thread.  Results not yet collected stay pollable until
  * the context is destroyed or a new server starts. */

@@ -50,7 +50,7 @@ EXPORTS = (
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
     "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min", "kde_density",
     "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md", "kde_lscv_H_eval", "kde_bw_lscv_H",
-    "kde_density_H", "kde_range_aggregates_2d",
+    "kde_density_H", "kde_range_aggregates_2d", "kde_cancel",
 )
 
 
@@ -165,6 +165,7 @@ def _load():
     lib.kde_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result)]
     lib.kde_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result), ctypes.c_double]
     lib.kde_server_stop.argtypes = [P]
+    lib.kde_cancel.argtypes = [P, ctypes.c_uint64]
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
     lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
@@ -653,6 +654,10 @@ def kde_server_stop(ctx) -> None:
     _check(ctx, lib.kde_server_stop(ctx))
 
 
+def kde_cancel(ctx, ticket: int) -> None:
+    _check(ctx, lib.kde_cancel(ctx, int(ticket)))
+
+
 class Context:
     """Owns a kde_ctx; methods forward to the kde_* functions above."""
 
@@ -766,6 +771,9 @@ class Context:
         if r is not None:
             self._tickets.pop(ticket, None)
         return r
+
+    def cancel(self, ticket: int):
+        kde_cancel(self.ctx, ticket)
 
     def server_stop(self):
         kde_server_stop(self.ctx)

@@ -48,6 +48,8 @@ struct SrvReq {
   std::vector<UnitCost> psi_c, lscv_c;
   double remaining = 0.0;
   bool finishing = false, done = false;
+  bool cancel = false;    // kde_cancel on an admitted request: dropped after the current iteration
+  bool injected = false;  // the failure hook names this request
   kde_result res;
   std::vector<double> g, gs;
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -220,9 +222,11 @@ void Server::loop() {
       }
       r->finishing = (!p.plugin || r->plugin_done) && (!p.lscv || r->lscv_done);
     }
+    for (auto& r : active)
+      if (ctx->opt_serve_fail_ticket != 0 && r->ticket == ctx->opt_serve_fail_ticket) r->injected = true;
     kde_status s = execute(ctx, it);
     for (auto& r : active) {
-      if (!r->finishing || s != KDE_OK) continue;
+      if (!r->finishing || s != KDE_OK || r->injected) continue;
       if (hipMemcpyAsync(h_st + r->slot, st.p + r->slot, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream) !=
           hipSuccess)
         s = KDE_E_DEVICE;
@@ -241,12 +245,18 @@ void Server::loop() {
     std::lock_guard<std::mutex> lk(mu);
     std::vector<std::shared_ptr<SrvReq>> keep;
     for (auto& r : active) {
-      if (s != KDE_OK || r->finishing) {
-        if (s == KDE_OK) {
+      // a request leaves when it is finished, when the pass failed (for all of
+      // its requests, or for this one through the failure hook), or when it
+      // was cancelled and not finishing in this pass
+      const bool cancelled = r->cancel && !r->finishing;
+      if (s != KDE_OK || r->finishing || r->injected || cancelled) {
+        if (s != KDE_OK || r->injected) {
+          finish_with(*this, r, KDE_E_DEVICE);
+        } else if (cancelled) {
+          finish_with(*this, r, KDE_E_CANCELLED);
+        } else {
           fill_result(r->plan, h_st[r->slot], r->res);
           finish_with(*this, r, r->res.status);
-        } else {
-          finish_with(*this, r, KDE_E_DEVICE);
         }
         (void)hipFree(r->block);
         r->block = nullptr;
@@ -397,6 +407,26 @@ kde_status kde_wait(kde_ctx* c, uint64_t ticket, kde_result* out, double timeout
   if (!s) return fail(c, KDE_E_INVAL, "no server on this context");
   std::unique_lock<std::mutex> lk(s->mu);
   return collect(c, *s, ticket, out, lk, timeout_s);
+}
+
+kde_status kde_cancel(kde_ctx* c, uint64_t ticket) {
+  if (!c) return KDE_E_INVAL;
+  Server* s = c->server.get();
+  if (!s) return fail(c, KDE_E_INVAL, "no server on this context");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto itr = s->all.find(ticket);
+  if (itr == s->all.end()) return fail(c, KDE_E_INVAL, "unknown ticket");
+  std::shared_ptr<SrvReq> r = itr->second;
+  if (r->done) return KDE_OK;
+  auto q = std::find(s->queue.begin(), s->queue.end(), r);
+  if (q != s->queue.end()) {
+    s->queue.erase(q);
+    kde::finish_with(*s, r, KDE_E_CANCELLED);
+    s->cv_done.notify_all();
+  } else {
+    r->cancel = true;
+  }
+  return KDE_OK;
 }
 
 kde_status kde_server_stop(kde_ctx* c) {

@@ -159,3 +159,59 @@ def test_admission_uses_the_request_footprint(kde):
         no = srv.wait(srv.submit(r), timeout_s=60)
         srv.server_stop()
     assert ok.status == kde.KDE_OK and no.status == kde.KDE_E_NOMEM
+
+
+def test_cancel_queued_and_admitted_requests(kde):
+    """A queued request leaves the queue at once; an admitted one leaves at the
+    end of the running iteration and frees its slot; the others complete with
+    the results they have alone; a collected ticket cannot be cancelled."""
+    long = kde.Request(workloads.draw("normal", 400_000, 2, np.float32), kde.KDE_METHOD_LSCV, 3,
+                       workloads.BATCH_GRID)
+    small = [kde.Request(workloads.draw("gamma", 3000 + 7 * k, 40 + k, np.float32),
+                         kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, 3, workloads.BATCH_GRID) for k in range(4)]
+    with kde.Context(0) as srv, kde.Context(0) as ref:
+        srv.set_option("serve_iter_evals", 1_000_000_000)
+        srv.server_start(8 << 30, 1)  # one slot: the small requests queue behind the long one
+        tl = srv.submit(long)
+        ts = [srv.submit(r) for r in small]
+        srv.cancel(ts[1])  # still queued
+        time.sleep(0.3)
+        srv.cancel(tl)  # admitted (about 1e13 evaluations, over a second of work)
+        rl = srv.wait(tl, timeout_s=60)
+        rs = [srv.wait(t, timeout_s=60) for t in ts]
+        with pytest.raises(kde.KdeError) as e:
+            srv.cancel(ts[0])
+        assert e.value.status == kde.KDE_E_INVAL
+        srv.server_stop()
+        alone = [ref.batch([r])[0] for r in small]
+    assert rl.status == kde.KDE_E_CANCELLED and 0 < rl.t_service_s < 1.0, (rl.status, rl.t_service_s)
+    assert rs[1].status == kde.KDE_E_CANCELLED and rs[1].t_service_s == 0
+    for k in (0, 2, 3):
+        assert rs[k].status == kde.KDE_OK
+        _check_same(rs[k], alone[k])
+
+
+def test_failure_hook_fails_one_request_and_the_rest_complete(kde):
+    """The host-forced failure hook: the named request ends with KDE_E_DEVICE,
+    the requests that shared its launches complete with their results
+    alone, its slot is released and the server keeps serving."""
+    reqs = _mix(kde, count=6, seed=31)
+    with kde.Context(0) as srv, kde.Context(0) as ref:
+        srv.set_option("serve_fail_ticket", 3)
+        srv.server_start(8 << 30, 8)
+        ts = [srv.submit(r) for r in reqs]
+        got = [srv.wait(t, timeout_s=120) for t in ts]
+        again = srv.wait(srv.submit(reqs[2]), timeout_s=120)
+        srv.server_stop()
+        srv.set_option("serve_fail_ticket", 1)
+        srv.server_start(8 << 30, 1)  # one slot: the second request needs the failed one's slot
+        first = srv.wait(srv.submit(reqs[0]), timeout_s=120)
+        second = srv.wait(srv.submit(reqs[1]), timeout_s=120)
+        srv.server_stop()
+        alone = [ref.batch([r])[0] for r in reqs]
+    assert ts[2] == 3 and got[2].status == kde.KDE_E_DEVICE
+    for k in (0, 1, 3, 4, 5):
+        _check_same(got[k], alone[k])
+    _check_same(again, alone[2])
+    assert first.status == kde.KDE_E_DEVICE
+    _check_same(second, alone[1])
