@@ -872,6 +872,10 @@ void launch_H(hipStream_t s, int D, int MH, bool f64, const float* y32, const do
     case 2: launch_H_units<DD, 2>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items); return; \
     default: launch_H_units<DD, 4>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items); return; \
   }
+  if (D == 2 && MH == 8) {
+    launch_H_units<2, 8>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items);
+    return;
+  }
   switch (D) {
     case 2: KDE_H_CASE(2);
     case 3: KDE_H_CASE(3);
@@ -1444,7 +1448,9 @@ kde_status h_pass(HRun& r, const double* H, int m, double* g, double* gs) {
   kde_ctx* c = r.c;
   hipStream_t st = c->stream;
   char* b = r.b;
-  const int MH = m == 1 ? 1 : m == 2 ? 2 : 4;
+  // matrices a block: as many as the pass has, up to 4 (8 for d <= 2, where
+  // the shared per-pair work is a larger share of the cost)
+  const int MH = m == 1 ? 1 : m == 2 ? 2 : (r.D == 2 && m >= 8) ? 8 : 4;
   const int chunks = (m + MH - 1) / MH;
   const MdState* dst = (const MdState*)(b + r.o_st);
   const HDesc* hd = (const HDesc*)(b + r.o_hd);

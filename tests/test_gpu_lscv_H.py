@@ -62,7 +62,7 @@ def test_H_eval_matches_oracle(kde, d, precision):
     print(f"d={d} {precision}: max |dg|/gscale {err.max():.2e}")
 
 
-@pytest.mark.parametrize("d", [3, 6])
+@pytest.mark.parametrize("d", [2, 3, 6])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_H_eval_does_not_depend_on_the_batch(kde, d, precision):
     """One matrix a pass, two, seven, and 67 (two passes of the 64-matrix
