@@ -284,6 +284,43 @@ typedef struct {
   double lscv_evals;        /* of them performed (less with the "prune" option) */
 } kde_result;
 
+/* ---------------------------------------------------------------- resumable jobs
+ * One request run on the caller's thread in slices of work, with checkpoints.
+ * A job owns its column's device block and walks the request's work in a
+ * fixed order (moments, plug-in stages, LSCV units, reductions, finalisation);
+ * every work unit writes its own partial sums and each reduction runs in a
+ * fixed order once its inputs are complete, so results are bitwise those of
+ * the same request in kde_batch however the work is sliced, and a job
+ * resumed from a checkpoint finishes with the results of an uninterrupted
+ * one.  A job uses its context's stream and workspace: destroy it before the
+ * context; while a server runs on the context, job calls return KDE_E_BUSY.
+ * The "prune" option is refused (its skipped work depends on the pass). */
+typedef struct kde_job kde_job;
+/* Plans the request and copies its samples (host or device) and explicit grid
+ * into the job's device block; the caller may free them on return.
+ * KDE_E_INVAL for an invalid request or with the prune option on. */
+kde_status kde_job_create(kde_ctx* ctx, const kde_request* req, kde_job** out);
+/* Runs the next work units until about max_evals pair-term evaluations are
+ * issued (at least one unit), and synchronises.  *done_out (may be NULL) is 1
+ * once the request is finished.  A device error makes the job unusable. */
+kde_status kde_job_run(kde_job* job, double max_evals, int* done_out);
+/* Pair-term evaluations issued so far and in all (any argument may be NULL). */
+kde_status kde_job_progress(const kde_job* job, double* evals_done, double* evals_total, int* done_out);
+/* The result of a finished job (as kde_poll fills it); KDE_E_BUSY before. */
+kde_status kde_job_result(kde_job* job, kde_result* out);
+/* Size of a checkpoint: a header, the column block (samples, working copies,
+ * partial sums: about kde_request_footprint bytes) and the curve. */
+kde_status kde_job_checkpoint_bytes(const kde_job* job, uint64_t* bytes);
+/* Writes the job's cursor, device state and block into buf[bytes] (host). */
+kde_status kde_job_checkpoint(kde_job* job, void* buf, uint64_t bytes);
+/* Loads a checkpoint into a job created for a request of the same shape
+ * (n, dtype, methods, stages, grid kind and size) on a context with the
+ * same precision and options, before its first kde_job_run; the job then
+ * continues the checkpointed request (its samples come with the
+ * checkpoint).  KDE_E_INVAL for a foreign, truncated or mismatched buffer. */
+kde_status kde_job_resume(kde_job* job, const void* buf, uint64_t bytes);
+void kde_job_destroy(kde_job* job);
+
 /* Device memory one request needs in a job or a server slot (its column
  * block: working copies of the samples, partial sums, grid, results), under
  * the options of ctx, or the defaults (mixed precision) when ctx is NULL.

@@ -50,7 +50,9 @@ EXPORTS = (
     "kde_server_start", "kde_submit", "kde_poll", "kde_wait", "kde_server_stop", "kde_autotune",
     "kde_ctx_graph_stats", "kde_request_footprint", "kde_plan_items", "kde_bw_lscv_min", "kde_density",
     "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md", "kde_lscv_H_eval", "kde_bw_lscv_H",
-    "kde_density_H", "kde_range_aggregates_2d", "kde_cancel",
+    "kde_density_H", "kde_range_aggregates_2d", "kde_cancel", "kde_job_create", "kde_job_run",
+    "kde_job_progress", "kde_job_result", "kde_job_checkpoint_bytes", "kde_job_checkpoint", "kde_job_resume",
+    "kde_job_destroy",
 )
 
 
@@ -166,6 +168,15 @@ def _load():
     lib.kde_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(kde_result), ctypes.c_double]
     lib.kde_server_stop.argtypes = [P]
     lib.kde_cancel.argtypes = [P, ctypes.c_uint64]
+    lib.kde_job_create.argtypes = [P, ctypes.POINTER(kde_request), ctypes.POINTER(P)]
+    lib.kde_job_run.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+    lib.kde_job_progress.argtypes = [P, PD, PD, ctypes.POINTER(ctypes.c_int)]
+    lib.kde_job_result.argtypes = [P, ctypes.POINTER(kde_result)]
+    lib.kde_job_checkpoint_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.kde_job_checkpoint.argtypes = [P, ctypes.c_void_p, ctypes.c_uint64]
+    lib.kde_job_resume.argtypes = [P, ctypes.c_void_p, ctypes.c_uint64]
+    lib.kde_job_destroy.argtypes = [P]
+    lib.kde_job_destroy.restype = None
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
     lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
@@ -656,6 +667,100 @@ def kde_server_stop(ctx) -> None:
 
 def kde_cancel(ctx, ticket: int) -> None:
     _check(ctx, lib.kde_cancel(ctx, int(ticket)))
+
+
+def kde_job_create(ctx, request: Request):
+    """(job handle, n_h or 0): a resumable job for one request; inputs are copied."""
+    req, keep, n_h = _make_request(request)
+    job = ctypes.c_void_p()
+    _check(ctx, lib.kde_job_create(ctx, ctypes.byref(req), ctypes.byref(job)))
+    del keep
+    return job, (n_h if request.methods & KDE_METHOD_LSCV else 0)
+
+
+def kde_job_run(ctx, job, max_evals: float) -> bool:
+    """Runs the next slice of about max_evals pair-term evaluations; True once finished."""
+    done = ctypes.c_int()
+    _check(ctx, lib.kde_job_run(job, float(max_evals), ctypes.byref(done)))
+    return bool(done.value)
+
+
+def kde_job_progress(job):
+    """(evaluations issued, evaluations in all, finished)."""
+    a, b, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    st = lib.kde_job_progress(job, ctypes.byref(a), ctypes.byref(b), ctypes.byref(d))
+    if st != KDE_OK:
+        raise KdeError(st, "kde_job_progress")
+    return a.value, b.value, bool(d.value)
+
+
+def kde_job_result(ctx, job, n_h: int = 0):
+    """Result of a finished job, None before."""
+    return _collect(ctx, lambda _c, _j, out: lib.kde_job_result(_j, out), job, n_h)
+
+
+def kde_job_checkpoint_bytes(job) -> int:
+    b = ctypes.c_uint64()
+    st = lib.kde_job_checkpoint_bytes(job, ctypes.byref(b))
+    if st != KDE_OK:
+        raise KdeError(st, "kde_job_checkpoint_bytes")
+    return b.value
+
+
+def kde_job_checkpoint(ctx, job) -> np.ndarray:
+    """The job's checkpoint as a uint8 array."""
+    buf = np.empty(kde_job_checkpoint_bytes(job), np.uint8)
+    _check(ctx, lib.kde_job_checkpoint(job, buf.ctypes.data, buf.size))
+    return buf
+
+
+def kde_job_resume(ctx, job, buf) -> None:
+    b = np.ascontiguousarray(np.asarray(buf, np.uint8))
+    _check(ctx, lib.kde_job_resume(job, b.ctypes.data, b.size))
+
+
+def kde_job_destroy(job) -> None:
+    lib.kde_job_destroy(job)
+
+
+class Job:
+    """A resumable request on a Context (destroy it, or leave its with-block,
+    before the context closes)."""
+
+    def __init__(self, context, request: Request):
+        self.ctx = context.ctx
+        self.job, self.n_h = kde_job_create(self.ctx, request)
+
+    def run(self, max_evals: float) -> bool:
+        return kde_job_run(self.ctx, self.job, max_evals)
+
+    def run_to_end(self, slice_evals: float = 4e12):
+        while not self.run(slice_evals):
+            pass
+        return self.result()
+
+    def progress(self):
+        return kde_job_progress(self.job)
+
+    def result(self):
+        return kde_job_result(self.ctx, self.job, self.n_h)
+
+    def checkpoint(self) -> np.ndarray:
+        return kde_job_checkpoint(self.ctx, self.job)
+
+    def resume(self, buf) -> None:
+        kde_job_resume(self.ctx, self.job, buf)
+
+    def close(self):
+        if self.job:
+            kde_job_destroy(self.job)
+            self.job = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Context:

@@ -1,0 +1,138 @@
+"""Resumable jobs: a request run in slices, or checkpointed and resumed in
+another job (another context), ends with the results of the same request in
+kde_batch, bitwise; checkpoints of another shape or truncated ones are
+refused."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+A = 1 | 2 | 4  # ROT | PLUGIN | LSCV
+
+
+@pytest.fixture(scope="module")
+def kde():
+    import paper_1505_01998_amd as kde
+
+    return kde
+
+
+def _same(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return a.shape == b.shape and np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)],
+                                                                                               b[~np.isnan(b)])
+
+
+def _check_same(r, a):
+    assert r.status == a.status
+    assert _same([r.sigma, r.h_rot, r.h_plugin, r.h_lscv], [a.sigma, a.h_rot, a.h_plugin, a.h_lscv])
+    assert _same(r.plugin.psi, a.plugin.psi) and _same(r.plugin.kappa, a.plugin.kappa) and r.k_lscv == a.k_lscv
+    if a.g is not None:
+        assert _same(r.g, a.g) and _same(r.gscale, a.gscale)
+
+
+def _requests(kde):
+    x1 = workloads.draw("lognormal", 60_000, 5, np.float32)
+    x2 = workloads.draw("bimodal", 20_011, 6, np.float64)
+    return [kde.Request(x1, A, 3, workloads.BATCH_GRID),
+            kde.Request(x2, A, 2, np.geomspace(0.01, 2.0, 40)),
+            kde.Request(x1[:9000].copy(), kde.KDE_METHOD_LSCV, 3, ("paper", 64)),
+            kde.Request(x2[:5000].copy(), kde.KDE_METHOD_PLUGIN, 3)]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_sliced_job_equals_batch(kde, precision):
+    reqs = _requests(kde)
+    with kde.Context(0, precision) as c:
+        alone = [c.batch([r])[0] for r in reqs]
+        for r, a in zip(reqs, alone):
+            with kde.Job(c, r) as job:
+                _, total, _ = job.progress()
+                slices = 0
+                while not job.run(total / 7):
+                    slices += 1
+                done, total2, fin = job.progress()
+                assert fin and done == pytest.approx(total, rel=1e-12) and total2 == total
+                assert slices >= 5
+                _check_same(job.result(), a)
+
+
+def test_checkpoint_resume_in_another_context_is_bitwise(kde):
+    reqs = _requests(kde)
+    import torch
+
+    dev = kde.Request(torch.from_numpy(np.asarray(reqs[0].x)).to("cuda:0"), A, 3, workloads.BATCH_GRID)
+    with kde.Context(0) as c1, kde.Context(0) as c2:
+        alone = c1.batch([reqs[0]])[0]
+        for req in (reqs[0], dev):
+            for frac in (0.0, 0.05, 0.5, 0.97):
+                with kde.Job(c1, req) as job:
+                    _, total, _ = job.progress()
+                    if frac > 0:
+                        job.run(frac * total)
+                    ck = job.checkpoint()
+                    assert ck.size == kde.kde_job_checkpoint_bytes(job.job)
+                # a fresh job in another context, from a request of the same
+                # shape whose samples differ: the checkpoint's samples win
+                other = kde.Request(np.zeros(60_000, np.float32) + 1.0, A, 3, workloads.BATCH_GRID)
+                with kde.Job(c2, other) as job2:
+                    job2.resume(ck)
+                    res = job2.run_to_end(total / 3)
+                _check_same(res, alone)
+        # a checkpoint of a finished job resumes as finished
+        with kde.Job(c1, reqs[0]) as job:
+            job.run_to_end()
+            ck = job.checkpoint()
+        with kde.Job(c2, reqs[0]) as job2:
+            job2.resume(ck)
+            assert job2.progress()[2]
+            _check_same(job2.result(), alone)
+
+
+def test_resume_refuses_foreign_checkpoints(kde):
+    reqs = _requests(kde)
+    with kde.Context(0) as c:
+        with kde.Job(c, reqs[1]) as job:
+            job.run(1e9)
+            ck = job.checkpoint()
+            assert job.result() is None  # not finished
+        for bad_req, buf in ((reqs[0], ck), (reqs[1], ck[: ck.size // 2]), (reqs[1], np.zeros(4096, np.uint8))):
+            with kde.Job(c, bad_req) as j2:
+                with pytest.raises(kde.KdeError) as e:
+                    j2.resume(buf)
+                assert e.value.status == kde.KDE_E_INVAL
+        with kde.Job(c, reqs[1]) as j3:
+            j3.run(1e9)
+            with pytest.raises(kde.KdeError) as e:
+                j3.resume(ck)  # only before the first run
+            assert e.value.status == kde.KDE_E_INVAL
+        # another precision: refused
+    with kde.Context(0, "fp64") as c64:
+        with kde.Job(c64, reqs[1]) as j4:
+            with pytest.raises(kde.KdeError) as e:
+                j4.resume(ck)
+            assert e.value.status == kde.KDE_E_INVAL
+    with kde.Context(0) as c:
+        c.set_option("prune", 1)
+        with pytest.raises(kde.KdeError) as e:
+            kde.Job(c, reqs[1])
+        assert e.value.status == kde.KDE_E_INVAL
+        with pytest.raises(kde.KdeError) as e:
+            kde.Job(c, kde.Request(np.array([1.0]), kde.KDE_METHOD_ROT))
+        assert e.value.status == kde.KDE_E_INVAL
+
+
+def test_job_beside_a_server_is_refused(kde):
+    reqs = _requests(kde)
+    with kde.Context(0) as c:
+        with kde.Job(c, reqs[3]) as job:
+            c.server_start(1 << 30, 2)
+            with pytest.raises(kde.KdeError) as e:
+                job.run(1e12)
+            assert e.value.status == kde.KDE_E_BUSY
+            c.server_stop()
+            res = job.run_to_end()
+        assert res.status == kde.KDE_OK
