@@ -252,6 +252,83 @@ def batch_bench(args):
     }
 
 
+# Instruction-mix rooflines of the LSCV_H pair kernels at d = 2 (plain VALU at
+# 128 lanes/clk/CU, exp2 at 32, not overlapped): one matrix a block
+# (3 FMAs + add + fma + 5 shared ops = 10 plain) and four (5 + 5/4).
+LSCV_H_PEAK_MH1 = 1.0 / (10.0 / (256 * 128 * 2.4e9) + 1.0 / (256 * 32 * 2.4e9))
+LSCV_H_PEAK_MH4 = 1.0 / (6.25 / (256 * 128 * 2.4e9) + 1.0 / (256 * 32 * 2.4e9))
+
+
+def lscv_H_bench(args):
+    """The LSCV_H search (Nelder-Mead over full 2x2 bandwidth matrices, one
+    pass of the pair kernel per simplex step) on n = 1e5 two-dimensional
+    samples; a step is one whole search from the rule-of-thumb start."""
+    import torch
+
+    import paper_1505_01998_amd as kde
+
+    n, d = 100_000, 2
+    x = workloads.draw_matrix(n, d, 1998010, np.float32)
+    xd = torch.from_numpy(x).to("cuda:0")
+    torch.cuda.synchronize()
+    ctx = kde.Context(0, args.precision)
+    opts = dict(ftol=1e-7, xtol=1e-4, max_evals=400)
+    for i in range(args.warmup):
+        log(f"warmup search {i + 1}/{args.warmup}")
+        ctx.bw_lscv_H(xd, **opts)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        H, info = ctx.bw_lscv_H(xd, **opts)
+        log(f"timed search {i + 1}/{args.steps} done ({info.evals} evaluations)")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    launches, ms, evals_k = ctx.kernel_time("md_pairs")
+    ctx.close()
+    pairs = n * (n - 1) / 2
+    p = d * (d + 1) // 2
+    # passes: one of p + 1 matrices (the start), one of p per shrink, one matrix otherwise
+    shrinks = max(0, (info.evals - info.passes - p) // (p - 1))
+    multi = (p + 1) + p * shrinks
+    single = info.evals - multi
+    peak = info.evals / (single / LSCV_H_PEAK_MH1 + multi / LSCV_H_PEAK_MH4)
+    achieved = evals_k / (ms * 1e-3)
+    out = {
+        "metric": "(pair, matrix) evals/s (LSCV_H Nelder-Mead search, n=1e5, d=2)",
+        "value": info.evals * pairs / dt,
+        "unit": "pair-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "lscv-H", "n": n, "d": d, "precision": args.precision, **opts},
+        "search": {"evals": info.evals, "passes": info.passes, "converged": info.converged, "g": info.g,
+                   "H": np.asarray(H).tolist()},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Teval/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_H_units_f32<2,1> and <2,4>" if args.precision == "mixed" else "k_H_units_f64<2,*>",
+                     "launches": launches, "avg_launch_ms": ms / max(launches, 1),
+                     "evals_per_launch": evals_k / max(launches, 1)},
+    }
+    if args.cpu_budget > 0:
+        import oracle
+
+        oracle.build(force=False)
+        Hs = np.asarray(H)
+        n_s = 4000
+        t0 = time.perf_counter()
+        oracle.lscv_H(x[:n_s], Hs)
+        rate = n_s * (n_s - 1) / 2 / (time.perf_counter() - t0)
+        n_s = int(min(n, max(n_s, np.sqrt(2 * min(args.cpu_budget, 10.0) * rate))))
+        t0 = time.perf_counter()
+        oracle.lscv_H(x[:n_s], Hs)
+        dt_o = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_s * (n_s - 1) / 2 / dt_o, "unit": "pair-evals/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"g(H) at the found H on the first {n_s} samples ({dt_o:.1f} s)"}
+    return out
+
+
 def served_bench(args):
     """Served form (continuous batching) vs plain per-request calls on the same
     request stream: first at the stream's own arrival times, then load-matched
@@ -355,7 +432,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lognormal-1m",
-                    choices=workloads.WORKLOADS + ("batch-512", "served", "served-small"))
+                    choices=workloads.WORKLOADS + ("batch-512", "served", "served-small", "lscv-H"))
     ap.add_argument("--requests", type=int, default=32, help="served: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrival rate of the stream (req/s)")
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
@@ -396,6 +473,9 @@ def main():
         return
     if args.workload in ("served", "served-small"):
         print(json.dumps(served_bench(args)), flush=True)
+        return
+    if args.workload == "lscv-H":
+        print(json.dumps(lscv_H_bench(args)), flush=True)
         return
 
     import torch

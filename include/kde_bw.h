@@ -184,7 +184,9 @@ kde_status kde_autotune(kde_ctx* ctx, int64_t n, int32_t n_h, kde_tune_info* out
 
 /* Kernel timing.  While enabled, every launch of the pair kernels is bracketed
  * by HIP events on the stream it runs on.  kde_ctx_kernel_time reports, for
- * kernel family "lscv_pairs" or "psi_pairs", the number of launches, their
+ * kernel family "lscv_pairs", "psi_pairs" or "md_pairs" (the d-dimensional
+ * pair kernels: LSCV_h, LSCV_H, density with a bandwidth matrix), the number
+ * of launches, their
  * summed duration in ms and the summed pair-term evaluations since timing was
  * last enabled. */
 kde_status kde_ctx_set_timing(kde_ctx* ctx, int enable);

@@ -567,6 +567,7 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
 kde_status h_pass(HRun& r, const double* H, int m, double* g, double* gs) {
   kde_ctx* c = r.c;
   hipStream_t st = c->stream;
+  kde_status s;
   char* b = r.b;
   // matrices a block: as many as the pass has, up to 4 (8 for d <= 2, where
   // the shared per-pair work is a larger share of the cost)
@@ -589,9 +590,12 @@ kde_status h_pass(HRun& r, const double* H, int m, double* g, double* gs) {
         double acc = r.pairs[u0];
         size_t u1 = u0 + 1;
         while (u1 < (size_t)r.n_items && (acc + r.pairs[u1] <= budget || u1 - u0 < 2048)) acc += r.pairs[u1++];
+        kde_ctx::Pending pd{nullptr, nullptr, kFamMd, acc};
+        if ((s = timed_begin(c, pd))) return s;
         launch_md_one(st, r.D, r.f64, z32, z64, r.npad, dst, (const float*)(b + r.o_coef + 8),
                       (const double*)(b + r.o_coef), (const Unit*)(b + r.o_units), (int)u0, (int)(u1 - u0),
                       part + (size_t)2 * k * r.n_items, r.n_items);
+        if ((s = timed_end(c, pd))) return s;
         u0 = u1;
       }
     }
@@ -604,8 +608,16 @@ kde_status h_pass(HRun& r, const double* H, int m, double* g, double* gs) {
     size_t u1 = u0 + 1;
     while (u1 < total && (acc + r.pairs[u1 % r.n_items] * MH <= budget || u1 - u0 < 2048))
       acc += r.pairs[u1++ % r.n_items] * MH;
+    // pair-term evaluations: the unit's pairs times the matrices its chunk holds
+    kde_ctx::Pending pd{nullptr, nullptr, kFamMd, 0.0};
+    for (size_t u = u0; u < u1; ++u) {
+      const int chunk = (int)(u / r.n_items);
+      pd.evals += r.pairs[u % r.n_items] * std::min(MH, m - chunk * MH);
+    }
+    if ((s = timed_begin(c, pd))) return s;
     launch_H(st, r.D, MH, r.f64, (const float*)(b + r.o_y32), (const double*)(b + r.o_y64), r.npad, dst, hd, m,
              (const Unit*)(b + r.o_units), (int)u0, (int)(u1 - u0), part, r.n_items);
+    if ((s = timed_end(c, pd))) return s;
     u0 = u1;
   }
   launch_reduce_rows(st, (const RowDesc*)(b + r.o_rows), 2 * m);

@@ -503,11 +503,12 @@ static kde_status run_md(kde_ctx* c, const kde_matrix& x, const double* h_grid, 
   make_items(n, capped_seg(c, n, kSegRefHC, (double)chunks), items);
   const int n_items = (int)items.pairs.size();
   std::vector<Unit> units;
-  std::vector<double> cost;
+  std::vector<double> cost, ev;  // planning cost, pair-term evaluations
   for (int it = 0; it < n_items; ++it)
     for (int ch = 0; ch < chunks; ++ch) {
       units.push_back(Unit{0, items.row[it], items.jb[it], items.je[it], it, ch});
       cost.push_back(items.pairs[it] * std::min(hc, n_h - ch * hc) * (1.0 + 2.0 * D / hc));
+      ev.push_back(items.pairs[it] * std::min(hc, n_h - ch * hc));
     }
   std::vector<RowDesc> rows;
   // device layout
@@ -551,8 +552,12 @@ static kde_status run_md(kde_ctx* c, const kde_matrix& x, const double* h_grid, 
     double acc = cost[u0];
     size_t u1 = u0 + 1;
     while (u1 < units.size() && (acc + cost[u1] <= budget || u1 - u0 < 2048)) acc += cost[u1++];
+    kde_ctx::Pending pd{nullptr, nullptr, kFamMd, 0.0};
+    for (size_t u = u0; u < u1; ++u) pd.evals += ev[u];
+    if ((s = timed_begin(c, pd))) return s;
     launch_md(st, D, f64, y32, y64, npad, dst, (const float*)(b + o_c32), (const double*)(b + o_c64),
               (const Unit*)(b + o_units), (int)u0, (int)(u1 - u0), part, n_items, n_h);
+    if ((s = timed_end(c, pd))) return s;
     u0 = u1;
   }
   launch_reduce_rows(st, (const RowDesc*)(b + o_rows), 2 * n_h);

@@ -368,6 +368,8 @@ static kde_status run_density_H(kde_ctx* c, const kde_matrix& x, const double* H
   md_whiten(st, b + o_qr, true, m, D, mpad, dst, dst->linv, nullptr, zq);
   const dim3 grid(qblocks, pieces);
   double* part = (double*)(b + o_part);
+  kde_ctx::Pending pd{nullptr, nullptr, kFamMd, (double)m * (double)n};
+  if ((s = timed_begin(c, pd))) return s;
   switch (D) {
     case 2: launch_dq<2>(st, f64, grid, zq, m, mpad, y, npad, dst, piece_len, pieces, part); break;
     case 3: launch_dq<3>(st, f64, grid, zq, m, mpad, y, npad, dst, piece_len, pieces, part); break;
@@ -375,6 +377,7 @@ static kde_status run_density_H(kde_ctx* c, const kde_matrix& x, const double* H
     case 8: launch_dq<8>(st, f64, grid, zq, m, mpad, y, npad, dst, piece_len, pieces, part); break;
     default: launch_dq<16>(st, f64, grid, zq, m, mpad, y, npad, dst, piece_len, pieces, part); break;
   }
+  if ((s = timed_end(c, pd))) return s;
   k_dq_final<<<qblocks, kThreads, 0, st>>>(dst, part, m, pieces, (double*)(b + o_out));
   MdState hs;
   KDE_HIP_TRY(c, hipMemcpyAsync(&hs, dst, sizeof(MdState), hipMemcpyDeviceToHost, st));

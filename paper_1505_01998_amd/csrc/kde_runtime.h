@@ -203,9 +203,9 @@ struct kde_ctx {
   kde::IterPlan iter;
   // timing
   bool timing = false;
-  int64_t t_launches[2] = {0, 0};
-  double t_ms[2] = {0, 0};
-  double t_evals[2] = {0, 0};
+  int64_t t_launches[3] = {0, 0, 0};
+  double t_ms[3] = {0, 0, 0};
+  double t_evals[3] = {0, 0, 0};
   struct Pending {
     hipEvent_t a, b;
     int family;
@@ -219,7 +219,14 @@ struct kde_ctx {
 
 namespace kde {
 
-constexpr int kFamLscv = 0, kFamPsi = 1;
+// kernel families of the timing: LSCV pair kernels, psi pair kernels, and the
+// d-dimensional pair kernels (LSCV_h, LSCV_H, density with a bandwidth matrix)
+constexpr int kFamLscv = 0, kFamPsi = 1, kFamMd = 2;
+// While timing is on, bracket the launches between the two calls with events
+// on the context's stream (no-ops otherwise); p.family and p.evals name the
+// family and the launches' pair-term evaluations.
+kde_status timed_begin(kde_ctx* c, kde_ctx::Pending& p);
+kde_status timed_end(kde_ctx* c, kde_ctx::Pending& p);
 
 kde_status fail(kde_ctx* c, kde_status st, const std::string& msg);
 kde_status status_of(int st);

@@ -405,8 +405,6 @@ void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int i
   }
 }
 
-namespace {
-
 // ---- timing
 kde_status timed_begin(kde_ctx* c, kde_ctx::Pending& p) {
   if (!c->timing) return KDE_OK;
@@ -428,6 +426,8 @@ kde_status timed_end(kde_ctx* c, kde_ctx::Pending& p) {
   c->pending.push_back(p);
   return KDE_OK;
 }
+
+namespace {
 
 kde_status collect_timing(kde_ctx* c) {
   for (kde_ctx::Pending& p : c->pending) {
@@ -1136,7 +1136,7 @@ kde_status kde_ctx_set_timing(kde_ctx* c, int enable) {
   if (!c) return KDE_E_INVAL;
   if (serving(c)) return busy(c);
   c->timing = enable != 0;
-  for (int f = 0; f < 2; ++f) {
+  for (int f = 0; f < 3; ++f) {
     c->t_launches[f] = 0;
     c->t_ms[f] = 0.0;
     c->t_evals[f] = 0.0;
@@ -1151,6 +1151,8 @@ kde_status kde_ctx_kernel_time(kde_ctx* c, const char* family, int64_t* launches
     f = kde::kFamLscv;
   else if (!std::strcmp(family, "psi_pairs"))
     f = kde::kFamPsi;
+  else if (!std::strcmp(family, "md_pairs"))
+    f = kde::kFamMd;
   else
     return fail(c, KDE_E_INVAL, "unknown kernel family");
   if (launches) *launches = c->t_launches[f];

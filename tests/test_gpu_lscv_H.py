@@ -215,3 +215,21 @@ def test_H_throughput(kde, d):
     assert np.all(np.isfinite(g))
     print(f"d={d}: n=1e5, 64 matrices in one pass {t64:.3f} s, {pairs * 64 / t64:.3e} evals/s; "
           f"one matrix a call {t1 * 1e3:.2f} ms, {pairs / t1:.3e} evals/s")
+
+
+@pytest.mark.parametrize("d,m", [(2, 11), (3, 5), (6, 3)])
+def test_md_kernel_timing_counts_every_evaluation(kde, d, m):
+    """With timing on, the d-dimensional pair launches report exactly
+    m n(n-1)/2 (pair, matrix) evaluations for an m-matrix call (partial
+    chunks included), and the LSCV_h curve n(n-1)/2 per bandwidth."""
+    n = 3001
+    x = _sample(n, d, 12, np.float32)
+    Hs = _matrices(x, m, 3)
+    with kde.Context(0) as c:
+        c.set_timing(True)
+        c.lscv_H_eval(x, Hs)
+        launches, ms, evals = c.kernel_time("md_pairs")
+        assert launches >= 1 and ms > 0 and evals == n * (n - 1) / 2 * m
+        c.set_timing(True)
+        c.lscv_md_curve(x, np.geomspace(0.05, 2.0, 37))
+        assert c.kernel_time("md_pairs")[2] == n * (n - 1) / 2 * 37

@@ -145,3 +145,16 @@ def served_stream(count: int, seed: int = 1998005, rate: float = 200.0, n_lo: fl
 # multimodal columns lies well below h_rot).
 BATCH_GRID = ("log_rot", 1.0 / 64.0, 4.0, 128)
 BATCH_STAGES = 3
+
+
+def draw_matrix(n: int, d: int, seed: int, dtype=np.float32) -> np.ndarray:
+    """n x d samples, row-major: a two-component Gaussian mixture with
+    correlated coordinates (35% of the samples in a tighter component shifted
+    by 3 in every coordinate), the 2-D/d-D stand-in for the multivariate
+    selectors and consumers."""
+    rng = _rng(seed)
+    A = rng.standard_normal((d, d)) + 2 * np.eye(d)
+    comp = rng.random(n) < 0.35
+    z = rng.standard_normal((n, d)) @ A.T
+    z[comp] = 0.4 * z[comp] + 3.0
+    return np.ascontiguousarray(z.astype(dtype))
