@@ -252,16 +252,15 @@ def batch_bench(args):
     }
 
 
-# Instruction-mix rooflines of the LSCV_H pair kernels at d = 2 (plain VALU at
-# 128 lanes/clk/CU, exp2 at 32, not overlapped): one matrix a block
-# (3 FMAs + add + fma + 5 shared ops = 10 plain) and four (5 + 5/4).
-LSCV_H_PEAK_MH1 = 1.0 / (10.0 / (256 * 128 * 2.4e9) + 1.0 / (256 * 32 * 2.4e9))
-LSCV_H_PEAK_MH4 = 1.0 / (6.25 / (256 * 128 * 2.4e9) + 1.0 / (256 * 32 * 2.4e9))
+# Instruction-mix roofline of the LSCV_H sweep kernel at d = 2 (plain VALU at
+# 128 lanes/clk/CU, exp2 at 32, not overlapped): per pair 2 differences, the
+# squared norm (mul + fma), the two accumulations (add + fma) and one exp2.
+LSCV_H_PEAK_D2 = 1.0 / (6.0 / (256 * 128 * 2.4e9) + 1.0 / (256 * 32 * 2.4e9))
 
 
 def lscv_H_bench(args):
     """The LSCV_H search (Nelder-Mead over full 2x2 bandwidth matrices, one
-    pass of the pair kernel per simplex step) on n = 1e5 two-dimensional
+    sweep of the pair kernel per evaluated matrix) on n = 1e5 two-dimensional
     samples; a step is one whole search from the rule-of-thumb start."""
     import torch
 
@@ -287,12 +286,7 @@ def lscv_H_bench(args):
     launches, ms, evals_k = ctx.kernel_time("md_pairs")
     ctx.close()
     pairs = n * (n - 1) / 2
-    p = d * (d + 1) // 2
-    # passes: one of p + 1 matrices (the start), one of p per shrink, one matrix otherwise
-    shrinks = max(0, (info.evals - info.passes - p) // (p - 1))
-    multi = (p + 1) + p * shrinks
-    single = info.evals - multi
-    peak = info.evals / (single / LSCV_H_PEAK_MH1 + multi / LSCV_H_PEAK_MH4)
+    peak = LSCV_H_PEAK_D2
     achieved = evals_k / (ms * 1e-3)
     out = {
         "metric": "(pair, matrix) evals/s (LSCV_H Nelder-Mead search, n=1e5, d=2)",
@@ -306,7 +300,7 @@ def lscv_H_bench(args):
                    "H": np.asarray(H).tolist()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Teval/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_H_units_f32<2,1> and <2,4>" if args.precision == "mixed" else "k_H_units_f64<2,*>",
+                     "kernel": "k_HZ_units_f32<2>" if args.precision == "mixed" else "k_HZ_units_f64<2>",
                      "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                      "evals_per_launch": evals_k / max(launches, 1)},
     }

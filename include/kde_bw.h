@@ -446,17 +446,14 @@ kde_status kde_bw_lscv_md(kde_ctx* ctx, kde_matrix x, const double* h_grid, int3
  * K_H(v) = (2 pi)^(-d/2) |H|^(-1/2) exp(-v^T H^-1 v / 2),
  * R(K) = 2^-d pi^(-d/2) |H|^(-1/2); H in the units of the data (H = h^2 for
  * d = 1).  H holds m row-major d x d matrices, only their lower triangles are
- * read.  For d <= 4 one pass of the pair kernel evaluates up to 64 matrices:
- * each pair's whitened difference (Y = L^-1 (X - mean), Sigma = L L^T) gives
- * the monomials of its quadratic form once for all of them, four matrices a
- * block.  For 4 < d <= 16 each matrix has a sweep of its own over samples
- * whitened for it (Z = L_G^-1 Y, G = L^-1 H L^-T).  g_out[m]; gscale_out (may be
- * NULL) receives 2 n^-2 (A S1 + 2 B S2) + n^-1 R, the scale of the terms.
- * A matrix that is not positive definite (a Cholesky pivot at most 1e-12 of
- * its diagonal entry) gets g = +inf and scale 0.  The mixed form (d <= 4)
- * computes the quadratic form from FP32 coefficients and evaluates g exactly
- * at the matrix those coefficients represent (within FP32 rounding of H);
- * for d > 4 it rounds the re-whitened samples to FP32.
+ * read.  Each matrix gets a sweep of the pair triangle of its own over the
+ * samples whitened for it, Z = L_G^-1 L^-1 (X - mean) with Sigma = L L^T and
+ * G = L^-1 H L^-T = L_G L_G^T, so that v^T H^-1 v = |Z_i - Z_j|^2; a matrix's
+ * g does not depend on the other matrices of the call.  g_out[m];
+ * gscale_out (may be NULL) receives 2 n^-2 (A S1 + 2 B S2) + n^-1 R, the
+ * scale of the terms.  A matrix that is not positive definite (a Cholesky
+ * pivot at most 1e-12 of its diagonal entry) gets g = +inf and scale 0.  The
+ * mixed form rounds Z to FP32 and takes FP32 exponentials; |H| is FP64.
  * KDE_E_INVAL for a bad matrix (n < 2, d outside [1, KDE_MAX_D], a
  * non-finite value), a non-finite entry of H or m outside [1, KDE_MAX_H_EVAL];
  * KDE_E_DEGENERATE when the sample covariance is singular. */
@@ -466,7 +463,7 @@ kde_status kde_lscv_H_eval(kde_ctx* ctx, kde_matrix x, const double* H, int32_t 
 typedef struct {
   double g;          /* g(H_out) */
   int32_t evals;     /* evaluations of g */
-  int32_t passes;    /* passes of the pair kernel (a batch of matrices each) */
+  int32_t passes;    /* evaluation calls (a batch of matrices each) */
   int32_t converged; /* 1: both tolerances met; 0: stopped at max_evals */
   int32_t pad0;
 } kde_lscv_H_info;
@@ -481,7 +478,7 @@ typedef struct {
  * vertex.  Stops when max g - min g over the simplex is at most ftol |min g|
  * and every vertex lies within xtol of the best in every parameter, or after
  * max_evals evaluations.  The p + 1 starting vertices, and the p vertices of
- * a shrink, are evaluated in one pass each.  H_out receives the best vertex's
+ * a shrink, are evaluated in one call each.  H_out receives the best vertex's
  * matrix (row-major d x d); info may be NULL.  The mixed form's g carries
  * relative noise of about 1e-9 and below between nearby matrices, so an ftol
  * under that can run to max_evals.  Errors as kde_lscv_H_eval, and

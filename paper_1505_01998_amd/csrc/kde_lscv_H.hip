@@ -17,126 +17,29 @@ namespace kde {
 
 namespace {
 
-// ---- LSCV_H (Section 4.4.3): g(H) at bandwidth matrices H, batched for 1 <= d <= 4.
-// In whitened coordinates w = Y_i - Y_j the quadratic form of the pair is
-// v^T H^-1 v = w^T P w with P = G^-1, G = L^-1 H L^-T (Sigma = L L^T).  A pair's
-// monomials w_a w_b (a <= b < D) are formed once in registers and each matrix
-// then costs one dot product with its packed coefficients, one exp2 and two
-// accumulations.  The mixed form rounds the coefficients to FP32 and
-// evaluates g at the matrix they represent exactly (its determinant taken
-// from the rounded coefficients), so each g is a consistent evaluation at a
-// matrix within FP32 rounding of H.  Padding samples are masked by index
-// (their +inf coordinate would meet cross terms of either sign).
-constexpr int kMaxHD = 4;
-constexpr int kMaxMono = kMaxHD * (kMaxHD + 1) / 2;
-
+// ---- device part.  With G = L^-1 H L^-T = L_G L_G^T (Sigma = L L^T, Y the
+// sphered samples) the quadratic form of a pair is v^T H^-1 v = |L_G^-1 w|^2,
+// w = Y_i - Y_j.  Each matrix therefore gets the samples whitened for it,
+// Z = c M (X - mean) with M = L_G^-1 L^-1 (lower triangular; c folds the
+// exponent's factor: c^2 = log2(e)/4 in the mixed form, 1/4 in FP64), and
+// one sweep of the pair triangle in the layout of the sphered LSCV_h kernel:
+// a block holds 256 samples i (D coordinates in registers) and walks its
+// item's j-range in LDS tiles of D x 512 coordinates; each pair costs D
+// differences, the squared norm and one exponential (exp2(-|dz|^2) in FP32,
+// S2 from its square), with no per-pair coefficient.  Every matrix is
+// processed the same way whatever the batch, so g of a matrix does not
+// depend on the other matrices of the call.  The mixed form rounds Z to FP32
+// (compensated 64-term runs, FP64 above the lane); both forms evaluate g at H
+// itself.  Padding samples hold +inf in the first coordinate.
 struct HDesc {
-  float c32[kMaxMono];   // -log2(e)/4 * P_ab * (a == b ? 1 : 2), a <= b < D, FP32
-  int valid;             // H, G (and in the mixed form the rounded P) positive definite
+  double logdet;  // log |H|
+  int valid;      // H and G positive definite
   int pad0;
-  double c64[kMaxMono];  // -1/4 * P_ab * (a == b ? 1 : 2), FP64
-  double logdet64;       // log |H|
-  double logdet32;       // log |H32|, H32 = L P32^-1 L^T the matrix of the FP32 coefficients
 };
 
-// Cholesky factor of the d x d symmetric matrix A with the library's pivot
-// rule (a pivot at most 1e-12 of its diagonal entry fails) and log|A|.
-__device__ bool h_chol(const double (&A)[kMaxHD][kMaxHD], int d, double (&L)[kMaxHD][kMaxHD], double& logdet) {
-  for (int a = 0; a < kMaxHD; ++a)
-    for (int b = 0; b < kMaxHD; ++b) L[a][b] = 0.0;
-  logdet = 0.0;
-  for (int a = 0; a < d; ++a)
-    for (int b = 0; b <= a; ++b) {
-      double s = A[a][b];
-      for (int k = 0; k < b; ++k) s -= L[a][k] * L[b][k];
-      if (a == b) {
-        if (!(s > 1e-12 * A[a][a]) || !isfinite(s)) return false;
-        L[a][a] = sqrt(s);
-        logdet += 2.0 * log(L[a][a]);
-      } else {
-        L[a][b] = s / L[b][b];
-      }
-    }
-  return true;
-}
-
-// one thread per matrix (H row-major d x d, its lower triangle read): G,
-// P = G^-1, the packed coefficients over D coordinates and both determinants
-__global__ void k_H_prep(const MdState* st, const double* H, int m, int D, int f64, HDesc* out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m) return;
-  const int d = st->d;
-  HDesc o;
-  for (int q = 0; q < kMaxMono; ++q) {
-    o.c32[q] = 0.f;
-    o.c64[q] = 0.0;
-  }
-  o.valid = 0;
-  o.pad0 = 0;
-  o.logdet64 = o.logdet32 = 0.0;
-  double Hs[kMaxHD][kMaxHD], G[kMaxHD][kMaxHD], T[kMaxHD][kMaxHD], L[kMaxHD][kMaxHD];
-  const double* Hk = H + (int64_t)k * d * d;
-  for (int a = 0; a < kMaxHD; ++a)
-    for (int b = 0; b < kMaxHD; ++b) Hs[a][b] = (a < d && b < d) ? Hk[max(a, b) * d + min(a, b)] : 0.0;
-  double ldH, ldG;
-  bool ok = st->status == kStOk && h_chol(Hs, d, L, ldH);
-  if (ok) {
-    for (int a = 0; a < d; ++a)  // T = L^-1 H
-      for (int b = 0; b < d; ++b) {
-        double s = 0.0;
-        for (int c = 0; c <= a; ++c) s += st->linv[a * KDE_MAX_D + c] * Hs[c][b];
-        T[a][b] = s;
-      }
-    for (int a = 0; a < d; ++a)  // G = T L^-T (lower triangle, mirrored)
-      for (int b = 0; b <= a; ++b) {
-        double s = 0.0;
-        for (int c = 0; c <= b; ++c) s += T[a][c] * st->linv[b * KDE_MAX_D + c];
-        G[a][b] = G[b][a] = s;
-      }
-    ok = h_chol(G, d, L, ldG);
-  }
-  if (ok) {
-    double Li[kMaxHD][kMaxHD], P[kMaxHD][kMaxHD], P32[kMaxHD][kMaxHD];
-    for (int c = 0; c < d; ++c)  // L_G^-1, lower triangular
-      for (int a = 0; a < d; ++a) {
-        if (a < c) {
-          Li[a][c] = 0.0;
-          continue;
-        }
-        double s = (a == c) ? 1.0 : 0.0;
-        for (int q = c; q < a; ++q) s -= L[a][q] * Li[q][c];
-        Li[a][c] = s / L[a][a];
-      }
-    for (int a = 0; a < d; ++a)  // P = L_G^-T L_G^-1
-      for (int b = 0; b < d; ++b) {
-        double s = 0.0;
-        for (int q = max(a, b); q < d; ++q) s += Li[q][a] * Li[q][b];
-        P[a][b] = s;
-      }
-    int q = 0;
-    for (int a = 0; a < D; ++a)
-      for (int b = a; b < D; ++b, ++q) {
-        if (b >= d) continue;
-        const double w = (a == b) ? 0.25 : 0.5;
-        o.c64[q] = -w * P[a][b];
-        o.c32[q] = (float)(-kLog2ED * w * P[a][b]);
-        P32[a][b] = P32[b][a] = (double)o.c32[q] / (-kLog2ED * w);
-      }
-    double ldP32;
-    const bool ok32 = f64 || h_chol(P32, d, L, ldP32);
-    o.logdet64 = st->logdet + ldG;
-    o.logdet32 = f64 ? o.logdet64 : st->logdet - ldP32;
-    o.valid = ok32 ? 1 : 0;
-  }
-  out[k] = o;
-}
-
-// ---- LSCV_H for 4 < d <= 16: one matrix a sweep.  With G = L_G L_G^T the
-// quadratic form is |L_G^-1 w|^2, so the samples are whitened once more,
-// Z = M (X - mean) with M = L_G^-1 L^-1 (lower triangular), and the sphered
-// pair kernel runs on Z with the single coefficient -1/4 (S2 from e^2).
-// Both forms evaluate g at H itself; the mixed form rounds Z to FP32.
-__global__ void k_HT_prep(const MdState* st, const double* H, int m, HDesc* out, double* Mout) {
+// one thread per matrix (H row-major d x d, its lower triangle read): the
+// whitening map c M (row stride KDE_MAX_D) and log|H|
+__global__ void k_H_prep(const MdState* st, const double* H, int m, int f64, HDesc* out, double* Mout) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const int d = st->d;
@@ -144,15 +47,12 @@ __global__ void k_HT_prep(const MdState* st, const double* H, int m, HDesc* out,
   double* M = Mout + (int64_t)k * KDE_MAX_D * KDE_MAX_D;
   for (int q = 0; q < KDE_MAX_D * KDE_MAX_D; ++q) M[q] = 0.0;
   HDesc o;
-  for (int q = 0; q < kMaxMono; ++q) {
-    o.c32[q] = 0.f;
-    o.c64[q] = 0.0;
-  }
+  o.logdet = 0.0;
   o.valid = 0;
   o.pad0 = 0;
-  o.logdet64 = o.logdet32 = 0.0;
   const double* Hk = H + (int64_t)k * d * d;
-  // Cholesky of A with the library's pivot rule; returns log|A| or NaN
+  // Cholesky factor of A with the library's pivot rule (a pivot at most
+  // 1e-12 of its diagonal entry fails) and log|A|
   auto chol = [&](double& ld) {
     ld = 0.0;
     for (int a = 0; a < d; ++a)
@@ -202,198 +102,132 @@ __global__ void k_HT_prep(const MdState* st, const double* H, int m, HDesc* out,
       for (int q = c; q < a; ++q) s -= L[a][q] * T[q][c];
       T[a][c] = s / L[a][a];
     }
-  for (int a = 0; a < d; ++a)  // M = L_G^-1 L^-1
+  const double cf = f64 ? 0.5 : sqrt(0.25 * kLog2ED);
+  for (int a = 0; a < d; ++a)  // M = c L_G^-1 L^-1
     for (int b = 0; b <= a; ++b) {
       double s = 0.0;
       for (int c = b; c <= a; ++c) s += T[a][c] * st->linv[c * KDE_MAX_D + b];
-      M[a * KDE_MAX_D + b] = s;
+      M[a * KDE_MAX_D + b] = cf * s;
     }
-  o.logdet64 = o.logdet32 = st->logdet + ldG;
+  o.logdet = st->logdet + ldG;
   o.valid = 1;
   out[k] = o;
 }
 
-template <int D, int MH, bool MASK>
-__device__ __forceinline__ void h_run(const float (*tile)[kBJ], int jl, int jg, int n, const float (&yi)[D], int i,
-                                      const float (&ck)[MH][D * (D + 1) / 2], float (&a1)[MH], float (&c1)[MH],
-                                      float (&a2)[MH], float (&c2)[MH]) {
-  constexpr int NM = D * (D + 1) / 2;
-  float r1[MH], r2[MH];
-#pragma unroll
-  for (int k = 0; k < MH; ++k) r1[k] = r2[k] = 0.f;
-#pragma unroll 2
+// 64 consecutive j of the tile for lane i: exp2(-|z_i - z_j|^2) summed, and
+// its squares; MASK drops j <= i (the diagonal run of a wave)
+template <int D, bool MASK>
+__device__ __forceinline__ void hz_run(const float (*tile)[kBJ], int jl, int jg, const float (&zi)[D], int i,
+                                       float& a1, float& c1, float& a2, float& c2) {
+  float r1 = 0.f, r2 = 0.f;
+#pragma unroll 4
   for (int q = 0; q < kMdRun; ++q) {
-    float w[D], mono[NM];
+    float s = 0.f;
 #pragma unroll
-    for (int a = 0; a < D; ++a) w[a] = yi[a] - tile[a][jl + q];
-    int t = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = a; b < D; ++b) mono[t++] = w[a] * w[b];
-    const bool live = !MASK || (jg + q > i && jg + q < n);
-#pragma unroll
-    for (int k = 0; k < MH; ++k) {
-      float s = ck[k][0] * mono[0];
-#pragma unroll
-      for (int mm = 1; mm < NM; ++mm) s = __builtin_fmaf(ck[k][mm], mono[mm], s);
-      s = live ? s : -__builtin_inff();
-      const float e = __builtin_amdgcn_exp2f(s);
-      r1[k] += e;
-      r2[k] = __builtin_fmaf(e, e, r2[k]);
+    for (int a = 0; a < D; ++a) {
+      const float dd = zi[a] - tile[a][jl + q];
+      s = __builtin_fmaf(dd, dd, s);
     }
+    if (MASK) s = (jg + q > i) ? s : __builtin_inff();
+    const float e = __builtin_amdgcn_exp2f(-s);
+    r1 += e;
+    r2 = __builtin_fmaf(e, e, r2);
   }
-#pragma unroll
-  for (int k = 0; k < MH; ++k) {
-    md_fold(a1[k], c1[k], r1[k]);
-    md_fold(a2[k], c2[k], r2[k]);
-  }
+  md_fold(a1, c1, r1);
+  md_fold(a2, c2, r2);
 }
 
-// block b of a launch: global index u0 + b = chunk * n_items + item; 256
-// samples i x the item's j-range x matrices chunk*MH ... chunk*MH + MH - 1;
-// part[(2 k + s) * n_items + item], s = 0: S1, 1: S2
-template <int D, int MH>
-__device__ __forceinline__ void h_store(const double (&v1)[MH], const double (&v2)[MH], const Unit& u, int chunk,
-                                        int m, double* part, int n_items, double (*red)[2 * MH]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-  for (int k = 0; k < MH; ++k) {
-    const double s1 = md_wave_sum(v1[k]);
-    const double s2 = md_wave_sum(v2[k]);
-    if (lane == 0) {
-      red[wave][2 * k] = s1;
-      red[wave][2 * k + 1] = s2;
-    }
-  }
-  __syncthreads();
-  if (tid < 2 * MH) {
-    const int hk = chunk * MH + (tid >> 1);
-    if (hk < m) part[(int64_t)(2 * hk + (tid & 1)) * n_items + u.item] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-  }
-}
-
-template <int D, int MH>
-__global__ __launch_bounds__(kThreads) void k_H_units_f32(const float* __restrict__ y, int npad,
-                                                          const MdState* __restrict__ st,
-                                                          const HDesc* __restrict__ hd, int m,
-                                                          const Unit* __restrict__ units, int u0,
-                                                          double* __restrict__ part, int n_items) {
+// one block per unit of one matrix: part[2 k + {0, 1}][item] of that matrix
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_HZ_units_f32(const float* __restrict__ z, int npad,
+                                                           const MdState* __restrict__ st,
+                                                           const Unit* __restrict__ units, int u0,
+                                                           double* __restrict__ part, int n_items) {
   if (st->status != kStOk) return;
-  constexpr int NM = D * (D + 1) / 2;
-  const int gidx = u0 + blockIdx.x;
-  const int chunk = gidx / n_items;
-  const Unit u = units[gidx - chunk * n_items];
+  const Unit u = units[u0 + blockIdx.x];
   const int n = st->n;
   __shared__ float tile[D][kBJ];
-  __shared__ double red[4][2 * MH];
-  const int tid = threadIdx.x;
+  __shared__ double red[4][2];
+  const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int row0 = u.row * kBI;
   const int i = row0 + tid;
-  float yi[D];
+  float zi[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) yi[a] = (i < n) ? y[(int64_t)a * npad + i] : 0.f;
+  for (int a = 0; a < D; ++a) zi[a] = (i < n) ? z[(int64_t)a * npad + i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
-  float ck[MH][NM], a1[MH], c1[MH], a2[MH], c2[MH];
-#pragma unroll
-  for (int k = 0; k < MH; ++k) {
-    const int hk = chunk * MH + k;
-    const bool use = hk < m && hd[hk].valid;
-#pragma unroll
-    for (int mm = 0; mm < NM; ++mm) ck[k][mm] = use ? hd[hk].c32[mm] : 0.f;
-    a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
-  }
+  float a1 = 0.f, c1 = 0.f, a2 = 0.f, c2 = 0.f;
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
     for (int a = 0; a < D; ++a)
-      for (int q = tid; q < kBJ; q += kThreads) tile[a][q] = y[(int64_t)a * npad + t0 + q];
+      for (int q = tid; q < kBJ; q += kThreads) tile[a][q] = z[(int64_t)a * npad + t0 + q];
     __syncthreads();
     int js = max(t0, wave_i0);
     const int te = t0 + kBJ;
-    if (te > n) {  // the column's last tile: padding masked by index
-      for (; js < te; js += kMdRun) h_run<D, MH, true>(tile, js - t0, js, n, yi, i, ck, a1, c1, a2, c2);
-    } else if (js < te) {
+    if (js < te) {
       if (js == wave_i0) {
-        h_run<D, MH, true>(tile, js - t0, js, n, yi, i, ck, a1, c1, a2, c2);
+        hz_run<D, true>(tile, js - t0, js, zi, i, a1, c1, a2, c2);
         js += kMdRun;
       }
-      for (; js < te; js += kMdRun) h_run<D, MH, false>(tile, js - t0, js, n, yi, i, ck, a1, c1, a2, c2);
+      for (; js < te; js += kMdRun) hz_run<D, false>(tile, js - t0, js, zi, i, a1, c1, a2, c2);
     }
   }
   const bool valid = i < n;
-  double v1[MH], v2[MH];
-#pragma unroll
-  for (int k = 0; k < MH; ++k) {
-    v1[k] = valid ? (double)a1[k] - (double)c1[k] : 0.0;
-    v2[k] = valid ? (double)a2[k] - (double)c2[k] : 0.0;
+  const double v1 = md_wave_sum(valid ? (double)a1 - (double)c1 : 0.0);
+  const double v2 = md_wave_sum(valid ? (double)a2 - (double)c2 : 0.0);
+  if (lane == 0) {
+    red[wave][0] = v1;
+    red[wave][1] = v2;
   }
-  h_store<D, MH>(v1, v2, u, chunk, m, part, n_items, red);
+  __syncthreads();
+  if (tid < 2) part[(int64_t)tid * n_items + u.item] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
-template <int D, int MH>
-__global__ __launch_bounds__(kThreads) void k_H_units_f64(const double* __restrict__ y, int npad,
-                                                          const MdState* __restrict__ st,
-                                                          const HDesc* __restrict__ hd, int m,
-                                                          const Unit* __restrict__ units, int u0,
-                                                          double* __restrict__ part, int n_items) {
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_HZ_units_f64(const double* __restrict__ z, int npad,
+                                                           const MdState* __restrict__ st,
+                                                           const Unit* __restrict__ units, int u0,
+                                                           double* __restrict__ part, int n_items) {
   if (st->status != kStOk) return;
-  constexpr int NM = D * (D + 1) / 2;
   constexpr int kT = kBJ / 2;
-  const int gidx = u0 + blockIdx.x;
-  const int chunk = gidx / n_items;
-  const Unit u = units[gidx - chunk * n_items];
+  const Unit u = units[u0 + blockIdx.x];
   const int n = st->n;
   __shared__ double tile[D][kT];
-  __shared__ double red[4][2 * MH];
-  const int tid = threadIdx.x;
+  __shared__ double red[4][2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = u.row * kBI + tid;
-  double yi[D];
+  double zi[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) yi[a] = (i < n) ? y[(int64_t)a * npad + i] : 0.0;
-  double ck[MH][NM], s1[MH], s2[MH];
-#pragma unroll
-  for (int k = 0; k < MH; ++k) {
-    const int hk = chunk * MH + k;
-    const bool use = hk < m && hd[hk].valid;
-#pragma unroll
-    for (int mm = 0; mm < NM; ++mm) ck[k][mm] = use ? hd[hk].c64[mm] : 0.0;
-    s1[k] = s2[k] = 0.0;
-  }
+  for (int a = 0; a < D; ++a) zi[a] = (i < n) ? z[(int64_t)a * npad + i] : 0.0;
+  double s1 = 0.0, s2 = 0.0;
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += kT) {
     __syncthreads();
     for (int a = 0; a < D; ++a)
-      for (int q = tid; q < kT; q += kThreads) tile[a][q] = y[(int64_t)a * npad + t0 + q];
+      for (int q = tid; q < kT; q += kThreads) tile[a][q] = z[(int64_t)a * npad + t0 + q];
     __syncthreads();
     const int qa = max(0, i + 1 - t0), qb = min(kT, n - t0);
     for (int q = qa; q < qb; ++q) {
-      double w[D], mono[NM];
+      double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) w[a] = yi[a] - tile[a][q];
-      int t = 0;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = a; b < D; ++b) mono[t++] = w[a] * w[b];
-#pragma unroll
-      for (int k = 0; k < MH; ++k) {
-        double sq = 0.0;
-#pragma unroll
-        for (int mm = 0; mm < NM; ++mm) sq = fma(ck[k][mm], mono[mm], sq);
-        const double e = exp(sq);
-        s1[k] += e;
-        s2[k] = fma(e, e, s2[k]);
+      for (int a = 0; a < D; ++a) {
+        const double dd = zi[a] - tile[a][q];
+        s = fma(dd, dd, s);
       }
+      const double e = exp(-s);
+      s1 += e;
+      s2 = fma(e, e, s2);
     }
   }
   const bool valid = i < n;
-  double v1[MH], v2[MH];
-#pragma unroll
-  for (int k = 0; k < MH; ++k) {
-    v1[k] = valid ? s1[k] : 0.0;
-    v2[k] = valid ? s2[k] : 0.0;
+  const double v1 = md_wave_sum(valid ? s1 : 0.0);
+  const double v2 = md_wave_sum(valid ? s2 : 0.0);
+  if (lane == 0) {
+    red[wave][0] = v1;
+    red[wave][1] = v2;
   }
-  h_store<D, MH>(v1, v2, u, chunk, m, part, n_items, red);
+  __syncthreads();
+  if (tid < 2) part[(int64_t)tid * n_items + u.item] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
 // g(H) = 2 n^-2 (A S1 - 2 B S2) + n^-1 R with A = (4 pi)^(-d/2) |H|^(-1/2),
@@ -401,8 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_H_units_f64(const double* __restri
 // with LSCV_MULTI-Kx, -KKx, -rk), and the scale of its terms
 // 2 n^-2 (A S1 + 2 B S2) + n^-1 R; +inf (scale 0) for a matrix that is not
 // positive definite, NaN when the samples were rejected
-__global__ void k_H_final(const MdState* st, const HDesc* hd, int m, int f64, const double* sums, double* g,
-                          double* gs) {
+__global__ void k_H_final(const MdState* st, const HDesc* hd, int m, const double* sums, double* g, double* gs) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   if (st->status != kStOk) {
@@ -416,48 +249,36 @@ __global__ void k_H_final(const MdState* st, const HDesc* hd, int m, int f64, co
   }
   const int d = st->d;
   const double n = (double)st->n;
-  const double sq = exp(-0.5 * (f64 ? hd[k].logdet64 : hd[k].logdet32));
+  const double sq = exp(-0.5 * hd[k].logdet);
   const double A = pow(4.0 * kPiD, -0.5 * d) * sq, B = pow(2.0 * kPiD, -0.5 * d) * sq;
   const double R = pow(2.0, -(double)d) * pow(kPiD, -0.5 * d) * sq;
   g[k] = 2.0 / (n * n) * (A * sums[2 * k] - 2.0 * B * sums[2 * k + 1]) + R / n;
   gs[k] = 2.0 / (n * n) * (A * sums[2 * k] + 2.0 * B * sums[2 * k + 1]) + R / n;
 }
 
-template <int D, int MH>
-void launch_H_units(hipStream_t s, bool f64, const float* y32, const double* y64, int npad, const MdState* st,
-                    const HDesc* hd, int m, const Unit* units, int u0, int cnt, double* part, int n_items) {
-  if (f64)
-    k_H_units_f64<D, MH><<<cnt, kThreads, 0, s>>>(y64, npad, st, hd, m, units, u0, part, n_items);
-  else
-    k_H_units_f32<D, MH><<<cnt, kThreads, 0, s>>>(y32, npad, st, hd, m, units, u0, part, n_items);
-}
-
-void launch_H(hipStream_t s, int D, int MH, bool f64, const float* y32, const double* y64, int npad,
-              const MdState* st, const HDesc* hd, int m, const Unit* units, int u0, int cnt, double* part,
-              int n_items) {
-#define KDE_H_CASE(DD)                                                                                     \
-  switch (MH) {                                                                                            \
-    case 1: launch_H_units<DD, 1>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items); return; \
-    case 2: launch_H_units<DD, 2>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items); return; \
-    default: launch_H_units<DD, 4>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items); return; \
-  }
-  if (D == 2 && MH == 8) {
-    launch_H_units<2, 8>(s, f64, y32, y64, npad, st, hd, m, units, u0, cnt, part, n_items);
-    return;
-  }
+void launch_HZ(hipStream_t s, int D, bool f64, const float* z32, const double* z64, int npad, const MdState* st,
+               const Unit* units, int u0, int cnt, double* part, int n_items) {
+#define KDE_HZ_CASE(DD)                                                                                  \
+  if (f64)                                                                                               \
+    k_HZ_units_f64<DD><<<cnt, kThreads, 0, s>>>(z64, npad, st, units, u0, part, n_items);                \
+  else                                                                                                   \
+    k_HZ_units_f32<DD><<<cnt, kThreads, 0, s>>>(z32, npad, st, units, u0, part, n_items);                \
+  return
   switch (D) {
-    case 2: KDE_H_CASE(2);
-    case 3: KDE_H_CASE(3);
-    default: KDE_H_CASE(4);
+    case 2: KDE_HZ_CASE(2);
+    case 3: KDE_HZ_CASE(3);
+    case 4: KDE_HZ_CASE(4);
+    case 8: KDE_HZ_CASE(8);
+    default: KDE_HZ_CASE(16);
   }
-#undef KDE_H_CASE
+#undef KDE_HZ_CASE
 }
-
 
 }  // namespace
 
-// ---- LSCV_H on the host side: staging once per call, then passes of at
-// most kHPass matrices each (prep, pair units, row reduction, finalize).
+// ---- LSCV_H on the host side: staging once per call (moments, Sigma, its
+// Cholesky factor), then passes of at most kHPass matrices each (prep, per
+// matrix a whitening and a sweep, row reduction, finalize).
 namespace {
 
 constexpr int kHPass = 64;
@@ -466,17 +287,14 @@ struct HRun {
   kde_ctx* c = nullptr;
   int n = 0, d = 0, D = 0, npad = 0, n_items = 0;
   bool f64 = false;
-  bool one = false;           // d > kMaxHD: one matrix a sweep on re-whitened samples
   const void* raw = nullptr;  // the samples on the device
   bool raw_f64 = false;
   std::vector<double> pairs;  // per item
   char* b = nullptr;
   size_t o_st = 0, o_y32 = 0, o_y64 = 0, o_hin = 0, o_hd = 0, o_part = 0, o_sums = 0, o_g = 0, o_gs = 0,
-         o_units = 0, o_rows = 0, o_hm = 0, o_coef = 0;
+         o_units = 0, o_rows = 0, o_hm = 0;
   MdState state{};
   int passes = 0;
-  float coef32 = 0.f;  // host sources of the coefficient copies (live until the stage's sync)
-  double coef64 = 0.0;
 };
 
 // Item length of an LSCV_H pass: about 8192 blocks for a single matrix
@@ -497,7 +315,6 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   r.n = (int)x.n;
   r.d = x.d;
   r.D = md_width(r.d);
-  r.one = r.d > kMaxHD;
   r.npad = r.n + kPad;
   const int n = r.n, d = r.d, D = r.D;
   const int esz = x.dtype == KDE_F64 ? 8 : 4;
@@ -506,7 +323,7 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   make_items(n, h_seg(c, n), items);
   r.n_items = (int)items.pairs.size();
   r.pairs = items.pairs;
-  // one unit per item; a pass's block index runs over chunk * n_items + item
+  // one unit per item (each matrix's sweep launches all of them)
   std::vector<Unit> units;
   units.reserve(r.n_items);
   for (int it = 0; it < r.n_items; ++it) units.push_back(Unit{0, items.row[it], items.jb[it], items.je[it], it, 0});
@@ -530,8 +347,7 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   r.o_gs = take(8 * (size_t)kHPass);
   r.o_units = take(sizeof(Unit) * units.size());
   r.o_rows = take(sizeof(RowDesc) * 2 * (size_t)kHPass);
-  r.o_hm = r.one ? take(8 * (size_t)kHPass * KDE_MAX_D * KDE_MAX_D) : 0;
-  r.o_coef = take(16);
+  r.o_hm = take(8 * (size_t)kHPass * KDE_MAX_D * KDE_MAX_D);
   kde_status s;
   if ((s = ensure(c, c->mdbuf, at))) return s;
   char* b = r.b = c->mdbuf.p;
@@ -544,11 +360,6 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   r.raw_f64 = x.dtype == KDE_F64;
   if (!x.on_device)
     KDE_HIP_TRY(c, hipMemcpyAsync(b + o_raw, x.data, (size_t)n * d * esz, hipMemcpyHostToDevice, st));
-  // the single coefficient of the one-matrix sweep: -log2(e)/4 (FP32), -1/4 (FP64)
-  r.coef32 = (float)(-kLog2ED * 0.25);
-  r.coef64 = -0.25;
-  KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_coef, &r.coef64, 8, hipMemcpyHostToDevice, st));
-  KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_coef + 8, &r.coef32, 4, hipMemcpyHostToDevice, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_rows, rows.data(), sizeof(RowDesc) * rows.size(), hipMemcpyHostToDevice, st));
   MdState* dst = (MdState*)(b + r.o_st);
@@ -569,59 +380,33 @@ kde_status h_pass(HRun& r, const double* H, int m, double* g, double* gs) {
   hipStream_t st = c->stream;
   kde_status s;
   char* b = r.b;
-  // matrices a block: as many as the pass has, up to 4 (8 for d <= 2, where
-  // the shared per-pair work is a larger share of the cost)
-  const int MH = m == 1 ? 1 : m == 2 ? 2 : (r.D == 2 && m >= 8) ? 8 : 4;
-  const int chunks = (m + MH - 1) / MH;
   const MdState* dst = (const MdState*)(b + r.o_st);
   const HDesc* hd = (const HDesc*)(b + r.o_hd);
+  const double* hm = (const double*)(b + r.o_hm);
   double* part = (double*)(b + r.o_part);
+  float* z32 = r.f64 ? nullptr : (float*)(b + r.o_y32);
+  double* z64 = r.f64 ? (double*)(b + r.o_y64) : nullptr;
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_hin, H, 8 * (size_t)m * r.d * r.d, hipMemcpyHostToDevice, st));
+  k_H_prep<<<1, kHPass, 0, st>>>(dst, (const double*)(b + r.o_hin), m, r.f64 ? 1 : 0, (HDesc*)(b + r.o_hd),
+                                 (double*)hm);
   // launches of at most launch_evals pair-term evaluations and at least 2048 blocks
   const double budget = r.f64 ? c->opt_launch_evals / 5.0 : c->opt_launch_evals;
-  if (r.one) {
-    const double* hm = (const double*)(b + r.o_hm);
-    k_HT_prep<<<1, kHPass, 0, st>>>(dst, (const double*)(b + r.o_hin), m, (HDesc*)(b + r.o_hd), (double*)hm);
-    float* z32 = r.f64 ? nullptr : (float*)(b + r.o_y32);
-    double* z64 = r.f64 ? (double*)(b + r.o_y64) : nullptr;
-    for (int k = 0; k < m; ++k) {
-      md_whiten(st, r.raw, r.raw_f64, r.n, r.D, r.npad, dst, hm + (size_t)k * KDE_MAX_D * KDE_MAX_D, z32, z64);
-      for (size_t u0 = 0; u0 < (size_t)r.n_items;) {
-        double acc = r.pairs[u0];
-        size_t u1 = u0 + 1;
-        while (u1 < (size_t)r.n_items && (acc + r.pairs[u1] <= budget || u1 - u0 < 2048)) acc += r.pairs[u1++];
-        kde_ctx::Pending pd{nullptr, nullptr, kFamMd, acc};
-        if ((s = timed_begin(c, pd))) return s;
-        launch_md_one(st, r.D, r.f64, z32, z64, r.npad, dst, (const float*)(b + r.o_coef + 8),
-                      (const double*)(b + r.o_coef), (const Unit*)(b + r.o_units), (int)u0, (int)(u1 - u0),
-                      part + (size_t)2 * k * r.n_items, r.n_items);
-        if ((s = timed_end(c, pd))) return s;
-        u0 = u1;
-      }
+  for (int k = 0; k < m; ++k) {
+    md_whiten(st, r.raw, r.raw_f64, r.n, r.D, r.npad, dst, hm + (size_t)k * KDE_MAX_D * KDE_MAX_D, z32, z64);
+    for (size_t u0 = 0; u0 < (size_t)r.n_items;) {
+      double acc = r.pairs[u0];
+      size_t u1 = u0 + 1;
+      while (u1 < (size_t)r.n_items && (acc + r.pairs[u1] <= budget || u1 - u0 < 2048)) acc += r.pairs[u1++];
+      kde_ctx::Pending pd{nullptr, nullptr, kFamMd, acc};
+      if ((s = timed_begin(c, pd))) return s;
+      launch_HZ(st, r.D, r.f64, z32, z64, r.npad, dst, (const Unit*)(b + r.o_units), (int)u0, (int)(u1 - u0),
+                part + (size_t)2 * k * r.n_items, r.n_items);
+      if ((s = timed_end(c, pd))) return s;
+      u0 = u1;
     }
-  } else {
-    k_H_prep<<<1, kHPass, 0, st>>>(dst, (const double*)(b + r.o_hin), m, r.D, r.f64 ? 1 : 0, (HDesc*)(b + r.o_hd));
-  }
-  const size_t total = r.one ? 0 : (size_t)chunks * r.n_items;
-  for (size_t u0 = 0; u0 < total;) {
-    double acc = r.pairs[u0 % r.n_items] * MH;
-    size_t u1 = u0 + 1;
-    while (u1 < total && (acc + r.pairs[u1 % r.n_items] * MH <= budget || u1 - u0 < 2048))
-      acc += r.pairs[u1++ % r.n_items] * MH;
-    // pair-term evaluations: the unit's pairs times the matrices its chunk holds
-    kde_ctx::Pending pd{nullptr, nullptr, kFamMd, 0.0};
-    for (size_t u = u0; u < u1; ++u) {
-      const int chunk = (int)(u / r.n_items);
-      pd.evals += r.pairs[u % r.n_items] * std::min(MH, m - chunk * MH);
-    }
-    if ((s = timed_begin(c, pd))) return s;
-    launch_H(st, r.D, MH, r.f64, (const float*)(b + r.o_y32), (const double*)(b + r.o_y64), r.npad, dst, hd, m,
-             (const Unit*)(b + r.o_units), (int)u0, (int)(u1 - u0), part, r.n_items);
-    if ((s = timed_end(c, pd))) return s;
-    u0 = u1;
   }
   launch_reduce_rows(st, (const RowDesc*)(b + r.o_rows), 2 * m);
-  k_H_final<<<1, kHPass, 0, st>>>(dst, hd, m, r.f64 ? 1 : 0, (const double*)(b + r.o_sums), (double*)(b + r.o_g),
+  k_H_final<<<1, kHPass, 0, st>>>(dst, hd, m, (const double*)(b + r.o_sums), (double*)(b + r.o_g),
                                   (double*)(b + r.o_gs));
   KDE_HIP_TRY(c, hipMemcpyAsync(g, b + r.o_g, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(gs, b + r.o_gs, 8 * (size_t)m, hipMemcpyDeviceToHost, st));

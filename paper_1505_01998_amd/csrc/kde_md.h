@@ -79,10 +79,6 @@ void md_whiten(hipStream_t st, const void* raw, bool raw_f64, int n, int D, int 
 // moments, covariance, Cholesky factor of Sigma and the sphered samples
 void md_stage(hipStream_t st, const void* raw, bool raw_f64, int n, int d, int D, int npad, int nblk, double* ps,
               int* nf, double* pc, MdState* dst, float* y32, double* y64);
-// the sphered pair kernel with a single coefficient, D = 8 or 16
-void launch_md_one(hipStream_t s, int D, bool f64, const float* y32, const double* y64, int npad,
-                   const MdState* st, const float* c32, const double* c64, const Unit* units, int u0, int cnt,
-                   double* part, int n_items);
 
 }  // namespace kde
 

@@ -464,16 +464,6 @@ void md_stage(hipStream_t st, const void* raw, bool raw_f64, int n, int d, int D
                                                                      y64);
 }
 
-void launch_md_one(hipStream_t s, int D, bool f64, const float* y32, const double* y64, int npad,
-                   const MdState* st, const float* c32, const double* c64, const Unit* units, int u0, int cnt,
-                   double* part, int n_items) {
-  if (D <= 8)
-    launch_md_units<8, 1>(s, f64, y32, y64, npad, st, c32, c64, units, u0, cnt, part, n_items, 1);
-  else
-    launch_md_units<16, 1>(s, f64, y32, y64, npad, st, c32, c64, units, u0, cnt, part, n_items, 1);
-}
-
-
 // Runs the whole d-dimensional LSCV pass; results in c->mdbuf (state, g, gs, h).
 static kde_status run_md(kde_ctx* c, const kde_matrix& x, const double* h_grid, int32_t n_h, MdState* h_state,
                          std::vector<double>& g, std::vector<double>& gs, std::vector<double>& hv) {

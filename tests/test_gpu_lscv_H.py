@@ -48,7 +48,7 @@ def _matrices(x, k, seed):
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 12, 16])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_H_eval_matches_oracle(kde, d, precision):
-    """d <= 4: matrices batched four a block; d > 4: one sweep a matrix."""
+    """Seven matrices a call, d = 1 ... 16."""
     n = 2003 if d <= 8 else 1201
     x = _sample(n, d, 20 + d, np.float32 if precision == "mixed" else np.float64)
     Hs = _matrices(x, 7, 5 + d)
@@ -65,8 +65,8 @@ def test_H_eval_matches_oracle(kde, d, precision):
 @pytest.mark.parametrize("d", [2, 3, 6])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_H_eval_does_not_depend_on_the_batch(kde, d, precision):
-    """One matrix a pass, two, seven, and 67 (two passes of the 64-matrix
-    limit) give the same g for the same matrix."""
+    """One matrix a call, two, seven, and 67 (two passes of the 64-matrix
+    limit) give the same g for the same matrix, bitwise."""
     x = _sample(1501, d, 3, np.float32 if precision == "mixed" else np.float64)
     Hs = _matrices(x, 67, 11)
     with kde.Context(0, precision) as c:
@@ -74,9 +74,10 @@ def test_H_eval_does_not_depend_on_the_batch(kde, d, precision):
         g_one = np.array([c.lscv_H_eval(x, H)[0][0] for H in Hs[:7]])
         g_two = np.concatenate([c.lscv_H_eval(x, Hs[k:k + 2])[0] for k in range(0, 6, 2)])
         g_sev, _ = c.lscv_H_eval(x, Hs[:7])
-    assert np.allclose(g_one, g_all[:7], rtol=1e-12, atol=0)
-    assert np.allclose(g_two, g_all[:6], rtol=1e-12, atol=0)
-    assert np.allclose(g_sev, g_all[:7], rtol=1e-12, atol=0)
+    # every matrix is whitened for and swept on its own: bitwise the same
+    assert np.array_equal(g_one, g_all[:7])
+    assert np.array_equal(g_two, g_all[:6])
+    assert np.array_equal(g_sev, g_all[:7])
     o = np.array([oracle.lscv_H(x, H) for H in Hs[60:]])
     with kde.Context(0, precision) as c:
         _, gs = c.lscv_H_eval(x, Hs[60:])
@@ -195,8 +196,9 @@ def test_search_mixed_reaches_the_oracle_minimum(kde, d):
 
 @pytest.mark.parametrize("d", [2, 3, 4, 8])
 def test_H_throughput(kde, d):
-    """n = 1e5: one pass of 64 matrices, then 16 passes of one matrix each
-    (the search's usual step): (pair, matrix) evaluations per second."""
+    """n = 1e5: one call with 64 matrices, then 16 calls with one matrix each
+    (the search's usual step, staging included): (pair, matrix) evaluations
+    per second."""
     import time
 
     n = 100_000
