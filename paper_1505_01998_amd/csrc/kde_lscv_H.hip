@@ -183,6 +183,69 @@ __global__ __launch_bounds__(kThreads) void k_HZ_units_f32(const float* __restri
   if (tid < 2) part[(int64_t)tid * n_items + u.item] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
+// The same sweep for wide samples (D = 8, 16), where the LDS reads of the
+// tile (D per pair) become the limit: the j coordinates are the same for
+// every lane of a wave, so they are read with uniform addresses (scalar
+// loads through the scalar cache) and enter the arithmetic as scalar
+// operands, with no tile and no barrier.  Measured at n = 1e5, d = 8: 20%
+// faster than the tiled kernel; at D <= 3 the tiled kernel is faster.
+template <int D, bool MASK>
+__device__ __forceinline__ void hz_run_s(const float* __restrict__ z, int npad, int jg, const float (&zi)[D], int i,
+                                       float& a1, float& c1, float& a2, float& c2) {
+  float r1 = 0.f, r2 = 0.f;
+#pragma unroll 8
+  for (int q = 0; q < kMdRun; ++q) {
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const float dd = zi[a] - z[(int64_t)a * npad + jg + q];
+      s = __builtin_fmaf(dd, dd, s);
+    }
+    if (MASK) s = (jg + q > i) ? s : __builtin_inff();
+    const float e = __builtin_amdgcn_exp2f(-s);
+    r1 += e;
+    r2 = __builtin_fmaf(e, e, r2);
+  }
+  md_fold(a1, c1, r1);
+  md_fold(a2, c2, r2);
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_HZ_units_f32s(const float* __restrict__ z, int npad,
+                                                           const MdState* __restrict__ st,
+                                                           const Unit* __restrict__ units, int u0,
+                                                           double* __restrict__ part, int n_items) {
+  if (st->status != kStOk) return;
+  const Unit u = units[u0 + blockIdx.x];
+  const int n = st->n;
+  __shared__ double red[4][2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row0 = u.row * kBI;
+  const int i = row0 + tid;
+  float zi[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) zi[a] = (i < n) ? z[(int64_t)a * npad + i] : 0.f;
+  const int wave_i0 = __builtin_amdgcn_readfirstlane(row0 + wave * 64);
+  float a1 = 0.f, c1 = 0.f, a2 = 0.f, c2 = 0.f;
+  int js = __builtin_amdgcn_readfirstlane(max(u.j_begin, wave_i0));
+  const int je = __builtin_amdgcn_readfirstlane(u.j_end);
+  if (js < je && js == wave_i0) {
+    hz_run_s<D, true>(z, npad, js, zi, i, a1, c1, a2, c2);
+    js += kMdRun;
+  }
+  for (; js < je; js += kMdRun) hz_run_s<D, false>(z, npad, js, zi, i, a1, c1, a2, c2);
+  const bool valid = i < n;
+  const double v1 = md_wave_sum(valid ? (double)a1 - (double)c1 : 0.0);
+  const double v2 = md_wave_sum(valid ? (double)a2 - (double)c2 : 0.0);
+  if (lane == 0) {
+    red[wave][0] = v1;
+    red[wave][1] = v2;
+  }
+  __syncthreads();
+  if (tid < 2) part[(int64_t)tid * n_items + u.item] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_HZ_units_f64(const double* __restrict__ z, int npad,
                                                            const MdState* __restrict__ st,
@@ -261,6 +324,8 @@ void launch_HZ(hipStream_t s, int D, bool f64, const float* z32, const double* z
 #define KDE_HZ_CASE(DD)                                                                                  \
   if (f64)                                                                                               \
     k_HZ_units_f64<DD><<<cnt, kThreads, 0, s>>>(z64, npad, st, units, u0, part, n_items);                \
+  else if constexpr (DD >= 8)                                                                            \
+    k_HZ_units_f32s<DD><<<cnt, kThreads, 0, s>>>(z32, npad, st, units, u0, part, n_items);               \
   else                                                                                                   \
     k_HZ_units_f32<DD><<<cnt, kThreads, 0, s>>>(z32, npad, st, units, u0, part, n_items);                \
   return
