@@ -678,3 +678,41 @@ def test_range_aggregates_2d_strong_correlation_and_errors():
     with pytest.raises(oracle.OracleError) as e:
         oracle.density_H(z, [[1.0, 2.0], [2.0, 1.0]], z[:2])
     assert e.value.code == oracle.DEGENERATE
+
+
+def test_lscv_H_nelder_mead_path_matches_scipy_from_the_same_simplex():
+    """The oracle's search step by step: from the start of eq. (LSCV-H-start)
+    read as H0 = s^2 Sigma (Cholesky parameters, log-diagonal) and the stated
+    initial steps, scipy's Nelder-Mead with the standard coefficients
+    (reflection 1, expansion 2, contractions 1/2, shrink 1/2) reaches the same
+    best vertex after the same number of evaluations; the initial simplex
+    alone (max_evals = p + 1) gives one of its vertices, the one with the
+    smallest g."""
+    from scipy.optimize import minimize
+
+    rng = np.random.Generator(np.random.PCG64(23))
+    z = rng.standard_normal((300, 2)) @ np.array([[1.0, 0.0], [0.5, 0.7]]).T
+    z[:90] = 0.5 * z[:90] + [2.0, -1.0]
+    n, d = z.shape
+    s = (4 / (d + 2)) ** (1 / (d + 4)) * n ** (-1 / (d + 4))
+    C0 = np.linalg.cholesky(s * s * np.cov(z, rowvar=False))
+    th0 = np.array([np.log(C0[0, 0]), C0[1, 0], np.log(C0[1, 1])])
+    steps = np.array([0.25, 0.25 * np.sqrt(C0[0, 0] * C0[1, 1]), 0.25])
+    simplex = np.vstack([th0] + [th0 + np.eye(3)[k] * steps[k] for k in range(3)])
+
+    def H_of(th):
+        C = np.array([[np.exp(th[0]), 0.0], [th[1], np.exp(th[2])]])
+        return C @ C.T
+
+    f = [oracle.lscv_H(z, H_of(t)) for t in simplex]
+    H4, g4, ev4 = oracle.lscv_H_min(z, ftol=1e-300, xtol=1e-300, max_evals=4)
+    assert ev4 == 4 and np.allclose(H4, H_of(simplex[int(np.argmin(f))]), rtol=1e-14) and g4 == min(f)
+    for k in (12, 40, 90):
+        # the oracle stops at the first step boundary with at least k
+        # evaluations; scipy, given exactly that many, stops at the same one
+        H, g, ev = oracle.lscv_H_min(z, ftol=1e-300, xtol=1e-300, max_evals=k)
+        r = minimize(lambda t: oracle.lscv_H(z, H_of(t)), th0, method="Nelder-Mead",
+                     options={"initial_simplex": simplex, "maxfev": ev, "xatol": 0.0, "fatol": 0.0,
+                              "adaptive": False})
+        assert ev >= k and ev == r.nfev, (k, ev, r.nfev)
+        assert np.allclose(H, H_of(r.x), rtol=1e-9, atol=0) and g == pytest.approx(r.fun, rel=1e-12)
