@@ -50,9 +50,9 @@ PLANNER_BEGIN, PLANNER_END = "// ---- work items", "size_t take("
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32<16>",
-    "sources_sha256": "d560f63435d99aeb8de4eadc1bf570b3b27fa81e8821190b0ff20064a0636267",
-    "fetch_bytes": 2.6885e7,
-    "write_bytes": 8.5992e6,
+    "sources_sha256": "50bfae7b5352505104a7ae70d6b189d1ad7d75e5dcff89e2af3bb9e45491bbf8",
+    "fetch_bytes": 2.6881e+07,
+    "write_bytes": 8.5992e+06,
 }
 
 

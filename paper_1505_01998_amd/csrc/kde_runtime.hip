@@ -117,16 +117,19 @@ std::string check_grid(const kde_grid& g) {
 }
 
 // ---- work items
+// Pairs i < j with i in the row's 256 samples, j in [jb, je), both < n:
+// sum over i of max(0, je - max(jb, i + 1)) in closed form (rows i < jb
+// contribute je - jb each, rows i >= jb the arithmetic series je - 1 - i).
 double item_pairs(int64_t n, int64_t row, int64_t jb, int64_t je) {
   const int64_t i0 = row * kBI;
   const int64_t i1 = std::min<int64_t>(n, i0 + kBI);
   je = std::min<int64_t>(je, n);
-  double p = 0.0;
-  for (int64_t i = i0; i < i1; ++i) {
-    const int64_t b = std::max<int64_t>(jb, i + 1);
-    if (je > b) p += (double)(je - b);
-  }
-  return p;
+  int64_t p = 0;
+  const int64_t flat_end = std::min(i1, jb);  // i in [i0, flat_end): j from jb
+  if (flat_end > i0 && je > jb) p += (flat_end - i0) * (je - jb);
+  const int64_t a = std::max(i0, jb), b = std::min(i1, je - 1);  // i in [a, b): j from i + 1
+  if (b > a) p += (b - a) * ((je - 1 - a) + (je - b)) / 2;
+  return (double)p;
 }
 
 // Items of one column: row r sweeps j in [r*kBI, n) rounded up to kBJ, cut
