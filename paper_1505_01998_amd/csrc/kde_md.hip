@@ -205,6 +205,39 @@ __device__ __forceinline__ void md_run(const float (*tile)[kBJ], int jl, int jg,
   }
 }
 
+// md_run for wide samples (D = 8, 16): the j coordinates are the same for
+// every lane of a wave, so they are read with uniform addresses (scalar loads
+// through the scalar cache) instead of from an LDS tile
+template <int D, int HC, bool MASK>
+__device__ __forceinline__ void md_run_s(const float* __restrict__ y, int npad, int jg, const float (&yi)[D],
+                                         int i, const float (&ck)[HC], float (&a1)[HC], float (&c1)[HC],
+                                         float (&a2)[HC], float (&c2)[HC]) {
+  float r1[HC], r2[HC];
+#pragma unroll
+  for (int k = 0; k < HC; ++k) r1[k] = r2[k] = 0.f;
+#pragma unroll 2
+  for (int q = 0; q < kMdRun; ++q) {
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const float dd = yi[a] - y[(int64_t)a * npad + jg + q];
+      s = __builtin_fmaf(dd, dd, s);
+    }
+    if (MASK) s = (jg + q > i) ? s : __builtin_inff();
+#pragma unroll
+    for (int k = 0; k < HC; ++k) {
+      const float e = __builtin_amdgcn_exp2f(s * ck[k]);
+      r1[k] += e;
+      r2[k] = __builtin_fmaf(e, e, r2[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < HC; ++k) {
+    md_fold(a1[k], c1[k], r1[k]);
+    md_fold(a2[k], c2[k], r2[k]);
+  }
+}
+
 template <int D, int HC>
 __global__ __launch_bounds__(kThreads) void k_md_units_f32(const float* __restrict__ y, int npad,
                                                            const MdState* __restrict__ st,
@@ -214,7 +247,6 @@ __global__ __launch_bounds__(kThreads) void k_md_units_f32(const float* __restri
   if (st->status != kStOk) return;
   const Unit u = units[u0 + blockIdx.x];
   const int n = st->n;
-  __shared__ float tile[D][kBJ];
   __shared__ double red[4][2 * HC];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -223,26 +255,39 @@ __global__ __launch_bounds__(kThreads) void k_md_units_f32(const float* __restri
   float yi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) yi[a] = (i < n) ? y[(int64_t)a * npad + i] : 0.f;
-  const int wave_i0 = row0 + wave * 64;
+  const int wave_i0 = __builtin_amdgcn_readfirstlane(row0 + wave * 64);
   float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
     ck[k] = c32[u.chunk * HC + k];
     a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
   }
-  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
-    __syncthreads();
-    for (int a = 0; a < D; ++a)
-      for (int q = tid; q < kBJ; q += kThreads) tile[a][q] = y[(int64_t)a * npad + t0 + q];
-    __syncthreads();
-    int js = max(t0, wave_i0);
-    const int te = t0 + kBJ;
-    if (js < te) {
-      if (js == wave_i0) {
-        md_run<D, HC, true>(tile, js - t0, js, yi, i, ck, a1, c1, a2, c2);
-        js += kMdRun;
+  if constexpr (D >= 8) {
+    // wide samples: D tile reads a pair would limit the sweep; read the j
+    // coordinates with uniform addresses instead (no tile, no barrier)
+    int js = __builtin_amdgcn_readfirstlane(max(u.j_begin, wave_i0));
+    const int je = __builtin_amdgcn_readfirstlane(u.j_end);
+    if (js < je && js == wave_i0) {
+      md_run_s<D, HC, true>(y, npad, js, yi, i, ck, a1, c1, a2, c2);
+      js += kMdRun;
+    }
+    for (; js < je; js += kMdRun) md_run_s<D, HC, false>(y, npad, js, yi, i, ck, a1, c1, a2, c2);
+  } else {
+    __shared__ float tile[D][kBJ];
+    for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
+      __syncthreads();
+      for (int a = 0; a < D; ++a)
+        for (int q = tid; q < kBJ; q += kThreads) tile[a][q] = y[(int64_t)a * npad + t0 + q];
+      __syncthreads();
+      int js = max(t0, wave_i0);
+      const int te = t0 + kBJ;
+      if (js < te) {
+        if (js == wave_i0) {
+          md_run<D, HC, true>(tile, js - t0, js, yi, i, ck, a1, c1, a2, c2);
+          js += kMdRun;
+        }
+        for (; js < te; js += kMdRun) md_run<D, HC, false>(tile, js - t0, js, yi, i, ck, a1, c1, a2, c2);
       }
-      for (; js < te; js += kMdRun) md_run<D, HC, false>(tile, js - t0, js, yi, i, ck, a1, c1, a2, c2);
     }
   }
   const bool valid = i < n;
