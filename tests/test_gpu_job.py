@@ -136,3 +136,13 @@ def test_job_beside_a_server_is_refused(kde):
             c.server_stop()
             res = job.run_to_end()
         assert res.status == kde.KDE_OK
+
+
+def test_smallest_job(kde):
+    """Two samples, rule of thumb only: one run finishes the job."""
+    with kde.Context(0) as c:
+        r = kde.Request(np.array([0.0, 1.0]), kde.KDE_METHOD_ROT)
+        with kde.Job(c, r) as job:
+            assert job.run(1.0)
+            res = job.result()
+        assert res.status == kde.KDE_OK and res.h_rot == c.batch([r])[0].h_rot

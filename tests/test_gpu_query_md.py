@@ -175,3 +175,26 @@ def test_density_H_throughput(kde):
         dt = time.perf_counter() - t
     assert np.all(np.isfinite(f))
     print(f"density_H d=2: n=1e5, 4096 points in {dt * 1e3:.2f} ms, {1e5 * 4096 / dt:.3e} pair terms/s")
+
+
+def test_smallest_inputs(kde):
+    """The smallest inputs each call accepts: one sample for the density and
+    the 2-D aggregates, one query point, one box; three samples for LSCV_H
+    (two are collinear in 2-D: singular Sigma)."""
+    from scipy.stats import multivariate_normal
+
+    H = np.array([[0.3, 0.1], [0.1, 0.2]])
+    one = np.array([[0.4, -1.2]])
+    with kde.Context(0, "fp64") as c:
+        f = c.density_H(one, H, [[0.0, 0.0]])
+        assert f[0] == pytest.approx(multivariate_normal(one[0], H).pdf([0.0, 0.0]), rel=1e-13)
+        cnt, sx, sy, ax, ay = c.range_aggregates_2d(one, H, [[0.0, 1.0, -2.0, 0.0]])
+        oc, osx, osy = oracle.range_aggregates_2d(one, H, [[0.0, 1.0, -2.0, 0.0]])
+        assert cnt[0] == pytest.approx(oc[0], rel=1e-10) and 0 < cnt[0] < 1
+        assert sx[0] == pytest.approx(osx[0], rel=1e-9) and sy[0] == pytest.approx(osy[0], rel=1e-9)
+        three = np.array([[0.0, 0.0], [1.0, 0.3], [-0.2, 0.9]])
+        g, _ = c.lscv_H_eval(three, H)
+        assert g[0] == pytest.approx(oracle.lscv_H(three, H), rel=1e-12)
+        with pytest.raises(kde.KdeError) as e:
+            c.lscv_H_eval(three[:2], H)
+        assert e.value.status == kde.KDE_E_DEGENERATE
