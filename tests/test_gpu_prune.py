@@ -99,3 +99,19 @@ def test_prune_refused_by_the_server(kde):
         with pytest.raises(kde.KdeError) as e:
             c.server_start(1 << 30, 4)
         assert e.value.status == kde.KDE_E_INVAL
+
+
+def test_search_with_pruning_per_step(kde):
+    """The k-section search runs every step through the planner, so with the
+    prune option each step's pass is pruned.  Near the minimum neighbouring g
+    values differ by less than the pruning bound, so the two searches may
+    take different brackets there (measured: 0.16% apart in h); both end at
+    the same minimum value of g."""
+    x = workloads.draw("mixture", 200_000, 44, np.float32)
+    with kde.Context(0) as dense, kde.Context(0) as pr:
+        pr.set_option("prune", 1)
+        hd, infod = dense.bw_lscv_min(x, 1e-3, 1.0, 1e-4, 16)
+        hp, infop = pr.bw_lscv_min(x, 1e-3, 1.0, 1e-4, 16)
+    assert abs(infop["g"] - infod["g"]) <= 1e-7 * abs(infod["g"])
+    assert abs(hp / hd - 1.0) <= 1e-2
+    assert abs(infop["iterations"] - infod["iterations"]) <= 2
