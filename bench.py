@@ -180,6 +180,8 @@ def _apply_options(ctx, args):
         ctx.set_option("graph", args.graph)
     if getattr(args, "prune", -1) >= 0:
         ctx.set_option("prune", args.prune)
+    if getattr(args, "aging_ms", 0) > 0:
+        ctx.set_option("serve_aging_ms", args.aging_ms)
 
 
 def _lscv_kernel(ctx, args, n, n_h):
@@ -413,7 +415,8 @@ def served_bench(args):
         "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "requests": len(reqs), "rate_req_s": args.rate,
                    "n_range": [n_lo, n_hi], "n_h": n_h, "plugin_stages": workloads.BATCH_STAGES,
-                   "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "pair_evals": evals,
+                   "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "aging_ms": args.aging_ms,
+                   "pair_evals": evals,
                    "load_matched_rate_req_s": 0.7 * cap},
         **out,
         "speedup_req_s": out["served"]["req_per_s"] / out["plain"]["req_per_s"],
@@ -431,6 +434,7 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrival rate of the stream (req/s)")
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--aging-ms", type=int, default=0, help="served: aging time constant of the SRPT order (0 = off)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--accuracy", type=int, default=1,

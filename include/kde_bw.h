@@ -120,6 +120,10 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
  *                  iteration (an iteration also holds at least six rounds of
  *                  1024 blocks of its largest work unit)
+ *   "serve_aging_ms" server: aging of the smallest-remaining-work order: a
+ *                  request's remaining evaluations count divided by
+ *                  1 + waited / tau (tau in ms; 0: plain order), so large
+ *                  requests are not held back indefinitely under load
  *   "serve_fail_ticket" server, failure handling: the request with this
  *                  ticket (tickets count from 1 per server) is treated as if
  *                  its pass had failed: it ends with KDE_E_DEVICE and frees

@@ -6,7 +6,8 @@
 // resident.  Each scheduler iteration builds one executor pass over all
 // resident requests: the moments of newly admitted ones, then plug-in stage
 // units and LSCV units taken request by request, smallest remaining work
-// first, until the iteration's evaluation budget is used; a stage whose last
+// first (optionally aged by the time waited), until the iteration's
+// evaluation budget is used; a stage whose last
 // units are in the pass is finished in it, and requests whose work is all
 // done are finalised and copied back.  Requests arriving while an iteration
 // runs join the next one, so their work overlaps with the requests already
@@ -47,6 +48,7 @@ struct SrvReq {
   std::vector<Unit> psi_u, lscv_u;
   std::vector<UnitCost> psi_c, lscv_c;
   double remaining = 0.0;
+  double key = 0.0;  // the scheduler's order of this iteration
   bool finishing = false, done = false;
   bool cancel = false;    // kde_cancel on an admitted request: dropped after the current iteration
   bool injected = false;  // the failure hook names this request
@@ -156,13 +158,18 @@ void Server::loop() {
       active.push_back(r);
     }
     if (active.empty()) continue;
-    // one executor pass over the resident requests, smallest remaining first
+    // one executor pass over the resident requests, smallest remaining first;
+    // with aging (time constant tau) a request's remaining work counts as
+    // remaining / (1 + waited / tau), so long-waiting large requests move up
     it.clear();
     it.cols.assign(max_slots, ColDesc());
-    std::sort(active.begin(), active.end(),
-              [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
-                return a->remaining < b->remaining || (a->remaining == b->remaining && a->ticket < b->ticket);
-              });
+    {
+      const double now = now_s(), tau = ctx->opt_serve_aging_s;
+      for (auto& r : active) r->key = tau > 0.0 ? r->remaining / (1.0 + (now - r->t_submit) / tau) : r->remaining;
+    }
+    std::sort(active.begin(), active.end(), [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
+      return a->key < b->key || (a->key == b->key && a->ticket < b->ticket);
+    });
     // An iteration is one launch per pass, so it must hold several waves of its
     // largest units or the launch tail idles the chip: at least 6 rounds of
     // 1024 resident blocks of the largest unit any resident request has next.
