@@ -182,6 +182,8 @@ def _apply_options(ctx, args):
         ctx.set_option("prune", args.prune)
     if getattr(args, "aging_ms", 0) > 0:
         ctx.set_option("serve_aging_ms", args.aging_ms)
+    if getattr(args, "iter_evals", 0) > 0:
+        ctx.set_option("serve_iter_evals", int(args.iter_evals))
 
 
 def _lscv_kernel(ctx, args, n, n_h):
@@ -416,6 +418,7 @@ def served_bench(args):
         "config": {"workload": args.workload, "requests": len(reqs), "rate_req_s": args.rate,
                    "n_range": [n_lo, n_hi], "n_h": n_h, "plugin_stages": workloads.BATCH_STAGES,
                    "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "aging_ms": args.aging_ms,
+                   "prune": args.prune > 0, "iter_evals": args.iter_evals or None,
                    "pair_evals": evals,
                    "load_matched_rate_req_s": 0.7 * cap},
         **out,
@@ -435,6 +438,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--aging-ms", type=int, default=0, help="served: aging time constant of the SRPT order (0 = off)")
+    ap.add_argument("--iter-evals", type=float, default=0,
+                    help="served: pair-term evaluations per server iteration (0 = the library's default)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--accuracy", type=int, default=1,

@@ -119,7 +119,10 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  value to rounding, not bitwise, to the vector-ALU kernel)
  *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
  *                  iteration (an iteration also holds at least six rounds of
- *                  1024 blocks of its largest work unit)
+ *                  1024 blocks of its largest work unit).  Pruned sweeps are
+ *                  counted at their dense size, so with "prune" an iteration
+ *                  does less work than it counts; a larger value keeps the
+ *                  per-iteration host work small against it.
  *   "serve_aging_ms" server: aging of the smallest-remaining-work order: a
  *                  request's remaining evaluations count divided by
  *                  1 + waited / tau (tau in ms; 0: plain order), so large
@@ -135,9 +138,9 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  first use when the job holds at least 1e13 pair-term
  *                  evaluations; smaller jobs use a cached decision or
  *                  lscv_hc).  Results are bitwise those of any lscv_hc.
- *   "prune"        1: LSCV tile pruning on sorted samples (mixed precision,
- *                  synchronous calls and kde_batch; kde_server_start refuses
- *                  it).  Each LSCV column is sorted on the device (the pair
+ *   "prune"        1: LSCV tile pruning on sorted samples (mixed precision;
+ *                  synchronous calls, kde_batch, the server and jobs).
+ *                  Each LSCV column is sorted on the device (the pair
  *                  sums do not depend on the order); the first j-tile of every
  *                  row gives lower bounds L(h) of the positive pair sums; a
  *                  256 x 512 tile farther from its row than the chunk's cut
@@ -146,8 +149,9 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  S2 and every h of the chunk.  Results stay within 2^-34 of
  *                  the dense sums on top of the arithmetic error;
  *                  kde_result.lscv_evals counts what was evaluated.  The
- *                  plug-in passes are unchanged.  Graph replay is off while
- *                  pruning.
+ *                  plug-in passes are unchanged.  A column's pruned results
+ *                  are bitwise the same alone, in a batch, served or run as
+ *                  a job.  Graph replay is off while pruning.
  *   "graph"        1: the kernel launches of a synchronous call or kde_batch
  *                  are captured into a HIP graph; a later call with the same
  *                  signature (per request: validity, n, dtype, host/device,
@@ -300,11 +304,13 @@ typedef struct {
  * resumed from a checkpoint finishes with the results of an uninterrupted
  * one.  A job uses its context's stream and workspace: destroy it before the
  * context; while a server runs on the context, job calls return KDE_E_BUSY.
- * The "prune" option is refused (its skipped work depends on the pass). */
+ * The options in force at kde_job_create (lscv_hc, lscv_mfma, prune,
+ * fp64_kappa) stay the job's; a checkpoint carries its fp64_kappa and resumes
+ * only in a job of the same precision, lscv_hc, lscv_mfma and prune. */
 typedef struct kde_job kde_job;
 /* Plans the request and copies its samples (host or device) and explicit grid
  * into the job's device block; the caller may free them on return.
- * KDE_E_INVAL for an invalid request or with the prune option on. */
+ * KDE_E_INVAL for an invalid request. */
 kde_status kde_job_create(kde_ctx* ctx, const kde_request* req, kde_job** out);
 /* Runs the next work units until about max_evals pair-term evaluations are
  * issued (at least one unit), and synchronises.  *done_out (may be NULL) is 1

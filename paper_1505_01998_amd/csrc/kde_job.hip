@@ -48,7 +48,7 @@ using kde::fail;
 // Checkpoint header; the block bytes, then g and gscale (n_h each) follow.
 struct JobHeader {
   char magic[8];
-  int32_t version, n, f64, plugin, lscv, stages, n_h, hc, mfma, cond, prec, grid_kind;
+  int32_t version, n, f64, plugin, lscv, stages, n_h, hc, mfma, cond, prec, grid_kind, prune;
   int64_t items_psi, items_lscv, block_bytes;
   int32_t stats_done, plugin_done, prep_done, lscv_done, done, stage;
   int64_t psi_next, lscv_next;
@@ -58,7 +58,7 @@ struct JobHeader {
 };
 
 constexpr char kMagic[8] = {'K', 'D', 'E', 'J', 'O', 'B', '\0', '\0'};
-constexpr int32_t kVersion = 1;
+constexpr int32_t kVersion = 2;
 
 bool serving(const kde_ctx* c) { return c->server && kde::server_running(c->server.get()); }
 
@@ -86,7 +86,6 @@ kde_status kde_job_create(kde_ctx* c, const kde_request* req, kde_job** out) {
   if (!c || !req || !out) return KDE_E_INVAL;
   *out = nullptr;
   if (serving(c)) return fail(c, KDE_E_BUSY, "a server is running");
-  if (c->opt_prune) return fail(c, KDE_E_INVAL, "tile pruning (option prune) is not resumable; turn it off");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   std::unique_ptr<kde_job> j(new kde_job());
   j->c = c;
@@ -126,7 +125,8 @@ kde_status kde_job_create(kde_ctx* c, const kde_request* req, kde_job** out) {
     return s;
   }
   kde::psi_units_of(p, 0, j->psi_u, j->psi_c);
-  kde::lscv_units_of(p, 0, j->lscv_u, j->lscv_c);
+  // with tile pruning the sweep units name the pruned-sweep descriptor (2)
+  kde::lscv_units_of(p, p.prune ? 2 : 0, j->lscv_u, j->lscv_c);
   j->stage = p.stages == 3 ? 0 : 1;
   for (const kde::UnitCost& u : j->psi_c) j->total += u.evals * (3 - j->stage);
   for (const kde::UnitCost& u : j->lscv_c) j->total += u.evals;
@@ -162,10 +162,13 @@ kde_status kde_job_run(kde_job* j, double max_evals, int* done_out) {
   const kde::ColPlan& p = j->plan;
   kde::IterPlan& it = c->iter;
   it.clear();
-  it.cols.assign(1, kde::ColDesc());
+  // column table: the column at 0; with tile pruning its near-tile and
+  // pruned-sweep descriptors at 1 and 2
+  it.cols.assign(p.prune ? 3 : 1, kde::ColDesc());
   kde::ColDesc d;
   kde::bind_column(p, j->block, nullptr, j->st, d);
   it.cols[0] = d;
+  if (p.lscv && p.prune) kde::prune_descs(p, d, it.cols[1], it.cols[2]);
   double left = max_evals;
   bool first = true;
   if (!j->stats_done) {
@@ -195,9 +198,11 @@ kde_status kde_job_run(kde_job* j, double max_evals, int* done_out) {
   if (p.lscv && !j->lscv_done && (!p.plugin || j->plugin_done || left > 0.0)) {
     if (!j->prep_done) {
       it.ids_lscv_prep.push_back(0);
+      if (p.prune) kde::add_prune_setup(p, d, 0, 1, it);
       j->prep_done = true;
     }
-    take(j->lscv_u, j->lscv_c, j->lscv_next, left, first, it.lscv_units, it.lscv_cost, j->remaining);
+    take(j->lscv_u, j->lscv_c, j->lscv_next, left, first, p.prune ? it.prune_units : it.lscv_units,
+         p.prune ? it.prune_cost : it.lscv_cost, j->remaining);
     if (j->lscv_next == j->lscv_u.size()) {
       kde::lscv_rows_of(p, d, it.lscv_rows);
       it.ids_lscv_final.push_back(0);
@@ -280,6 +285,7 @@ kde_status kde_job_checkpoint(kde_job* j, void* buf, uint64_t bytes) {
   h.cond = j->cond;
   h.prec = j->prec;
   h.grid_kind = p.grid_kind;
+  h.prune = p.prune;
   h.items_psi = (int64_t)p.psi_items.pairs.size();
   h.items_lscv = (int64_t)p.lscv_items.pairs.size();
   h.block_bytes = (int64_t)p.bytes;
@@ -318,7 +324,7 @@ kde_status kde_job_resume(kde_job* j, const void* buf, uint64_t bytes) {
   const bool same = std::memcmp(h.magic, kMagic, sizeof(kMagic)) == 0 && h.version == kVersion && h.n == p.n &&
                     h.f64 == p.f64 && h.plugin == (int)p.plugin && h.lscv == (int)p.lscv && h.stages == p.stages &&
                     h.n_h == p.n_h && h.hc == j->hc && h.mfma == j->mfma && h.cond == j->cond &&
-                    h.prec == j->prec && h.grid_kind == p.grid_kind &&
+                    h.prec == j->prec && h.grid_kind == p.grid_kind && h.prune == (int)p.prune &&
                     h.items_psi == (int64_t)p.psi_items.pairs.size() &&
                     h.items_lscv == (int64_t)p.lscv_items.pairs.size() && h.block_bytes == (int64_t)p.bytes;
   if (!same)

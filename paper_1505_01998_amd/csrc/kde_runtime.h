@@ -268,6 +268,12 @@ void bind_column(const ColPlan& p, char* block, const void* raw, DevState* st, C
 // descriptors (near tiles, pruned sweep) in the pass's column table, else -1.
 void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int id, const void* host_raw,
                      IterPlan& it, int extra_id = -1);
+// Tile pruning: the two extra descriptors of a pruned column (near tiles:
+// sorted copy and near-tile slab; pruned sweep: sorted copy and main slab),
+// and the column's set-up in a pass (sort, near-tile units and rows, cut
+// preparation), with the descriptors at it.cols[extra_id], [extra_id + 1].
+void prune_descs(const ColPlan& p, const ColDesc& d, ColDesc& nd, ColDesc& sd);
+void add_prune_setup(const ColPlan& p, const ColDesc& d, int id, int extra_id, IterPlan& it);
 // Pieces used by the server to schedule a column's work over several passes.
 void psi_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost);
 void lscv_units_of(const ColPlan& p, int id, std::vector<Unit>& u, std::vector<UnitCost>& cost);

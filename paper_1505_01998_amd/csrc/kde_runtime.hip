@@ -356,6 +356,34 @@ void lscv_rows_of(const ColPlan& p, const ColDesc& d, std::vector<RowDesc>& rows
   for (int r = 0; r < 2 * p.n_h; ++r) rows.push_back(RowDesc{d.part + (size_t)r * m, d.sums + r, m, 0});
 }
 
+void prune_descs(const ColPlan& p, const ColDesc& d, ColDesc& nd, ColDesc& sd) {
+  nd = d;
+  sd = d;
+  float* xs = (float*)((char*)d.x32 - p.off_x32 + p.off_xs);
+  nd.x32 = sd.x32 = xs;
+  nd.part = (double*)((char*)d.x32 - p.off_x32 + p.off_near_part);
+  nd.n_items = (int)p.near_items.pairs.size();
+}
+
+void add_prune_setup(const ColPlan& p, const ColDesc& d, int id, int extra_id, IterPlan& it) {
+  ColDesc nd, sd;
+  prune_descs(p, d, nd, sd);
+  if ((int)it.cols.size() < extra_id + 2) it.cols.resize(extra_id + 2);
+  it.cols[extra_id] = nd;
+  it.cols[extra_id + 1] = sd;
+  it.sorts.push_back(SortJob{d.x32, sd.x32, p.n + kPad});
+  const int m = (int)p.near_items.pairs.size();
+  for (int r = 0; r < m; ++r)
+    for (int ch = 0; ch < p.n_chunks; ++ch) {
+      it.near_units.push_back(Unit{extra_id, p.near_items.row[r], p.near_items.jb[r], p.near_items.je[r], r, ch});
+      const int valid = std::min(p.hc, p.n_h - ch * p.hc);
+      it.near_cost.push_back(UnitCost{p.near_items.pairs[r], p.near_items.pairs[r] * valid});
+    }
+  for (int r = 0; r < 2 * p.n_h; ++r)
+    it.near_rows.push_back(RowDesc{nd.part + (size_t)r * m, d.near_sums + r, m, 0});
+  it.ids_prune.push_back(id);
+}
+
 void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int id, const void* host_raw,
                      IterPlan& it, int extra_id) {
   if ((int)it.cols.size() <= id) it.cols.resize(id + 1);
@@ -379,26 +407,7 @@ void add_full_column(const kde_ctx* c, const ColPlan& p, const ColDesc& d, int i
       it.uploads.push_back(Upload{(void*)d.h_in, p.grid_h.data(), sizeof(double) * p.n_h});
     it.ids_lscv_prep.push_back(id);
     if (p.prune && extra_id >= 0) {
-      // near descriptor: sorted copy, near-tile slab; sweep descriptor: sorted copy, main slab
-      ColDesc nd = d, sd = d;
-      float* xs = (float*)((char*)d.x32 - p.off_x32 + p.off_xs);
-      nd.x32 = sd.x32 = xs;
-      nd.part = (double*)((char*)d.x32 - p.off_x32 + p.off_near_part);
-      nd.n_items = (int)p.near_items.pairs.size();
-      if ((int)it.cols.size() < extra_id + 2) it.cols.resize(extra_id + 2);
-      it.cols[extra_id] = nd;
-      it.cols[extra_id + 1] = sd;
-      it.sorts.push_back(SortJob{d.x32, xs, p.n + kPad});
-      const int m = (int)p.near_items.pairs.size();
-      for (int r = 0; r < m; ++r)
-        for (int ch = 0; ch < p.n_chunks; ++ch) {
-          it.near_units.push_back(Unit{extra_id, p.near_items.row[r], p.near_items.jb[r], p.near_items.je[r], r, ch});
-          const int valid = std::min(p.hc, p.n_h - ch * p.hc);
-          it.near_cost.push_back(UnitCost{p.near_items.pairs[r], p.near_items.pairs[r] * valid});
-        }
-      for (int r = 0; r < 2 * p.n_h; ++r)
-        it.near_rows.push_back(RowDesc{nd.part + (size_t)r * m, d.near_sums + r, m, 0});
-      it.ids_prune.push_back(id);
+      add_prune_setup(p, d, id, extra_id, it);
       lscv_units_of(p, extra_id + 1, it.prune_units, it.prune_cost);
     } else {
       lscv_units_of(p, id, it.lscv_units, it.lscv_cost);
@@ -617,10 +626,12 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
   // LSCV
   const int hc = all64 ? 8 : c->job_hc;
   kde::launch_lscv_prep(st, cols, ids(L.o_lp), (int)it.ids_lscv_prep.size(), hc);
-  if (!it.sorts.empty()) {
-    // tile pruning: sort, near-tile lower bounds, cut distances
-    for (const SortJob& j : it.sorts)
-      KDE_HIP_TRY(c, kde::sort_keys(c->sort_tmp.p, L.sort_tmp, j.in, j.out, j.count, st));
+  // tile pruning: sort, near-tile lower bounds and cut distances of the
+  // columns whose LSCV work starts in this pass, then the pruned units (a
+  // served column's pruned units may span several passes)
+  for (const SortJob& j : it.sorts)
+    KDE_HIP_TRY(c, kde::sort_keys(c->sort_tmp.p, L.sort_tmp, j.in, j.out, j.count, st));
+  if (!it.near_units.empty()) {
     const Unit* nu = (const Unit*)(d + L.o_nu);
     s = for_each_launch(c, it.near_cost, false, [&](int u0, int cnt, double) -> kde_status {
       kde::launch_lscv_units(st, hc, 0, 0, 0, cols, nu, u0, cnt);
@@ -629,6 +640,8 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
     if (s) return s;
     kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_nr), (int)it.near_rows.size());
     kde::launch_lscv_prune_prep(st, cols, ids(L.o_pp), (int)it.ids_prune.size(), hc, kPruneEps);
+  }
+  if (!it.prune_units.empty()) {
     const Unit* pru = (const Unit*)(d + L.o_pu);
     s = for_each_launch(c, it.prune_cost, false, [&](int u0, int cnt, double evals) -> kde_status {
       kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};

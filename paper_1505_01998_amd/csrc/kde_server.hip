@@ -74,6 +74,9 @@ struct Server {
   DevBuf<DevState> st;
   DevState* h_st = nullptr;
   IterPlan it;
+  // column table of a pass: slot s at s; with tile pruning, its near-tile and
+  // pruned-sweep descriptors at max_slots + 2 s and max_slots + 2 s + 1
+  int extra_id(int slot) const { return max_slots + 2 * slot; }
   void loop();
 };
 
@@ -150,7 +153,8 @@ void Server::loop() {
       init_state(r->plan, ctx->opt_fp64_kappa, h_st[r->slot]);
       (void)hipMemcpyAsync(st.p + r->slot, h_st + r->slot, sizeof(DevState), hipMemcpyHostToDevice, ctx->stream);
       psi_units_of(r->plan, r->slot, r->psi_u, r->psi_c);
-      lscv_units_of(r->plan, r->slot, r->lscv_u, r->lscv_c);
+      // a pruned column's sweep units name its pruned-sweep descriptor
+      lscv_units_of(r->plan, r->plan.prune ? extra_id(r->slot) + 1 : r->slot, r->lscv_u, r->lscv_c);
       r->stage = r->plan.stages == 3 ? 0 : 1;
       r->remaining = 0.0;
       for (const UnitCost& u : r->psi_c) r->remaining += u.evals * (3 - r->stage);
@@ -162,7 +166,7 @@ void Server::loop() {
     // with aging (time constant tau) a request's remaining work counts as
     // remaining / (1 + waited / tau), so long-waiting large requests move up
     it.clear();
-    it.cols.assign(max_slots, ColDesc());
+    it.cols.assign(3 * (size_t)max_slots, ColDesc());
     {
       const double now = now_s(), tau = ctx->opt_serve_aging_s;
       for (auto& r : active) r->key = tau > 0.0 ? r->remaining / (1.0 + (now - r->t_submit) / tau) : r->remaining;
@@ -187,6 +191,8 @@ void Server::loop() {
       ColDesc d;
       bind_column(p, r->block, r->dev_x, st.p + r->slot, d);
       it.cols[r->slot] = d;
+      if (p.lscv && p.prune && r->prep_done && !r->lscv_done)
+        prune_descs(p, d, it.cols[extra_id(r->slot)], it.cols[extra_id(r->slot) + 1]);
       if (!r->stats_done) {
         if (p.raw_in_block) it.uploads.push_back(Upload{(void*)d.raw, r->host_x.data(), p.raw_bytes});
         if (p.lscv && p.grid_kind == KDE_GRID_EXPLICIT)
@@ -217,9 +223,11 @@ void Server::loop() {
       if (p.lscv && !r->lscv_done) {
         if (!r->prep_done) {
           it.ids_lscv_prep.push_back(r->slot);
+          if (p.prune) add_prune_setup(p, d, r->slot, extra_id(r->slot), it);
           r->prep_done = true;
         }
-        take_units(r->lscv_u, r->lscv_c, r->lscv_next, left, first, it.lscv_units, it.lscv_cost, r->remaining);
+        take_units(r->lscv_u, r->lscv_c, r->lscv_next, left, first, p.prune ? it.prune_units : it.lscv_units,
+                   p.prune ? it.prune_cost : it.lscv_cost, r->remaining);
         first = false;
         if (r->lscv_next == r->lscv_u.size()) {
           lscv_rows_of(p, d, it.lscv_rows);
@@ -334,7 +342,6 @@ kde_status kde_server_start(kde_ctx* c, uint64_t hbm_budget_bytes, int32_t max_s
   if (c->server && c->server->running) return fail(c, KDE_E_BUSY, "a server is already running");
   if (max_slots < 1 || max_slots > KDE_MAX_BATCH || hbm_budget_bytes == 0)
     return fail(c, KDE_E_INVAL, "max_slots must be in [1, KDE_MAX_BATCH] and the budget > 0");
-  if (c->opt_prune) return fail(c, KDE_E_INVAL, "tile pruning (option prune) is for synchronous calls; turn it off");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   c->server.reset();
   // served requests run the LSCV variant the options name (the variant does

@@ -116,10 +116,6 @@ def test_resume_refuses_foreign_checkpoints(kde):
                 j4.resume(ck)
             assert e.value.status == kde.KDE_E_INVAL
     with kde.Context(0) as c:
-        c.set_option("prune", 1)
-        with pytest.raises(kde.KdeError) as e:
-            kde.Job(c, reqs[1])
-        assert e.value.status == kde.KDE_E_INVAL
         with pytest.raises(kde.KdeError) as e:
             kde.Job(c, kde.Request(np.array([1.0]), kde.KDE_METHOD_ROT))
         assert e.value.status == kde.KDE_E_INVAL

@@ -93,12 +93,60 @@ def test_pruned_batch_results_equal_pruned_alone(kde):
         assert np.array_equal(a.g, b.g) and a.k_lscv == b.k_lscv and a.lscv_evals == b.lscv_evals
 
 
-def test_prune_refused_by_the_server(kde):
-    with kde.Context(0) as c:
-        c.set_option("prune", 1)
-        with pytest.raises(kde.KdeError) as e:
-            c.server_start(1 << 30, 4)
-        assert e.value.status == kde.KDE_E_INVAL
+def _same_result(r, a):
+    assert r.status == a.status == 0
+    assert [r.h_rot, r.h_plugin, r.h_lscv, r.k_lscv] == [a.h_rot, a.h_plugin, a.h_lscv, a.k_lscv]
+    assert np.array_equal(r.g, a.g) and np.array_equal(r.gscale, a.gscale)
+    assert r.lscv_evals == a.lscv_evals and r.lscv_evals_dense == a.lscv_evals_dense
+
+
+def test_pruned_served_and_job_results_equal_pruned_batch(kde):
+    """With the prune option the sort, near tiles and cuts of a column run in
+    the server iteration (or job slice) where its LSCV work starts, and its
+    pruned sweep is split over later ones: results and the count of
+    evaluations performed are bitwise those of the pruned batch.  A pruned
+    job's checkpoint resumes in another pruned job, not in a dense one."""
+    A = kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV
+    reqs = [kde.Request(workloads.draw(f, 20000 + 9001 * k, 80 + k, np.float32), A, 3, workloads.BATCH_GRID)
+            for k, f in enumerate(workloads.BATCH_FAMILIES)]
+    with kde.Context(0) as pr, kde.Context(0) as srv:
+        pr.set_option("prune", 1)
+        alone = [pr.batch([r])[0] for r in reqs]
+        srv.set_option("prune", 1)
+        srv.set_option("serve_iter_evals", 1_000_000_000)
+        srv.server_start(8 << 30, 4)
+        tickets = [srv.submit(r) for r in reqs]
+        served = [srv.wait(t, timeout_s=120) for t in tickets]
+        srv.server_stop()
+        sliced = []
+        for r in reqs[:2]:
+            with kde.Job(pr, r) as job:
+                _, total, _ = job.progress()
+                slices = 0
+                while not job.run(total / 9):
+                    slices += 1
+                assert slices >= 5
+                sliced.append(job.result())
+        with kde.Job(pr, reqs[2]) as job:
+            _, total, _ = job.progress()
+            job.run(0.6 * total)
+            assert not job.progress()[2]
+            ck = job.checkpoint()
+        with kde.Job(srv, reqs[2]) as job2:
+            job2.resume(ck)
+            resumed = job2.run_to_end(total / 4)
+    with kde.Context(0) as dense:
+        with kde.Job(dense, reqs[2]) as j3:
+            with pytest.raises(kde.KdeError) as e:
+                j3.resume(ck)
+            assert e.value.status == kde.KDE_E_INVAL
+    assert any(a.lscv_evals < 0.9 * a.lscv_evals_dense for a in alone)
+    for r, a in zip(served, alone):
+        _same_result(r, a)
+    for r, a in zip(sliced, alone[:2]):
+        _same_result(r, a)
+    _same_result(resumed, alone[2])
+    print("performed fractions: " + ", ".join(f"{a.lscv_evals / a.lscv_evals_dense:.3f}" for a in alone))
 
 
 def test_search_with_pruning_per_step(kde):
