@@ -50,9 +50,9 @@ PLANNER_BEGIN, PLANNER_END = "// ---- work items", "size_t take("
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32<16>",
-    "sources_sha256": "50bfae7b5352505104a7ae70d6b189d1ad7d75e5dcff89e2af3bb9e45491bbf8",
-    "fetch_bytes": 2.6881e+07,
-    "write_bytes": 8.5992e+06,
+    "sources_sha256": "1a3baaa8959cf84243d22db0754de15c6312815fcecb9b21277b629894f3ecf6",
+    "fetch_bytes": 2.6875e+07,
+    "write_bytes": 8.5991e+06,
 }
 
 
@@ -438,6 +438,9 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--aging-ms", type=int, default=0, help="served: aging time constant of the SRPT order (0 = off)")
+    ap.add_argument("--ceiling", type=int, default=1,
+                    help="after the timed steps, measure the LSCV kernel's steady-state rate and the ceiling of its "
+                         "inner loop (0 = skip, e.g. under counter collection)")
     ap.add_argument("--iter-evals", type=float, default=0,
                     help="served: pair-term evaluations per server iteration (0 = the library's default)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
@@ -533,6 +536,14 @@ def main():
     launches, ms, evals_k = ctx.kernel_time("lscv_pairs")
     p_launches, p_ms, p_evals = ctx.kernel_time("psi_pairs")
     kernel = _lscv_kernel(ctx, args, n, n_h)
+    steady = ceiling = None
+    if args.ceiling and args.precision == "mixed" and args.prune <= 0 and args.mfma <= 0 and args.autotune <= 0:
+        # outside the timed region: the same kernel's steady-state rate (the
+        # tuner's trial: launches of B and 2B identical units, differenced)
+        # and the ceiling of its inner loop run from one LDS tile
+        hc = args.hc if args.hc > 0 else 16
+        steady = ctx.autotune(n, n_h)[1][hc]
+        ceiling = ctx.lscv_ceiling(hc)
     ctx.close()
 
     ms_step = dt * 1e3 / args.steps
@@ -567,6 +578,9 @@ def main():
             "avg_launch_ms": ms / max(launches, 1),
             "evals_per_launch": evals_k / max(launches, 1),
             "fp32_flop_frac": achieved * LSCV_FLOP_PER_EVAL / (FP32_PEAK_TFLOPS * 1e12),
+            "steady_state": None if steady is None else steady / 1e12,
+            "inner_loop_ceiling": None if ceiling is None else ceiling / 1e12,
+            "frac_of_inner_loop_ceiling": None if ceiling is None else achieved / ceiling,
         },
         "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals},
         "result": {"h_plugin": h_pi, "h_lscv": float(w.grid[int(np.argmin(g))]), "k_lscv": int(np.argmin(g))},

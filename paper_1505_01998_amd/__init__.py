@@ -52,7 +52,7 @@ EXPORTS = (
     "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md", "kde_lscv_H_eval", "kde_bw_lscv_H",
     "kde_density_H", "kde_range_aggregates_2d", "kde_cancel", "kde_job_create", "kde_job_run",
     "kde_job_progress", "kde_job_result", "kde_job_checkpoint_bytes", "kde_job_checkpoint", "kde_job_resume",
-    "kde_job_destroy",
+    "kde_job_destroy", "kde_lscv_ceiling",
 )
 
 
@@ -178,6 +178,7 @@ def _load():
     lib.kde_job_destroy.argtypes = [P]
     lib.kde_job_destroy.restype = None
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
+    lib.kde_lscv_ceiling.argtypes = [P, I32, PD]
     lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_md.argtypes = [P, kde_matrix, PD, I32, PD, ctypes.POINTER(I32)]
@@ -453,6 +454,14 @@ def kde_autotune(ctx, n: int, n_h: int):
     t = kde_tune_info()
     _check(ctx, lib.kde_autotune(ctx, int(n), int(n_h), ctypes.byref(t)))
     return t.hc, {8: t.evals_per_s[0], 16: t.evals_per_s[1], 32: t.evals_per_s[2]}
+
+
+def kde_lscv_ceiling(ctx, hc: int = 16) -> float:
+    """Pair-term evaluations per second of the LSCV sweep's inner loop run
+    from one LDS tile (no staging, barriers, masks or partial sums)."""
+    r = ctypes.c_double()
+    _check(ctx, lib.kde_lscv_ceiling(ctx, int(hc), ctypes.byref(r)))
+    return r.value
 
 
 def kde_bw_rot(ctx, x) -> float:
@@ -806,6 +815,9 @@ class Context:
 
     def autotune(self, n, n_h):
         return kde_autotune(self.ctx, n, n_h)
+
+    def lscv_ceiling(self, hc=16):
+        return kde_lscv_ceiling(self.ctx, hc)
 
     def graph_stats(self):
         return kde_ctx_graph_stats(self.ctx)

@@ -120,6 +120,9 @@ void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColD
 // Tile pruning: per column, the cut distance of every bandwidth chunk from
 // the near-tile sums (relative bound eps on every skipped share).
 void launch_lscv_prune_prep(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int hc, double eps);
+// The sweep's inner loop over one LDS tile (x: kBJ samples, c32: hc
+// coefficients), reps times per block; out: blocks x 4 doubles.
+void launch_lscv_ceiling(hipStream_t s, int hc, const float* x, const float* c32, int reps, double* out, int blocks);
 void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, int prune, const ColDesc* cols, const Unit* units,
                        int u0, int n_units);
 void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows);

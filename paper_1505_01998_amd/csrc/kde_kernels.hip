@@ -572,6 +572,34 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __re
   }
 }
 
+// Ceiling of the sweep's inner loop on the part: lscv_run<HC, false> over one
+// LDS tile of kBJ samples staged once, `reps` times per block, with no further
+// staging, barriers, masks or partial-sum writes (each wave stores one sum so
+// that nothing is dropped).  Evaluations per launch:
+// blocks x kThreads x reps x kBJ x HC.
+template <int HC>
+__global__ __launch_bounds__(kThreads) void k_lscv_ceiling(const float* __restrict__ x, const float* __restrict__ c32,
+                                                           int reps, double* __restrict__ out) {
+  __shared__ float4 tile[kBJ / 4];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x)[q];
+  __syncthreads();
+  const float xi = x[tid] + 0.5f;
+  float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
+#pragma unroll
+  for (int k = 0; k < HC; ++k) {
+    ck[k] = c32[k];
+    a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
+  }
+  for (int r = 0; r < reps; ++r)
+    for (int js = 0; js < kBJ; js += kRun) lscv_run<HC, false>(tile, js, js, xi, 0, ck, a1, c1, a2, c2);
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < HC; ++k) v += ((double)a1[k] - (double)c1[k]) + ((double)a2[k] - (double)c2[k]);
+  v = wave_sum(v);
+  if ((tid & 63) == 0) out[(int64_t)blockIdx.x * (kThreads / 64) + (tid >> 6)] = v;
+}
+
 // Tile pruning on sorted samples: the same sweep over a column sorted
 // ascending, whose j-tiles therefore lie at growing distance from the unit's
 // row of i.  A uniform scan of the tiles' first samples finds the first tile
@@ -1062,6 +1090,15 @@ void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, int prune, cons
       case 32: k_lscv_units_f32<32><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
       default: k_lscv_units_f32<16><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
     }
+  }
+}
+
+void launch_lscv_ceiling(hipStream_t s, int hc, const float* x, const float* c32, int reps, double* out, int blocks) {
+  if (blocks <= 0) return;
+  switch (hc) {
+    case 8: k_lscv_ceiling<8><<<blocks, kThreads, 0, s>>>(x, c32, reps, out); break;
+    case 32: k_lscv_ceiling<32><<<blocks, kThreads, 0, s>>>(x, c32, reps, out); break;
+    default: k_lscv_ceiling<16><<<blocks, kThreads, 0, s>>>(x, c32, reps, out); break;
   }
 }
 

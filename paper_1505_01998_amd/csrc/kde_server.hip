@@ -74,9 +74,11 @@ struct Server {
   DevBuf<DevState> st;
   DevState* h_st = nullptr;
   IterPlan it;
-  // column table of a pass: slot s at s; with tile pruning, its near-tile and
-  // pruned-sweep descriptors at max_slots + 2 s and max_slots + 2 s + 1
-  int extra_id(int slot) const { return max_slots + 2 * slot; }
+  // column table of a pass: slot s at s, for the slots below `top` (one past
+  // the highest resident slot); with tile pruning, slot s's near-tile and
+  // pruned-sweep descriptors at top + 2 s and top + 2 s + 1
+  int top = 0;
+  int extra_id(int slot) const { return top + 2 * slot; }
   void loop();
 };
 
@@ -92,11 +94,12 @@ void finish_with(Server& s, const std::shared_ptr<SrvReq>& r, kde_status st) {
 }
 
 // Adds units [next, end) of one list to the pass while the budget lasts; at
-// least one unit when `force`.
+// least one unit when `force`.  col >= 0 replaces the units' descriptor index.
 void take_units(const std::vector<Unit>& u, const std::vector<UnitCost>& cu, size_t& next, double& budget,
-                bool force, std::vector<Unit>& out, std::vector<UnitCost>& out_c, double& remaining) {
+                bool force, std::vector<Unit>& out, std::vector<UnitCost>& out_c, double& remaining, int col = -1) {
   while (next < u.size() && (budget > 0.0 || force)) {
     out.push_back(u[next]);
+    if (col >= 0) out.back().col = col;
     out_c.push_back(cu[next]);
     budget -= cu[next].evals;
     remaining -= cu[next].evals;
@@ -153,8 +156,7 @@ void Server::loop() {
       init_state(r->plan, ctx->opt_fp64_kappa, h_st[r->slot]);
       (void)hipMemcpyAsync(st.p + r->slot, h_st + r->slot, sizeof(DevState), hipMemcpyHostToDevice, ctx->stream);
       psi_units_of(r->plan, r->slot, r->psi_u, r->psi_c);
-      // a pruned column's sweep units name its pruned-sweep descriptor
-      lscv_units_of(r->plan, r->plan.prune ? extra_id(r->slot) + 1 : r->slot, r->lscv_u, r->lscv_c);
+      lscv_units_of(r->plan, r->slot, r->lscv_u, r->lscv_c);
       r->stage = r->plan.stages == 3 ? 0 : 1;
       r->remaining = 0.0;
       for (const UnitCost& u : r->psi_c) r->remaining += u.evals * (3 - r->stage);
@@ -166,7 +168,9 @@ void Server::loop() {
     // with aging (time constant tau) a request's remaining work counts as
     // remaining / (1 + waited / tau), so long-waiting large requests move up
     it.clear();
-    it.cols.assign(3 * (size_t)max_slots, ColDesc());
+    top = 0;
+    for (auto& r : active) top = std::max(top, r->slot + 1);
+    it.cols.assign((ctx->opt_prune ? 3 : 1) * (size_t)top, ColDesc());
     {
       const double now = now_s(), tau = ctx->opt_serve_aging_s;
       for (auto& r : active) r->key = tau > 0.0 ? r->remaining / (1.0 + (now - r->t_submit) / tau) : r->remaining;
@@ -226,8 +230,9 @@ void Server::loop() {
           if (p.prune) add_prune_setup(p, d, r->slot, extra_id(r->slot), it);
           r->prep_done = true;
         }
+        // a pruned column's sweep units name its pruned-sweep descriptor
         take_units(r->lscv_u, r->lscv_c, r->lscv_next, left, first, p.prune ? it.prune_units : it.lscv_units,
-                   p.prune ? it.prune_cost : it.lscv_cost, r->remaining);
+                   p.prune ? it.prune_cost : it.lscv_cost, r->remaining, p.prune ? extra_id(r->slot) + 1 : -1);
         first = false;
         if (r->lscv_next == r->lscv_u.size()) {
           lscv_rows_of(p, d, it.lscv_rows);

@@ -186,3 +186,54 @@ extern "C" kde_status kde_autotune(kde_ctx* c, int64_t n, int32_t n_h, kde_tune_
   }
   return KDE_OK;
 }
+
+// The sweep's inner loop from one LDS tile (no staging, barriers, masks or
+// partial sums): samples spread over [0, 4), coefficients of h log-spaced over
+// [0.01, 1], so the exponentials cover the same range as a real grid.  A
+// warm-up launch, then one launch of kCeilReps repetitions timed by events.
+extern "C" kde_status kde_lscv_ceiling(kde_ctx* c, int32_t hc, double* evals_per_s) {
+  constexpr int kCeilBlocks = 8192, kCeilReps = 64;
+  if (!c || !evals_per_s) return KDE_E_INVAL;
+  if (hc != 8 && hc != 16 && hc != 32) return kde::fail(c, KDE_E_INVAL, "hc must be 8, 16 or 32");
+  if (c->server && kde::server_running(c->server.get()))
+    return kde::fail(c, KDE_E_BUSY, "a server is running on this context");
+  if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  std::vector<float> hx(kde::kBJ), hcf(32);
+  for (int j = 0; j < kde::kBJ; ++j) hx[j] = 4.0f * (float)j / (float)kde::kBJ;
+  for (int k = 0; k < 32; ++k) {
+    const double h = std::exp(std::log(0.01) + std::log(100.0) * k / 31.0);
+    hcf[k] = (float)(-1.4426950408889634 / (4.0 * h * h));
+  }
+  const size_t o_x = 0, o_c = 4 * (size_t)kde::kBJ, o_out = o_c + 4 * 32;
+  const size_t bytes = o_out + sizeof(double) * 4 * (size_t)kCeilBlocks;
+  kde_status s;
+  if ((s = kde::ensure(c, c->tune_buf, bytes))) return s;
+  char* b = c->tune_buf.p;
+  KDE_HIP_TRY(c, hipMemcpyAsync(b + o_x, hx.data(), 4 * hx.size(), hipMemcpyHostToDevice, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(b + o_c, hcf.data(), 4 * hcf.size(), hipMemcpyHostToDevice, c->stream));
+  const float* x = (const float*)(b + o_x);
+  const float* cf = (const float*)(b + o_c);
+  double* out = (double*)(b + o_out);
+  hipEvent_t ev[2];
+  int made = 0;
+  hipError_t he = hipSuccess;
+  for (; made < 2 && he == hipSuccess; ++made) he = hipEventCreate(&ev[made]);
+  if (he != hipSuccess) --made;
+  float ms = 0.f;
+  if (he == hipSuccess) {
+    kde::launch_lscv_ceiling(c->stream, hc, x, cf, 1, out, kCeilBlocks);
+    he = hipEventRecord(ev[0], c->stream);
+  }
+  if (he == hipSuccess) {
+    kde::launch_lscv_ceiling(c->stream, hc, x, cf, kCeilReps, out, kCeilBlocks);
+    he = hipEventRecord(ev[1], c->stream);
+  }
+  if (he == hipSuccess) he = hipGetLastError();
+  if (he == hipSuccess) he = hipEventSynchronize(ev[1]);
+  if (he == hipSuccess) he = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+  if (he != hipSuccess) return kde::fail(c, KDE_E_DEVICE, std::string("ceiling trial: ") + hipGetErrorString(he));
+  const double evals = (double)kCeilBlocks * kde::kThreads * kCeilReps * kde::kBJ * hc;
+  *evals_per_s = ms > 0.f ? evals / (ms * 1e-3) : 0.0;
+  return KDE_OK;
+}

@@ -87,3 +87,30 @@ def test_autotuned_jobs_equal_default(kde):
         assert a.h_lscv == b.h_lscv and a.h_plugin == b.h_plugin
         assert np.array_equal(a.g, b.g)
     assert hc in (8, 16, 32)
+
+
+def test_inner_loop_ceiling(kde):
+    """The inner loop run from one LDS tile bounds the sweep: the kernel's
+    steady-state rate (the tuner's differenced trial) stays within noise of
+    it, and a full sweep of a column is no faster."""
+    import time
+
+    x = workloads.draw("lognormal", 200_000, 9, np.float32)
+    grid = np.geomspace(0.002, 0.6, 64)
+    with kde.Context(0) as c:
+        ceil16 = c.lscv_ceiling(16)
+        ceil8 = c.lscv_ceiling(8)
+        _, rates = c.autotune(x.size, grid.size)
+        c.lscv_curve(x, grid)
+        t = time.perf_counter()
+        c.lscv_curve(x, grid)
+        dt = time.perf_counter() - t
+        for bad in (0, 12, 64):
+            with pytest.raises(kde.KdeError) as e:
+                c.lscv_ceiling(bad)
+            assert e.value.status == kde.KDE_E_INVAL
+    sweep = x.size * (x.size - 1) / 2 * grid.size / dt
+    assert ceil16 > 1e12 and ceil8 > 1e12
+    assert rates[16] <= 1.05 * ceil16 and sweep <= 1.05 * ceil16
+    print(f"inner-loop ceiling {ceil16:.3e} (hc 16), {ceil8:.3e} (hc 8); steady state {rates[16]:.3e}; "
+          f"sweep n=2e5 {sweep:.3e} evals/s")
