@@ -43,15 +43,15 @@ LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 # WRITE_SIZE passes, each scaled by the ratio the same counter shows for a
 # plain 1 GiB copy (fetch x2.0, write x1.0).  Valid only for the kernel
 # source they were taken on; reported as null once that source changes.
-# The kernels and the planner's work-item code (which sizes the units, and so
+# The kernels, their shared header and the planner's work-item code (which sizes the units, and so
 # the partial-sum writes per launch) decide the traffic.
-TRAFFIC_SOURCES = ("kde_kernels.hip", "kde_runtime.hip")
+TRAFFIC_SOURCES = ("kde_internal.h", "kde_kernels.hip", "kde_runtime.hip")
 PLANNER_BEGIN, PLANNER_END = "// ---- work items", "size_t take("
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32<16>",
-    "sources_sha256": "1a3baaa8959cf84243d22db0754de15c6312815fcecb9b21277b629894f3ecf6",
-    "fetch_bytes": 2.6875e+07,
+    "sources_sha256": "54f97a7fbab376e2ee898de726bf7fd84d802f5d2d4e2536f618a7cffa4fd30d",
+    "fetch_bytes": 2.6887e+07,
     "write_bytes": 8.5991e+06,
 }
 
@@ -550,7 +550,8 @@ def main():
     value = evals_step / (ms_step * 1e-3)
     achieved = evals_k / (ms * 1e-3)
     out = {
-        "metric": "pair-kernel evals/s (LSCV+plug-in, n=1M)",
+        "metric": "pair-kernel evals/s (LSCV+plug-in, n=1M)" if n == 1_000_000 else
+                  f"pair-kernel evals/s (LSCV+plug-in, n={n})",
         "value": value,
         "unit": "pair-evals/s",
         "n_gpus": 1,

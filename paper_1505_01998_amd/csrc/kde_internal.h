@@ -30,6 +30,40 @@ constexpr int kGridExplicit = 0;
 constexpr int kGridPaper = 1;    // linear over sigma * [h0/4, 4 h0]
 constexpr int kGridLogRot = 2;   // log-spaced over h_rot * [lo, hi]
 
+// e^x in FP64 for the pair loops (arguments <= 0: x = -D^2 c), by Cody and
+// Waite's argument reduction: k = nearest integer to x / ln 2, r = x - k ln 2
+// with ln 2 split into a head of 29 significant bits (k * head is exact for
+// |k| < 2^24, so x - k * head is exact) and a tail, |r| <= ln(2) / 2; then
+// the Taylor series of e^r to degree 13 (truncation below 5e-18 relative)
+// and the scaling by 2^k.  About 2 ulp.  Arguments below -1100 (and -inf)
+// are raised to -1100, which underflows to exactly 0; no NaN arrives here
+// (samples are finite, and masked pairs carry -inf).
+__device__ __forceinline__ double exp_cw(double x) {
+  constexpr double kInvLn2 = 1.4426950408889634;
+  constexpr double kLn2Head = 0x1.62e42ffp-1;         // ln 2 rounded to 29 bits
+  constexpr double kLn2Tail = -4.2009150726810846e-11;  // ln 2 - head
+  x = fmax(x, -1100.0);
+  const double k = rint(x * kInvLn2);
+  double r = __builtin_fma(-k, kLn2Head, x);
+  r = __builtin_fma(-k, kLn2Tail, r);
+  // 1 / j! for j = 13 .. 0
+  double p = 1.6059043836821613e-10;
+  p = __builtin_fma(p, r, 2.08767569878681e-09);
+  p = __builtin_fma(p, r, 2.505210838544172e-08);
+  p = __builtin_fma(p, r, 2.755731922398589e-07);
+  p = __builtin_fma(p, r, 2.7557319223985893e-06);
+  p = __builtin_fma(p, r, 2.48015873015873e-05);
+  p = __builtin_fma(p, r, 1.984126984126984e-04);
+  p = __builtin_fma(p, r, 1.388888888888889e-03);
+  p = __builtin_fma(p, r, 8.333333333333333e-03);
+  p = __builtin_fma(p, r, 4.1666666666666664e-02);
+  p = __builtin_fma(p, r, 0.16666666666666666);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
 // Device-resident state of one column of a job.  All scalar steps of the
 // method run on the device and read/write this struct, so a whole job is a
 // chain of kernels on one stream with one copy back at the end.

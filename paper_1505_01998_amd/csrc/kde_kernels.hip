@@ -392,7 +392,7 @@ __device__ __forceinline__ void psi_run64(const double* __restrict__ tile, int j
     double t = d * d;
     if (MASK) t = (jg + q > i) ? t : kInfD;
     const double w = fmin(t * ig2, (double)kWMax);
-    const double term = herm_w64<R>(w) * exp(t * cg);
+    const double term = herm_w64<R>(w) * exp_cw(t * cg);
     s += term;
     a += fabs(term);
   }
@@ -726,7 +726,7 @@ __device__ __forceinline__ void lscv_run64(const double* __restrict__ tile, int 
     if (MASK) t = (jg + q > i) ? t : kInfD;
 #pragma unroll
     for (int k = 0; k < HC; ++k) {
-      const double e = exp(t * ck[k]);
+      const double e = exp_cw(t * ck[k]);
       s1[k] += e;
       s2[k] = __builtin_fma(e, e, s2[k]);
     }

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_HZ_units_f64(const double* __restr
         const double dd = zi[a] - tile[a][q];
         s = fma(dd, dd, s);
       }
-      const double e = exp(-s);
+      const double e = exp_cw(-s);
       s1 += e;
       s2 = fma(e, e, s2);
     }

@@ -351,7 +351,7 @@ __global__ __launch_bounds__(kThreads) void k_md_units_f64(const double* __restr
       }
 #pragma unroll
       for (int k = 0; k < HC; ++k) {
-        const double e = exp(s * ck[k]);
+        const double e = exp_cw(s * ck[k]);
         s1[k] += e;
         s2[k] = fma(e, e, s2[k]);
       }

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_density_f64(const ColDesc* __restr
     __syncthreads();
     for (int k = 0; k < kBJ; ++k) {
       const double d = xq - tile[k];
-      s += exp(d * d * cd);
+      s += exp_cw(d * d * cd);
     }
   }
   if (qi < m) part[(int64_t)qi * pieces + blockIdx.y] = s;

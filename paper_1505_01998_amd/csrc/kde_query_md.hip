@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_dq_units(const double* __restrict_
           d2 = fma(t, t, d2);
         }
         if (F64)
-          s64 += exp(-0.5 * d2);
+          s64 += exp_cw(-0.5 * d2);
         else
           run += __builtin_amdgcn_exp2f((float)(-0.5 * kLog2ED * d2));
       }
