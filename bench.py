@@ -36,6 +36,11 @@ import workloads  # noqa: E402
 CUS, CLOCK_HZ = 256, 2.4e9
 VALU_LANES, TRANS_LANES = 128, 32
 LSCV_PEAK = 1.0 / (3.0 / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ))  # 11.23e12/s
+# The psi pass at the same issue model: per pair 12, 11, 10 plain FP32
+# instructions for r = 8, 6, 4 (sub, mul, mul, min, mul, r/2 Horner, mul,
+# add, add) and one exp2; three stages of equal pair count, so the bound of
+# the pass is their harmonic mean (5.22e12 pairs/s).
+PSI_PEAK = 3.0 / sum(p / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ) for p in (12, 11, 10))
 FP32_PEAK_TFLOPS = 157.3
 LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 
@@ -583,7 +588,9 @@ def main():
             "inner_loop_ceiling": None if ceiling is None else ceiling / 1e12,
             "frac_of_inner_loop_ceiling": None if ceiling is None else achieved / ceiling,
         },
-        "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals},
+        "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals,
+                       "achieved": p_evals / (p_ms * 1e-3) / 1e12 if p_ms > 0 else None, "peak": PSI_PEAK / 1e12,
+                       "unit": "Tpair/s", "frac": p_evals / (p_ms * 1e-3) / PSI_PEAK if p_ms > 0 else None},
         "result": {"h_plugin": h_pi, "h_lscv": float(w.grid[int(np.argmin(g))]), "k_lscv": int(np.argmin(g))},
         "prune": None if args.prune <= 0 else {
             "performed_frac": performed[-1],
