@@ -39,7 +39,7 @@ LSCV_PEAK = 1.0 / (3.0 / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANE
 # The psi pass at the same issue model: per pair 12, 11, 10 plain FP32
 # instructions for r = 8, 6, 4 (sub, mul, mul, min, mul, r/2 Horner, mul,
 # add, add) and one exp2; three stages of equal pair count, so the bound of
-# the pass is their harmonic mean (5.22e12 pairs/s).
+# the pass is their harmonic mean (5.24e12 pairs/s).
 PSI_PEAK = 3.0 / sum(p / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ) for p in (12, 11, 10))
 FP32_PEAK_TFLOPS = 157.3
 LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
