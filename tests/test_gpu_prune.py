@@ -163,3 +163,28 @@ def test_search_with_pruning_per_step(kde):
     assert abs(infop["g"] - infod["g"]) <= 1e-7 * abs(infod["g"])
     assert abs(hp / hd - 1.0) <= 1e-2
     assert abs(infop["iterations"] - infod["iterations"]) <= 2
+
+
+def test_pruned_degenerate_and_smallest_columns(kde):
+    """With pruning on, a column of zero spread ends DEGENERATE and a
+    two-sample column finishes, alone, in a batch, served and as a job."""
+    L = kde.KDE_METHOD_LSCV
+    reqs = [kde.Request(np.full(5000, 2.5, np.float32), L, 3, workloads.BATCH_GRID),
+            kde.Request(np.array([0.0, 1.0], np.float32), L, 3, np.geomspace(0.1, 2.0, 8)),
+            kde.Request(workloads.draw("bimodal", 7001, 90, np.float32), L, 3, workloads.BATCH_GRID)]
+    with kde.Context(0) as pr:
+        pr.set_option("prune", 1)
+        alone = [pr.batch([r])[0] for r in reqs]
+        batch = pr.batch(reqs)
+        jobs = []
+        for r in reqs:
+            with kde.Job(pr, r) as job:
+                jobs.append(job.run_to_end(1e8))
+        pr.server_start(1 << 30, 4)
+        served = [pr.wait(pr.submit(r), timeout_s=60) for r in reqs]
+        pr.server_stop()
+    assert [a.status for a in alone] == [kde.KDE_E_DEGENERATE, kde.KDE_OK, kde.KDE_OK]
+    for got in (batch, jobs, served):
+        assert [g.status for g in got] == [a.status for a in alone]
+        for g, a in zip(got[1:], alone[1:]):
+            assert np.array_equal(g.g, a.g) and g.k_lscv == a.k_lscv and g.lscv_evals == a.lscv_evals
