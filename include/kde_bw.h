@@ -196,8 +196,9 @@ kde_status kde_autotune(kde_ctx* ctx, int64_t n, int32_t n_h, kde_tune_info* out
  * tile staging, barriers, masks or partial-sum writes.  *evals_per_s
  * receives its pair-term evaluations per second (one ~0.1 s launch, timed
  * with events on the context's stream).  The rate bounds what the sweep can
- * reach with this instruction mix.  KDE_E_INVAL for hc other than 8, 16, 32;
- * KDE_E_BUSY while a server runs. */
+ * reach with this instruction mix.  It measures the mixed form's kernel
+ * whatever the context's precision.  KDE_E_INVAL for hc other than 8, 16,
+ * 32; KDE_E_BUSY while a server runs. */
 kde_status kde_lscv_ceiling(kde_ctx* ctx, int32_t hc, double* evals_per_s);
 
 /* Kernel timing.  While enabled, every launch of the pair kernels is bracketed
