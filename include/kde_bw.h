@@ -480,6 +480,22 @@ kde_status kde_bw_lscv_md(kde_ctx* ctx, kde_matrix x, const double* h_grid, int3
  * KDE_E_DEGENERATE when the sample covariance is singular. */
 kde_status kde_lscv_H_eval(kde_ctx* ctx, kde_matrix x, const double* H, int32_t m, double* g_out,
                            double* gscale_out);
+/* The same evaluation for a caller that evaluates g(H) many times over one
+ * sample (its own optimiser over H): kde_lscv_H_prepare stages the samples
+ * once (the moments, Sigma and its factor, the sphered working copy and the
+ * pass layout of kde_lscv_H_eval) into a device buffer owned by the handle,
+ * copying the samples in (host or device; the caller may free them on
+ * return); kde_lscv_H_eval_prepared then gives g and its scale at m matrices
+ * exactly as kde_lscv_H_eval does on the same sample, bitwise.  The handle
+ * keeps its context (and must be released before it) and the precision the
+ * context had at prepare: a later change of precision makes the evaluation
+ * return KDE_E_INVAL.  Errors as for kde_lscv_H_eval; KDE_E_BUSY while a
+ * server runs.  Calls with one handle must not overlap. */
+typedef struct kde_lscv_H_prep kde_lscv_H_prep;
+kde_status kde_lscv_H_prepare(kde_ctx* ctx, kde_matrix x, kde_lscv_H_prep** out);
+kde_status kde_lscv_H_eval_prepared(kde_lscv_H_prep* prep, const double* H, int32_t m, double* g_out,
+                                    double* gscale_out);
+void kde_lscv_H_release(kde_lscv_H_prep* prep);
 
 typedef struct {
   double g;          /* g(H_out) */

@@ -52,7 +52,7 @@ EXPORTS = (
     "kde_range_aggregates", "kde_lscv_md_curve", "kde_bw_lscv_md", "kde_lscv_H_eval", "kde_bw_lscv_H",
     "kde_density_H", "kde_range_aggregates_2d", "kde_cancel", "kde_job_create", "kde_job_run",
     "kde_job_progress", "kde_job_result", "kde_job_checkpoint_bytes", "kde_job_checkpoint", "kde_job_resume",
-    "kde_job_destroy", "kde_lscv_ceiling",
+    "kde_job_destroy", "kde_lscv_ceiling", "kde_lscv_H_prepare", "kde_lscv_H_eval_prepared", "kde_lscv_H_release",
 )
 
 
@@ -183,6 +183,9 @@ def _load():
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_md.argtypes = [P, kde_matrix, PD, I32, PD, ctypes.POINTER(I32)]
     lib.kde_lscv_H_eval.argtypes = [P, kde_matrix, PD, I32, PD, PD]
+    lib.kde_lscv_H_prepare.argtypes = [P, kde_matrix, ctypes.POINTER(ctypes.c_void_p)]
+    lib.kde_lscv_H_eval_prepared.argtypes = [ctypes.c_void_p, PD, I32, PD, PD]
+    lib.kde_lscv_H_release.argtypes = [ctypes.c_void_p]
     lib.kde_density_H.argtypes = [P, kde_matrix, PD, PD, I32, PD]
     lib.kde_range_aggregates_2d.argtypes = [P, kde_matrix, PD, PD, I32, PD, PD, PD, PD, PD]
     lib.kde_bw_lscv_H.argtypes = [P, kde_matrix, ctypes.c_double, ctypes.c_double, I32, PD,
@@ -195,8 +198,9 @@ def _load():
     lib.kde_plan_items.argtypes = [I64, I32, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                    ctypes.POINTER(I32), ctypes.POINTER(I32), PD]
     for name in EXPORTS:
-        if name not in ("kde_ctx_destroy", "kde_last_error"):
+        if name not in ("kde_ctx_destroy", "kde_last_error", "kde_job_destroy", "kde_lscv_H_release"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.kde_lscv_H_release.restype = None
     return lib
 
 
@@ -368,6 +372,61 @@ def kde_lscv_H_eval(ctx, x, H):
     _check(ctx, lib.kde_lscv_H_eval(ctx, m, _pd(Hs.ravel()), int(k), _pd(g), _pd(gs)))
     del keep
     return g, gs
+
+
+def _H_stack(H, d):
+    Hs = np.ascontiguousarray(np.asarray(H, np.float64))
+    if Hs.ndim == 2:
+        Hs = Hs[None]
+    if Hs.ndim != 3 or Hs.shape[1:] != (d, d):
+        raise ValueError("H must be m x d x d for d-dimensional samples")
+    return Hs
+
+
+class HPrep:
+    """A sample staged once for repeated LSCV_H evaluations
+    (kde_lscv_H_prepare / kde_lscv_H_eval_prepared / kde_lscv_H_release)."""
+
+    def __init__(self, ctx, x):
+        m, keep = make_matrix(x)
+        self.ctx, self.d = ctx, m.d
+        h = ctypes.c_void_p()
+        _check(ctx, lib.kde_lscv_H_prepare(ctx, m, ctypes.byref(h)))
+        del keep
+        self.handle = h
+
+    def eval(self, H):
+        """(g, gscale) at bandwidth matrices H (m x d x d, or one d x d)."""
+        Hs = _H_stack(H, self.d)
+        k = Hs.shape[0]
+        g, gs = np.empty(k, np.float64), np.empty(k, np.float64)
+        _check(self.ctx, lib.kde_lscv_H_eval_prepared(self.handle, _pd(Hs.ravel()), int(k), _pd(g), _pd(gs)))
+        return g, gs
+
+    def close(self):
+        if self.handle:
+            lib.kde_lscv_H_release(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def kde_lscv_H_prepare(ctx, x) -> HPrep:
+    """Stages x once for repeated LSCV_H evaluations."""
+    return HPrep(ctx, x)
+
+
+def kde_lscv_H_eval_prepared(prep: HPrep, H):
+    """(g, gscale) at bandwidth matrices H over a prepared sample."""
+    return prep.eval(H)
+
+
+def kde_lscv_H_release(prep: HPrep) -> None:
+    prep.close()
 
 
 def kde_density_H(ctx, x, H, points):
@@ -836,6 +895,9 @@ class Context:
 
     def lscv_H_eval(self, x, H):
         return kde_lscv_H_eval(self.ctx, x, H)
+
+    def lscv_H_prepare(self, x):
+        return HPrep(self.ctx, x)
 
     def bw_lscv_H(self, x, ftol=1e-10, xtol=1e-6, max_evals=2000):
         return kde_bw_lscv_H(self.ctx, x, ftol, xtol, max_evals)

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "kde_md.h"
@@ -371,7 +372,10 @@ int64_t h_seg(const kde_ctx* c, int64_t n) {
   return seg >= n ? 0 : seg;
 }
 
-kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
+// Stages the samples into `buf` (the context's workspace, or a prepared
+// handle's own buffer); with own_samples the samples are copied into it even
+// when they are on the device, so the staged state outlives the caller's.
+kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r, DevBuf<char>& buf, bool own_samples) {
   if (!x.data || x.n < 2 || x.n > KDE_MAX_N || x.d < 1 || x.d > KDE_MAX_D ||
       (x.dtype != KDE_F32 && x.dtype != KDE_F64))
     return fail(c, KDE_E_INVAL, "need a row-major n x d matrix, 2 <= n <= KDE_MAX_N, 1 <= d <= KDE_MAX_D");
@@ -398,7 +402,8 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
     at += al256(bytes);
     return o;
   };
-  const size_t o_raw = x.on_device ? 0 : take((size_t)n * d * esz);
+  const bool copy_raw = !x.on_device || own_samples;
+  const size_t o_raw = copy_raw ? take((size_t)n * d * esz) : 0;
   const size_t o_ps = take(8 * (size_t)kMdBlocks * KDE_MAX_D), o_nf = take(4 * (size_t)kMdBlocks),
                o_pc = take(8 * (size_t)kMdBlocks * KDE_MAX_D * KDE_MAX_D);
   r.o_st = take(sizeof(MdState));
@@ -414,17 +419,18 @@ kde_status h_stage(kde_ctx* c, const kde_matrix& x, HRun& r) {
   r.o_rows = take(sizeof(RowDesc) * 2 * (size_t)kHPass);
   r.o_hm = take(8 * (size_t)kHPass * KDE_MAX_D * KDE_MAX_D);
   kde_status s;
-  if ((s = ensure(c, c->mdbuf, at))) return s;
-  char* b = r.b = c->mdbuf.p;
+  if ((s = ensure(c, buf, at))) return s;
+  char* b = r.b = buf.p;
   double* part = (double*)(b + r.o_part);
   double* sums = (double*)(b + r.o_sums);
   std::vector<RowDesc> rows;
   for (int q = 0; q < 2 * kHPass; ++q) rows.push_back(RowDesc{part + (size_t)q * r.n_items, sums + q, r.n_items, 0});
   hipStream_t st = c->stream;
-  const void* raw = r.raw = x.on_device ? x.data : (const void*)(b + o_raw);
+  const void* raw = r.raw = copy_raw ? (const void*)(b + o_raw) : x.data;
   r.raw_f64 = x.dtype == KDE_F64;
-  if (!x.on_device)
-    KDE_HIP_TRY(c, hipMemcpyAsync(b + o_raw, x.data, (size_t)n * d * esz, hipMemcpyHostToDevice, st));
+  if (copy_raw)
+    KDE_HIP_TRY(c, hipMemcpyAsync(b + o_raw, x.data, (size_t)n * d * esz,
+                                  x.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_units, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice, st));
   KDE_HIP_TRY(c, hipMemcpyAsync(b + r.o_rows, rows.data(), sizeof(RowDesc) * rows.size(), hipMemcpyHostToDevice, st));
   MdState* dst = (MdState*)(b + r.o_st);
@@ -629,19 +635,75 @@ kde_status h_search(HRun& r, double ftol, double xtol, int max_evals, double* H_
 
 }  // namespace kde
 
+// A prepared sample for repeated g(H) evaluations: the staged, sphered
+// samples, Sigma and the pass layout, in a device buffer of the handle's own
+// (the caller's samples are copied in), so calls on the context in between
+// do not disturb it.
+struct kde_lscv_H_prep {
+  kde_ctx* c = nullptr;
+  kde::HRun r;
+  kde::DevBuf<char> buf;
+};
+
+namespace {
+
+kde_status check_H(kde_ctx* c, int d, const double* H, int32_t m) {
+  if (m < 1 || m > KDE_MAX_H_EVAL) return kde::fail(c, KDE_E_INVAL, "matrix count outside [1, KDE_MAX_H_EVAL]");
+  if (d >= 1 && d <= KDE_MAX_D)
+    for (int64_t q = 0; q < (int64_t)m * d * d; ++q)
+      if (!std::isfinite(H[q])) return kde::fail(c, KDE_E_INVAL, "bandwidth matrix holds a non-finite value");
+  return KDE_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+kde_status kde_lscv_H_prepare(kde_ctx* c, kde_matrix x, kde_lscv_H_prep** out) {
+  if (!c || !out) return KDE_E_INVAL;
+  *out = nullptr;
+  if (c->server && kde::server_running(c->server.get())) return kde::fail(c, KDE_E_BUSY, "a server is running");
+  if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  std::unique_ptr<kde_lscv_H_prep> p(new kde_lscv_H_prep());
+  p->c = c;
+  kde_status s = kde::h_stage(c, x, p->r, p->buf, true);
+  if (s) {
+    if (p->buf.p) (void)hipFree(p->buf.p);
+    return s;
+  }
+  *out = p.release();
+  return KDE_OK;
+}
+
+kde_status kde_lscv_H_eval_prepared(kde_lscv_H_prep* p, const double* H, int32_t m, double* g_out,
+                                    double* gscale_out) {
+  if (!p || !g_out || !H) return KDE_E_INVAL;
+  kde_ctx* c = p->c;
+  if (c->server && kde::server_running(c->server.get())) return kde::fail(c, KDE_E_BUSY, "a server is running");
+  if ((c->prec == KDE_PREC_FP64) != p->r.f64)
+    return kde::fail(c, KDE_E_INVAL, "the context's precision changed since the sample was prepared");
+  kde_status s = check_H(c, p->r.d, H, m);
+  if (s) return s;
+  if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
+  return kde::h_eval(p->r, H, m, g_out, gscale_out);
+}
+
+void kde_lscv_H_release(kde_lscv_H_prep* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->c->device);
+  if (p->buf.p) (void)hipFree(p->buf.p);
+  delete p;
+}
 
 kde_status kde_lscv_H_eval(kde_ctx* c, kde_matrix x, const double* H, int32_t m, double* g_out,
                            double* gscale_out) {
   if (!c || !g_out || !H) return KDE_E_INVAL;
   if (c->server && kde::server_running(c->server.get())) return kde::fail(c, KDE_E_BUSY, "a server is running");
-  if (m < 1 || m > KDE_MAX_H_EVAL) return kde::fail(c, KDE_E_INVAL, "matrix count outside [1, KDE_MAX_H_EVAL]");
-  if (x.d >= 1 && x.d <= KDE_MAX_D)
-    for (int64_t q = 0; q < (int64_t)m * x.d * x.d; ++q)
-      if (!std::isfinite(H[q])) return kde::fail(c, KDE_E_INVAL, "bandwidth matrix holds a non-finite value");
+  kde_status s0 = check_H(c, x.d, H, m);
+  if (s0) return s0;
   if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde::HRun r;
-  kde_status s = kde::h_stage(c, x, r);
+  kde_status s = kde::h_stage(c, x, r, c->mdbuf, false);
   if (s) return s;
   return kde::h_eval(r, H, m, g_out, gscale_out);
 }
@@ -654,7 +716,7 @@ kde_status kde_bw_lscv_H(kde_ctx* c, kde_matrix x, double ftol, double xtol, int
     return kde::fail(c, KDE_E_INVAL, "need ftol > 0, xtol > 0 and max_evals >= 1");
   if (hipSetDevice(c->device) != hipSuccess) return kde::fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   kde::HRun r;
-  kde_status s = kde::h_stage(c, x, r);
+  kde_status s = kde::h_stage(c, x, r, c->mdbuf, false);
   if (s) return s;
   return kde::h_search(r, ftol, xtol, max_evals, H_out, info);
 }

@@ -235,3 +235,44 @@ def test_md_kernel_timing_counts_every_evaluation(kde, d, m):
         c.set_timing(True)
         c.lscv_md_curve(x, np.geomspace(0.05, 2.0, 37))
         assert c.kernel_time("md_pairs")[2] == n * (n - 1) / 2 * 37
+
+
+@pytest.mark.parametrize("d", [2, 5])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_prepared_sample_equals_eval(kde, d, precision):
+    """A prepared sample gives kde_lscv_H_eval's g bitwise, over several
+    passes of matrices and between other calls on the context; it owns a copy
+    of the samples (a device column may be freed after prepare); a later
+    change of the context's precision is refused."""
+    import torch
+
+    x = _sample(6000, d, 80 + d, np.float32)
+    H = _matrices(x, 70, 3 + d)
+    other = _sample(3000, d, 90 + d, np.float32)
+    with kde.Context(0, precision) as c:
+        g_ref, gs_ref = c.lscv_H_eval(x, H)
+        xd = torch.from_numpy(x).to("cuda:0")
+        with c.lscv_H_prepare(xd) as prep:
+            del xd
+            torch.cuda.synchronize()
+            g1, gs1 = prep.eval(H)
+            c.lscv_H_eval(other, H[:5])  # reuses the context's workspace
+            c.density_H(other, H[0], other[:10].astype(np.float64))
+            g2, _ = prep.eval(H[3])
+            g3, gs3 = kde.kde_lscv_H_eval_prepared(prep, H[::-1])
+            c.set_precision("fp64" if precision == "mixed" else "mixed")
+            with pytest.raises(kde.KdeError) as e:
+                prep.eval(H[0])
+            assert e.value.status == kde.KDE_E_INVAL
+    assert np.array_equal(g1, g_ref) and np.array_equal(gs1, gs_ref)
+    assert g2[0] == g_ref[3]
+    assert np.array_equal(g3, g_ref[::-1]) and np.array_equal(gs3, gs_ref[::-1])
+    with kde.Context(0) as c:
+        with pytest.raises(kde.KdeError) as e:
+            c.lscv_H_prepare(_sample(50, 17, 1))
+        assert e.value.status == kde.KDE_E_INVAL
+        with c.lscv_H_prepare(x) as prep:
+            for bad in (np.full((d, d), np.nan), np.zeros((0, d, d))):
+                with pytest.raises(kde.KdeError) as e:
+                    prep.eval(bad)
+                assert e.value.status == kde.KDE_E_INVAL
