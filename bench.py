@@ -189,6 +189,8 @@ def _apply_options(ctx, args):
         ctx.set_option("serve_aging_ms", args.aging_ms)
     if getattr(args, "iter_evals", 0) > 0:
         ctx.set_option("serve_iter_evals", int(args.iter_evals))
+    if getattr(args, "iter_ms", 0) > 0:
+        ctx.set_option("serve_iter_ms", args.iter_ms)
 
 
 def _lscv_kernel(ctx, args, n, n_h):
@@ -424,6 +426,7 @@ def served_bench(args):
                    "n_range": [n_lo, n_hi], "n_h": n_h, "plugin_stages": workloads.BATCH_STAGES,
                    "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "aging_ms": args.aging_ms,
                    "prune": args.prune > 0, "iter_evals": args.iter_evals or None,
+                   "iter_ms": args.iter_ms or None,
                    "pair_evals": evals,
                    "load_matched_rate_req_s": 0.7 * cap},
         **out,
@@ -446,6 +449,8 @@ def main():
     ap.add_argument("--ceiling", type=int, default=1,
                     help="after the timed steps, measure the LSCV kernel's steady-state rate and the ceiling of its "
                          "inner loop (0 = skip, e.g. under counter collection)")
+    ap.add_argument("--iter-ms", type=int, default=0,
+                    help="served: target duration of a server iteration in ms (0 = size by evaluations only)")
     ap.add_argument("--iter-evals", type=float, default=0,
                     help="served: pair-term evaluations per server iteration (0 = the library's default)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))

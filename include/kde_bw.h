@@ -123,6 +123,13 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  counted at their dense size, so with "prune" an iteration
  *                  does less work than it counts; a larger value keeps the
  *                  per-iteration host work small against it.
+ *   "serve_iter_ms" server: target duration of a full scheduler iteration
+ *                  (0: off, iterations sized by serve_iter_evals alone).  The
+ *                  server measures each iteration that used its whole
+ *                  budget and moves the next budget towards this duration,
+ *                  within [1, 64] x serve_iter_evals: with "prune", whose
+ *                  sweeps do less than they count, iterations keep their
+ *                  length.  Results do not depend on it.
  *   "serve_aging_ms" server: aging of the smallest-remaining-work order: a
  *                  request's remaining evaluations count divided by
  *                  1 + waited / tau (tau in ms; 0: plain order), so large

@@ -171,6 +171,7 @@ struct kde_ctx {
   double opt_serve_iter_evals = 1e12;  // server: pair-term evaluations per iteration (minimum)
   uint64_t opt_serve_fail_ticket = 0;  // server: the request whose pass is reported failed (0: none)
   double opt_serve_aging_s = 0.0;      // server: aging time constant of the SRPT order (0: plain SRPT)
+  double opt_serve_iter_s = 0.0;       // server: target iteration duration (0: size by serve_iter_evals only)
   int opt_autotune = 0;            // synchronous jobs pick the LSCV variant with the tile autotuner
   int opt_graph = 0;               // synchronous jobs replay a captured graph of their launches
   int opt_prune = 0;               // LSCV tile pruning on sorted samples (mixed form, synchronous jobs)

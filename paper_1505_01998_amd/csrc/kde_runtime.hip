@@ -1090,6 +1090,8 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_autotune = value < 0 ? 0 : (value != 0);
   } else if (k == "serve_iter_evals") {
     c->opt_serve_iter_evals = value <= 0 ? 1e12 : (double)value;
+  } else if (k == "serve_iter_ms") {
+    c->opt_serve_iter_s = value <= 0 ? 0.0 : (double)value * 1e-3;
   } else if (k == "serve_aging_ms") {
     c->opt_serve_aging_s = value <= 0 ? 0.0 : (double)value * 1e-3;
   } else if (k == "serve_fail_ticket") {

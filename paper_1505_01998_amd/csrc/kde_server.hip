@@ -79,6 +79,9 @@ struct Server {
   // pruned-sweep descriptors at top + 2 s and top + 2 s + 1
   int top = 0;
   int extra_id(int slot) const { return top + 2 * slot; }
+  // with serve_iter_ms: the counted evaluations an iteration takes, adapted
+  // so that full iterations last about the target time
+  double iter_budget = 0.0;
   void loop();
 };
 
@@ -188,7 +191,10 @@ void Server::loop() {
       if (r->plan.lscv && !r->lscv_done && r->lscv_next < r->lscv_c.size())
         max_unit = std::max(max_unit, r->lscv_c[r->lscv_next].evals);
     }
-    double left = std::max(ctx->opt_serve_iter_evals, 6.0 * 1024.0 * max_unit);
+    const double base = ctx->opt_serve_iter_s > 0.0 ? std::max(iter_budget, ctx->opt_serve_iter_evals)
+                                                    : ctx->opt_serve_iter_evals;
+    double left = std::max(base, 6.0 * 1024.0 * max_unit);
+    const double left0 = left;
     bool first = true;
     for (auto& r : active) {
       ColPlan& p = r->plan;
@@ -244,6 +250,7 @@ void Server::loop() {
     }
     for (auto& r : active)
       if (ctx->opt_serve_fail_ticket != 0 && r->ticket == ctx->opt_serve_fail_ticket) r->injected = true;
+    const double t_exec = now_s();
     kde_status s = execute(ctx, it);
     for (auto& r : active) {
       if (!r->finishing || s != KDE_OK || r->injected) continue;
@@ -262,6 +269,15 @@ void Server::loop() {
       }
     }
     if (s == KDE_OK) s = sync_and_check(ctx);
+    if (s == KDE_OK && ctx->opt_serve_iter_s > 0.0 && left <= 0.0) {
+      // a full iteration: move the budget towards the target duration (by
+      // the square root of the ratio, within [1, 64] x serve_iter_evals)
+      const double dt = now_s() - t_exec;
+      if (dt > 1e-4) {
+        const double want = left0 * std::sqrt(ctx->opt_serve_iter_s / dt);
+        iter_budget = std::min(64.0 * ctx->opt_serve_iter_evals, std::max(ctx->opt_serve_iter_evals, want));
+      }
+    }
     std::lock_guard<std::mutex> lk(mu);
     std::vector<std::shared_ptr<SrvReq>> keep;
     for (auto& r : active) {

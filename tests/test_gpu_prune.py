@@ -114,6 +114,7 @@ def test_pruned_served_and_job_results_equal_pruned_batch(kde):
         alone = [pr.batch([r])[0] for r in reqs]
         srv.set_option("prune", 1)
         srv.set_option("serve_iter_evals", 1_000_000_000)
+        srv.set_option("serve_iter_ms", 20)  # budgets adapt between iterations; results may not
         srv.server_start(8 << 30, 4)
         tickets = [srv.submit(r) for r in reqs]
         served = [srv.wait(t, timeout_s=120) for t in tickets]
