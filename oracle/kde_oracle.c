@@ -18,8 +18,9 @@
  *  - psi-hat normalisation: the n*K^(r)(0) diagonal term is inside the
  *    1/(n^2 g^(r+1)) factor, i.e. psi_r(g) = n^-2 sum_{i,j} K^(r)_g(X_i-X_j).
  *  - LSCV_h in one dimension is written in data units: the kernel at h is
- *    N(0, h^2); R(K) = (4 pi)^(-1/2).  (The paper works in sphered units; the
- *    two are related by g_data(sigma*h) = g_sphered(h) / sigma.)
+ *    N(0, h^2); R(K) = (4 pi)^(-1/2).  The paper's LSCV_h takes the bandwidth
+ *    matrix h^2 * Sigma (a kernel N(0, h^2 sigma^2) on the data), so its
+ *    objective at h is this one at sigma*h: g_paper(h) = g_data(sigma*h).
  *  - variance: two-pass form, equal in exact arithmetic to the one-pass form
  *    of eq. (PLUGIN-VarianceEstimator), same n-1 denominator.
  *  - K^(r) for r = 8 (three-stage plug-in) follows from the Hermite recurrence;
