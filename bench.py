@@ -19,7 +19,9 @@ import os
 import sys
 import time
 
-import numpy as np
+T_START = time.perf_counter()
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -29,18 +31,22 @@ import workloads  # noqa: E402
 
 # MI355X: 256 CUs at 2.4 GHz.  Per CU and clock the vector units retire 128
 # FP32 lanes of add/mul/fma (157.3 TFLOP/s counting an FMA as 2) and 32 lanes
-# of v_exp_f32.  Microbenchmarks on gfx950 show the two do not overlap: an
-# exp occupies issue like ~3 plain FP32 ops.  One LSCV (pair, h) term is
-# 1 mul + 1 exp + 1 add + 1 fma, so the term rate is bounded by
+# of v_exp_f32; the library's issue-rate probe (kde_issue_rates, run in every
+# default line) measures both on the part with unpacked FP32 instructions.
+# The exponential does not overlap the plain stream (measured), so one LSCV
+# (pair, h) term -- 1 mul + 1 exp + 1 add + 1 fma -- is bounded by
 #   1 / (3 / (CUS * 128 * f) + 1 / (CUS * 32 * f)).
 CUS, CLOCK_HZ = 256, 2.4e9
 VALU_LANES, TRANS_LANES = 128, 32
 LSCV_PEAK = 1.0 / (3.0 / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ))  # 11.23e12/s
-# The psi pass at the same issue model: per pair 12, 11, 10 plain FP32
-# instructions for r = 8, 6, 4 (sub, mul, mul, min, mul, r/2 Horner, mul,
-# add, add) and one exp2; three stages of equal pair count, so the bound of
-# the pass is their harmonic mean (5.24e12 pairs/s).
-PSI_PEAK = 3.0 / sum(p / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ) for p in (12, 11, 10))
+# The psi pass at the same issue model.  With the samples pre-scaled by 1/g
+# (one O(n) pass per stage) a pair needs sub, mul (w = u^2), mul (exp2
+# argument), r/2 Horner ops for He_r in w and two fma (the term and its
+# absolute value): 5 + r/2 plain FP32 instructions (PSI_PLAIN, r = 8, 6, 4)
+# and one exp2.  Three stages of equal pair count, so the bound of the pass
+# is their harmonic mean (6.55e12 pairs/s).
+PSI_PLAIN = (9, 8, 7)
+PSI_PEAK = 3.0 / sum(p / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ) for p in PSI_PLAIN)
 FP32_PEAK_TFLOPS = 157.3
 LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 
@@ -183,6 +189,8 @@ def _apply_options(ctx, args):
         ctx.set_option("autotune", args.autotune)
     if args.graph >= 0:
         ctx.set_option("graph", args.graph)
+    if getattr(args, "persistent", -1) >= 0:
+        ctx.set_option("persistent", args.persistent)
     if getattr(args, "prune", -1) >= 0:
         ctx.set_option("prune", args.prune)
     if getattr(args, "aging_ms", 0) > 0:
@@ -200,7 +208,7 @@ def _lscv_kernel(ctx, args, n, n_h):
         return "k_lscv_units_f64<8>"
     if args.prune > 0:
         hc = ctx.autotune(n, n_h)[0] if args.autotune > 0 else (args.hc if args.hc > 0 else 16)
-        return f"k_lscv_units_prune<{hc}> (evals counted dense)"
+        return f"k_lscv_units_prune<{hc}>"
     if args.autotune > 0:
         return f"k_lscv_units_f32<{ctx.autotune(n, n_h)[0]}>"
     if args.mfma > 0:
@@ -253,7 +261,7 @@ def batch_bench(args):
         "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": "batch-512", "columns": len(specs), "n_range": [1000, 200000], "n_h": n_h,
                    "plugin_stages": workloads.BATCH_STAGES, "precision": args.precision,
-                   "autotune": args.autotune > 0},
+                   "autotune": args.autotune > 0, "persistent": args.persistent != 0},
         "columns_per_s": len(specs) / t_batch,
         "plain": {"columns_per_s": len(specs) / t_plain, "value": evals / t_plain, "seconds": t_plain},
         "speedup_vs_plain": t_plain / t_batch,
@@ -334,38 +342,37 @@ def lscv_H_bench(args):
     return out
 
 
-def served_bench(args):
-    """Served form (continuous batching) vs plain per-request calls on the same
-    request stream: first at the stream's own arrival times, then load-matched
-    at 0.7 x the plain form's measured capacity."""
+def served_block(kde, args, n_req: int, n_lo: float = 2e3, n_hi: float = 2e6):
+    """Served form (continuous batching) vs plain per-request calls on the
+    first n_req requests of the seeded served stream (Poisson arrivals at
+    args.rate, n log-uniform in [n_lo, n_hi], the four batch families; plug-in
+    with three stages and LSCV over 128 h each): first at the stream's own
+    arrival times, then load-matched at 0.7 x the plain form's measured
+    capacity.  Every served result is compared with the plain one."""
     import threading
 
-    import paper_1505_01998_amd as kde
-
-    n_lo, n_hi = (2e3, 2e6) if args.workload == "served" else (2e3, 6e4)
-    stream = workloads.served_stream(args.requests, rate=args.rate, n_lo=n_lo, n_hi=n_hi)
+    stream = workloads.served_stream(n_req, rate=args.rate, n_lo=n_lo, n_hi=n_hi)
     cols = [a.spec.column() for a in stream]
     reqs = _requests_of(kde, cols)
     n_h = workloads.BATCH_GRID[3]
     evals = sum(a.spec.n * (a.spec.n - 1) / 2 * (n_h + workloads.BATCH_STAGES) for a in stream)
-    log(f"{len(reqs)} requests, {evals:.3e} pair-evals, arrivals over {stream[-1].t:.2f} s")
+    log(f"served: {len(reqs)} requests, {evals:.3e} pair-evals, arrivals over {stream[-1].t:.2f} s")
 
     def pct(v, q):
         return float(np.percentile(np.asarray(v), q))
 
     def run_plain(ctx, times):
-        lat, t_start = [], time.perf_counter()
+        lat, res_all, t_start = [], [], time.perf_counter()
         for r, t in zip(reqs, times):
             now = time.perf_counter() - t_start
             if now < t:
                 time.sleep(t - now)
             res = ctx.batch([r])[0]
             assert res.status == kde.KDE_OK
+            res_all.append(res)
             lat.append(time.perf_counter() - t_start - t)
-            if len(lat) % max(1, len(reqs) // 8) == 0:
-                log(f"  plain: {len(lat)}/{len(reqs)} done")
         span = time.perf_counter() - t_start - times[0]
-        return lat, span
+        return lat, span, res_all
 
     def run_served(ctx, times):
         ctx.server_start(args.hbm_budget_gb << 30, args.slots)
@@ -381,74 +388,120 @@ def served_bench(args):
 
         th = threading.Thread(target=feeder)
         th.start()
-        lat, done_at = [], []
+        lat, done_at, res_all = [], [], []
         for k in range(len(reqs)):
             while tickets[k] is None:
                 time.sleep(0.0005)
             res = ctx.wait(tickets[k])
             assert res.status == kde.KDE_OK, res.status
+            res_all.append(res)
             lat.append(res.t_queue_s + res.t_service_s)
             done_at.append(time.perf_counter() - t_start)
-            if len(lat) % max(1, len(reqs) // 8) == 0:
-                log(f"  served: {len(lat)}/{len(reqs)} collected")
         th.join()
         ctx.server_stop()
-        return lat, max(done_at) - times[0]
+        return lat, max(done_at) - times[0], res_all
 
-    def summary(lat, span):
-        return {"req_per_s": len(lat) / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "mean_s": float(np.mean(lat)),
-                "makespan_s": span}
+    def summary(lat, span, _res):
+        return {"req_per_s": len(lat) / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+                "mean_s": float(np.mean(lat)), "makespan_s": span}
+
+    def same(a, b):
+        return all(x.h_lscv == y.h_lscv and x.h_plugin == y.h_plugin and np.array_equal(x.g, y.g)
+                   for x, y in zip(a, b))
 
     out = {}
     ctx = kde.Context(0, args.precision)
     _apply_options(ctx, args)
     ctx.batch(reqs[:1])  # warm-up: code objects, allocations
     arrivals = [a.t for a in stream]
-    log("plain at the stream's arrival times")
-    out["plain"] = summary(*run_plain(ctx, arrivals))
-    log("served at the stream's arrival times")
-    out["served"] = summary(*run_served(ctx, arrivals))
+    log("served: plain at the stream's arrival times")
+    plain = run_plain(ctx, arrivals)
+    out["plain"] = summary(*plain)
+    log("served: served at the stream's arrival times")
+    served = run_served(ctx, arrivals)
+    out["served"] = summary(*served)
     cap = out["plain"]["req_per_s"]
     scale = args.rate / (0.7 * cap)
     matched = [t * scale for t in arrivals]
-    log(f"load-matched: rate {0.7 * cap:.3f} req/s")
-    out["plain_load_matched"] = summary(*run_plain(ctx, matched))
-    out["served_load_matched"] = summary(*run_served(ctx, matched))
+    log(f"served: load-matched at {0.7 * cap:.3f} req/s")
+    plain_lm = run_plain(ctx, matched)
+    out["plain_load_matched"] = summary(*plain_lm)
+    served_lm = run_served(ctx, matched)
+    out["served_load_matched"] = summary(*served_lm)
     ctx.close()
+    ns = [a.spec.n for a in stream]
     return {
-        "metric": "served req/s + p99 latency vs plain",
-        "value": out["served"]["req_per_s"],
-        "unit": "req/s",
-        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": out["served"]["makespan_s"] * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "requests": len(reqs), "rate_req_s": args.rate,
-                   "n_range": [n_lo, n_hi], "n_h": n_h, "plugin_stages": workloads.BATCH_STAGES,
-                   "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "aging_ms": args.aging_ms,
-                   "prune": args.prune > 0, "iter_evals": args.iter_evals or None,
-                   "iter_ms": args.iter_ms or None,
-                   "pair_evals": evals,
-                   "load_matched_rate_req_s": 0.7 * cap},
+        "requests": len(reqs),
+        "stream": f"first {len(reqs)} requests of the seeded served stream (seed 1998005, Poisson {args.rate:g} "
+                  f"req/s, n log-uniform in [{n_lo:g}, {n_hi:g}]; this prefix has n from {min(ns)} to {max(ns)})",
+        "pair_evals": evals,
+        "load_matched_rate_req_s": 0.7 * cap,
         **out,
         "speedup_req_s": out["served"]["req_per_s"] / out["plain"]["req_per_s"],
+        "speedup_req_s_load_matched": out["served_load_matched"]["req_per_s"] /
+                                      out["plain_load_matched"]["req_per_s"],
+        "results_bitwise_equal_plain": same(plain[2], served[2]) and same(plain[2], served_lm[2]),
+        "p99_note": f"p99 over {len(reqs)} latencies (linear interpolation between the two largest)"
+                    if len(reqs) < 100 else f"p99 over {len(reqs)} latencies",
     }
+
+
+def served_bench(args):
+    """The served block alone, as its own line."""
+    import paper_1505_01998_amd as kde
+
+    n_lo, n_hi = (2e3, 2e6) if args.workload == "served" else (2e3, 6e4)
+    blk = served_block(kde, args, args.requests, n_lo, n_hi)
+    return {
+        "metric": "served req/s + p99 latency vs plain",
+        "value": blk["served"]["req_per_s"],
+        "unit": "req/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": blk["served"]["makespan_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "requests": blk["requests"], "rate_req_s": args.rate,
+                   "n_range": [n_lo, n_hi], "n_h": workloads.BATCH_GRID[3], "plugin_stages": workloads.BATCH_STAGES,
+                   "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "aging_ms": args.aging_ms,
+                   "prune": args.prune > 0, "iter_evals": args.iter_evals or None, "iter_ms": args.iter_ms or None},
+        "served": blk,
+    }
+
+
+def elapsed():
+    return time.perf_counter() - T_START
+
+
+def issue_probe(kde):
+    """The device's measured issue rates (per clock and CU) next to the ones
+    the roofline assumes."""
+    with kde.Context(0) as c:
+        r = c.issue_rates()
+    return {**{k: r[k] for k in ("clock_hz", "cus")},
+            "lanes_per_clk_cu": {k: r[k] for k in ("add_f32", "mul_f32", "fma_f32", "exp_f32")},
+            "lscv_terms_per_clk_cu": {"spread": r["lscv_mix"], "zero": r["lscv_mix_zero"]},
+            "assumed_lanes_per_clk_cu": {"plain_f32": VALU_LANES, "exp_f32": TRANS_LANES}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run from process start (s): warm-up stops after one step "
+                         "longer than 10 s, and the timed steps are cut to what fits before the legs after them")
     ap.add_argument("--workload", default="lognormal-1m",
                     choices=workloads.WORKLOADS + ("batch-512", "served", "served-small", "lscv-H"))
-    ap.add_argument("--requests", type=int, default=32, help="served: requests taken from the stream")
+    ap.add_argument("--requests", type=int, default=32, help="served workloads: requests taken from the stream")
+    ap.add_argument("--served-requests", type=int, default=24,
+                    help="single-column workloads: requests of the served block carried in the same line (0 = none)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrival rate of the stream (req/s)")
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--aging-ms", type=int, default=0, help="served: aging time constant of the SRPT order (0 = off)")
     ap.add_argument("--ceiling", type=int, default=1,
-                    help="after the timed steps, measure the LSCV kernel's steady-state rate and the ceiling of its "
-                         "inner loop (0 = skip, e.g. under counter collection)")
+                    help="after the timed steps, measure the LSCV kernel's steady-state rate, the ceiling of its "
+                         "inner loop and the device's issue rates (0 = skip, e.g. under counter collection)")
     ap.add_argument("--iter-ms", type=int, default=0,
                     help="served: target duration of a server iteration in ms (0 = size by evaluations only)")
     ap.add_argument("--iter-evals", type=float, default=0,
@@ -464,6 +517,8 @@ def main():
                     help="LSCV tile pruning on sorted samples (1/0; -1 = default, off)")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay captured HIP graphs of repeated jobs (1/0; -1 = default, off)")
+    ap.add_argument("--persistent", type=int, default=-1,
+                    help="dense LSCV pass as one persistent launch over a device work queue (1/0; -1 = default, on)")
     ap.add_argument("--autotune", type=int, default=-1,
                     help="pick the LSCV variant with the tile autotuner (1/0; -1 = default, off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -507,23 +562,43 @@ def main():
     torch.cuda.synchronize()
     ctx = kde.Context(0, args.precision)
     _apply_options(ctx, args)
+    log(f"{elapsed():.0f} s: set up {w.name}")
 
-    performed = []
+    skipped = []
 
     def step():
         if args.prune > 0:
             # one job for both selectors, so the performed LSCV evaluations come back
             r = ctx.batch([kde.Request(xd, kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, w.stages, w.grid)])[0]
             assert r.status == kde.KDE_OK, r.status
-            performed.append(r.lscv_evals / r.lscv_evals_dense)
+            skipped.append((r.lscv_evals_dense - r.lscv_evals, r.lscv_evals / r.lscv_evals_dense))
             return r.h_plugin, r.plugin, r.g, r.gscale
         h_pi, info = ctx.bw_plugin(xd, w.stages)
         g, gs, _ = ctx.lscv_curve(xd, w.grid)
         return h_pi, info, g, gs
 
-    for i in range(args.warmup):
-        log(f"warmup step {i + 1}/{args.warmup}")
+    # Reserve for the legs after the timed region (accuracy, served block,
+    # CPU baseline, probes), scaled from the step time where it matters.
+    t_step = None
+    warm = 0
+    for i in range(max(args.warmup, 0)):
+        t = time.perf_counter()
         step()
+        torch.cuda.synchronize()
+        t_step = time.perf_counter() - t
+        warm += 1
+        log(f"{elapsed():.0f} s: warmup step {i + 1}/{args.warmup} took {t_step:.1f} s")
+        if t_step > 10.0:
+            break
+    reserve = (15.0 if args.accuracy else 0.0) + (args.cpu_budget + 10.0 if args.cpu_budget > 0 else 0.0) + \
+              (90.0 if args.served_requests > 0 else 0.0) + (15.0 if args.ceiling else 0.0)
+    steps = args.steps
+    if t_step is not None:
+        fit = int((args.budget_s - elapsed() - reserve) // max(t_step, 1e-3))
+        steps = max(1, min(args.steps, fit))
+    if steps < args.steps:
+        log(f"{elapsed():.0f} s: timing {steps} of the {args.steps} requested steps to stay within "
+            f"{args.budget_s:.0f} s (step {t_step:.1f} s, {reserve:.0f} s reserved for the later legs)")
     # kernel timing brackets every launch with events, which the graph option
     # does not capture; with graphs the kernels are timed on one extra
     # (eager) step after the timed region
@@ -532,41 +607,50 @@ def main():
         ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         h_pi, info, g, gs = step()
-        if args.steps <= 20 or (i + 1) % 50 == 0:
-            log(f"timed step {i + 1}/{args.steps} done")
+        if steps <= 20 or (i + 1) % 50 == 0:
+            log(f"{elapsed():.0f} s: timed step {i + 1}/{steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     graph_stats = ctx.graph_stats()
+    timed_skipped = sum(s for s, _ in skipped[-steps:]) if skipped else 0.0
     if use_graph:
         ctx.set_timing(True)
         step()
         torch.cuda.synchronize()
+        timed_skipped = skipped[-1][0] if skipped else 0.0
     launches, ms, evals_k = ctx.kernel_time("lscv_pairs")
     p_launches, p_ms, p_evals = ctx.kernel_time("psi_pairs")
     kernel = _lscv_kernel(ctx, args, n, n_h)
-    steady = ceiling = None
+    steady = ceiling = probe = None
     if args.ceiling and args.precision == "mixed" and args.prune <= 0 and args.mfma <= 0 and args.autotune <= 0:
         # outside the timed region: the same kernel's steady-state rate (the
-        # tuner's trial: launches of B and 2B identical units, differenced)
-        # and the ceiling of its inner loop run from one LDS tile
+        # tuner's trial: launches of B and 2B identical units, differenced),
+        # the ceiling of its inner loop run from one LDS tile, and the issue
+        # rates of the part
         hc = args.hc if args.hc > 0 else 16
         steady = ctx.autotune(n, n_h)[1][hc]
         ceiling = ctx.lscv_ceiling(hc)
+        probe = issue_probe(kde)
     ctx.close()
+    log(f"{elapsed():.0f} s: timed region done ({steps} steps, {dt:.1f} s)")
 
-    ms_step = dt * 1e3 / args.steps
+    ms_step = dt * 1e3 / steps
     value = evals_step / (ms_step * 1e-3)
-    achieved = evals_k / (ms * 1e-3)
+    # under pruning the kernel is credited only with the evaluations it performed
+    performed_k = evals_k - timed_skipped
+    achieved = performed_k / (ms * 1e-3)
     out = {
         "metric": "pair-kernel evals/s (LSCV+plug-in, n=1M)" if n == 1_000_000 else
                   f"pair-kernel evals/s (LSCV+plug-in, n={n})",
         "value": value,
         "unit": "pair-evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "steps_requested": args.steps,
+        "warmup": warm,
+        "warmup_requested": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -575,7 +659,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "family": w.family, "n": n, "n_h": n_h, "plugin_stages": w.stages,
                    "precision": args.precision, "input_dtype": str(np.dtype(w.dtype)), "autotune": args.autotune > 0,
-                   "graph": use_graph, "graph_captures_replays": list(graph_stats), "prune": args.prune > 0},
+                   "graph": use_graph, "graph_captures_replays": list(graph_stats), "prune": args.prune > 0,
+                   "persistent": args.persistent != 0},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -587,26 +672,36 @@ def main():
             "kernel": kernel,
             "launches": launches,
             "avg_launch_ms": ms / max(launches, 1),
-            "evals_per_launch": evals_k / max(launches, 1),
+            "evals_per_launch": performed_k / max(launches, 1),
             "fp32_flop_frac": achieved * LSCV_FLOP_PER_EVAL / (FP32_PEAK_TFLOPS * 1e12),
             "steady_state": None if steady is None else steady / 1e12,
             "inner_loop_ceiling": None if ceiling is None else ceiling / 1e12,
             "frac_of_inner_loop_ceiling": None if ceiling is None else achieved / ceiling,
+            "issue_probe": probe,
         },
         "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals,
                        "achieved": p_evals / (p_ms * 1e-3) / 1e12 if p_ms > 0 else None, "peak": PSI_PEAK / 1e12,
                        "unit": "Tpair/s", "frac": p_evals / (p_ms * 1e-3) / PSI_PEAK if p_ms > 0 else None},
         "result": {"h_plugin": h_pi, "h_lscv": float(w.grid[int(np.argmin(g))]), "k_lscv": int(np.argmin(g))},
         "prune": None if args.prune <= 0 else {
-            "performed_frac": performed[-1],
-            "performed_evals_per_s": (pairs * n_h * performed[-1] + pairs * w.stages) / (ms_step * 1e-3),
-            "note": "value counts the dense method's evaluations; the pruned sweep skips tiles whose total is "
-                    "below 2^-34 of every sum"},
+            "performed_frac": skipped[-1][1],
+            "performed_evals_per_s": (pairs * n_h * skipped[-1][1] + pairs * w.stages) / (ms_step * 1e-3),
+            "note": "value counts the dense method's evaluations; roofline.achieved counts the evaluations the "
+                    "pruned sweep performed (every skipped tile's total is below 2^-34 of every sum)"},
     }
     if args.accuracy and args.precision == "mixed":
         out["accuracy"] = accuracy(kde, xd, w, h_pi, info, g, gs)
+        log(f"{elapsed():.0f} s: accuracy leg done")
+    del xd
+    torch.cuda.empty_cache()
+    if args.served_requests > 0:
+        out["served"] = served_block(kde, args, args.served_requests)
+        log(f"{elapsed():.0f} s: served block done")
     if args.cpu_budget > 0:
-        out["cpu_baseline"] = cpu_baseline(w, x, args.cpu_budget)
+        left = args.budget_s - elapsed() - 10.0
+        out["cpu_baseline"] = cpu_baseline(w, x, max(2.0, min(args.cpu_budget, left / 2)))
+        log(f"{elapsed():.0f} s: cpu baseline done")
+    out["wall_s"] = elapsed()
     print(json.dumps(out), flush=True)
 
 

@@ -49,7 +49,7 @@ typedef enum {
   KDE_OK = 0,
   KDE_E_INVAL = 1,      /* bad argument or sample column */
   KDE_E_DEGENERATE = 2, /* sigma = 0, or a functional estimate of the wrong sign */
-  KDE_E_NOMEM = 3,      /* device or host allocation failed */
+  KDE_E_NOMEM = 3,      /* allocation failed, or a served request exceeds the server's HBM budget */
   KDE_E_DEVICE = 4,     /* HIP runtime error */
   KDE_E_BUSY = 5,       /* reserved: result not ready */
   KDE_E_CANCELLED = 6   /* reserved: request cancelled */
@@ -95,6 +95,9 @@ typedef struct {
  * The context owns a HIP stream of default priority, a device workspace that
  * grows on demand, and per-kernel timing counters. */
 kde_status kde_ctx_create(int device, kde_prec prec, kde_ctx** out);
+/* Stops a running server, then releases every prepared LSCV_H sample
+ * (kde_lscv_H_prepare) and every resumable job (kde_job_create) created on
+ * the context and not yet released; those handles must not be used after. */
 void kde_ctx_destroy(kde_ctx* ctx);
 
 /* Text of the last failure on this context; owned by the context and valid
@@ -158,7 +161,13 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  kde_result.lscv_evals counts what was evaluated.  The
  *                  plug-in passes are unchanged.  A column's pruned results
  *                  are bitwise the same alone, in a batch, served or run as
- *                  a job.  Graph replay is off while pruning.
+ *                  a job.
+ *   "persistent"   1 (default): the dense mixed-precision LSCV pass of a job
+ *                  (synchronous call, batch, server iteration, job slice) is
+ *                  one launch of about as many blocks as the device holds,
+ *                  which take the pass's work units in order, largest first,
+ *                  from a device counter; 0: launches of bounded work
+ *                  ("launch_evals").  Results are bitwise the same.
  *   "graph"        1: the kernel launches of a synchronous call or kde_batch
  *                  are captured into a HIP graph; a later call with the same
  *                  signature (per request: validity, n, dtype, host/device,
@@ -182,7 +191,7 @@ kde_status kde_ctx_graph_stats(kde_ctx* ctx, int64_t* captures, int64_t* replays
  * from one pair distance as in Section 4.5).  Times the vector-ALU kernel
  * with 8, 16 and 32 bandwidths per block on trial launches shaped like a
  * column of n samples with an n_h-point grid (the planner's longest work
- * items, about 0.05 s of work each, on an all-zero column in buffers of the
+ * items, about 0.05 s of work each, on an evenly spread column in buffers of the
  * context) and caches the fastest per shape (quarter octave of n, n_h) in the
  * context; the default 16 is kept unless another is 2% faster.  The variant
  * never changes a result: items and summation order do not depend on it.
@@ -207,6 +216,26 @@ kde_status kde_autotune(kde_ctx* ctx, int64_t n, int32_t n_h, kde_tune_info* out
  * whatever the context's precision.  KDE_E_INVAL for hc other than 8, 16,
  * 32; KDE_E_BUSY while a server runs. */
 kde_status kde_lscv_ceiling(kde_ctx* ctx, int32_t hc, double* evals_per_s);
+/* Issue-rate probe of the vector ALU on this device: the rates that bound
+ * the pair kernels of Section 4.4 (psi_r sums, LSCV sums with the pair
+ * distance reused across bandwidths as in Section 4.5), which run from
+ * registers and LDS.  Register-only loops of eight independent chains per
+ * lane, about 0.05-0.2 s per case, timed with events on the context's stream;
+ * results are per clock and per compute unit at the device's reported engine
+ * clock (clock_hz) over its cus compute units.  add_f32, mul_f32, fma_f32:
+ * plain (unpacked) FP32 vector lanes issued; exp_f32: v_exp_f32 lanes;
+ * lscv_mix: LSCV pair-bandwidth terms (one mul, one exp2, one add, one fma)
+ * with exponents spread over (2^-71, 1]; lscv_mix_zero: the same loop with
+ * every distance 0 (every exponential is exp2(0)).  KDE_E_BUSY while a
+ * server runs; KDE_E_DEVICE on a HIP error. */
+typedef struct {
+  double clock_hz;
+  int32_t cus;
+  int32_t pad0;
+  double add_f32, mul_f32, fma_f32, exp_f32;
+  double lscv_mix, lscv_mix_zero;
+} kde_issue_info;
+kde_status kde_issue_rates(kde_ctx* ctx, kde_issue_info* out);
 
 /* Kernel timing.  While enabled, every launch of the pair kernels is bracketed
  * by HIP events on the stream it runs on.  kde_ctx_kernel_time reports, for
@@ -384,17 +413,23 @@ kde_status kde_batch(kde_ctx* ctx, const kde_request* reqs, int32_t n_req, kde_r
 
 /* ---------------------------------------------------------------- serving
  * A server runs on a context (one at a time; while it runs, the synchronous
- * calls and option setters of that context return KDE_E_BUSY).  Requests
- * submitted from any thread queue in FIFO order and are admitted while the
- * sum of the device footprints of admitted requests stays within
- * hbm_budget_bytes and fewer than max_slots are resident (a request larger
- * than the whole budget is rejected with KDE_E_NOMEM).  Admitted requests
- * stay resident on the device (samples, partial sums, state) until done.
- * Continuous batching: every scheduler iteration launches, in shared
- * launches, the next work units of every resident request, smallest
- * remaining work first, within the iteration's evaluation budget;
- * requests admitted while others run join the next iteration.  Each result
- * is bitwise identical to the same request run alone through kde_batch. */
+ * calls and option setters of that context return KDE_E_BUSY).  The server
+ * reserves hbm_budget_bytes of device memory when it starts (KDE_E_NOMEM if
+ * the device cannot) and places every admitted request's block inside it.
+ * Requests submitted from any thread queue in arrival order and are admitted
+ * while the sum of the device footprints (kde_request_footprint) of admitted
+ * requests stays within the budget and fewer than max_slots are resident (a
+ * request larger than the whole budget is rejected with KDE_E_NOMEM).  The
+ * first queued request that does not fit keeps its room: later requests are
+ * admitted before it only within the rest of the budget, so it is admitted as
+ * soon as enough resident work has finished.  Admitted requests stay resident
+ * on the device (samples, partial sums, state) until done.  Continuous
+ * batching: every scheduler iteration launches, in shared launches, the next
+ * work units of every resident request, smallest remaining work first,
+ * within the iteration's evaluation budget; requests admitted while others
+ * run join the next iteration, and the next iteration is enqueued before the
+ * previous one has ended.  Each result is bitwise identical to the same
+ * request run alone through kde_batch. */
 kde_status kde_server_start(kde_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots);
 /* Copies the column (host or device) and grid; the caller may free them on
  * return.  Invalid requests are rejected here with KDE_E_INVAL. */

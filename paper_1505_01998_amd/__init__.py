@@ -53,6 +53,7 @@ EXPORTS = (
     "kde_density_H", "kde_range_aggregates_2d", "kde_cancel", "kde_job_create", "kde_job_run",
     "kde_job_progress", "kde_job_result", "kde_job_checkpoint_bytes", "kde_job_checkpoint", "kde_job_resume",
     "kde_job_destroy", "kde_lscv_ceiling", "kde_lscv_H_prepare", "kde_lscv_H_eval_prepared", "kde_lscv_H_release",
+    "kde_issue_rates",
 )
 
 
@@ -82,6 +83,12 @@ class kde_plugin_info(ctypes.Structure):
 
 class kde_tune_info(ctypes.Structure):
     _fields_ = [("hc", ctypes.c_int32), ("pad0", ctypes.c_int32), ("evals_per_s", ctypes.c_double * 3)]
+
+
+class kde_issue_info(ctypes.Structure):
+    _fields_ = [("clock_hz", ctypes.c_double), ("cus", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("add_f32", ctypes.c_double), ("mul_f32", ctypes.c_double), ("fma_f32", ctypes.c_double),
+                ("exp_f32", ctypes.c_double), ("lscv_mix", ctypes.c_double), ("lscv_mix_zero", ctypes.c_double)]
 
 
 class kde_lscv_min_info(ctypes.Structure):
@@ -179,6 +186,7 @@ def _load():
     lib.kde_job_destroy.restype = None
     lib.kde_autotune.argtypes = [P, I64, I32, ctypes.POINTER(kde_tune_info)]
     lib.kde_lscv_ceiling.argtypes = [P, I32, PD]
+    lib.kde_issue_rates.argtypes = [P, ctypes.POINTER(kde_issue_info)]
     lib.kde_density.argtypes = [P, kde_column, ctypes.c_double, PD, I32, PD]
     lib.kde_lscv_md_curve.argtypes = [P, kde_matrix, PD, I32, PD, PD, PD]
     lib.kde_bw_lscv_md.argtypes = [P, kde_matrix, PD, I32, PD, ctypes.POINTER(I32)]
@@ -390,10 +398,12 @@ class HPrep:
     def __init__(self, ctx, x):
         m, keep = make_matrix(x)
         self.ctx, self.d = ctx, m.d
+        self.handle = None
         h = ctypes.c_void_p()
         _check(ctx, lib.kde_lscv_H_prepare(ctx, m, ctypes.byref(h)))
         del keep
         self.handle = h
+        _dependents(ctx).add(self)
 
     def eval(self, H):
         """(g, gscale) at bandwidth matrices H (m x d x d, or one d x d)."""
@@ -408,11 +418,33 @@ class HPrep:
             lib.kde_lscv_H_release(self.handle)
             self.handle = None
 
+    def _forget(self):
+        # the context was destroyed, which released the handle
+        self.handle = None
+
     def __enter__(self):
         return self
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Handles created on each context (by its address): kde_ctx_destroy releases
+# them, so Context.close tells them to forget theirs first.
+_DEPENDENTS = {}
+
+
+def _dependents(ctx):
+    import weakref
+
+    key = ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
+    return _DEPENDENTS.setdefault(key, weakref.WeakSet())
 
 
 def kde_lscv_H_prepare(ctx, x) -> HPrep:
@@ -521,6 +553,15 @@ def kde_lscv_ceiling(ctx, hc: int = 16) -> float:
     r = ctypes.c_double()
     _check(ctx, lib.kde_lscv_ceiling(ctx, int(hc), ctypes.byref(r)))
     return r.value
+
+
+def kde_issue_rates(ctx) -> dict:
+    """Measured vector-ALU issue rates of the device, per clock and per CU:
+    {"clock_hz", "cus", "add_f32", "mul_f32", "fma_f32", "exp_f32",
+    "lscv_mix", "lscv_mix_zero"}."""
+    r = kde_issue_info()
+    _check(ctx, lib.kde_issue_rates(ctx, ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in kde_issue_info._fields_ if k != "pad0"}
 
 
 def kde_bw_rot(ctx, x) -> float:
@@ -792,12 +833,13 @@ def kde_job_destroy(job) -> None:
 
 
 class Job:
-    """A resumable request on a Context (destroy it, or leave its with-block,
-    before the context closes)."""
+    """A resumable request on a Context; closing the context releases it."""
 
     def __init__(self, context, request: Request):
         self.ctx = context.ctx
+        self.job = None
         self.job, self.n_h = kde_job_create(self.ctx, request)
+        _dependents(self.ctx).add(self)
 
     def run(self, max_evals: float) -> bool:
         return kde_job_run(self.ctx, self.job, max_evals)
@@ -824,6 +866,15 @@ class Job:
             kde_job_destroy(self.job)
             self.job = None
 
+    def _forget(self):
+        self.job = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def __enter__(self):
         return self
 
@@ -839,6 +890,9 @@ class Context:
 
     def close(self):
         if self.ctx:
+            key = self.ctx.value if isinstance(self.ctx, ctypes.c_void_p) else int(self.ctx)
+            for dep in list(_DEPENDENTS.pop(key, ())):
+                dep._forget()
             kde_ctx_destroy(self.ctx)
             self.ctx = None
 
@@ -877,6 +931,9 @@ class Context:
 
     def lscv_ceiling(self, hc=16):
         return kde_lscv_ceiling(self.ctx, hc)
+
+    def issue_rates(self):
+        return kde_issue_rates(self.ctx)
 
     def graph_stats(self):
         return kde_ctx_graph_stats(self.ctx)

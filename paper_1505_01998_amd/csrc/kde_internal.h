@@ -84,8 +84,10 @@ struct DevState {
   double h_plugin;
   double h_best, margin;
   double fp64_kappa;  // kappa threshold for the FP64 re-run (0 = never)
-  float cf[2];      // FP32 pair coefficients of the current psi pass: 1/g^2, -log2(e)/(2 g^2)
+  float psi_scale;  // FP32 1/g of the current psi pass (the scaled copy is x32 * psi_scale)
+  int psi_fast;     // the scaled copy's range keeps every Hermite value finite (no clamp needed)
   double cd[2];     // FP64 pair coefficients: 1/g^2, -1/(2 g^2)
+  float xmin, xmax; // range of the FP32 working copy
   double pruned_evals;  // LSCV pair-term evaluations skipped by tile pruning (exact count)
 };
 
@@ -95,8 +97,10 @@ struct DevState {
 struct ColDesc {
   const void* raw;      // input samples, float32 or float64
   float* x32;           // padded FP32 working copy [n + kPad]
+  float* y32;           // psi pass: the working copy times 1/g of the current stage [n + kPad] (may be null)
   double* x64;          // padded FP64 working copy [n + kPad] (may be null)
   double* stat;         // moment partials [kStatBlocks]
+  float* stat_mm;       // minimum and maximum partials of the FP32 working copy [2][kStatBlocks]
   int* stat_nf;         // non-finite counts [kStatBlocks]
   double* psi_part;     // psi partials [2][n_items_psi]
   double* psi_sums;     // [2]
@@ -141,7 +145,9 @@ struct RowDesc {
 // ---- launchers (kde_kernels.hip); all asynchronous on `s` ----
 // Column-level launches act on the columns cols[ids[0 .. n_ids)].
 void launch_stats(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int max_blocks);
-void launch_psi_begin(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage);
+// Pilot bandwidth of the stage and, for the mixed form, the scaled copy
+// y32 = x32 / g of every active column.
+void launch_psi_begin(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage, int f64);
 void launch_psi_finish(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage, int was_f64,
                        int conditional);
 void launch_plugin_final(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids);
@@ -160,6 +166,14 @@ void launch_lscv_ceiling(hipStream_t s, int hc, const float* x, const float* c32
 void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, int prune, const ColDesc* cols, const Unit* units,
                        int u0, int n_units);
 void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows);
+// Persistent form of the dense FP32 LSCV sweep: `blocks` blocks take units
+// [0, n_units) from the device counter *next (which must be 0; clear it
+// with launch_zero_ints in the same stream).  lscv_queue_blocks: the blocks
+// the current device holds at once for variant hc (0 on failure).
+void launch_zero_ints(hipStream_t s, int* p, int n);
+int lscv_queue_blocks(int hc);
+void launch_lscv_units_queue(hipStream_t s, int hc, const ColDesc* cols, const Unit* units, int n_units, int* next,
+                             int blocks);
 
 // ---- ascending sort of FP32 keys (kde_sort.hip): temporary bytes for
 // `count` keys (0 on failure), and the sort itself.

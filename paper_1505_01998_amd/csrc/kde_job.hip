@@ -133,12 +133,15 @@ kde_status kde_job_create(kde_ctx* c, const kde_request* req, kde_job** out) {
   j->remaining = j->total;
   j->res.g_out = j->res.gscale_out = nullptr;
   kde::init_result(j->res, KDE_OK);
+  c->jobs.push_back(j.get());
   *out = j.release();
   return KDE_OK;
 }
 
 void kde_job_destroy(kde_job* j) {
   if (!j) return;
+  auto& v = j->c->jobs;
+  v.erase(std::remove(v.begin(), v.end(), j), v.end());
   (void)hipSetDevice(j->c->device);
   if (j->block) (void)hipFree(j->block);
   if (j->st) (void)hipFree(j->st);

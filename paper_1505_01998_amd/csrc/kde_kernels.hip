@@ -46,6 +46,12 @@ constexpr int kRun = 64;  // j per plain-FP32 run before a compensated fold
 // Squared scaled distance beyond which a psi term is zero in FP32; clamping
 // keeps the Hermite polynomial finite when the distance is huge or infinite.
 constexpr float kWMax = 4096.0f;
+// A column whose scaled copy (samples / g) spans at most this range has every
+// squared scaled distance below 4e8, where He_8 stays far inside the FP32
+// range, so its psi sweep needs no clamp except on masked and padded pairs.
+constexpr double kPsiFastRange = 2.0e4;
+// exp2 factor of the psi term: e^(-w/2) = exp2(w * kPsiExp2)
+constexpr float kPsiExp2 = (float)(-0.5 * 1.4426950408889634074);
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int t = threadIdx.x;
@@ -58,6 +64,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   double r = sh[0];
   __syncthreads();
   return r;
+}
+
+// Block-wide minimum and maximum (every thread receives both).
+__device__ __forceinline__ void block_minmax(float& lo, float& hi, float* sh) {
+  const int t = threadIdx.x;
+  sh[t] = lo;
+  sh[kThreads + t] = hi;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[t] = fminf(sh[t], sh[t + s]);
+      sh[kThreads + t] = fmaxf(sh[kThreads + t], sh[kThreads + t + s]);
+    }
+    __syncthreads();
+  }
+  lo = sh[0];
+  hi = sh[kThreads];
+  __syncthreads();
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -199,12 +223,17 @@ __global__ __launch_bounds__(kThreads) void k_stats_dev(const ColDesc* __restric
   const int chunk = (c.n + nblk - 1) / nblk;
   const int b0 = blockIdx.x * chunk;
   const int b1 = min(c.n, b0 + chunk);
+  __shared__ float shm[2 * kThreads];
   double s = 0.0;
+  float lo = kInfF, hi = -kInfF;
   for (int i = b0 + threadIdx.x; i < b1; i += kThreads) {
     const double v = load_raw(c, i);
     const double d = v - mean;
     s += d * d;
-    y32[i] = (float)(v - shift);
+    const float w = (float)(v - shift);
+    y32[i] = w;
+    lo = fminf(lo, w);
+    hi = fmaxf(hi, w);
     if (y64) y64[i] = v;
   }
   for (int i = c.n + blockIdx.x * kThreads + threadIdx.x; i < c.n + kPad; i += nblk * kThreads) {
@@ -212,7 +241,12 @@ __global__ __launch_bounds__(kThreads) void k_stats_dev(const ColDesc* __restric
     if (y64) y64[i] = kInfD;
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) c.stat[blockIdx.x] = s;
+  block_minmax(lo, hi, shm);
+  if (threadIdx.x == 0) {
+    c.stat[blockIdx.x] = s;
+    c.stat_mm[blockIdx.x] = lo;
+    c.stat_mm[kStatBlocks + blockIdx.x] = hi;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_stats_final(const ColDesc* __restrict__ cols,
@@ -220,11 +254,20 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(const ColDesc* __restr
   const ColDesc c = cols[ids[blockIdx.x]];
   const int nblk = stat_blocks(c.n);
   __shared__ double sh[kThreads];
+  __shared__ float shm[2 * kThreads];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) s += c.stat[b];
+  float lo = kInfF, hi = -kInfF;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    s += c.stat[b];
+    lo = fminf(lo, c.stat_mm[b]);
+    hi = fmaxf(hi, c.stat_mm[kStatBlocks + b]);
+  }
   s = block_sum(s, sh);
+  block_minmax(lo, hi, shm);
   if (threadIdx.x == 0) {
     DevState& d = *c.st;
+    d.xmin = lo;
+    d.xmax = hi;
     const double n = d.n;
     d.var = s / (n - 1.0);
     d.sigma = sqrt(d.var);
@@ -265,10 +308,22 @@ __global__ void k_psi_begin(const ColDesc* __restrict__ cols, const int* __restr
   d.active = 1;
   d.g[stage] = g;
   const double ig2 = 1.0 / (g * g);
-  d.cf[0] = (float)ig2;
-  d.cf[1] = (float)(-0.5 * kLog2E * ig2);
+  d.psi_scale = (float)(1.0 / g);
+  d.psi_fast = ((double)d.xmax - (double)d.xmin) * (double)d.psi_scale <= kPsiFastRange ? 1 : 0;
   d.cd[0] = ig2;
   d.cd[1] = -0.5 * ig2;
+}
+
+// Scaled copy of the mixed form's psi pass: y = x32 * (1/g) in FP32 (padding
+// stays +inf).  Grid (blocks, columns); inactive columns are skipped.
+__global__ __launch_bounds__(kThreads) void k_psi_scale(const ColDesc* __restrict__ cols,
+                                                        const int* __restrict__ ids) {
+  const ColDesc c = cols[ids[blockIdx.y]];
+  if (!c.st->active) return;
+  const float s = c.st->psi_scale;
+  const int m = c.n + kPad;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += gridDim.x * kThreads)
+    c.y32[i] = i < c.n ? c.x32[i] * s : kInfF;
 }
 
 // psi_sums[0] = sum_{i<j} He_r(u) e^{-u^2/2}, psi_sums[1] = sum of its
@@ -312,24 +367,34 @@ __global__ void k_plugin_final(const ColDesc* __restrict__ cols, const int* __re
 }
 
 // ------------------------------------------------------------------ psi pair kernels
-template <int R, bool MASK>
-__device__ __forceinline__ void psi_run(const float4* __restrict__ tile, int jl, int jg, float xi, int i, float ig2,
-                                        float cg, float& aS, float& cS, float& aA, float& cA) {
+// Mixed form.  The samples are pre-scaled by 1/g (y = x / g, one O(n) pass
+// per stage), so a pair's w = u^2 = (y_i - y_j)^2 needs no per-pair scaling;
+// the term He_r(u) e^(-u^2/2) is formed as He_r in w (Horner, the integer
+// coefficients exact in FP32) times exp2(w * kPsiExp2), and both the term
+// and its absolute value are accumulated by one fma each (|He_r| as a source
+// modifier).  Per pair: sub, mul, mul, exp2, r/2 Horner ops, 2 fma.
+// MASK (a wave's diagonal run): pairs with j <= i get w = kWMax, whose
+// exponential is exactly 0 and whose He_r is finite.  CLAMP (padded tiles,
+// or a column whose scaled range could overflow He_r): w = min(w, kWMax),
+// so an infinite or huge distance also gives exactly 0.
+template <int R, bool MASK, bool CLAMP>
+__device__ __forceinline__ void psi_run(const float4* __restrict__ tile, int jl, int jg, float yi, int i, float& aS,
+                                        float& cS, float& aA, float& cA) {
   float rs = 0.f, ra = 0.f;
 #pragma unroll 4
   for (int q = 0; q < kRun / 4; ++q) {
     const float4 v = tile[(jl >> 2) + q];
-    const float xs[4] = {v.x, v.y, v.z, v.w};
+    const float ys[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float d = xi - xs[u];
-      float t = d * d;
-      if (MASK) t = (jg + 4 * q + u > i) ? t : kInfF;
-      const float w = fminf(t * ig2, kWMax);
-      const float e = __builtin_amdgcn_exp2f(t * cg);
-      const float term = herm_w<R>(w) * e;
-      rs += term;
-      ra += fabsf(term);
+      const float d = yi - ys[u];
+      float w = d * d;
+      if (CLAMP) w = fminf(w, kWMax);
+      if (MASK) w = (jg + 4 * q + u > i) ? w : kWMax;
+      const float e = __builtin_amdgcn_exp2f(w * kPsiExp2);
+      const float hw = herm_w<R>(w);
+      rs = __builtin_fmaf(hw, e, rs);
+      ra = __builtin_fmaf(fabsf(hw), e, ra);
     }
   }
   kahan_add(aS, cS, rs);
@@ -343,30 +408,38 @@ __global__ __launch_bounds__(kThreads) void k_psi_units_f32(const ColDesc* __res
   const Unit u = units[u0 + blockIdx.x];
   const ColDesc c = cols[u.col];
   if (!c.st->active) return;
-  const float* x = c.x32;
+  const float* y = c.y32;
   const int n = c.n;
+  const bool fast = c.st->psi_fast != 0;
   __shared__ float4 tile[kBJ / 4];
   __shared__ double red[2][4];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int row0 = u.row * kBI;
   const int i = row0 + tid;
-  const float xi = (i < n) ? x[i] : 0.f;
+  const float yi = (i < n) ? y[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
-  const float ig2 = c.st->cf[0], cg = c.st->cf[1];
   float aS = 0.f, cS = 0.f, aA = 0.f, cA = 0.f;
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
     __syncthreads();
-    for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
+    for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(y + t0)[q];
     __syncthreads();
     int js = max(t0, wave_i0);
     const int te = t0 + kBJ;
     if (js < te) {
+      const bool clamp = !fast || te > n;  // uniform: padded tile or unsafe range
       if (js == wave_i0) {
-        psi_run<R, true>(tile, js - t0, js, xi, i, ig2, cg, aS, cS, aA, cA);
+        if (clamp)
+          psi_run<R, true, true>(tile, js - t0, js, yi, i, aS, cS, aA, cA);
+        else
+          psi_run<R, true, false>(tile, js - t0, js, yi, i, aS, cS, aA, cA);
         js += kRun;
       }
-      for (; js < te; js += kRun) psi_run<R, false>(tile, js - t0, js, xi, i, ig2, cg, aS, cS, aA, cA);
+      if (clamp) {
+        for (; js < te; js += kRun) psi_run<R, false, true>(tile, js - t0, js, yi, i, aS, cS, aA, cA);
+      } else {
+        for (; js < te; js += kRun) psi_run<R, false, false>(tile, js - t0, js, yi, i, aS, cS, aA, cA);
+      }
     }
   }
   const bool valid = i < n;
@@ -515,16 +588,16 @@ __device__ __forceinline__ void lscv_run(const float4* __restrict__ tile, int jl
   }
 }
 
+// One LSCV work unit of the vector-ALU sweep: the unit's row of 256 samples
+// i against its j-range, for the HC bandwidths of its chunk; the block's
+// FP64 partial sums go to the unit's own slots.
 template <int HC>
-__global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __restrict__ cols,
-                                                             const Unit* __restrict__ units, int u0) {
-  const Unit u = units[u0 + blockIdx.x];
+__device__ __forceinline__ void lscv_unit_f32(const ColDesc* __restrict__ cols, const Unit& u, float4* tile,
+                                              double (*red)[2 * HC]) {
   const ColDesc c = cols[u.col];
-  if (c.st->status != kStOk) return;
+  if (c.st->status != kStOk) return;  // uniform over the block
   const float* x = c.x32;
   const int n = c.n;
-  __shared__ float4 tile[kBJ / 4];
-  __shared__ double red[4][2 * HC];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int row0 = u.row * kBI;
@@ -570,6 +643,44 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __re
       c.part[(int64_t)(2 * h + (tid & 1)) * c.n_items + u.item] = v;
     }
   }
+}
+
+template <int HC>
+__global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __restrict__ cols,
+                                                             const Unit* __restrict__ units, int u0) {
+  __shared__ float4 tile[kBJ / 4];
+  __shared__ double red[4][2 * HC];
+  lscv_unit_f32<HC>(cols, units[u0 + blockIdx.x], tile, red);
+}
+
+// Persistent form: a grid of about as many blocks as the chip holds at once
+// takes units [0, n_units) in list order (largest first) from a device
+// counter, one unit per block at a time, until the list is exhausted; every
+// block reaches the end of the list and exits.  One launch covers a whole
+// pass, so there is no partly filled last round per launch, and the longest
+// units start first wherever a block frees up.  *next must be 0 at launch.
+template <int HC>
+__global__ __launch_bounds__(kThreads) void k_lscv_units_f32_queue(const ColDesc* __restrict__ cols,
+                                                                   const Unit* __restrict__ units, int n_units,
+                                                                   int* __restrict__ next) {
+  __shared__ float4 tile[kBJ / 4];
+  __shared__ double red[4][2 * HC];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(next, 1);
+    __syncthreads();
+    const int k = cur;
+    __syncthreads();
+    if (k >= n_units) break;
+    lscv_unit_f32<HC>(cols, units[k], tile, red);
+  }
+}
+
+// Clears n ints (the work counters of a pass) with a kernel, so the pass
+// stays replayable from a graph.
+__global__ void k_zero_ints(int* __restrict__ p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
 }
 
 // Ceiling of the sweep's inner loop on the part: lscv_run<HC, false> over one
@@ -1025,8 +1136,10 @@ void launch_stats(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids,
   k_stats_final<<<n_ids, kThreads, 0, s>>>(cols, ids);
 }
 
-void launch_psi_begin(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage) {
-  if (n_ids > 0) k_psi_begin<<<id_blocks(n_ids), kThreads, 0, s>>>(cols, ids, n_ids, stage);
+void launch_psi_begin(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage, int f64) {
+  if (n_ids <= 0) return;
+  k_psi_begin<<<id_blocks(n_ids), kThreads, 0, s>>>(cols, ids, n_ids, stage);
+  if (!f64) k_psi_scale<<<dim3(128, n_ids), kThreads, 0, s>>>(cols, ids);
 }
 
 void launch_psi_finish(hipStream_t s, const ColDesc* cols, const int* ids, int n_ids, int stage, int was_f64,
@@ -1061,6 +1174,35 @@ void launch_psi_units(hipStream_t s, int r, int f64, int conditional, const ColD
       case 6: k_psi_units_f32<6><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
       default: k_psi_units_f32<4><<<n_units, kThreads, 0, s>>>(cols, units, u0); break;
     }
+  }
+}
+
+void launch_zero_ints(hipStream_t s, int* p, int n) {
+  if (n > 0) k_zero_ints<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+}
+
+int lscv_queue_blocks(int hc) {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  hipError_t e;
+  switch (hc) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<8>, kThreads, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<32>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<16>, kThreads, 0); break;
+  }
+  if (e != hipSuccess || per_cu < 1) return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
+void launch_lscv_units_queue(hipStream_t s, int hc, const ColDesc* cols, const Unit* units, int n_units, int* next,
+                             int blocks) {
+  if (n_units <= 0) return;
+  blocks = max(1, min(blocks, n_units));
+  switch (hc) {
+    case 8: k_lscv_units_f32_queue<8><<<blocks, kThreads, 0, s>>>(cols, units, n_units, next); break;
+    case 32: k_lscv_units_f32_queue<32><<<blocks, kThreads, 0, s>>>(cols, units, n_units, next); break;
+    default: k_lscv_units_f32_queue<16><<<blocks, kThreads, 0, s>>>(cols, units, n_units, next); break;
   }
 }
 

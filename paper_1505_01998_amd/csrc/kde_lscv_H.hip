@@ -671,6 +671,7 @@ kde_status kde_lscv_H_prepare(kde_ctx* c, kde_matrix x, kde_lscv_H_prep** out) {
     if (p->buf.p) (void)hipFree(p->buf.p);
     return s;
   }
+  c->preps.push_back(p.get());
   *out = p.release();
   return KDE_OK;
 }
@@ -690,7 +691,10 @@ kde_status kde_lscv_H_eval_prepared(kde_lscv_H_prep* p, const double* H, int32_t
 
 void kde_lscv_H_release(kde_lscv_H_prep* p) {
   if (!p) return;
-  (void)hipSetDevice(p->c->device);
+  kde_ctx* c = p->c;
+  auto& v = c->preps;
+  v.erase(std::remove(v.begin(), v.end(), p), v.end());
+  (void)hipSetDevice(c->device);
   if (p->buf.p) (void)hipFree(p->buf.p);
   delete p;
 }

@@ -59,6 +59,7 @@ struct ColPlan {
   bool want_x64 = false;
   bool raw_in_block = false;
   size_t raw_bytes = 0, off_raw = 0;
+  size_t off_y32 = 0, off_mm = 0;
   size_t off_x32 = 0, off_x64 = 0, off_stat = 0, off_nf = 0, off_psi_part = 0, off_psi_sums = 0, off_hin = 0,
          off_h = 0, off_c32 = 0, off_c64 = 0, off_part = 0, off_sums = 0, off_g = 0, off_gs = 0, bytes = 0;
 };
@@ -111,6 +112,7 @@ struct PassLayout {
   size_t o_cols = 0, o_stats = 0, o_pf = 0, o_lp = 0, o_lu = 0, o_lr = 0, o_lf = 0, bytes = 0;
   size_t o_nu = 0, o_nr = 0, o_pp = 0, o_pu = 0;  // tile pruning: near units/rows, prune ids, pruned units
   size_t sort_tmp = 0;                            // temporary bytes of the largest sort
+  size_t o_ctr = 0;                               // work counters of the persistent launches (ints)
   size_t o_begin[3] = {0, 0, 0}, o_finish[3] = {0, 0, 0}, o_psu[3] = {0, 0, 0}, o_pr[3] = {0, 0, 0},
          o_pc[3] = {0, 0, 0};
 };
@@ -129,6 +131,7 @@ struct JobGraph {
   const void* blocks = nullptr;  // device buffers the graph's kernels address
   const void* st = nullptr;
   const void* blob = nullptr;
+  const void* sort_tmp = nullptr;  // tile pruning: the sorts' temporary storage
   std::vector<ColPlan> plans;
   std::vector<int> plan_req;
   std::vector<ColDesc> cols;
@@ -175,12 +178,18 @@ struct kde_ctx {
   int opt_autotune = 0;            // synchronous jobs pick the LSCV variant with the tile autotuner
   int opt_graph = 0;               // synchronous jobs replay a captured graph of their launches
   int opt_prune = 0;               // LSCV tile pruning on sorted samples (mixed form, synchronous jobs)
+  int opt_persistent = 1;          // dense FP32 LSCV pass as one persistent launch over a device work queue
+  int queue_blocks[3] = {-1, -1, -1};  // resident blocks of the persistent LSCV kernel for hc 8, 16, 32 (-1: not asked)
   kde::DevBuf<char> sort_tmp;      // temporary storage of the column sorts
   kde::DevBuf<char> qbuf;          // query points / ranges, partials and outputs of the consumers
   kde::DevBuf<char> mdbuf;         // d-dimensional LSCV: samples, moments, whitened copy, partials
   std::vector<kde::JobGraph> graphs;  // at most kde::kMaxGraphs, least recently used replaced
   uint64_t graph_clock = 0;
   int64_t graph_captures = 0, graph_replays = 0;
+  // prepared LSCV_H samples and resumable jobs created on this context;
+  // kde_ctx_destroy releases those still alive
+  std::vector<kde_lscv_H_prep*> preps;
+  std::vector<kde_job*> jobs;
   // LSCV variant of the current job (from the options, or the autotuner)
   int job_hc = 16;
   int job_mfma = 0;
@@ -294,6 +303,8 @@ kde_status upload_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status execute(kde_ctx* c, IterPlan& it);
 kde_status sync_and_check(kde_ctx* c);
+// Folds the timed launches that have completed into the counters (no wait).
+kde_status collect_ready_timing(kde_ctx* c);
 kde_status ensure_pinned_bytes(kde_ctx* c, char*& p, size_t& cap, size_t bytes);
 
 // Grows a device buffer to hold at least `count` elements (contents are lost).

@@ -254,8 +254,10 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
   p.off_x32 = take(at, 4 * xn);
   if (p.want_x64) p.off_x64 = take(at, 8 * xn);
   p.off_stat = take(at, 8 * kStatBlocks);
+  p.off_mm = take(at, 8 * kStatBlocks);
   p.off_nf = take(at, 4 * kStatBlocks);
   if (p.plugin) {
+    if (!all64) p.off_y32 = take(at, 4 * xn);
     p.off_psi_part = take(at, 16 * p.psi_items.pairs.size());
     p.off_psi_sums = take(at, 16);
   }
@@ -286,8 +288,10 @@ void bind_column(const ColPlan& p, char* b, const void* raw, DevState* st, ColDe
   d.x32 = (float*)(b + p.off_x32);
   d.x64 = p.want_x64 ? (double*)(b + p.off_x64) : nullptr;
   d.stat = (double*)(b + p.off_stat);
+  d.stat_mm = (float*)(b + p.off_mm);
   d.stat_nf = (int*)(b + p.off_nf);
   if (p.plugin) {
+    d.y32 = p.off_y32 ? (float*)(b + p.off_y32) : nullptr;
     d.psi_part = (double*)(b + p.off_psi_part);
     d.psi_sums = (double*)(b + p.off_psi_sums);
   }
@@ -526,6 +530,33 @@ struct Blob {
 
 }  // namespace
 
+// Blocks of the persistent LSCV kernel that the device holds at once, asked
+// once per variant (0: unavailable, use sliced launches).
+int queue_blocks(kde_ctx* c, int hc) {
+  const int v = hc == 8 ? 0 : (hc == 32 ? 2 : 1);
+  if (c->queue_blocks[v] < 0) c->queue_blocks[v] = kde::lscv_queue_blocks(hc);
+  return c->queue_blocks[v];
+}
+
+kde_status collect_ready_timing(kde_ctx* c) {
+  std::vector<kde_ctx::Pending> later;
+  for (kde_ctx::Pending& p : c->pending) {
+    if (hipEventQuery(p.b) != hipSuccess) {
+      later.push_back(p);
+      continue;
+    }
+    float ms = 0.f;
+    KDE_HIP_TRY(c, hipEventElapsedTime(&ms, p.a, p.b));
+    c->t_launches[p.family] += 1;
+    c->t_ms[p.family] += ms;
+    c->t_evals[p.family] += p.evals;
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.swap(later);
+  return KDE_OK;
+}
+
 kde_status sync_and_check(kde_ctx* c) {
   KDE_HIP_TRY(c, hipGetLastError());
   KDE_HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -562,6 +593,8 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
   L.o_nr = b.add(it.near_rows.data(), vbytes(it.near_rows));
   L.o_pp = b.add(it.ids_prune.data(), vbytes(it.ids_prune));
   L.o_pu = b.add(it.prune_units.data(), vbytes(it.prune_units));
+  static const int kZeroCounters[64] = {};
+  L.o_ctr = b.add(kZeroCounters, sizeof(kZeroCounters));
   L.bytes = b.bytes;
   L.sort_tmp = 0;
   for (const SortJob& j : it.sorts) {
@@ -569,6 +602,11 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
     if (t == 0) return fail(c, KDE_E_DEVICE, "sort temporary size query failed");
     L.sort_tmp = std::max(L.sort_tmp, t);
   }
+  // a device buffer that must grow may still be read by work in flight on the
+  // stream (the server enqueues an iteration before the previous one ends):
+  // wait for the stream before replacing it
+  if ((L.sort_tmp > c->sort_tmp.cap && c->sort_tmp.p) || (b.bytes + 256 > c->blob.cap && c->blob.p))
+    KDE_HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (L.sort_tmp && (s = ensure(c, c->sort_tmp, L.sort_tmp))) return s;
   if ((s = ensure_pinned_bytes(c, c->h_blob, c->h_blob_cap, b.bytes + 256))) return s;
   if ((s = ensure(c, c->blob, b.bytes + 256))) return s;
@@ -597,7 +635,7 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
   for (int q = 0; q < 3; ++q) {
     if (it.ids_begin[q].empty() && it.psi_units[q].empty() && it.ids_finish[q].empty()) continue;
     const int r = 8 - 2 * q;
-    kde::launch_psi_begin(st, cols, ids(L.o_begin[q]), (int)it.ids_begin[q].size(), q);
+    kde::launch_psi_begin(st, cols, ids(L.o_begin[q]), (int)it.ids_begin[q].size(), q, all64 ? 1 : 0);
     const Unit* pu = (const Unit*)(d + L.o_psu[q]);
     s = for_each_launch(c, it.psi_cost[q], all64, [&](int u0, int cnt, double evals) -> kde_status {
       kde_ctx::Pending pd{nullptr, nullptr, kde::kFamPsi, evals};
@@ -653,14 +691,27 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
     if (s) return s;
   }
   const Unit* lu = (const Unit*)(d + L.o_lu);
-  s = for_each_launch(c, it.lscv_cost, all64, [&](int u0, int cnt, double evals) -> kde_status {
+  const int qb = (!all64 && !c->job_mfma && c->opt_persistent && !it.lscv_units.empty()) ? queue_blocks(c, hc) : 0;
+  if (qb > 0) {
+    // the whole dense pass in one persistent launch over a device work queue
+    double evals = 0.0;
+    for (const UnitCost& u : it.lscv_cost) evals += u.evals;
+    int* ctr = (int*)(d + L.o_ctr);
+    kde::launch_zero_ints(st, ctr, 1);
     kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
-    kde_status s2 = timed_begin(c, pd);
-    if (s2) return s2;
-    kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->job_mfma, 0, cols, lu, u0, cnt);
-    return timed_end(c, pd);
-  });
-  if (s) return s;
+    if ((s = timed_begin(c, pd))) return s;
+    kde::launch_lscv_units_queue(st, hc, cols, lu, (int)it.lscv_units.size(), ctr, qb);
+    if ((s = timed_end(c, pd))) return s;
+  } else {
+    s = for_each_launch(c, it.lscv_cost, all64, [&](int u0, int cnt, double evals) -> kde_status {
+      kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
+      kde_status s2 = timed_begin(c, pd);
+      if (s2) return s2;
+      kde::launch_lscv_units(st, hc, all64 ? 1 : 0, c->job_mfma, 0, cols, lu, u0, cnt);
+      return timed_end(c, pd);
+    });
+    if (s) return s;
+  }
   kde::launch_reduce_rows(st, (const RowDesc*)(d + L.o_lr), (int)it.lscv_rows.size());
   kde::launch_lscv_finalize(st, cols, ids(L.o_lf), (int)it.ids_lscv_final.size(), all64 ? 1 : 0);
   KDE_HIP_TRY(c, hipGetLastError());
@@ -723,6 +774,8 @@ std::string job_signature(const kde_ctx* c, const kde_request* reqs, int32_t n_r
   put(c->opt_seg);
   put(c->opt_launch_evals);
   put(c->opt_fp64_kappa);
+  put(c->opt_prune);
+  put(c->opt_persistent);
   for (int32_t k = 0; k < n_req; ++k) {
     const kde_request& r = reqs[k];
     const int ok = st[k] == KDE_OK;
@@ -816,6 +869,7 @@ kde_status capture_job(kde_ctx* c, std::string sig) {
   g.blocks = c->blocks.p;
   g.st = c->st.p;
   g.blob = c->blob.p;
+  g.sort_tmp = c->sort_tmp.p;
   g.plans = c->plans;
   g.plan_req = c->plan_req;
   g.cols = c->iter.cols;
@@ -837,7 +891,7 @@ kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std:
   st.assign(n_req, KDE_OK);
   msg.assign(n_req, "");
   if ((s = kde::select_variant(c, reqs, n_req))) return s;
-  const bool use_graph = c->opt_graph && !c->opt_prune && !c->timing && c->stream != nullptr;
+  const bool use_graph = c->opt_graph && !c->timing && c->stream != nullptr;
   std::string sig;
   if (use_graph) {
     for (int32_t k = 0; k < n_req; ++k) {
@@ -847,7 +901,7 @@ kde_status run_requests(kde_ctx* c, const kde_request* reqs, int32_t n_req, std:
     sig = job_signature(c, reqs, n_req, st);
     for (kde::JobGraph& g : c->graphs)
       if (g.exec && g.sig == sig && g.blocks == c->blocks.p && g.st == c->st.p && g.blob == c->blob.p &&
-          !g.plans.empty())
+          g.sort_tmp == c->sort_tmp.p && !g.plans.empty())
         return replay_job(c, g, reqs);
   }
   c->plans.clear();
@@ -1025,6 +1079,9 @@ void kde_ctx_destroy(kde_ctx* c) {
   c->server.reset();
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  // handles created on the context and not yet released
+  while (!c->preps.empty()) kde_lscv_H_release(c->preps.back());
+  while (!c->jobs.empty()) kde_job_destroy(c->jobs.back());
   (void)hipFree(c->stage.p);
   (void)hipFree(c->blocks.p);
   (void)hipFree(c->st.p);
@@ -1084,6 +1141,8 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_mfma = value < 0 ? 0 : (value != 0);
   } else if (k == "prune") {
     c->opt_prune = value < 0 ? 0 : (value != 0);
+  } else if (k == "persistent") {
+    c->opt_persistent = value < 0 ? 1 : (value != 0);
   } else if (k == "graph") {
     c->opt_graph = value < 0 ? 0 : (value != 0);
   } else if (k == "autotune") {

@@ -1,18 +1,27 @@
 // kde_server.hip -- continuous-batching server for bandwidth-selection requests.
 //
 // One scheduler thread per context.  Clients submit requests (copied on
-// submit), which wait in a FIFO queue until admission: a free slot and room
-// in the HBM budget for the request's device block.  Admitted requests stay
-// resident.  Each scheduler iteration builds one executor pass over all
-// resident requests: the moments of newly admitted ones, then plug-in stage
-// units and LSCV units taken request by request, smallest remaining work
-// first (optionally aged by the time waited), until the iteration's
-// evaluation budget is used; a stage whose last
-// units are in the pass is finished in it, and requests whose work is all
-// done are finalised and copied back.  Requests arriving while an iteration
-// runs join the next one, so their work overlaps with the requests already
-// on the device.  Every request keeps the work decomposition and reduction
-// order it has alone, so its results are bitwise those of kde_batch.
+// submit), which queue in arrival order until admission: a free slot, room
+// in the HBM budget and a place for the request's device block in the
+// server's arena (one allocation of the whole budget, made when the server
+// starts; kde_arena.h).  The first queued request that does not fit keeps its
+// room, and later smaller requests pass it only within the rest of the
+// budget (kde_admit.h), so a large request is not held up indefinitely and
+// small ones are not held up behind it.  Admitted requests stay resident.
+// Each scheduler iteration builds one executor pass over all resident
+// requests: the moments of newly admitted ones, then plug-in stage units and
+// LSCV units taken request by request, smallest remaining work first
+// (optionally aged by the time waited), until the iteration's evaluation
+// budget is used; a stage whose last units are in the pass is finished in it,
+// and requests whose work is all done are finalised.  Iterations are
+// pipelined two deep: the next iteration is planned, packed and enqueued
+// while the previous one runs on the device, and only then is the previous
+// one waited for and its finished requests copied back (on a second stream)
+// and retired, so the device does not idle for the host's planning.
+// Requests arriving while an iteration runs join the next one, so their work
+// overlaps with the requests already on the device.  Every request keeps the
+// work decomposition and reduction order it has alone, so its results are
+// bitwise those of kde_batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +30,8 @@
 #include <cstring>
 #include <unordered_map>
 
+#include "kde_admit.h"
+#include "kde_arena.h"
 #include "kde_runtime.h"
 
 namespace kde {
@@ -40,7 +51,10 @@ struct SrvReq {
   std::vector<char> host_x;  // copy of host samples
   void* dev_x = nullptr;     // copy of device samples
   ColPlan plan;
+  uint64_t fp = 0;           // footprint in the arena (rounded block size)
+  double work = 0.0;         // pair-term evaluations of the whole request
   char* block = nullptr;
+  int64_t block_off = -1;    // the block's offset in the arena
   int slot = -1;
   bool stats_done = false, plugin_done = false, prep_done = false, lscv_done = false;
   int stage = 0;
@@ -50,8 +64,10 @@ struct SrvReq {
   double remaining = 0.0;
   double key = 0.0;  // the scheduler's order of this iteration
   bool finishing = false, done = false;
-  bool cancel = false;    // kde_cancel on an admitted request: dropped after the current iteration
+  bool cancel = false;    // kde_cancel on an admitted request: dropped at the next iteration
   bool injected = false;  // the failure hook names this request
+  bool dropped = false;   // cancelled while resident: leaves without a result
+  int64_t retire_iter = -1;  // the iteration at whose end the request leaves (-1: still working)
   kde_result res;
   std::vector<double> g, gs;
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -73,6 +89,12 @@ struct Server {
   std::thread th;
   DevBuf<DevState> st;
   DevState* h_st = nullptr;
+  DevBuf<char> arena_mem;  // the HBM budget, reserved at start
+  Arena arena;
+  hipStream_t copy_stream = nullptr;  // result copies of a finished iteration
+  hipEvent_t ev[4] = {};              // start / end of the two iterations in the pipeline
+  char* h_blob_alt = nullptr;         // second pinned staging blob (iterations alternate)
+  size_t h_blob_alt_cap = 0;
   IterPlan it;
   // column table of a pass: slot s at s, for the slots below `top` (one past
   // the highest resident slot); with tile pruning, slot s's near-tile and
@@ -83,6 +105,7 @@ struct Server {
   // so that full iterations last about the target time
   double iter_budget = 0.0;
   void loop();
+  void release_block(SrvReq& r);
 };
 
 namespace {
@@ -113,49 +136,135 @@ void take_units(const std::vector<Unit>& u, const std::vector<UnitCost>& cu, siz
 
 }  // namespace
 
+// Returns a request's block to the arena and its slot (mu held).
+void Server::release_block(SrvReq& r) {
+  if (r.block_off >= 0) arena.release(r.block_off);
+  r.block_off = -1;
+  r.block = nullptr;
+  used -= r.fp;
+  free_slots.push_back(r.slot);
+}
+
 void Server::loop() {
   kde_ctx* ctx = c;
   (void)hipSetDevice(ctx->device);
   const bool cond = ctx->prec != KDE_PREC_FP64 && ctx->opt_fp64_kappa > 0.0;
+  // the iteration in flight on the device (if any)
+  struct Flight {
+    bool on = false;
+    int64_t id = -1;
+    int ev = 0;  // its events: ev[ev], ev[ev + 1]
+    bool full = false;
+    double left0 = 0.0;
+  } prev;
+  int64_t iter_id = 0;
+  int ev_next = 0;
+  // Waits for the iteration in flight and retires the requests that leave at
+  // its end; on a failure every resident request ends with KDE_E_DEVICE.
+  auto retire = [&](const Flight& f, kde_status s) {
+    if (s == KDE_OK && f.on) {
+      const hipError_t e = hipEventSynchronize(ev[f.ev + 1]);
+      if (e != hipSuccess) s = fail(ctx, KDE_E_DEVICE, std::string("server iteration: ") + hipGetErrorString(e));
+    }
+    if (s == KDE_OK) s = collect_ready_timing(ctx);
+    // finished requests: state and curves, copied on the side stream (the
+    // main stream already runs the next iteration)
+    if (s == KDE_OK) {
+      for (auto& r : active) {
+        if (r->retire_iter != f.id || r->dropped || r->injected) continue;
+        hipError_t e = hipMemcpyAsync(h_st + r->slot, st.p + r->slot, sizeof(DevState), hipMemcpyDeviceToHost,
+                                      copy_stream);
+        if (e == hipSuccess && r->plan.lscv) {
+          ColDesc d;
+          bind_column(r->plan, r->block, r->dev_x, st.p + r->slot, d);
+          r->g.assign(r->plan.n_h, 0.0);
+          r->gs.assign(r->plan.n_h, 0.0);
+          e = hipMemcpyAsync(r->g.data(), d.g, sizeof(double) * r->plan.n_h, hipMemcpyDeviceToHost, copy_stream);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(r->gs.data(), d.gs, sizeof(double) * r->plan.n_h, hipMemcpyDeviceToHost, copy_stream);
+        }
+        if (e != hipSuccess) s = fail(ctx, KDE_E_DEVICE, std::string("result copy: ") + hipGetErrorString(e));
+      }
+      const hipError_t e = hipStreamSynchronize(copy_stream);
+      if (s == KDE_OK && e != hipSuccess) s = fail(ctx, KDE_E_DEVICE, std::string("result copy: ") + hipGetErrorString(e));
+    }
+    if (s != KDE_OK) (void)hipStreamSynchronize(ctx->stream);  // nothing may still use the blocks
+    if (s == KDE_OK && f.on && f.full && ctx->opt_serve_iter_s > 0.0) {
+      // a full iteration: move the budget towards the target duration (by
+      // the square root of the ratio, within [1, 64] x serve_iter_evals)
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[f.ev], ev[f.ev + 1]) == hipSuccess && ms > 0.1f) {
+        const double want = f.left0 * std::sqrt(ctx->opt_serve_iter_s / (ms * 1e-3));
+        iter_budget = std::min(64.0 * ctx->opt_serve_iter_evals, std::max(ctx->opt_serve_iter_evals, want));
+      }
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    std::vector<std::shared_ptr<SrvReq>> keep;
+    for (auto& r : active) {
+      if (s == KDE_OK && r->retire_iter != f.id) {
+        keep.push_back(r);
+        continue;
+      }
+      if (s != KDE_OK || r->injected) {
+        finish_with(*this, r, KDE_E_DEVICE);
+      } else if (r->dropped) {
+        finish_with(*this, r, KDE_E_CANCELLED);
+      } else {
+        fill_result(r->plan, h_st[r->slot], r->res);
+        finish_with(*this, r, r->res.status);
+      }
+      release_block(*r);
+    }
+    active.swap(keep);
+    cv_done.notify_all();
+  };
   for (;;) {
     std::vector<std::shared_ptr<SrvReq>> admitted;
     {
       std::unique_lock<std::mutex> lk(mu);
       for (;;) {
-        // admission: FIFO, slots and HBM budget
-        while (!queue.empty() && !free_slots.empty()) {
-          std::shared_ptr<SrvReq> r = queue.front();
-          const uint64_t fp = r->plan.bytes;
-          if (fp > budget) {
-            queue.pop_front();
-            finish_with(*this, r, KDE_E_NOMEM);
+        // requests larger than the whole budget never fit
+        for (auto q = queue.begin(); q != queue.end();) {
+          if ((*q)->fp > budget) {
+            finish_with(*this, *q, KDE_E_NOMEM);
+            q = queue.erase(q);
             cv_done.notify_all();
-            continue;
+          } else {
+            ++q;
           }
-          if (used + fp > budget) break;
-          queue.pop_front();
+        }
+        std::vector<uint64_t> fps;
+        std::vector<double> work;
+        for (auto& r : queue) {
+          fps.push_back(r->fp);
+          work.push_back(r->work);
+        }
+        std::vector<Resident> res;
+        for (auto& r : active) res.push_back(Resident{r->fp, r->retire_iter >= 0 ? 0.0 : r->remaining});
+        std::vector<int64_t> offs(queue.size(), -1);
+        const std::vector<size_t> take = admit(fps, work, res, budget, used, (int)free_slots.size(), [&](size_t k) {
+          offs[k] = arena.alloc(fps[k]);
+          return offs[k] >= 0;
+        });
+        for (size_t t = 0; t < take.size(); ++t) {
+          std::shared_ptr<SrvReq> r = queue[take[t]];
+          r->block_off = offs[take[t]];
+          r->block = arena_mem.p + r->block_off;
           r->slot = free_slots.back();
           free_slots.pop_back();
-          used += fp;
           admitted.push_back(r);
         }
-        if (!admitted.empty() || !active.empty()) break;
-        if (stopping) return;
+        for (size_t t = take.size(); t-- > 0;) queue.erase(queue.begin() + (long)take[t]);
+        bool busy_now = !admitted.empty() || prev.on;
+        for (auto& r : active) busy_now = busy_now || r->retire_iter < 0;
+        if (busy_now) break;
+        if (stopping && active.empty()) return;
         cv_work.wait_for(lk, std::chrono::milliseconds(50));
       }
     }
-    // device blocks and initial state of newly admitted requests
+    // initial state of newly admitted requests
     for (auto& r : admitted) {
       r->t_admit = now_s();
-      if (hipMalloc((void**)&r->block, r->plan.bytes) != hipSuccess) {
-        r->block = nullptr;
-        std::lock_guard<std::mutex> lk(mu);
-        used -= r->plan.bytes;
-        free_slots.push_back(r->slot);
-        finish_with(*this, r, KDE_E_NOMEM);
-        cv_done.notify_all();
-        continue;
-      }
       init_state(r->plan, ctx->opt_fp64_kappa, h_st[r->slot]);
       (void)hipMemcpyAsync(st.p + r->slot, h_st + r->slot, sizeof(DevState), hipMemcpyHostToDevice, ctx->stream);
       psi_units_of(r->plan, r->slot, r->psi_u, r->psi_c);
@@ -166,9 +275,24 @@ void Server::loop() {
       for (const UnitCost& u : r->lscv_c) r->remaining += u.evals;
       active.push_back(r);
     }
-    if (active.empty()) continue;
-    // one executor pass over the resident requests, smallest remaining first;
-    // with aging (time constant tau) a request's remaining work counts as
+    // the requests this iteration works on: resident ones that do not leave
+    // at the end of the iteration in flight; a cancelled one leaves now
+    const int64_t cur = iter_id++;
+    std::vector<std::shared_ptr<SrvReq>> work;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto& r : active) {
+        if (r->retire_iter >= 0) continue;
+        if (r->cancel) {
+          r->dropped = true;
+          r->retire_iter = cur;
+          continue;
+        }
+        work.push_back(r);
+      }
+    }
+    // one executor pass over them, smallest remaining first; with aging (time
+    // constant tau) a request's remaining work counts as
     // remaining / (1 + waited / tau), so long-waiting large requests move up
     it.clear();
     top = 0;
@@ -176,16 +300,16 @@ void Server::loop() {
     it.cols.assign((ctx->opt_prune ? 3 : 1) * (size_t)top, ColDesc());
     {
       const double now = now_s(), tau = ctx->opt_serve_aging_s;
-      for (auto& r : active) r->key = tau > 0.0 ? r->remaining / (1.0 + (now - r->t_submit) / tau) : r->remaining;
+      for (auto& r : work) r->key = tau > 0.0 ? r->remaining / (1.0 + (now - r->t_submit) / tau) : r->remaining;
     }
-    std::sort(active.begin(), active.end(), [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
+    std::sort(work.begin(), work.end(), [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
       return a->key < b->key || (a->key == b->key && a->ticket < b->ticket);
     });
     // An iteration is one launch per pass, so it must hold several waves of its
     // largest units or the launch tail idles the chip: at least 6 rounds of
     // 1024 resident blocks of the largest unit any resident request has next.
     double max_unit = 0.0;
-    for (auto& r : active) {
+    for (auto& r : work) {
       if (r->plan.plugin && !r->plugin_done && r->psi_next < r->psi_c.size())
         max_unit = std::max(max_unit, r->psi_c[r->psi_next].evals);
       if (r->plan.lscv && !r->lscv_done && r->lscv_next < r->lscv_c.size())
@@ -196,7 +320,7 @@ void Server::loop() {
     double left = std::max(base, 6.0 * 1024.0 * max_unit);
     const double left0 = left;
     bool first = true;
-    for (auto& r : active) {
+    for (auto& r : work) {
       ColPlan& p = r->plan;
       ColDesc d;
       bind_column(p, r->block, r->dev_x, st.p + r->slot, d);
@@ -247,63 +371,49 @@ void Server::loop() {
         }
       }
       r->finishing = (!p.plugin || r->plugin_done) && (!p.lscv || r->lscv_done);
-    }
-    for (auto& r : active)
       if (ctx->opt_serve_fail_ticket != 0 && r->ticket == ctx->opt_serve_fail_ticket) r->injected = true;
-    const double t_exec = now_s();
-    kde_status s = execute(ctx, it);
-    for (auto& r : active) {
-      if (!r->finishing || s != KDE_OK || r->injected) continue;
-      if (hipMemcpyAsync(h_st + r->slot, st.p + r->slot, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream) !=
-          hipSuccess)
-        s = KDE_E_DEVICE;
-      if (r->plan.lscv) {
-        r->g.assign(r->plan.n_h, 0.0);
-        r->gs.assign(r->plan.n_h, 0.0);
-        const ColDesc& d = it.cols[r->slot];
-        if (hipMemcpyAsync(r->g.data(), d.g, sizeof(double) * r->plan.n_h, hipMemcpyDeviceToHost, ctx->stream) !=
-                hipSuccess ||
-            hipMemcpyAsync(r->gs.data(), d.gs, sizeof(double) * r->plan.n_h, hipMemcpyDeviceToHost, ctx->stream) !=
-                hipSuccess)
-          s = KDE_E_DEVICE;
+      if (r->finishing || r->injected) r->retire_iter = cur;
+    }
+    kde_status s = KDE_OK;
+    Flight now;
+    if (!work.empty()) {
+      // iterations alternate between two pinned staging blobs: the previous
+      // iteration's upload may still be pending
+      std::swap(ctx->h_blob, h_blob_alt);
+      std::swap(ctx->h_blob_cap, h_blob_alt_cap);
+      now.on = true;
+      now.id = cur;
+      now.ev = ev_next;
+      now.full = left <= 0.0;
+      now.left0 = left0;
+      ev_next ^= 2;
+      hipError_t e = hipEventRecord(ev[now.ev], ctx->stream);
+      if (e != hipSuccess) s = fail(ctx, KDE_E_DEVICE, std::string("event: ") + hipGetErrorString(e));
+      if (s == KDE_OK) s = execute(ctx, it);
+      if (s == KDE_OK) {
+        e = hipEventRecord(ev[now.ev + 1], ctx->stream);
+        if (e != hipSuccess) s = fail(ctx, KDE_E_DEVICE, std::string("event: ") + hipGetErrorString(e));
       }
     }
-    if (s == KDE_OK) s = sync_and_check(ctx);
-    if (s == KDE_OK && ctx->opt_serve_iter_s > 0.0 && left <= 0.0) {
-      // a full iteration: move the budget towards the target duration (by
-      // the square root of the ratio, within [1, 64] x serve_iter_evals)
-      const double dt = now_s() - t_exec;
-      if (dt > 1e-4) {
-        const double want = left0 * std::sqrt(ctx->opt_serve_iter_s / dt);
-        iter_budget = std::min(64.0 * ctx->opt_serve_iter_evals, std::max(ctx->opt_serve_iter_evals, want));
-      }
+    if (s != KDE_OK) {
+      // the pass could not be enqueued: every resident request fails
+      Flight all;
+      all.on = false;
+      retire(all, s);
+      prev.on = false;
+      continue;
     }
-    std::lock_guard<std::mutex> lk(mu);
-    std::vector<std::shared_ptr<SrvReq>> keep;
-    for (auto& r : active) {
-      // a request leaves when it is finished, when the pass failed (for all of
-      // its requests, or for this one through the failure hook), or when it
-      // was cancelled and not finishing in this pass
-      const bool cancelled = r->cancel && !r->finishing;
-      if (s != KDE_OK || r->finishing || r->injected || cancelled) {
-        if (s != KDE_OK || r->injected) {
-          finish_with(*this, r, KDE_E_DEVICE);
-        } else if (cancelled) {
-          finish_with(*this, r, KDE_E_CANCELLED);
-        } else {
-          fill_result(r->plan, h_st[r->slot], r->res);
-          finish_with(*this, r, r->res.status);
-        }
-        (void)hipFree(r->block);
-        r->block = nullptr;
-        used -= r->plan.bytes;
-        free_slots.push_back(r->slot);
-      } else {
-        keep.push_back(r);
-      }
+    // the previous iteration ends while this one runs
+    if (prev.on) retire(prev, KDE_OK);
+    if (now.on) {
+      prev = now;
+    } else {
+      prev.on = false;
+      // requests that left with no iteration in flight (cancelled)
+      Flight none;
+      none.id = cur;
+      retire(none, KDE_OK);
     }
-    active.swap(keep);
-    cv_done.notify_all();
   }
 }
 
@@ -312,7 +422,12 @@ void ServerDeleter::operator()(Server* s) const {
   for (auto& kv : s->all)
     if (kv.second->dev_x) (void)hipFree(kv.second->dev_x);
   (void)hipFree(s->st.p);
+  (void)hipFree(s->arena_mem.p);
   if (s->h_st) (void)hipHostFree(s->h_st);
+  if (s->h_blob_alt) (void)hipHostFree(s->h_blob_alt);
+  for (hipEvent_t e : s->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   delete s;
 }
 
@@ -379,6 +494,22 @@ kde_status kde_server_start(kde_ctx* c, uint64_t hbm_budget_bytes, int32_t max_s
     s->h_st = nullptr;
     return fail(c, KDE_E_NOMEM, "pinned host allocation failed");
   }
+  // the whole budget, reserved once; request blocks are placed inside it
+  const uint64_t arena_bytes = hbm_budget_bytes / kde::Arena::kAlign * kde::Arena::kAlign;
+  if (arena_bytes == 0) return fail(c, KDE_E_INVAL, "the budget holds no block");
+  if ((st = kde::ensure(c, s->arena_mem, (size_t)arena_bytes)))
+    return fail(c, KDE_E_NOMEM, "the HBM budget could not be reserved on the device");
+  s->arena.reset(arena_bytes);
+  s->budget = arena_bytes;
+  if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+    s->copy_stream = nullptr;
+    return fail(c, KDE_E_DEVICE, "stream creation failed");
+  }
+  for (hipEvent_t& e : s->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      return fail(c, KDE_E_DEVICE, "event creation failed");
+    }
   for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->running = true;
   Server* raw = s.get();
@@ -400,6 +531,11 @@ kde_status kde_submit(kde_ctx* c, const kde_request* req, uint64_t* ticket) {
     e = kde::plan_column(c, *req, r->plan);
   }
   if (!e.empty()) return fail(c, KDE_E_INVAL, e);
+  r->fp = kde::Arena::round(r->plan.bytes);
+  {
+    const double pairs = 0.5 * (double)r->plan.n * (double)(r->plan.n - 1);
+    r->work = pairs * ((r->plan.lscv ? r->plan.n_h : 0) + r->plan.stages);
+  }
   const size_t bytes = r->plan.raw_bytes;
   if (req->x.on_device) {
     if (hipMalloc(&r->dev_x, bytes) != hipSuccess) return fail(c, KDE_E_NOMEM, "device copy of the column failed");

@@ -14,8 +14,10 @@
 // identical units (a row of 256 samples against a j-range as long as the
 // column's, capped at 8192) are timed and the difference is divided into the
 // extra work, which cancels launch overhead and the partly filled last round
-// of blocks.  Pair terms cost the same whatever the sample values, so the
-// trial column is all zeros.  The rate is then scaled by the share of the
+// of blocks.  The trial column's samples are spread evenly and the grid's
+// exponentials cover the range of a real one: the part draws less power on
+// an all-zero column and then runs a few per cent faster than on real data.
+// The rate is then scaled by the share of the
 // variant's bandwidth slots that the grid fills (a 100-point grid fills 100
 // of 104 slots at 8 per block, 112 at 16, 128 at 32).  Decisions are cached
 // per context by shape (quarter octave of n, grid size).
@@ -53,7 +55,7 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     out = hit->second;
     return KDE_OK;
   }
-  // trial column: L zero samples (+ padding), one row against j in [0, L)
+  // trial column: L samples (+ padding), one row against j in [0, L)
   const int L = (int)std::min<int64_t>(((n + kBJ - 1) / kBJ) * kBJ, kTrialMaxJ);
   const int B2 = 2 * kTrialUnits;
   const size_t xn = (size_t)L + kPad;
@@ -68,10 +70,23 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
   kde_status s;
   if ((s = ensure(c, c->tune_buf, at))) return s;
   char* b = c->tune_buf.p;
-  // zero samples and state (status OK); coefficients -1, so masked pairs
-  // (infinite distance) give exp2(-inf) = 0 as in a real pass
+  // zero state (status OK); samples spread evenly over [0, 4) with +inf
+  // padding and coefficients of 32 bandwidths log-spaced over [0.01, 1], so
+  // the exponentials span the range of a real grid (on an all-zero column
+  // every exponential is exp2(0), and the part then runs a few per cent
+  // faster than on real data)
   KDE_HIP_TRY(c, hipMemsetAsync(b, 0, o_units, c->stream));
-  KDE_HIP_TRY(c, hipMemsetD32Async((hipDeviceptr_t)(b + o_c), 0xBF800000u, 32, c->stream));
+  {
+    std::vector<float> hx(xn), hcf(32);
+    for (size_t j = 0; j < xn; ++j) hx[j] = j < (size_t)L ? 4.0f * (float)j / (float)L : HUGE_VALF;
+    for (int k = 0; k < 32; ++k) {
+      const double h = std::exp(std::log(0.01) + std::log(100.0) * k / 31.0);
+      hcf[k] = (float)(-1.4426950408889634 / (4.0 * h * h));
+    }
+    KDE_HIP_TRY(c, hipMemcpyAsync(b + o_x, hx.data(), 4 * xn, hipMemcpyHostToDevice, c->stream));
+    KDE_HIP_TRY(c, hipMemcpyAsync(b + o_c, hcf.data(), 4 * 32, hipMemcpyHostToDevice, c->stream));
+    KDE_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   // every unit writes its own partial slots (item = unit index)
   std::vector<Unit> u(B2);
   for (int k = 0; k < B2; ++k) u[k] = Unit{0, 0, 0, L, k, 0};

@@ -180,3 +180,28 @@ def _check_stored_oracle(out, specs):
             assert gap <= 2 * float(np.max(np.abs(r.g[idx] - ref["g"][m]))), (k, r.k_lscv, ks)
     print(f"batch-512 vs stored oracle: {len(ref['col'])} columns, max |dg|/gscale {worst:.2e}, "
           f"{ties} near ties")
+
+
+def test_persistent_pass_bitwise_equals_sliced(kde):
+    """The dense LSCV pass as one persistent launch over a device work queue
+    gives bitwise the sums of the sliced launches, for a single column and for
+    a batch of uneven columns (units of many columns in one queue)."""
+    x = workloads.draw("bimodal", 70_001, 31, np.float32)
+    grid = np.geomspace(0.003, 1.5, 77)
+    cols = [workloads.draw(f, 900 + 1531 * k, 40 + k, np.float32) for k, f in
+            enumerate(workloads.BATCH_FAMILIES * 3)]
+    reqs = [kde.Request(c, kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV, 3,
+                        workloads.BATCH_GRID) for c in cols]
+    out = {}
+    for persistent in (0, 1):
+        with kde.Context(0) as c:
+            c.set_option("persistent", persistent)
+            c.set_option("launch_evals", int(2e9))  # several sliced launches
+            s = c.lscv_sums(x, grid)
+            res = c.batch(reqs)
+            out[persistent] = (s, res)
+    (s0, r0), (s1, r1) = out[0], out[1]
+    assert np.array_equal(s0[0], s1[0]) and np.array_equal(s0[1], s1[1])
+    for a, b in zip(r0, r1):
+        assert a.status == b.status == kde.KDE_OK
+        assert np.array_equal(a.g, b.g) and a.h_lscv == b.h_lscv and a.h_plugin == b.h_plugin

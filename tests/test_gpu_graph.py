@@ -110,3 +110,32 @@ def test_batch_replays_and_signature_changes(kde):
         assert g.graph_stats() == (captures, replays)
     # n0 changes the shapes once: two captures, three replays
     assert (captures, replays) == (2, 3)
+
+
+def test_pruned_jobs_replay(kde):
+    """With tile pruning the job's column sorts are kernels of the library, so
+    a pruned job is captured and replayed like a dense one; every replay is
+    bitwise the eager pruned job, evaluation counts included."""
+    import torch
+
+    grid = np.geomspace(0.002, 1.0, 64)
+    A = kde.KDE_METHOD_ROT | kde.KDE_METHOD_PLUGIN | kde.KDE_METHOD_LSCV
+    with kde.Context(0) as g, kde.Context(0) as e:
+        for c in (g, e):
+            c.set_option("prune", 1)
+        g.set_option("graph", 1)
+        for rep in range(3):
+            cols = [workloads.draw(f, 6000 + 17 * k, 300 + 10 * rep + k, np.float32)
+                    for k, f in enumerate(workloads.BATCH_FAMILIES)]
+            reqs = [kde.Request(x, A, 3, grid) for x in cols]
+            rg = g.batch(reqs)
+            re_ = e.batch(reqs)
+            for a, b in zip(rg, re_):
+                assert a.status == b.status == kde.KDE_OK
+                assert _same(a.g, b.g) and a.h_lscv == b.h_lscv and a.h_plugin == b.h_plugin, rep
+                assert a.lscv_evals == b.lscv_evals < a.lscv_evals_dense
+            y = torch.randn(1 << 18, device="cuda:0")
+            (y * y).sum().item()
+            torch.cuda.synchronize()
+        captures, replays = g.graph_stats()
+    assert (captures, replays) == (1, 2)

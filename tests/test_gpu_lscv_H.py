@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -276,3 +277,29 @@ def test_prepared_sample_equals_eval(kde, d, precision):
                 with pytest.raises(kde.KdeError) as e:
                     prep.eval(bad)
                 assert e.value.status == kde.KDE_E_INVAL
+
+
+def test_context_close_releases_prepared_samples_and_jobs(kde):
+    """Closing a context releases the prepared samples and resumable jobs
+    created on it; closing those handles afterwards (explicitly, or when they
+    are collected) does nothing."""
+    import gc
+
+    x = workloads.draw_matrix(3000, 2, 5, np.float32)
+    col = workloads.draw("normal", 4000, 6, np.float32)
+    c = kde.Context(0)
+    prep = c.lscv_H_prepare(x)
+    g0, _ = prep.eval(np.eye(2) * 0.2)
+    job = kde.Job(c, kde.Request(col, kde.KDE_METHOD_ROT | kde.KDE_METHOD_LSCV, 3, ("log_rot", 0.25, 4.0, 16)))
+    extra = c.lscv_H_prepare(x)
+    c.close()
+    assert prep.handle is None and extra.handle is None and job.job is None
+    prep.close()
+    job.close()
+    del extra
+    gc.collect()
+    # a fresh context still works and gives the same value
+    with kde.Context(0) as c2:
+        with c2.lscv_H_prepare(x) as p2:
+            g1, _ = p2.eval(np.eye(2) * 0.2)
+    assert np.array_equal(g0, g1)

@@ -9,8 +9,9 @@ Tolerances (mixed precision):
   * raw pair sums s1, s2 (positive terms): 1e-5 relative, plus the FP32 range
     limit of the mixed form (pairs * 2^-126: a term below the smallest normal
     FP32 may flush to zero).
-  * chosen grid index: equal, or a near tie: g_oracle[k_gpu] - min g_oracle
-    <= 2 max|dg| (reported).
+  * chosen grid index: equal to the oracle's argmin of eq. (LSCV-finalH).  A
+    case may be named a near tie explicitly (none is); it then passes only if
+    g_oracle[k_gpu] - min g_oracle <= 2 max|dg|, and the margin is printed.
 FP64 form: 1e-10 on the same quantities.
 """
 import json
@@ -58,12 +59,17 @@ def check_curve(g, gs, oc, tol, label=""):
     return float(err.max())
 
 
-def check_argmin(k_gpu, g_gpu, oc, label=""):
+def check_argmin(k_gpu, g_gpu, oc, label="", near_tie_ok=False):
+    """The GPU selects the oracle's grid index.  Only a case passed with
+    near_tie_ok may differ, by a margin within twice the measured error."""
     k_or, _, _ = oracle.argmin(oc.g)
     if k_gpu == k_or:
         return
-    dg = np.abs(g_gpu - oc.g).max()
-    assert oc.g[k_gpu] - oc.g[k_or] <= 2 * dg, (label, k_gpu, k_or)
+    dg = float(np.abs(g_gpu - oc.g).max())
+    margin = float(oc.g[k_gpu] - oc.g[k_or])
+    print(f"{label}: GPU index {k_gpu}, oracle {k_or}, oracle margin {margin:.3e}, max |dg| {dg:.3e}")
+    assert near_tie_ok, (label, k_gpu, k_or, margin, dg)
+    assert margin <= 2 * dg, (label, k_gpu, k_or, margin, dg)
 
 
 # ---------------------------------------------------------------- rule of thumb

@@ -91,9 +91,8 @@ def test_autotuned_jobs_equal_default(kde):
 
 def test_inner_loop_ceiling(kde):
     """The inner loop run from one LDS tile bounds the sweep: a full sweep of
-    a column is no faster (within noise).  The tuner's steady-state trial runs
-    on an all-zero column (every exponential of 0) and measures 2-3% above
-    the ceiling's spread samples; it stays within 10%."""
+    a column and the tuner's steady-state trial (on evenly spread samples, like
+    the ceiling's) are no faster, within noise."""
     import time
 
     x = workloads.draw("lognormal", 200_000, 9, np.float32)
@@ -112,6 +111,6 @@ def test_inner_loop_ceiling(kde):
             assert e.value.status == kde.KDE_E_INVAL
     sweep = x.size * (x.size - 1) / 2 * grid.size / dt
     assert ceil16 > 1e12 and ceil8 > 1e12
-    assert rates[16] <= 1.10 * ceil16 and sweep <= 1.05 * ceil16
+    assert rates[16] <= 1.05 * ceil16 and sweep <= 1.05 * ceil16
     print(f"inner-loop ceiling {ceil16:.3e} (hc 16), {ceil8:.3e} (hc 8); steady state {rates[16]:.3e}; "
           f"sweep n=2e5 {sweep:.3e} evals/s")
