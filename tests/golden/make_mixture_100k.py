@@ -25,6 +25,8 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 import workloads  # noqa: E402
 
+CHUNK = 16
+
 
 def main(out: str) -> None:
     w = workloads.workload("mixture-100k")
@@ -58,17 +60,28 @@ def main(out: str) -> None:
                          "seconds": time.time() - t}
         save()
         print(f"plug-in done in {time.time() - t:.0f} s: h={p.h!r}", flush=True)
-    if "lscv" not in doc:
+    # g(h) at each grid point is a sum of its own: the grid is run in chunks,
+    # each added to the file when done, so an interrupted run resumes.
+    parts = doc.setdefault("lscv_parts", {})
+    for k0 in range(0, grid.size, CHUNK):
+        if str(k0) in parts:
+            continue
         t = time.time()
-        c = oracle.lscv_curve(x, grid)
-        k, at_edge, margin = oracle.argmin(c.g)
-        doc["lscv"] = {"h": [float(v) for v in grid], "g": [float(v) for v in c.g],
-                       "gscale": [float(v) for v in c.gscale], "s1": [float(v) for v in c.s1],
-                       "s2": [float(v) for v in c.s2], "argmin": int(k), "at_edge": bool(at_edge),
-                       "margin": float(margin), "seconds": time.time() - t}
+        c = oracle.lscv_curve(x, grid[k0:k0 + CHUNK])
+        parts[str(k0)] = {"g": [float(v) for v in c.g], "gscale": [float(v) for v in c.gscale],
+                          "s1": [float(v) for v in c.s1], "s2": [float(v) for v in c.s2],
+                          "seconds": time.time() - t}
         save()
-        print(f"lscv over {grid.size} h done in {time.time() - t:.0f} s: k*={k}", flush=True)
-
+        print(f"lscv grid {k0}..{min(k0 + CHUNK, grid.size) - 1} done in {time.time() - t:.0f} s", flush=True)
+    if "lscv" not in doc:
+        keys = sorted(parts, key=int)
+        cat = {f: [v for key in keys for v in parts[key][f]] for f in ("g", "gscale", "s1", "s2")}
+        k, at_edge, margin = oracle.argmin(np.array(cat["g"]))
+        doc["lscv"] = {"h": [float(v) for v in grid], **cat, "argmin": int(k), "at_edge": bool(at_edge),
+                       "margin": float(margin), "seconds": sum(parts[key]["seconds"] for key in keys)}
+        del doc["lscv_parts"]
+        save()
+        print(f"lscv over {grid.size} h: k*={k}", flush=True)
 
 if __name__ == "__main__":
     main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "mixture_100k_oracle.json"))
