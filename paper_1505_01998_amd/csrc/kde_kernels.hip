@@ -84,6 +84,13 @@ __device__ __forceinline__ void block_minmax(float& lo, float& hi, float* sh) {
   __syncthreads();
 }
 
+// A wave-uniform float kept in a scalar register: the bandwidth coefficients
+// of the LSCV sweeps are the same for every lane, and holding them in SGPRs
+// instead of VGPRs frees HC vector registers per lane (more waves per SIMD).
+__device__ __forceinline__ float uniform_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -608,7 +615,7 @@ __device__ __forceinline__ void lscv_unit_f32(const ColDesc* __restrict__ cols, 
   float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    ck[k] = cc[k];
+    ck[k] = uniform_f32(cc[k]);
     a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
   }
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
@@ -660,7 +667,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __re
 // pass, so there is no partly filled last round per launch, and the longest
 // units start first wherever a block frees up.  *next must be 0 at launch.
 template <int HC>
-__global__ __launch_bounds__(kThreads) void k_lscv_units_f32_queue(const ColDesc* __restrict__ cols,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 1))) void k_lscv_units_f32_queue(const ColDesc* __restrict__ cols,
                                                                    const Unit* __restrict__ units, int n_units,
                                                                    int* __restrict__ next) {
   __shared__ float4 tile[kBJ / 4];
@@ -669,7 +676,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32_queue(const ColDesc
   for (;;) {
     if (threadIdx.x == 0) cur = atomicAdd(next, 1);
     __syncthreads();
-    const int k = cur;
+    const int k = __builtin_amdgcn_readfirstlane(cur);  // uniform: unit and column loads stay scalar
     __syncthreads();
     if (k >= n_units) break;
     lscv_unit_f32<HC>(cols, units[k], tile, red);
@@ -699,7 +706,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_ceiling(const float* __restri
   float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    ck[k] = c32[k];
+    ck[k] = uniform_f32(c32[k]);
     a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
   }
   for (int r = 0; r < reps; ++r)
@@ -749,7 +756,7 @@ void k_lscv_units_prune(const ColDesc* __restrict__ cols, const Unit* __restrict
   float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    ck[k] = cc[k];
+    ck[k] = uniform_f32(cc[k]);
     a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
   }
   for (int t0 = u.j_begin; t0 < j_end; t0 += kBJ) {
