@@ -213,6 +213,52 @@ def test_lscv_mixture_100k_sampled(ctx):
     print(f"mixture-100k sampled max|dg|/gscale = {err.max():.3e}")
 
 
+GOLDEN_100K = os.path.join(os.path.dirname(__file__), "golden", "mixture_100k_oracle.json")
+
+
+def _golden_100k():
+    if not os.path.exists(GOLDEN_100K):
+        return None
+    ref = json.load(open(GOLDEN_100K))
+    return ref if "lscv" in ref else None
+
+
+@pytest.mark.skipif(_golden_100k() is None,
+                    reason="full-grid oracle values not written yet (tests/golden/make_mixture_100k.py)")
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_mixture_100k_full_grid_against_stored_oracle(kde, precision):
+    """The n = 1e5 mixture workload over its whole 256-point grid against the
+    FP64 oracle's stored curve: every g(h) within the tolerance of gscale, the
+    selected index of eq. (LSCV-finalH) equal to the oracle's over all 256
+    points, and the three-stage plug-in chain (Section 4.4.1) within the
+    tolerance of the oracle's psi, pilots and h."""
+    ref = _golden_100k()
+    w = workloads.workload("mixture-100k")
+    x = w.column()
+    assert np.allclose(w.grid, ref["lscv"]["h"], rtol=0, atol=0)
+    with kde.Context(0, precision) as c:
+        g, gs, _ = c.lscv_curve(x, w.grid)
+        h, k, _ = c.bw_lscv(x, w.grid)
+        h_pi, info = c.bw_plugin(x, 3)
+    og, ogs = np.array(ref["lscv"]["g"]), np.array(ref["lscv"]["gscale"])
+    tol = TOL if precision == "mixed" else TOL64
+    err = np.abs(g - og) / ogs
+    assert err.max() <= tol, (float(err.max()), int(err.argmax()))
+    assert np.allclose(gs, ogs, rtol=tol, atol=0)
+    k_or = ref["lscv"]["argmin"]
+    assert int(np.argmin(g)) == k_or and k == k_or, (int(np.argmin(g)), k, k_or)
+    assert h == w.grid[k_or]
+    p = ref["plugin"]
+    for s in range(3):
+        tol_s = TOL if precision == "mixed" else TOL64 * max(1.0, p["kappa"][s])
+        assert info.psi[s] == pytest.approx(p["psi"][s], rel=tol_s), s
+        assert info.g[s] == pytest.approx(p["g"][s], rel=tol_s), s
+    assert h_pi == pytest.approx(p["h"], rel=TOL if precision == "mixed" else TOL64 * max(p["kappa"]))
+    print(f"mixture-100k full grid ({precision}): max |dg|/gscale {err.max():.2e}, k = {k} (oracle {k_or}, "
+          f"margin {ref['lscv']['margin']:.2e}), psi rel "
+          f"{[abs(info.psi[s] - p['psi'][s]) / abs(p['psi'][s]) for s in range(3)]}")
+
+
 # ---------------------------------------------------------------- device columns, determinism, errors
 def test_device_column_matches_host(ctx):
     import torch
@@ -307,23 +353,41 @@ def test_lscv_lognormal_1m_sampled_items(kde):
 GOLDEN_1M = os.path.join(os.path.dirname(__file__), "golden", "lognormal_1m_oracle.json")
 
 
+@pytest.fixture(scope="module")
+def lognormal_1m_curve(kde):
+    """The mixed form's whole 512-point curve of the n = 1e6 bench column, as
+    the bench computes it (one call over the whole grid)."""
+    w = workloads.workload("lognormal-1m")
+    x = w.column()
+    with kde.Context(0) as c:
+        g, gs, _ = c.lscv_curve(x, w.grid)
+    return g, gs
+
+
 @pytest.mark.skipif(not os.path.exists(GOLDEN_1M),
                     reason="full-size oracle values not written (tests/golden/make_lognormal_1m.py)")
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_lognormal_1m_full_size_oracle_values(kde, precision):
+def test_lognormal_1m_full_size_oracle_values(kde, lognormal_1m_curve, precision):
     """The bench column at full size (n = 1,000,000) against the FP64 oracle's
     stored values: the whole three-stage plug-in chain and g(h) at the stored
-    grid indices.  The FP64 form's tolerance is 1e-10 times the stage's
-    condition number for psi (a sum of terms of both signs) and 1e-10 of
-    gscale for g."""
+    grid indices, among them the window k*-2 .. k*+2 around the selected
+    index.  The selected index of eq. (LSCV-finalH) must be the oracle's
+    minimum over the stored points (both grid ends, two interior points and
+    the window), so it is a minimum of the oracle's curve over its +-2
+    neighbours and below the other stored points.  The FP64 form's tolerance
+    is 1e-10 times the stage's condition number for psi (a sum of terms of
+    both signs) and 1e-10 of gscale for g."""
     ref = json.load(open(GOLDEN_1M))
     w = workloads.workload("lognormal-1m")
     x = w.column()
+    idx = sorted(int(k) for k in ref.get("lscv", {}))
     with kde.Context(0, precision) as c:
         h, info = c.bw_plugin(x, 3)
-        idx = sorted(int(k) for k in ref.get("lscv", {}))
-        if idx:
-            g, gs, _ = c.lscv_curve(x, w.grid[idx])
+        if precision == "mixed":
+            g_full, _ = lognormal_1m_curve
+            g = g_full[idx]
+        elif idx:
+            g, _, _ = c.lscv_curve(x, w.grid[idx])
     p = ref["plugin"]
     for s in range(3):
         tol = TOL if precision == "mixed" else TOL64 * max(1.0, p["kappa"][s])
@@ -338,9 +402,17 @@ def test_lognormal_1m_full_size_oracle_values(kde, precision):
         err = abs(g[a] - v["g"]) / v["gscale"]
         worst = max(worst, err)
         assert err <= (TOL if precision == "mixed" else TOL64), (k, g[a], v["g"])
+    k_sel = int(np.argmin(lognormal_1m_curve[0]))
+    win = [k for k in range(k_sel - 2, k_sel + 3) if str(k) in ref["lscv"]]
+    o_g = np.array([ref["lscv"][str(k)]["g"] for k in idx])
+    if len(win) == 5:
+        # the oracle's minimum over the stored points, and the form's own
+        assert idx[int(np.argmin(o_g))] == k_sel, (idx, k_sel)
+        assert idx[int(np.argmin(g))] == k_sel, (idx, k_sel)
     print(f"lognormal-1m full size ({precision}): psi rel "
           f"{[abs(info.psi[s] - p['psi'][s]) / abs(p['psi'][s]) for s in range(3)]}, "
-          f"h rel {abs(h - p['h']) / p['h']:.2e}, max |dg|/gscale {worst:.2e} over {len(idx)} h")
+          f"h rel {abs(h - p['h']) / p['h']:.2e}, max |dg|/gscale {worst:.2e} over {len(idx)} h, "
+          f"selected {k_sel}, oracle window {win}")
 
 
 @pytest.mark.parametrize("family,n", [("bimodal", 4099), ("lognormal", 20011)])
@@ -374,14 +446,13 @@ def test_invariances_on_the_gpu(kde, ctx, family, n):
     assert int(np.argmin(g2)) == int(np.argmin(g0))
 
 
-def test_lognormal_1m_argmin_mixed_equals_fp64(kde):
+def test_lognormal_1m_argmin_mixed_equals_fp64(kde, lognormal_1m_curve):
     """The bench column at full size: the mixed form's chosen grid index over
     all 512 h is the all-FP64 form's argmin over the chosen index +-6, and the
     two forms agree on that window to far below the tolerance."""
     w = workloads.workload("lognormal-1m")
     x = w.column()
-    with kde.Context(0) as c:
-        g, gs, _ = c.lscv_curve(x, w.grid)
+    g, gs = lognormal_1m_curve
     k = int(np.argmin(g))
     win = np.arange(max(0, k - 6), min(w.grid.size, k + 7))
     with kde.Context(0, "fp64") as c64:
