@@ -213,7 +213,9 @@ def _lscv_kernel(ctx, args, n, n_h):
         return f"k_lscv_units_f32<{ctx.autotune(n, n_h)[0]}>"
     if args.mfma > 0:
         return "k_lscv_units_mfma"
-    return f"k_lscv_units_f32<{args.hc if args.hc > 0 else 16}>"
+    hc = args.hc if args.hc > 0 else 16
+    # the dense pass runs as one persistent launch unless switched off
+    return f"k_lscv_units_f32<{hc}>" if getattr(args, "persistent", -1) == 0 else f"k_lscv_units_f32_queue<{hc}>"
 
 
 def batch_bench(args):
@@ -342,28 +344,46 @@ def lscv_H_bench(args):
     return out
 
 
-def served_block(kde, args, n_req: int, n_lo: float = 2e3, n_hi: float = 2e6):
-    """Served form (continuous batching) vs plain per-request calls on the
-    first n_req requests of the seeded served stream (Poisson arrivals at
-    args.rate, n log-uniform in [n_lo, n_hi], the four batch families; plug-in
-    with three stages and LSCV over 128 h each): first at the stream's own
-    arrival times, then load-matched at 0.7 x the plain form's measured
-    capacity.  Every served result is compared with the plain one."""
+def served_prefix(n_max: int, budget_s: float, evals_per_s: float, n_lo: float = 2e3, n_hi: float = 2e6,
+                  rate: float = 200.0):
+    """The longest prefix (at most n_max, at least 4 requests) of the seeded
+    served stream whose four runs (plain and served, at the stream's arrival
+    times and load-matched) are expected to fit budget_s at the measured pair
+    throughput; the load-matched runs stretch the arrivals to 0.7x capacity."""
+    stream = workloads.served_stream(n_max, rate=rate, n_lo=n_lo, n_hi=n_hi)
+    work = np.cumsum([a.spec.n * (a.spec.n - 1) / 2 * (workloads.BATCH_GRID[3] + workloads.BATCH_STAGES)
+                      for a in stream]) / evals_per_s
+    est = work * (2.0 + 2.0 / 0.7) + 0.05 * np.arange(1, len(stream) + 1)
+    fit = int(np.searchsorted(est, budget_s, side="right"))
+    return stream[:max(4, min(fit, len(stream)))]
+
+
+def served_block(kde, args, stream, n_lo: float = 2e3, n_hi: float = 2e6):
+    """Served form (continuous batching) vs plain per-request calls on a
+    prefix of the seeded served stream (Poisson arrivals at args.rate, n
+    log-uniform in [n_lo, n_hi], the four batch families; plug-in with three
+    stages and LSCV over 128 h each): first at the stream's own arrival
+    times, then load-matched at 0.7 x the plain form's measured capacity.
+    Every served result is compared with the plain one."""
     import threading
 
-    stream = workloads.served_stream(n_req, rate=args.rate, n_lo=n_lo, n_hi=n_hi)
     cols = [a.spec.column() for a in stream]
     reqs = _requests_of(kde, cols)
     n_h = workloads.BATCH_GRID[3]
     evals = sum(a.spec.n * (a.spec.n - 1) / 2 * (n_h + workloads.BATCH_STAGES) for a in stream)
-    log(f"served: {len(reqs)} requests, {evals:.3e} pair-evals, arrivals over {stream[-1].t:.2f} s")
+    log(f"{elapsed():.0f} s: served: {len(reqs)} requests, {evals:.3e} pair-evals, "
+        f"arrivals over {stream[-1].t:.2f} s")
 
     def pct(v, q):
         return float(np.percentile(np.asarray(v), q))
 
-    def run_plain(ctx, times):
+    def progress(tag, k, t_start):
+        if k == len(reqs) or (k % max(1, len(reqs) // 8)) == 0:
+            log(f"{elapsed():.0f} s: served: {tag} {k}/{len(reqs)} done ({time.perf_counter() - t_start:.1f} s)")
+
+    def run_plain(ctx, times, tag):
         lat, res_all, t_start = [], [], time.perf_counter()
-        for r, t in zip(reqs, times):
+        for k, (r, t) in enumerate(zip(reqs, times)):
             now = time.perf_counter() - t_start
             if now < t:
                 time.sleep(t - now)
@@ -371,10 +391,11 @@ def served_block(kde, args, n_req: int, n_lo: float = 2e3, n_hi: float = 2e6):
             assert res.status == kde.KDE_OK
             res_all.append(res)
             lat.append(time.perf_counter() - t_start - t)
+            progress(tag, k + 1, t_start)
         span = time.perf_counter() - t_start - times[0]
         return lat, span, res_all
 
-    def run_served(ctx, times):
+    def run_served(ctx, times, tag):
         ctx.server_start(args.hbm_budget_gb << 30, args.slots)
         tickets = [None] * len(reqs)
         t_start = time.perf_counter()
@@ -397,6 +418,7 @@ def served_block(kde, args, n_req: int, n_lo: float = 2e3, n_hi: float = 2e6):
             res_all.append(res)
             lat.append(res.t_queue_s + res.t_service_s)
             done_at.append(time.perf_counter() - t_start)
+            progress(tag, k + 1, t_start)
         th.join()
         ctx.server_stop()
         return lat, max(done_at) - times[0], res_all
@@ -414,26 +436,25 @@ def served_block(kde, args, n_req: int, n_lo: float = 2e3, n_hi: float = 2e6):
     _apply_options(ctx, args)
     ctx.batch(reqs[:1])  # warm-up: code objects, allocations
     arrivals = [a.t for a in stream]
-    log("served: plain at the stream's arrival times")
-    plain = run_plain(ctx, arrivals)
+    plain = run_plain(ctx, arrivals, "plain at arrival times")
     out["plain"] = summary(*plain)
-    log("served: served at the stream's arrival times")
-    served = run_served(ctx, arrivals)
+    served = run_served(ctx, arrivals, "served at arrival times")
     out["served"] = summary(*served)
     cap = out["plain"]["req_per_s"]
     scale = args.rate / (0.7 * cap)
     matched = [t * scale for t in arrivals]
-    log(f"served: load-matched at {0.7 * cap:.3f} req/s")
-    plain_lm = run_plain(ctx, matched)
+    log(f"{elapsed():.0f} s: served: load-matched at {0.7 * cap:.3f} req/s")
+    plain_lm = run_plain(ctx, matched, "plain load-matched")
     out["plain_load_matched"] = summary(*plain_lm)
-    served_lm = run_served(ctx, matched)
+    served_lm = run_served(ctx, matched, "served load-matched")
     out["served_load_matched"] = summary(*served_lm)
     ctx.close()
     ns = [a.spec.n for a in stream]
     return {
         "requests": len(reqs),
         "stream": f"first {len(reqs)} requests of the seeded served stream (seed 1998005, Poisson {args.rate:g} "
-                  f"req/s, n log-uniform in [{n_lo:g}, {n_hi:g}]; this prefix has n from {min(ns)} to {max(ns)})",
+                  f"req/s over 60 s, n log-uniform in [{n_lo:g}, {n_hi:g}]; this prefix has n from {min(ns)} to "
+                  f"{max(ns)})",
         "pair_evals": evals,
         "load_matched_rate_req_s": 0.7 * cap,
         **out,
@@ -451,7 +472,8 @@ def served_bench(args):
     import paper_1505_01998_amd as kde
 
     n_lo, n_hi = (2e3, 2e6) if args.workload == "served" else (2e3, 6e4)
-    blk = served_block(kde, args, args.requests, n_lo, n_hi)
+    stream = workloads.served_stream(args.requests, rate=args.rate, n_lo=n_lo, n_hi=n_hi)
+    blk = served_block(kde, args, stream, n_lo, n_hi)
     return {
         "metric": "served req/s + p99 latency vs plain",
         "value": blk["served"]["req_per_s"],
@@ -487,14 +509,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--budget-s", type=float, default=420.0,
+    ap.add_argument("--budget-s", type=float, default=450.0,
                     help="wall-clock budget of the whole run from process start (s): warm-up stops after one step "
                          "longer than 10 s, and the timed steps are cut to what fits before the legs after them")
     ap.add_argument("--workload", default="lognormal-1m",
                     choices=workloads.WORKLOADS + ("batch-512", "served", "served-small", "lscv-H"))
     ap.add_argument("--requests", type=int, default=32, help="served workloads: requests taken from the stream")
-    ap.add_argument("--served-requests", type=int, default=24,
-                    help="single-column workloads: requests of the served block carried in the same line (0 = none)")
+    ap.add_argument("--served-requests", type=int, default=100,
+                    help="single-column workloads: most requests of the served block carried in the same line "
+                         "(0 = none); the prefix actually run is the longest that fits --served-budget-s")
+    ap.add_argument("--served-budget-s", type=float, default=220.0,
+                    help="single-column workloads: seconds of the budget reserved for the served block")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrival rate of the stream (req/s)")
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=64)
@@ -591,7 +616,7 @@ def main():
         if t_step > 10.0:
             break
     reserve = (15.0 if args.accuracy else 0.0) + (args.cpu_budget + 10.0 if args.cpu_budget > 0 else 0.0) + \
-              (90.0 if args.served_requests > 0 else 0.0) + (15.0 if args.ceiling else 0.0)
+              (args.served_budget_s if args.served_requests > 0 else 0.0) + (15.0 if args.ceiling else 0.0)
     steps = args.steps
     if t_step is not None:
         fit = int((args.budget_s - elapsed() - reserve) // max(t_step, 1e-3))
@@ -695,7 +720,11 @@ def main():
     del xd
     torch.cuda.empty_cache()
     if args.served_requests > 0:
-        out["served"] = served_block(kde, args, args.served_requests)
+        # the longest stream prefix whose four runs fit the served block's
+        # share of the budget at the throughput just measured
+        left = args.budget_s - elapsed() - (args.cpu_budget + 10.0 if args.cpu_budget > 0 else 0.0)
+        stream = served_prefix(args.served_requests, max(20.0, min(args.served_budget_s, left)), value)
+        out["served"] = served_block(kde, args, stream)
         log(f"{elapsed():.0f} s: served block done")
     if args.cpu_budget > 0:
         left = args.budget_s - elapsed() - 10.0

@@ -126,16 +126,21 @@ class Arrival:
     spec: ColumnSpec
 
 
-def served_stream(count: int, seed: int = 1998005, rate: float = 200.0, n_lo: float = 2e3, n_hi: float = 2e6):
-    """The first `count` requests of the served workload: Poisson arrivals at
-    `rate` per second, n log-uniform in [n_lo, n_hi], family uniform over the
-    four batch families; each request draws from its own child seed."""
+def served_stream(count: int | None = None, seed: int = 1998005, rate: float = 200.0, duration: float = 60.0,
+                  n_lo: float = 2e3, n_hi: float = 2e6):
+    """The served workload: Poisson arrivals at `rate` per second over
+    `duration` seconds, n log-uniform in [n_lo, n_hi], family uniform over the
+    four batch families; each request draws from its own child seed.  The
+    whole stream is drawn first, so the first `count` requests (all when
+    None) are the same prefix whatever count is asked for."""
     rng = _rng(seed)
-    gaps = rng.exponential(1.0 / rate, count)
-    ns = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count))).astype(np.int64)
-    fam = rng.integers(0, len(BATCH_FAMILIES), count)
+    m = int(rate * duration + 10.0 * np.sqrt(rate * duration) + 10)
+    t = np.cumsum(rng.exponential(1.0 / rate, m))
+    ns = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), m))).astype(np.int64)
+    fam = rng.integers(0, len(BATCH_FAMILIES), m)
+    total = int(np.searchsorted(t, duration, side="right"))
+    count = total if count is None else min(int(count), total)
     kids = np.random.SeedSequence(seed).spawn(count)
-    t = np.cumsum(gaps)
     return [Arrival(float(t[k]), ColumnSpec(BATCH_FAMILIES[int(fam[k])], int(ns[k]), int(kids[k].generate_state(1)[0])))
             for k in range(count)]
 
