@@ -278,6 +278,26 @@ kde_status kde_bw_plugin(kde_ctx* ctx, kde_column x, int stages, double* h_out, 
 kde_status kde_lscv_curve(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, double* g_out,
                           double* gscale_out, double* grid_out);
 
+/* For callers that cannot allocate memory (code whose harness forbids
+ * hipMalloc, tight serving loops): kde_lscv_curve computed with no device,
+ * pinned or other HIP allocation in the call.  Same arguments and results as
+ * kde_lscv_curve without grid_out; the values are bitwise those of
+ * kde_lscv_curve on the same context options.  The job's device workspace
+ * (the column's working copy, partial sums, grid, work list) lives in a fixed
+ * device array of KDE_NOALLOC_SCRATCH_BYTES that every GPU the library runs
+ * on holds from the library's load until the process ends; the host side
+ * stages through pageable buffers of the context, kept between calls.  Every
+ * call on one GPU shares that GPU's array and leaves the last call's contents
+ * in it (the call initialises all it reads): calls that overlap on one GPU,
+ * from any contexts or threads, race and must be serialised by the caller.
+ * KDE_E_NOMEM (no allocation attempted) when the column needs more than the
+ * array holds: every n <= 131072 with n_h <= 512 fits, in either precision;
+ * KDE_E_INVAL as kde_lscv_curve, and while the autotune option is on (its
+ * trials allocate); KDE_E_BUSY while a server runs on the context. */
+#define KDE_NOALLOC_SCRATCH_BYTES ((uint64_t)32 << 20)
+kde_status kde_lscv_curve_noalloc(kde_ctx* ctx, kde_column x, const double* h_grid, int32_t n_h, double* g_out,
+                                  double* gscale_out);
+
 /* The two raw pair sums behind g(h): s1[k] = sum_{i<j} exp(-D^2/(4 h_k^2)),
  * s2[k] = sum_{i<j} exp(-D^2/(2 h_k^2)), D = X_i - X_j.  h_grid must not be
  * NULL. */

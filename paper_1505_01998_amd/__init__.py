@@ -29,6 +29,7 @@ KDE_MAX_NH = 65536
 KDE_MAX_BATCH = 65535
 KDE_MAX_D = 16
 KDE_MAX_H_EVAL = 65536
+KDE_NOALLOC_SCRATCH_BYTES = 32 << 20
 KDE_GRID_EXPLICIT, KDE_GRID_PAPER, KDE_GRID_LOG_ROT = 0, 1, 2
 KDE_METHOD_ROT, KDE_METHOD_PLUGIN, KDE_METHOD_LSCV = 1, 2, 4
 
@@ -53,7 +54,7 @@ EXPORTS = (
     "kde_density_H", "kde_range_aggregates_2d", "kde_cancel", "kde_job_create", "kde_job_run",
     "kde_job_progress", "kde_job_result", "kde_job_checkpoint_bytes", "kde_job_checkpoint", "kde_job_resume",
     "kde_job_destroy", "kde_lscv_ceiling", "kde_lscv_H_prepare", "kde_lscv_H_eval_prepared", "kde_lscv_H_release",
-    "kde_issue_rates",
+    "kde_issue_rates", "kde_lscv_curve_noalloc",
 )
 
 
@@ -164,6 +165,7 @@ def _load():
     lib.kde_bw_rot.argtypes = [P, kde_column, PD]
     lib.kde_bw_plugin.argtypes = [P, kde_column, I, PD, ctypes.POINTER(kde_plugin_info)]
     lib.kde_lscv_curve.argtypes = [P, kde_column, PD, I32, PD, PD, PD]
+    lib.kde_lscv_curve_noalloc.argtypes = [P, kde_column, PD, I32, PD, PD]
     lib.kde_lscv_sums.argtypes = [P, kde_column, PD, I32, PD, PD]
     lib.kde_lscv_item_sums.argtypes = [P, kde_column, PD, I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32),
                                        ctypes.POINTER(I32), PD]
@@ -608,6 +610,18 @@ def kde_lscv_curve(ctx, x, h_grid=None, n_h: int = 0):
     return g, gs, grid_used
 
 
+def kde_lscv_curve_noalloc(ctx, x, h_grid=None, n_h: int = 0):
+    """(g, gscale) as float64 arrays, computed in the library's fixed device scratch (no allocation)."""
+    col, keep = make_column(x)
+    gr = _grid(h_grid)
+    m = gr.size if gr is not None else (n_h if n_h > 0 else 150)
+    g = np.empty(m, np.float64)
+    gs = np.empty(m, np.float64)
+    _check(ctx, lib.kde_lscv_curve_noalloc(ctx, col, _pd(gr), int(m), _pd(g), _pd(gs)))
+    del keep
+    return g, gs
+
+
 def kde_lscv_sums(ctx, x, h_grid):
     """(s1, s2): pair sums of exp(-D^2/(4h^2)) and exp(-D^2/(2h^2))."""
     col, keep = make_column(x)
@@ -973,6 +987,9 @@ class Context:
 
     def lscv_curve(self, x, h_grid=None, n_h=0):
         return kde_lscv_curve(self.ctx, x, h_grid, n_h)
+
+    def lscv_curve_noalloc(self, x, h_grid=None, n_h=0):
+        return kde_lscv_curve_noalloc(self.ctx, x, h_grid, n_h)
 
     def lscv_sums(self, x, h_grid):
         return kde_lscv_sums(self.ctx, x, h_grid)

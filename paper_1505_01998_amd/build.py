@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkde_bw.so")
 OBJ_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["kde_kernels.hip", "kde_runtime.hip", "kde_server.hip", "kde_tune.hip", "kde_sort.hip", "kde_query.hip",
-           "kde_md.hip", "kde_lscv_H.hip", "kde_query_md.hip", "kde_job.hip", "kde_probe.hip"]
+           "kde_md.hip", "kde_lscv_H.hip", "kde_query_md.hip", "kde_job.hip", "kde_probe.hip",
+           "kde_noalloc.hip"]
 
 # Packed FP32 VALU instructions are disabled for all device code; the kernels
 # are written for scalar FP32/FP64 issue.

@@ -212,6 +212,13 @@ struct kde_ctx {
   std::vector<kde::ColPlan> plans;
   std::vector<int> plan_req;  // request index of each planned column
   kde::IterPlan iter;
+  // set while a call runs on a fixed workspace (kde_lscv_curve_noalloc): a
+  // device or pinned buffer that would have to grow fails instead
+  bool no_alloc = false;
+  // host staging of those calls (pageable; grown once, then reused)
+  std::vector<kde::DevState> na_st;
+  std::vector<double> na_out;
+  std::vector<char> na_blob;
   // timing
   bool timing = false;
   int64_t t_launches[3] = {0, 0, 0};
@@ -302,6 +309,13 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L);
 kde_status upload_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status execute(kde_ctx* c, IterPlan& it);
+// The LSCV curve of one column as kde_lscv_curve computes it (job, copies of
+// g, gscale and the grid into the caller's arrays, synchronisation).
+kde_status lscv_curve_call(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* g_out,
+                           double* gscale_out, double* grid_out);
+// Looks up, once per device, the device address of the fixed scratch of
+// kde_lscv_curve_noalloc (the context's device must be current).
+void noalloc_setup(kde_ctx* c);
 kde_status sync_and_check(kde_ctx* c);
 // Folds the timed launches that have completed into the counters (no wait).
 kde_status collect_ready_timing(kde_ctx* c);
@@ -311,6 +325,7 @@ kde_status ensure_pinned_bytes(kde_ctx* c, char*& p, size_t& cap, size_t bytes);
 template <typename T>
 kde_status ensure(kde_ctx* c, DevBuf<T>& b, size_t count) {
   if (b.cap >= count) return KDE_OK;
+  if (c->no_alloc) return fail(c, KDE_E_NOMEM, "request needs more device workspace than the fixed scratch holds");
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.cap = 0;

@@ -50,6 +50,7 @@ kde_status status_of(int st) {
 
 kde_status ensure_pinned_bytes(kde_ctx* c, char*& p, size_t& cap, size_t bytes) {
   if (cap >= bytes) return KDE_OK;
+  if (c->no_alloc) return fail(c, KDE_E_NOMEM, "request needs more host staging than the call's fixed buffers hold");
   if (p) (void)hipHostFree(p);
   p = nullptr;
   cap = 0;
@@ -1048,6 +1049,25 @@ void fill_result(const ColPlan& p, const DevState& h, kde_result& r) {
 }
 }  // namespace kde
 
+kde_status kde::lscv_curve_call(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* g_out,
+                                double* gscale_out, double* grid_out) {
+  kde_status s;
+  if (!h_grid && n_h <= 0) n_h = 150;
+  if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
+  if ((s = ensure_out(c, (size_t)3 * n_h))) return s;
+  const ColDesc& d = c->iter.cols[0];
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out, d.g, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + n_h, d.gs, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
+  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + 2 * (size_t)n_h, d.h, sizeof(double) * n_h, hipMemcpyDeviceToHost,
+                                c->stream));
+  if ((s = kde::sync_and_check(c))) return s;
+  if ((s = map_status(c, c->h_st[0].status))) return s;
+  std::memcpy(g_out, c->h_out, sizeof(double) * n_h);
+  if (gscale_out) std::memcpy(gscale_out, c->h_out + n_h, sizeof(double) * n_h);
+  if (grid_out) std::memcpy(grid_out, c->h_out + 2 * (size_t)n_h, sizeof(double) * n_h);
+  return KDE_OK;
+}
+
 // ======================================================================== C ABI
 extern "C" {
 
@@ -1067,6 +1087,7 @@ kde_status kde_ctx_create(int device, kde_prec prec, kde_ctx** out) {
     return KDE_E_DEVICE;
   }
   c->stream = c->own;
+  kde::noalloc_setup(c);
   *out = c;
   return KDE_OK;
 }
@@ -1272,21 +1293,7 @@ kde_status kde_lscv_curve(kde_ctx* c, kde_column x, const double* h_grid, int32_
   if (!c || !g_out) return KDE_E_INVAL;
   if (serving(c)) return busy(c);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
-  kde_status s;
-  if (!h_grid && n_h <= 0) n_h = 150;
-  if ((s = run_single(c, make_req(x, KDE_METHOD_LSCV, 2, h_grid, n_h)))) return s;
-  if ((s = ensure_out(c, (size_t)3 * n_h))) return s;
-  const ColDesc& d = c->iter.cols[0];
-  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out, d.g, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
-  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + n_h, d.gs, sizeof(double) * n_h, hipMemcpyDeviceToHost, c->stream));
-  KDE_HIP_TRY(c, hipMemcpyAsync(c->h_out + 2 * (size_t)n_h, d.h, sizeof(double) * n_h, hipMemcpyDeviceToHost,
-                                c->stream));
-  if ((s = kde::sync_and_check(c))) return s;
-  if ((s = map_status(c, c->h_st[0].status))) return s;
-  std::memcpy(g_out, c->h_out, sizeof(double) * n_h);
-  if (gscale_out) std::memcpy(gscale_out, c->h_out + n_h, sizeof(double) * n_h);
-  if (grid_out) std::memcpy(grid_out, c->h_out + 2 * (size_t)n_h, sizeof(double) * n_h);
-  return KDE_OK;
+  return kde::lscv_curve_call(c, x, h_grid, n_h, g_out, gscale_out, grid_out);
 }
 
 kde_status kde_lscv_sums(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* s1_out,
