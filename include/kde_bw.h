@@ -49,7 +49,9 @@ typedef enum {
   KDE_OK = 0,
   KDE_E_INVAL = 1,      /* bad argument or sample column */
   KDE_E_DEGENERATE = 2, /* sigma = 0, or a functional estimate of the wrong sign */
-  KDE_E_NOMEM = 3,      /* allocation failed, or a served request exceeds the server's HBM budget */
+  KDE_E_NOMEM = 3,      /* device or pinned allocation failed; a served request larger than the
+                         * server's whole HBM budget; a kde_lscv_curve_noalloc column larger than
+                         * its fixed scratch */
   KDE_E_DEVICE = 4,     /* HIP runtime error */
   KDE_E_BUSY = 5,       /* reserved: result not ready */
   KDE_E_CANCELLED = 6   /* reserved: request cancelled */
@@ -113,6 +115,10 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
 
 /* Tuning knobs by name (value < 0 restores the default):
  *   "lscv_hc"      bandwidths per pass of the LSCV pair kernel (8, 16 or 32)
+ *   "lscv_tj"      samples per LDS tile of the persistent dense LSCV sweep
+ *                  (256, 512 or 1024; other than 512 only with lscv_hc 16,
+ *                  else the pass falls back to sliced launches).  Results
+ *                  are bitwise those of any tile size.
  *   "seg"          j-range per work item, rounded to the tile (0 = whole row)
  *   "launch_evals" pair-term evaluations per kernel launch (launch splitting)
  *   "fp64_kappa"   mixed precision: kappa above which a plug-in stage is re-run
@@ -121,7 +127,7 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  (mixed precision with lscv_hc 16; results identical in
  *                  value to rounding, not bitwise, to the vector-ALU kernel)
  *   "serve_iter_evals" server: minimum pair-term evaluations per scheduler
- *                  iteration (an iteration also holds at least six rounds of
+ *                  iteration (an iteration also holds at least 24 rounds of
  *                  1024 blocks of its largest work unit).  Pruned sweeps are
  *                  counted at their dense size, so with "prune" an iteration
  *                  does less work than it counts; a larger value keeps the
@@ -142,12 +148,13 @@ kde_status kde_ctx_set_precision(kde_ctx* ctx, kde_prec prec);
  *                  its pass had failed: it ends with KDE_E_DEVICE and frees
  *                  its slot while the requests sharing its launches complete
  *                  (0: off).  Forced from the host; every kernel runs as usual.
- *   "autotune"     1: synchronous calls and kde_batch run the LSCV pass with
- *                  the bandwidths per block that kde_autotune measured fastest
- *                  for the job's largest LSCV column (tuning that shape on
- *                  first use when the job holds at least 1e13 pair-term
- *                  evaluations; smaller jobs use a cached decision or
- *                  lscv_hc).  Results are bitwise those of any lscv_hc.
+ *   "autotune"     1: synchronous calls and kde_batch run the LSCV pass in
+ *                  the variant (bandwidths per block, tile size) that
+ *                  kde_autotune measured fastest for the job's largest LSCV
+ *                  column (tuning that shape on first use when the job holds
+ *                  at least 1e13 pair-term evaluations; smaller jobs use a
+ *                  cached decision or lscv_hc / lscv_tj).  Results are
+ *                  bitwise those of any variant.
  *   "prune"        1: LSCV tile pruning on sorted samples (mixed precision;
  *                  synchronous calls, kde_batch, the server and jobs).
  *                  Each LSCV column is sorted on the device (the pair
@@ -188,21 +195,29 @@ kde_status kde_ctx_set_option(kde_ctx* ctx, const char* key, int64_t value);
 kde_status kde_ctx_graph_stats(kde_ctx* ctx, int64_t* captures, int64_t* replays);
 
 /* Tile autotuner of the LSCV pair pass (eq. LSCV-gh over a grid, every h
- * from one pair distance as in Section 4.5).  Times the vector-ALU kernel
- * with 8, 16 and 32 bandwidths per block on trial launches shaped like a
- * column of n samples with an n_h-point grid (the planner's longest work
- * items, about 0.05 s of work each, on an evenly spread column in buffers of the
- * context) and caches the fastest per shape (quarter octave of n, n_h) in the
- * context; the default 16 is kept unless another is 2% faster.  The variant
- * never changes a result: items and summation order do not depend on it.
- * out->hc receives the choice, out->evals_per_s the measured rates (pair-term
- * evaluations per second for 8, 16, 32).  A cached shape returns at once.
- * KDE_E_INVAL for n outside [2, KDE_MAX_N], n_h outside [1, KDE_MAX_NH] or a
- * context in FP64 precision; KDE_E_BUSY while a server runs. */
+ * from one pair distance as in Section 4.5).  Times the persistent dense
+ * sweep in five variants (bandwidths per block, samples per LDS tile) =
+ * (8, 512), (16, 256), (16, 512), (16, 1024), (32, 512) on trial launches of
+ * a column shaped like n samples with an n_h-point grid (rows of an evenly
+ * spread column of min(n, 8192) samples in buffers of the context; B and 2B
+ * units differenced) and caches the fastest per shape (quarter octave of n,
+ * n_h) in the context; the default (16, 512) is kept unless another is 2%
+ * faster.  A variant is a candidate only if its trial partial sums for the
+ * first 8 bandwidths are bitwise those of the default: the variant never
+ * changes a result, since items and summation order do not depend on it.
+ * out->hc and out->tj receive the choice, out->evals_per_s[v] the measured
+ * rate of variant v in the order above (pair-term evaluations per second,
+ * scaled by the share of its bandwidth slots the grid fills; 0 if the
+ * variant could not run), out->parity[v] 1 when it passed the gate.  A cached
+ * shape returns at once.  KDE_E_INVAL for n outside [2, KDE_MAX_N], n_h
+ * outside [1, KDE_MAX_NH] or a context in FP64 precision; KDE_E_BUSY while a
+ * server runs. */
 typedef struct {
   int32_t hc;
+  int32_t tj;
+  double evals_per_s[5];
+  int32_t parity[5];
   int32_t pad0;
-  double evals_per_s[3];
 } kde_tune_info;
 kde_status kde_autotune(kde_ctx* ctx, int64_t n, int32_t n_h, kde_tune_info* out);
 /* Measures the ceiling of the LSCV sweep's inner loop on this device: the

@@ -83,7 +83,12 @@ class kde_plugin_info(ctypes.Structure):
 
 
 class kde_tune_info(ctypes.Structure):
-    _fields_ = [("hc", ctypes.c_int32), ("pad0", ctypes.c_int32), ("evals_per_s", ctypes.c_double * 3)]
+    _fields_ = [("hc", ctypes.c_int32), ("tj", ctypes.c_int32), ("evals_per_s", ctypes.c_double * 5),
+                ("parity", ctypes.c_int32 * 5), ("pad0", ctypes.c_int32)]
+
+
+# variants of the persistent LSCV sweep, in the order of kde_tune_info's arrays
+TUNE_VARIANTS = ((8, 512), (16, 256), (16, 512), (16, 1024), (32, 512))
 
 
 class kde_issue_info(ctypes.Structure):
@@ -541,12 +546,16 @@ def kde_ctx_graph_stats(ctx):
 
 
 def kde_autotune(ctx, n: int, n_h: int):
-    """(hc, {8: rate, 16: rate, 32: rate}) -- the LSCV variant the tile autotuner
-    picks for a column of n samples and an n_h-point grid, with the measured
-    pair-term evaluations per second of each."""
+    """((hc, tj), {(hc, tj): rate}, {(hc, tj): parity}) -- the persistent LSCV
+    sweep variant (bandwidths per block, samples per LDS tile) the tile
+    autotuner picks for a column of n samples and an n_h-point grid, with the
+    measured pair-term evaluations per second of each variant and whether its
+    partial sums passed the bitwise parity gate."""
     t = kde_tune_info()
     _check(ctx, lib.kde_autotune(ctx, int(n), int(n_h), ctypes.byref(t)))
-    return t.hc, {8: t.evals_per_s[0], 16: t.evals_per_s[1], 32: t.evals_per_s[2]}
+    rates = {v: t.evals_per_s[k] for k, v in enumerate(TUNE_VARIANTS)}
+    parity = {v: bool(t.parity[k]) for k, v in enumerate(TUNE_VARIANTS)}
+    return (t.hc, t.tj), rates, parity
 
 
 def kde_lscv_ceiling(ctx, hc: int = 16) -> float:

@@ -166,14 +166,21 @@ void launch_lscv_ceiling(hipStream_t s, int hc, const float* x, const float* c32
 void launch_lscv_units(hipStream_t s, int hc, int f64, int mfma, int prune, const ColDesc* cols, const Unit* units,
                        int u0, int n_units);
 void launch_reduce_rows(hipStream_t s, const RowDesc* rows, int n_rows);
-// Persistent form of the dense FP32 LSCV sweep: `blocks` blocks take units
-// [0, n_units) from the device counter *next (which must be 0; clear it
-// with launch_zero_ints in the same stream).  lscv_queue_blocks: the blocks
-// the current device holds at once for variant hc (0 on failure).
+// Persistent form of the dense FP32 LSCV sweep: `blocks` blocks take the
+// n_units units from kQueueGroups groups, group g being units
+// [group_begin[g], group_begin[g + 1]) (device array of kQueueGroups + 1
+// ints, group_begin[kQueueGroups] = n_units) with device counter next[g]
+// (kQueueGroups ints, all 0 at launch: clear them with launch_zero_ints in
+// the same stream).  Variants (hc bandwidths per block, tj samples per LDS
+// tile): (8, 512), (16, 256), (16, 512), (16, 1024), (32, 512);
+// lscv_queue_variant says whether one exists.  lscv_queue_blocks: the blocks
+// the current device holds at once for a variant (0 on failure).
+constexpr int kQueueGroups = 8;
 void launch_zero_ints(hipStream_t s, int* p, int n);
-int lscv_queue_blocks(int hc);
-void launch_lscv_units_queue(hipStream_t s, int hc, const ColDesc* cols, const Unit* units, int n_units, int* next,
-                             int blocks);
+bool lscv_queue_variant(int hc, int tj);
+int lscv_queue_blocks(int hc, int tj);
+void launch_lscv_units_queue(hipStream_t s, int hc, int tj, const ColDesc* cols, const Unit* units, int n_units,
+                             const int* group_begin, int* next, int blocks);
 
 // ---- ascending sort of FP32 keys (kde_sort.hip): temporary bytes for
 // `count` keys (0 on failure), and the sort itself.

@@ -94,6 +94,7 @@ kde_status kde_job_create(kde_ctx* c, const kde_request* req, kde_job** out) {
   j->prec = (int)c->prec;
   j->cond = c->prec != KDE_PREC_FP64 && c->opt_fp64_kappa > 0.0;
   c->job_hc = j->hc;
+  c->job_tj = c->opt_tj;
   c->job_mfma = j->mfma;
   // plan as a host column so the block holds the samples (a checkpoint then
   // carries them); device samples are copied into the block below
@@ -160,6 +161,7 @@ kde_status kde_job_run(kde_job* j, double max_evals, int* done_out) {
   if ((int)c->prec != j->prec) return fail(c, KDE_E_INVAL, "the context's precision changed since the job began");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KDE_E_DEVICE, "hipSetDevice failed");
   c->job_hc = j->hc;
+  c->job_tj = c->opt_tj;
   c->job_mfma = j->mfma;
   j->started = true;
   const kde::ColPlan& p = j->plan;

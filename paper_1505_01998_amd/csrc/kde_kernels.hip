@@ -597,8 +597,12 @@ __device__ __forceinline__ void lscv_run(const float4* __restrict__ tile, int jl
 
 // One LSCV work unit of the vector-ALU sweep: the unit's row of 256 samples
 // i against its j-range, for the HC bandwidths of its chunk; the block's
-// FP64 partial sums go to the unit's own slots.
-template <int HC>
+// FP64 partial sums go to the unit's own slots.  TJ: samples per LDS tile
+// (256, 512 or 1024; a unit's j-range is a multiple of 512, so a 1024 tile
+// may end half full).  The tile size changes only how often the block stages
+// and synchronises: every lane still folds its terms in runs of 64 j in
+// ascending j order, so every (unit, h) sum is bitwise the same for all TJ.
+template <int HC, int TJ>
 __device__ __forceinline__ void lscv_unit_f32(const ColDesc* __restrict__ cols, const Unit& u, float4* tile,
                                               double (*red)[2 * HC]) {
   const ColDesc c = cols[u.col];
@@ -618,12 +622,12 @@ __device__ __forceinline__ void lscv_unit_f32(const ColDesc* __restrict__ cols, 
     ck[k] = uniform_f32(cc[k]);
     a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
   }
-  for (int t0 = u.j_begin; t0 < u.j_end; t0 += kBJ) {
+  for (int t0 = u.j_begin; t0 < u.j_end; t0 += TJ) {
+    const int te = min(t0 + TJ, u.j_end);
     __syncthreads();
-    for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
+    for (int q = tid; q < (te - t0) / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x + t0)[q];
     __syncthreads();
     int js = max(t0, wave_i0);
-    const int te = t0 + kBJ;
     if (js < te) {
       if (js == wave_i0) {
         lscv_run<HC, true>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
@@ -657,29 +661,41 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __re
                                                              const Unit* __restrict__ units, int u0) {
   __shared__ float4 tile[kBJ / 4];
   __shared__ double red[4][2 * HC];
-  lscv_unit_f32<HC>(cols, units[u0 + blockIdx.x], tile, red);
+  lscv_unit_f32<HC, kBJ>(cols, units[u0 + blockIdx.x], tile, red);
 }
 
 // Persistent form: a grid of about as many blocks as the chip holds at once
-// takes units [0, n_units) in list order (largest first) from a device
-// counter, one unit per block at a time, until the list is exhausted; every
-// block reaches the end of the list and exits.  One launch covers a whole
-// pass, so there is no partly filled last round per launch, and the longest
-// units start first wherever a block frees up.  *next must be 0 at launch.
-template <int HC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 1))) void k_lscv_units_f32_queue(const ColDesc* __restrict__ cols,
-                                                                   const Unit* __restrict__ units, int n_units,
-                                                                   int* __restrict__ next) {
-  __shared__ float4 tile[kBJ / 4];
+// takes the pass's units from device counters, one unit per block at a time,
+// until the list is exhausted.  The list comes in kQueueGroups groups of
+// about equal work, each a contiguous stretch of (column, j) positions kept
+// largest first; group g is units [group_begin[g], group_begin[g + 1]) with
+// counter next[g].  Block b starts on group b % kQueueGroups (workgroups are
+// dealt round-robin to the eight dies, so a die's blocks stream the sample
+// tiles of one stretch of the column, which stays in that die's L2), and
+// when its group is drained it moves on to the next ones, taking what is
+// left there.  A block leaves a group once its counter passes the group's
+// end, so every block reaches the end of the last group and exits.  One
+// launch covers a whole pass; the longest units start first wherever a
+// block frees up.  next[0 .. kQueueGroups) must be 0 at launch.
+template <int HC, int TJ>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 1))) void
+k_lscv_units_f32_queue(const ColDesc* __restrict__ cols, const Unit* __restrict__ units,
+                       const int* __restrict__ group_begin, int* __restrict__ next) {
+  __shared__ float4 tile[TJ / 4];
   __shared__ double red[4][2 * HC];
   __shared__ int cur;
-  for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(next, 1);
-    __syncthreads();
-    const int k = __builtin_amdgcn_readfirstlane(cur);  // uniform: unit and column loads stay scalar
-    __syncthreads();
-    if (k >= n_units) break;
-    lscv_unit_f32<HC>(cols, units[k], tile, red);
+  const int g0 = (int)(blockIdx.x % kQueueGroups);
+  for (int q = 0; q < kQueueGroups; ++q) {
+    const int g = (g0 + q) % kQueueGroups;
+    const int base = group_begin[g], len = group_begin[g + 1] - base;
+    for (;;) {
+      if (threadIdx.x == 0) cur = atomicAdd(next + g, 1);
+      __syncthreads();
+      const int k = __builtin_amdgcn_readfirstlane(cur);  // uniform: unit and column loads stay scalar
+      __syncthreads();
+      if (k >= len) break;
+      lscv_unit_f32<HC, TJ>(cols, units[base + k], tile, red);
+    }
   }
 }
 
@@ -1188,28 +1204,50 @@ void launch_zero_ints(hipStream_t s, int* p, int n) {
   if (n > 0) k_zero_ints<<<(n + 255) / 256, 256, 0, s>>>(p, n);
 }
 
-int lscv_queue_blocks(int hc) {
+// The persistent sweep's variants: (bandwidths per block, samples per LDS
+// tile).  The autotuner chooses among them; (16, 512) is the default.
+namespace {
+template <int HC, int TJ>
+int queue_blocks_of() {
   int dev = 0, per_cu = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  hipError_t e;
-  switch (hc) {
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<8>, kThreads, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<32>, kThreads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<16>, kThreads, 0); break;
-  }
-  if (e != hipSuccess || per_cu < 1) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lscv_units_f32_queue<HC, TJ>, kThreads, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    return 0;
   return per_cu * prop.multiProcessorCount;
 }
+}  // namespace
 
-void launch_lscv_units_queue(hipStream_t s, int hc, const ColDesc* cols, const Unit* units, int n_units, int* next,
-                             int blocks) {
+bool lscv_queue_variant(int hc, int tj) {
+  return (tj == 512 && (hc == 8 || hc == 16 || hc == 32)) || (hc == 16 && (tj == 256 || tj == 1024));
+}
+
+int lscv_queue_blocks(int hc, int tj) {
+  if (tj == 256) return queue_blocks_of<16, 256>();
+  if (tj == 1024) return queue_blocks_of<16, 1024>();
+  switch (hc) {
+    case 8: return queue_blocks_of<8, 512>();
+    case 32: return queue_blocks_of<32, 512>();
+    default: return queue_blocks_of<16, 512>();
+  }
+}
+
+void launch_lscv_units_queue(hipStream_t s, int hc, int tj, const ColDesc* cols, const Unit* units, int n_units,
+                             const int* group_begin, int* next, int blocks) {
   if (n_units <= 0) return;
   blocks = max(1, min(blocks, n_units));
-  switch (hc) {
-    case 8: k_lscv_units_f32_queue<8><<<blocks, kThreads, 0, s>>>(cols, units, n_units, next); break;
-    case 32: k_lscv_units_f32_queue<32><<<blocks, kThreads, 0, s>>>(cols, units, n_units, next); break;
-    default: k_lscv_units_f32_queue<16><<<blocks, kThreads, 0, s>>>(cols, units, n_units, next); break;
+  if (tj == 256) {
+    k_lscv_units_f32_queue<16, 256><<<blocks, kThreads, 0, s>>>(cols, units, group_begin, next);
+  } else if (tj == 1024) {
+    k_lscv_units_f32_queue<16, 1024><<<blocks, kThreads, 0, s>>>(cols, units, group_begin, next);
+  } else {
+    switch (hc) {
+      case 8: k_lscv_units_f32_queue<8, 512><<<blocks, kThreads, 0, s>>>(cols, units, group_begin, next); break;
+      case 32: k_lscv_units_f32_queue<32, 512><<<blocks, kThreads, 0, s>>>(cols, units, group_begin, next); break;
+      default: k_lscv_units_f32_queue<16, 512><<<blocks, kThreads, 0, s>>>(cols, units, group_begin, next); break;
+    }
   }
 }
 

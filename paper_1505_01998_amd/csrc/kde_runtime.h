@@ -93,6 +93,7 @@ struct IterPlan {
   std::vector<int> ids_lscv_prep;
   std::vector<Unit> lscv_units;
   std::vector<UnitCost> lscv_cost;
+  int lscv_groups[kQueueGroups + 1] = {};  // persistent form: group g is lscv_units [lscv_groups[g], [g + 1])
   std::vector<RowDesc> lscv_rows;
   std::vector<int> ids_lscv_final;
   // tile pruning: sorts, near-tile units and rows, cut preparation, pruned units
@@ -113,6 +114,7 @@ struct PassLayout {
   size_t o_nu = 0, o_nr = 0, o_pp = 0, o_pu = 0;  // tile pruning: near units/rows, prune ids, pruned units
   size_t sort_tmp = 0;                            // temporary bytes of the largest sort
   size_t o_ctr = 0;                               // work counters of the persistent launches (ints)
+  size_t o_lg = 0;                                // group offsets of the persistent dense LSCV pass
   size_t o_begin[3] = {0, 0, 0}, o_finish[3] = {0, 0, 0}, o_psu[3] = {0, 0, 0}, o_pr[3] = {0, 0, 0},
          o_pc[3] = {0, 0, 0};
 };
@@ -146,9 +148,18 @@ constexpr size_t kMaxGraphs = 8;
 constexpr double kPruneEps = 5.820766091346741e-11;
 
 // Variant of the LSCV pass chosen by the tile autotuner for one shape.
+// Variants of the persistent dense LSCV sweep the autotuner chooses among:
+// (bandwidths per block, samples per LDS tile); index 2 is the default.
+constexpr int kQueueVariants = 5;
+constexpr int kQueueHC[kQueueVariants] = {8, 16, 16, 16, 32};
+constexpr int kQueueTJ[kQueueVariants] = {512, 256, 512, 1024, 512};
+constexpr int kQueueDefault = 2;
+
 struct TuneChoice {
-  int hc = 16;                 // bandwidths per block (8, 16, 32)
-  double rate[3] = {0, 0, 0};  // measured evals/s of hc 8, 16, 32
+  int hc = 16;  // bandwidths per block
+  int tj = 512;  // samples per LDS tile
+  double rate[kQueueVariants] = {0, 0, 0, 0, 0};  // measured evals/s of each variant (0: rejected)
+  bool parity[kQueueVariants] = {true, true, true, true, true};  // partial sums bitwise equal to the default's
 };
 
 struct Server;
@@ -178,8 +189,10 @@ struct kde_ctx {
   int opt_autotune = 0;            // synchronous jobs pick the LSCV variant with the tile autotuner
   int opt_graph = 0;               // synchronous jobs replay a captured graph of their launches
   int opt_prune = 0;               // LSCV tile pruning on sorted samples (mixed form, synchronous jobs)
+  int opt_tj = 512;                // samples per LDS tile of the persistent dense sweep (256, 512, 1024)
   int opt_persistent = 1;          // dense FP32 LSCV pass as one persistent launch over a device work queue
-  int queue_blocks[3] = {-1, -1, -1};  // resident blocks of the persistent LSCV kernel for hc 8, 16, 32 (-1: not asked)
+  // resident blocks of the persistent LSCV kernel per variant (kde::kQueueVariants order; -1: not asked)
+  int queue_blocks[5] = {-1, -1, -1, -1, -1};
   kde::DevBuf<char> sort_tmp;      // temporary storage of the column sorts
   kde::DevBuf<char> qbuf;          // query points / ranges, partials and outputs of the consumers
   kde::DevBuf<char> mdbuf;         // d-dimensional LSCV: samples, moments, whitened copy, partials
@@ -192,6 +205,7 @@ struct kde_ctx {
   std::vector<kde_job*> jobs;
   // LSCV variant of the current job (from the options, or the autotuner)
   int job_hc = 16;
+  int job_tj = 512;  // samples per LDS tile of the persistent dense sweep
   int job_mfma = 0;
   // autotuner: decisions per shape (quarter-octave bucket of n, n_h) and its trial buffer
   std::map<std::pair<int, int>, kde::TuneChoice> tune_cache;
@@ -309,6 +323,11 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L);
 kde_status upload_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L);
 kde_status execute(kde_ctx* c, IterPlan& it);
+// Blocks the device holds at once of the persistent dense LSCV sweep's
+// variant (hc, tj), cached per context (0: no such variant or no answer).
+int queue_blocks(kde_ctx* c, int hc, int tj);
+// Whether the dense LSCV pass of an executor plan runs as one persistent launch.
+bool lscv_queue_form(kde_ctx* c, const IterPlan& it);
 // The LSCV curve of one column as kde_lscv_curve computes it (job, copies of
 // g, gscale and the grid into the caller's arrays, synchronisation).
 kde_status lscv_curve_call(kde_ctx* c, kde_column x, const double* h_grid, int32_t n_h, double* g_out,

@@ -225,7 +225,10 @@ std::string plan_column(const kde_ctx* c, const kde_request& r, ColPlan& p) {
   p.f64 = r.x.dtype == KDE_F64;
   p.stages = p.plugin ? r.stages : 0;
   p.hc = all64 ? 8 : c->job_hc;
-  if (p.plugin) make_items(p.n, capped_seg(c, p.n, 1, 1.0), p.psi_items);
+  // psi items are cut like one LSCV chunk's (about 7.6e6 pairs a block at
+  // the default launch size): a stage's pass then spans ~30 rounds of the
+  // blocks the chip holds, so its partly filled last round costs little
+  if (p.plugin) make_items(p.n, capped_seg(c, p.n, kSegRefHC, 1.0), p.psi_items);
   if (p.lscv) {
     p.n_h = r.grid.n_h;
     p.n_chunks = (p.n_h + p.hc - 1) / p.hc;
@@ -492,6 +495,53 @@ void sort_units(std::vector<Unit>& u, std::vector<UnitCost>& cost, bool scatter 
   cost.swap(c2);
 }
 
+// Groups of the persistent dense sweep: the largest-first list is split,
+// keeping that order inside each group, into kQueueGroups stretches of about
+// equal work in (column, j) position, so that the blocks starting on one die
+// read the sample tiles of one stretch of the column.  Positions are bucketed
+// (4096 buckets over the columns laid end to end) and the buckets cut where
+// the running work passes each equal share: O(units), no second sort.
+void group_units(std::vector<Unit>& u, std::vector<UnitCost>& cost, const std::vector<ColDesc>& cols,
+                 int (&begin)[kQueueGroups + 1]) {
+  constexpr int kBuckets = 4096;
+  std::vector<double> col_off(cols.size() + 1, 0.0);
+  for (size_t c = 0; c < cols.size(); ++c) col_off[c + 1] = col_off[c] + (double)std::max(cols[c].n, 1);
+  const double total_pos = std::max(col_off.back(), 1.0);
+  auto bucket = [&](const Unit& x) {
+    const double pos = col_off[x.col] + (double)x.j_begin;
+    return std::min(kBuckets - 1, (int)(pos / total_pos * kBuckets));
+  };
+  std::vector<double> work(kBuckets, 0.0);
+  double total = 0.0;
+  for (size_t k = 0; k < u.size(); ++k) {
+    work[bucket(u[k])] += cost[k].evals;
+    total += cost[k].evals;
+  }
+  std::vector<int> group_of(kBuckets, kQueueGroups - 1);
+  double run = 0.0;
+  int g = 0;
+  for (int b = 0; b < kBuckets; ++b) {
+    group_of[b] = g;
+    run += work[b];
+    while (g < kQueueGroups - 1 && run >= total * (double)(g + 1) / kQueueGroups) ++g;
+  }
+  std::vector<int> count(kQueueGroups, 0);
+  for (const Unit& x : u) ++count[group_of[bucket(x)]];
+  begin[0] = 0;
+  for (int q = 0; q < kQueueGroups; ++q) begin[q + 1] = begin[q] + count[q];
+  std::vector<int> at(begin, begin + kQueueGroups);
+  std::vector<Unit> u2(u.size());
+  std::vector<UnitCost> c2(u.size());
+  for (size_t k = 0; k < u.size(); ++k) {
+    const int q = group_of[bucket(u[k])];
+    u2[at[q]] = u[k];
+    c2[at[q]] = cost[k];
+    ++at[q];
+  }
+  u.swap(u2);
+  cost.swap(c2);
+}
+
 // Launch ranges over units [0, n) whose summed evaluations stay within
 // budget, with at least 2048 blocks per launch when the list has them, so a
 // launch fills the chip.  FP64 terms cost about five times the FP32 ones.
@@ -533,10 +583,20 @@ struct Blob {
 
 // Blocks of the persistent LSCV kernel that the device holds at once, asked
 // once per variant (0: unavailable, use sliced launches).
-int queue_blocks(kde_ctx* c, int hc) {
-  const int v = hc == 8 ? 0 : (hc == 32 ? 2 : 1);
-  if (c->queue_blocks[v] < 0) c->queue_blocks[v] = kde::lscv_queue_blocks(hc);
-  return c->queue_blocks[v];
+int queue_blocks(kde_ctx* c, int hc, int tj) {
+  for (int v = 0; v < kQueueVariants; ++v)
+    if (kQueueHC[v] == hc && kQueueTJ[v] == tj) {
+      if (c->queue_blocks[v] < 0) c->queue_blocks[v] = kde::lscv_queue_blocks(hc, tj);
+      return c->queue_blocks[v];
+    }
+  return 0;
+}
+
+// The dense LSCV pass of `it` runs as one persistent launch (mixed form, the
+// vector-ALU sweep, option persistent, a variant the device can hold).
+bool lscv_queue_form(kde_ctx* c, const IterPlan& it) {
+  return c->prec != KDE_PREC_FP64 && !c->job_mfma && c->opt_persistent && !it.lscv_units.empty() &&
+         queue_blocks(c, c->job_hc, c->job_tj) > 0;
 }
 
 kde_status collect_ready_timing(kde_ctx* c) {
@@ -571,6 +631,11 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
     sort_units(it.psi_cond_units[q], it.psi_cond_cost[q]);
   }
   sort_units(it.lscv_units, it.lscv_cost);
+  if (lscv_queue_form(c, it)) {
+    group_units(it.lscv_units, it.lscv_cost, it.cols, it.lscv_groups);
+  } else {
+    for (int q = 0; q <= kQueueGroups; ++q) it.lscv_groups[q] = q == 0 ? 0 : (int)it.lscv_units.size();
+  }
   sort_units(it.near_units, it.near_cost);
   sort_units(it.prune_units, it.prune_cost, true);
   // one blob: column table, id lists, units, rows
@@ -596,6 +661,7 @@ kde_status pack_pass(kde_ctx* c, IterPlan& it, PassLayout& L) {
   L.o_pu = b.add(it.prune_units.data(), vbytes(it.prune_units));
   static const int kZeroCounters[64] = {};
   L.o_ctr = b.add(kZeroCounters, sizeof(kZeroCounters));
+  L.o_lg = b.add(it.lscv_groups, sizeof(it.lscv_groups));
   L.bytes = b.bytes;
   L.sort_tmp = 0;
   for (const SortJob& j : it.sorts) {
@@ -692,16 +758,16 @@ kde_status launch_pass(kde_ctx* c, const IterPlan& it, const PassLayout& L) {
     if (s) return s;
   }
   const Unit* lu = (const Unit*)(d + L.o_lu);
-  const int qb = (!all64 && !c->job_mfma && c->opt_persistent && !it.lscv_units.empty()) ? queue_blocks(c, hc) : 0;
-  if (qb > 0) {
-    // the whole dense pass in one persistent launch over a device work queue
+  if (lscv_queue_form(c, it)) {
+    // the whole dense pass in one persistent launch over device work queues
     double evals = 0.0;
     for (const UnitCost& u : it.lscv_cost) evals += u.evals;
     int* ctr = (int*)(d + L.o_ctr);
-    kde::launch_zero_ints(st, ctr, 1);
+    kde::launch_zero_ints(st, ctr, kde::kQueueGroups);
     kde_ctx::Pending pd{nullptr, nullptr, kde::kFamLscv, evals};
     if ((s = timed_begin(c, pd))) return s;
-    kde::launch_lscv_units_queue(st, hc, cols, lu, (int)it.lscv_units.size(), ctr, qb);
+    kde::launch_lscv_units_queue(st, hc, c->job_tj, cols, lu, (int)it.lscv_units.size(), (const int*)(d + L.o_lg), ctr,
+                                 kde::queue_blocks(c, hc, c->job_tj));
     if ((s = timed_end(c, pd))) return s;
   } else {
     s = for_each_launch(c, it.lscv_cost, all64, [&](int u0, int cnt, double evals) -> kde_status {
@@ -771,6 +837,7 @@ std::string job_signature(const kde_ctx* c, const kde_request* reqs, int32_t n_r
   put(n_req);
   put(c->prec);
   put(c->job_hc);
+  put(c->job_tj);
   put(c->job_mfma);
   put(c->opt_seg);
   put(c->opt_launch_evals);
@@ -1156,6 +1223,10 @@ kde_status kde_ctx_set_option(kde_ctx* c, const char* key, int64_t value) {
     c->opt_seg = value < 0 ? -1 : value;
   } else if (k == "launch_evals") {
     c->opt_launch_evals = value <= 0 ? 4e12 : (double)value;
+  } else if (k == "lscv_tj") {
+    if (value < 0) value = 512;
+    if (value != 256 && value != 512 && value != 1024) return fail(c, KDE_E_INVAL, "lscv_tj must be 256, 512 or 1024");
+    c->opt_tj = (int)value;
   } else if (k == "fp64_kappa") {
     c->opt_fp64_kappa = value < 0 ? 1e3 : (double)value;
   } else if (k == "lscv_mfma") {
@@ -1213,7 +1284,7 @@ kde_status kde_plan_items(int64_t n, int32_t n_h, int64_t seg, int32_t cap, int3
     kde::make_items(n, kde::capped_seg(&o, n, kde::kSegRefHC, (double)((n_h + kde::kSegRefHC - 1) / kde::kSegRefHC)),
                     it);
   else
-    kde::make_items(n, kde::capped_seg(&o, n, 1, 1.0), it);
+    kde::make_items(n, kde::capped_seg(&o, n, kde::kSegRefHC, 1.0), it);
   const int32_t m = (int32_t)it.pairs.size();
   *n_items = m;
   for (int32_t k = 0; k < std::min(m, cap); ++k) {

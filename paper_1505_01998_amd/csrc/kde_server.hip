@@ -305,9 +305,12 @@ void Server::loop() {
     std::sort(work.begin(), work.end(), [](const std::shared_ptr<SrvReq>& a, const std::shared_ptr<SrvReq>& b) {
       return a->key < b->key || (a->key == b->key && a->ticket < b->ticket);
     });
-    // An iteration is one launch per pass, so it must hold several waves of its
-    // largest units or the launch tail idles the chip: at least 6 rounds of
-    // 1024 resident blocks of the largest unit any resident request has next.
+    // An iteration is one launch per pass, so it must hold many rounds of its
+    // largest units or the launch tail idles the chip (about half a unit per
+    // block at the end of every launch): at least 24 rounds of 1024 resident
+    // blocks of the largest unit any resident request has next, which keeps
+    // that idle share near 2% (at 6 rounds the served form lost ~3% of the
+    // plain form's throughput on streams of large requests).
     double max_unit = 0.0;
     for (auto& r : work) {
       if (r->plan.plugin && !r->plugin_done && r->psi_next < r->psi_c.size())
@@ -317,7 +320,7 @@ void Server::loop() {
     }
     const double base = ctx->opt_serve_iter_s > 0.0 ? std::max(iter_budget, ctx->opt_serve_iter_evals)
                                                     : ctx->opt_serve_iter_evals;
-    double left = std::max(base, 6.0 * 1024.0 * max_unit);
+    double left = std::max(base, 24.0 * 1024.0 * max_unit);
     const double left0 = left;
     bool first = true;
     for (auto& r : work) {
@@ -483,6 +486,7 @@ kde_status kde_server_start(kde_ctx* c, uint64_t hbm_budget_bytes, int32_t max_s
   // served requests run the LSCV variant the options name (the variant does
   // not change any result, only the speed)
   c->job_hc = c->opt_hc;
+  c->job_tj = c->opt_tj;
   c->job_mfma = c->opt_mfma;
   std::unique_ptr<Server, kde::ServerDeleter> s(new Server());
   s->c = c;

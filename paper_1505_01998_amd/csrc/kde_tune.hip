@@ -1,26 +1,33 @@
 // kde_tune.hip -- tile autotuner for the LSCV pair pass.
 //
-// The LSCV pass (Section 4.4.2, every grid h of eq. LSCV-gh from one pair
-// distance, Section 4.5) has three vector-ALU kernel variants: 8, 16 or 32
-// bandwidths per block.  They trade register pressure (waves per SIMD)
-// against how far the pair distance is amortised, and waste different amounts
-// of work on the padded last chunk of a grid.  Work items are sized
-// independently of the variant and every (item, h) sum is accumulated in the
-// same order by all of them, so the variant changes the speed and never a
-// result.  (The matrix-core form folds shorter runs, so its sums differ in
-// rounding; it stays an explicit option and is not a candidate.)
+// The dense LSCV pass (Section 4.4.2, every grid h of eq. LSCV-gh from one
+// pair distance, Section 4.5) runs as one persistent launch, in one of five
+// variants (kQueueHC x kQueueTJ): 8, 16 or 32 bandwidths per block with
+// 512-sample LDS tiles, and 16 bandwidths with 256- or 1024-sample tiles.
+// The bandwidths per block trade register pressure (waves per SIMD) against
+// how far the pair distance is amortised and how much of a padded last chunk
+// is wasted; the tile size trades staging and barrier frequency against LDS.
+// Work items are sized independently of the variant and every (item, h) sum
+// is accumulated in the same order by all of them, so the variant changes
+// the speed and never a result.  (The matrix-core form folds shorter runs,
+// so its sums differ in rounding; it stays an explicit option and is not a
+// candidate.)
 //
-// The tuner measures each variant's steady-state rate: launches of B and 2B
-// identical units (a row of 256 samples against a j-range as long as the
-// column's, capped at 8192) are timed and the difference is divided into the
-// extra work, which cancels launch overhead and the partly filled last round
-// of blocks.  The trial column's samples are spread evenly and the grid's
-// exponentials cover the range of a real one: the part draws less power on
-// an all-zero column and then runs a few per cent faster than on real data.
-// The rate is then scaled by the share of the
-// variant's bandwidth slots that the grid fills (a 100-point grid fills 100
-// of 104 slots at 8 per block, 112 at 16, 128 at 32).  Decisions are cached
-// per context by shape (quarter octave of n, grid size).
+// The tuner measures each variant's steady-state rate on the persistent
+// kernel itself: launches over B and 2B units of a trial column are timed and
+// the difference is divided into the extra work, which cancels launch
+// overhead and the drain at the end of a launch.  The trial units are the
+// rows of a column of L samples (L as long as the column, capped at 8192)
+// against the rest of the row, cycled; the samples are spread evenly and the
+// grid's exponentials cover the range of a real one (the part draws less
+// power on an all-zero column and then runs a few per cent faster).  Before
+// a variant may be chosen it must pass a parity gate: its partial sums of
+// every trial unit for the first 8 bandwidths must be bitwise those of the
+// default variant (16, 512), the property the decomposition guarantees.  The
+// rate is scaled by the share of the variant's bandwidth slots that the grid
+// fills (a 100-point grid fills 100 of 104 slots at 8 per block, 112 at 16,
+// 128 at 32).  Decisions are cached per context by shape (quarter octave of
+// n, grid size).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,15 +41,20 @@ namespace kde {
 
 namespace {
 
-constexpr int kTrialUnits = 4096;          // B: 4096 and 8192 units per variant (16 and 32 per CU)
-constexpr int kTrialMaxJ = 8192;            // j-range of a trial unit (samples)
+constexpr int kTrialUnits = 4096;          // B: about 4096 and 8192 units per variant
+constexpr int kTrialMaxJ = 8192;            // trial column length (samples)
 constexpr double kTuneMinJobEvals = 1e13;  // jobs smaller than this use the cached or default variant
 constexpr double kSwitchGain = 1.02;       // a variant replaces the default only when this much faster
-
-constexpr int kVariants[3] = {8, 16, 32};  // bandwidths per block
+constexpr int kGateH = 8;                  // bandwidths every variant's parity gate compares
 
 std::pair<int, int> shape_key(int64_t n, int n_h) {
   return {(int)std::floor(4.0 * std::log2((double)std::max<int64_t>(n, 2))), n_h};
+}
+
+// Pairs i < j of the trial unit for row r of an L-sample column, j in [r*kBI, L).
+double trial_pairs(int L, int r) {
+  const double i0 = (double)r * kBI, len = (double)L - i0;
+  return (double)kBI * len - 0.5 * (double)kBI * ((double)kBI + 1.0);
 }
 
 }  // namespace
@@ -55,9 +67,12 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     out = hit->second;
     return KDE_OK;
   }
-  // trial column: L samples (+ padding), one row against j in [0, L)
+  // trial column: L samples (+ padding), R rows; unit k is row k % R against
+  // j in [row * kBI, L), so B and 2B units are whole copies of the row cycle
   const int L = (int)std::min<int64_t>(((n + kBJ - 1) / kBJ) * kBJ, kTrialMaxJ);
-  const int B2 = 2 * kTrialUnits;
+  const int R = L / kBI;
+  const int B = std::max(1, kTrialUnits / R) * R;
+  const int B2 = 2 * B;
   const size_t xn = (size_t)L + kPad;
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -66,16 +81,21 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     return o;
   };
   const size_t o_x = take(4 * xn), o_c = take(4 * 32), o_part = take(16 * 32 * (size_t)B2),
-               o_st = take(sizeof(DevState)), o_col = take(sizeof(ColDesc)), o_units = take(sizeof(Unit) * B2);
+               o_st = take(sizeof(DevState)), o_col = take(sizeof(ColDesc)), o_units = take(sizeof(Unit) * B2),
+               o_ctr = take(sizeof(int) * kQueueGroups), o_gb = take(sizeof(int) * 2 * (kQueueGroups + 1));
   kde_status s;
   if ((s = ensure(c, c->tune_buf, at))) return s;
   char* b = c->tune_buf.p;
   // zero state (status OK); samples spread evenly over [0, 4) with +inf
-  // padding and coefficients of 32 bandwidths log-spaced over [0.01, 1], so
-  // the exponentials span the range of a real grid (on an all-zero column
-  // every exponential is exp2(0), and the part then runs a few per cent
-  // faster than on real data)
+  // padding and coefficients of 32 bandwidths log-spaced over [0.01, 1]
   KDE_HIP_TRY(c, hipMemsetAsync(b, 0, o_units, c->stream));
+  std::vector<Unit> u(B2);
+  double extra_pairs = 0.0;  // pairs of the extra B units of the 2B launch
+  for (int k = 0; k < B2; ++k) {
+    const int r = k % R;
+    u[k] = Unit{0, r, r * kBI, L, k, 0};
+    if (k >= B) extra_pairs += trial_pairs(L, r);
+  }
   {
     std::vector<float> hx(xn), hcf(32);
     for (size_t j = 0; j < xn; ++j) hx[j] = j < (size_t)L ? 4.0f * (float)j / (float)L : HUGE_VALF;
@@ -85,22 +105,40 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     }
     KDE_HIP_TRY(c, hipMemcpyAsync(b + o_x, hx.data(), 4 * xn, hipMemcpyHostToDevice, c->stream));
     KDE_HIP_TRY(c, hipMemcpyAsync(b + o_c, hcf.data(), 4 * 32, hipMemcpyHostToDevice, c->stream));
+    KDE_HIP_TRY(c, hipMemcpyAsync(b + o_units, u.data(), sizeof(Unit) * B2, hipMemcpyHostToDevice, c->stream));
+    // one group holding all units: first for the B launches, then for 2B
+    std::vector<int> gb(2 * (kQueueGroups + 1));
+    for (int q = 0; q <= kQueueGroups; ++q) {
+      gb[q] = q == 0 ? 0 : B;
+      gb[kQueueGroups + 1 + q] = q == 0 ? 0 : B2;
+    }
+    KDE_HIP_TRY(c, hipMemcpyAsync(b + o_gb, gb.data(), sizeof(int) * gb.size(), hipMemcpyHostToDevice, c->stream));
     KDE_HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
-  // every unit writes its own partial slots (item = unit index)
-  std::vector<Unit> u(B2);
-  for (int k = 0; k < B2; ++k) u[k] = Unit{0, 0, 0, L, k, 0};
-  KDE_HIP_TRY(c, hipMemcpyAsync(b + o_units, u.data(), sizeof(Unit) * B2, hipMemcpyHostToDevice, c->stream));
   const ColDesc* cols = (const ColDesc*)(b + o_col);
   const Unit* dev_units = (const Unit*)(b + o_units);
+  int* ctr = (int*)(b + o_ctr);
+  const int* groups_B = (const int*)(b + o_gb);
+  const int* groups_B2 = groups_B + kQueueGroups + 1;
   hipEvent_t ev[3];
   int made = 0;
   hipError_t he = hipSuccess;
   for (; made < 3 && he == hipSuccess; ++made) he = hipEventCreate(&ev[made]);
   if (he != hipSuccess) --made;
   TuneChoice r;
-  for (int v = 0; v < 3 && he == hipSuccess; ++v) {
-    const int hc = kVariants[v];
+  std::vector<double> ref, got((size_t)2 * kGateH * B2);
+  // the default variant first: its partial sums are the gate's reference
+  int order[kQueueVariants];
+  order[0] = kQueueDefault;
+  for (int v = 0, k = 1; v < kQueueVariants; ++v)
+    if (v != kQueueDefault) order[k++] = v;
+  for (int q = 0; q < kQueueVariants && he == hipSuccess; ++q) {
+    const int v = order[q];
+    const int hc = kQueueHC[v], tj = kQueueTJ[v];
+    const int blocks = queue_blocks(c, hc, tj);
+    r.rate[v] = 0.0;
+    r.parity[v] = false;
+    if (blocks <= 0) continue;
     ColDesc d;
     std::memset(&d, 0, sizeof(d));
     d.x32 = (float*)(b + o_x);
@@ -113,17 +151,21 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     // synchronous, as `d` is reused for the next variant
     he = hipMemcpyAsync(b + o_col, &d, sizeof(d), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-    // warm-up, then B units and 2B units back to back
+    // warm-up, then B units and 2B units back to back (the 2B launch writes
+    // every unit's partial slots, which the gate reads)
     if (he == hipSuccess) {
-      launch_lscv_units(c->stream, hc, 0, 0, 0, cols, dev_units, 0, kTrialUnits);
+      launch_zero_ints(c->stream, ctr, kQueueGroups);
+      launch_lscv_units_queue(c->stream, hc, tj, cols, dev_units, B, groups_B, ctr, blocks);
+      launch_zero_ints(c->stream, ctr, kQueueGroups);
       he = hipEventRecord(ev[0], c->stream);
     }
     if (he == hipSuccess) {
-      launch_lscv_units(c->stream, hc, 0, 0, 0, cols, dev_units, 0, kTrialUnits);
+      launch_lscv_units_queue(c->stream, hc, tj, cols, dev_units, B, groups_B, ctr, blocks);
+      launch_zero_ints(c->stream, ctr, kQueueGroups);
       he = hipEventRecord(ev[1], c->stream);
     }
     if (he == hipSuccess) {
-      launch_lscv_units(c->stream, hc, 0, 0, 0, cols, dev_units, 0, B2);
+      launch_lscv_units_queue(c->stream, hc, tj, cols, dev_units, B2, groups_B2, ctr, blocks);
       he = hipEventRecord(ev[2], c->stream);
     }
     if (he == hipSuccess) he = hipGetLastError();
@@ -131,16 +173,21 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
     float t1 = 0.f, t2 = 0.f;
     if (he == hipSuccess) he = hipEventElapsedTime(&t1, ev[0], ev[1]);
     if (he == hipSuccess) he = hipEventElapsedTime(&t2, ev[1], ev[2]);
-    const double slots = 256.0 * L * hc * kTrialUnits;  // (pair, h) slots of the extra B units
+    if (he == hipSuccess)
+      he = hipMemcpy(got.data(), b + o_part, sizeof(double) * got.size(), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) break;
+    if (v == kQueueDefault) ref = got;
+    r.parity[v] = std::memcmp(got.data(), ref.data(), sizeof(double) * got.size()) == 0;
     const double fill = (double)n_h / (double)(((n_h + hc - 1) / hc) * hc);
-    r.rate[v] = (t2 > t1) ? slots / ((t2 - t1) * 1e-3) * fill : 0.0;
+    r.rate[v] = (t2 > t1) ? extra_pairs * hc / ((t2 - t1) * 1e-3) * fill : 0.0;
   }
   for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
   if (he != hipSuccess) return fail(c, KDE_E_DEVICE, std::string("autotune trial: ") + hipGetErrorString(he));
-  int best = 1;  // the default variant, 16 bandwidths per block
-  for (int v = 0; v < 3; ++v)
-    if (r.rate[v] > r.rate[best] * kSwitchGain) best = v;
-  r.hc = kVariants[best];
+  int best = kQueueDefault;
+  for (int v = 0; v < kQueueVariants; ++v)
+    if (r.parity[v] && r.rate[v] > r.rate[best] * kSwitchGain) best = v;
+  r.hc = kQueueHC[best];
+  r.tj = kQueueTJ[best];
   c->tune_cache[key] = r;
   out = r;
   return KDE_OK;
@@ -148,6 +195,7 @@ kde_status tune_shape(kde_ctx* c, int64_t n, int n_h, TuneChoice& out) {
 
 kde_status select_variant(kde_ctx* c, const kde_request* reqs, int32_t n_req) {
   c->job_hc = c->opt_hc;
+  c->job_tj = c->opt_tj;
   c->job_mfma = c->opt_mfma;
   if (!c->opt_autotune || c->prec == KDE_PREC_FP64) return KDE_OK;
   // the job's largest LSCV column decides; malformed requests are skipped
@@ -180,6 +228,7 @@ kde_status select_variant(kde_ctx* c, const kde_request* reqs, int32_t n_req) {
     return KDE_OK;
   }
   c->job_hc = t.hc;
+  c->job_tj = t.tj;
   c->job_mfma = 0;
   return KDE_OK;
 }
@@ -197,7 +246,11 @@ extern "C" kde_status kde_autotune(kde_ctx* c, int64_t n, int32_t n_h, kde_tune_
   if (s) return s;
   if (out) {
     out->hc = t.hc;
-    for (int v = 0; v < 3; ++v) out->evals_per_s[v] = t.rate[v];
+    out->tj = t.tj;
+    for (int v = 0; v < kde::kQueueVariants; ++v) {
+      out->evals_per_s[v] = t.rate[v];
+      out->parity[v] = t.parity[v] ? 1 : 0;
+    }
   }
   return KDE_OK;
 }

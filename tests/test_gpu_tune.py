@@ -27,30 +27,42 @@ def test_variants_bitwise_equal(kde):
         for hc in (8, 16, 32):
             c.set_option("lscv_hc", hc)
             out[hc] = c.lscv_sums(x, grid)
-    for hc in (8, 32):
-        assert np.array_equal(out[hc][0], out[16][0]) and np.array_equal(out[hc][1], out[16][1]), hc
+        c.set_option("lscv_hc", 16)
+        for tj in (256, 1024):
+            c.set_option("lscv_tj", tj)
+            out[(16, tj)] = c.lscv_sums(x, grid)
+        with pytest.raises(kde.KdeError) as e:
+            c.set_option("lscv_tj", 768)
+        assert e.value.status == kde.KDE_E_INVAL
+    for v in (8, 32, (16, 256), (16, 1024)):
+        assert np.array_equal(out[v][0], out[16][0]) and np.array_equal(out[v][1], out[16][1]), v
     o = oracle.lscv_curve(x, grid)
     assert np.allclose(out[16][0], o.s1, rtol=1e-5) and np.allclose(out[16][1], o.s2, rtol=1e-5)
 
 
 def test_autotune_choice_and_cache(kde):
+    """Every variant of the persistent sweep runs and passes the tuner's
+    bitwise parity gate; the choice is the default (16, 512) unless another
+    variant is 2% faster; a second call for the same shape, or for a column in
+    the same quarter octave of n, returns the cached decision at once."""
     with kde.Context(0) as c:
         t0 = time.perf_counter()
-        hc, rates = c.autotune(200_000, 128)
+        choice, rates, parity = c.autotune(200_000, 128)
         t1 = time.perf_counter()
-        hc2, rates2 = c.autotune(200_000, 128)
+        again = c.autotune(200_000, 128)
         t2 = time.perf_counter()
-        # same quarter octave of n: the cached decision
-        hc3, rates3 = c.autotune(205_000, 128)
-    print(f"autotune n=2e5 n_h=128: hc={hc} rates={ {k: f'{v:.3e}' for k, v in rates.items()} } "
-          f"first {t1 - t0:.3f} s, cached {t2 - t1:.6f} s")
-    assert hc in (8, 16, 32)
+        near = c.autotune(205_000, 128)
+    print(f"autotune n=2e5 n_h=128: {choice} rates={ {k: f'{v:.3e}' for k, v in rates.items()} } "
+          f"parity={parity} first {t1 - t0:.3f} s, cached {t2 - t1:.6f} s")
+    assert choice in kde.TUNE_VARIANTS
+    assert set(rates) == set(kde.TUNE_VARIANTS)
     assert all(v > 1e11 for v in rates.values())
+    assert all(parity.values())
     # the default is kept unless another variant is 2% faster
-    assert rates[hc] >= rates[16]
-    if hc != 16:
-        assert rates[hc] > 1.02 * rates[16]
-    assert (hc2, rates2) == (hc, rates) and (hc3, rates3) == (hc, rates)
+    assert rates[choice] >= rates[(16, 512)]
+    if choice != (16, 512):
+        assert rates[choice] > 1.02 * rates[(16, 512)]
+    assert again == (choice, rates, parity) and near == (choice, rates, parity)
     assert t2 - t1 < 0.05
 
 
@@ -80,13 +92,13 @@ def test_autotuned_jobs_equal_default(kde):
         g_p, gs_p, _ = plain.lscv_curve(big, grid)
         r_t = tuned.batch(small)
         r_p = plain.batch(small)
-        hc, _ = tuned.autotune(big.size, grid.size)  # cached by the first call
+        choice, _, _ = tuned.autotune(big.size, grid.size)  # cached by the first call
     assert np.array_equal(g_t, g_p) and np.array_equal(gs_t, gs_p)
     for a, b in zip(r_t, r_p):
         assert a.status == b.status == kde.KDE_OK
         assert a.h_lscv == b.h_lscv and a.h_plugin == b.h_plugin
         assert np.array_equal(a.g, b.g)
-    assert hc in (8, 16, 32)
+    assert choice in kde.TUNE_VARIANTS
 
 
 def test_inner_loop_ceiling(kde):
@@ -100,7 +112,7 @@ def test_inner_loop_ceiling(kde):
     with kde.Context(0) as c:
         ceil16 = c.lscv_ceiling(16)
         ceil8 = c.lscv_ceiling(8)
-        _, rates = c.autotune(x.size, grid.size)
+        _, rates, _ = c.autotune(x.size, grid.size)
         c.lscv_curve(x, grid)
         t = time.perf_counter()
         c.lscv_curve(x, grid)
@@ -111,6 +123,6 @@ def test_inner_loop_ceiling(kde):
             assert e.value.status == kde.KDE_E_INVAL
     sweep = x.size * (x.size - 1) / 2 * grid.size / dt
     assert ceil16 > 1e12 and ceil8 > 1e12
-    assert rates[16] <= 1.05 * ceil16 and sweep <= 1.05 * ceil16
-    print(f"inner-loop ceiling {ceil16:.3e} (hc 16), {ceil8:.3e} (hc 8); steady state {rates[16]:.3e}; "
+    assert rates[(16, 512)] <= 1.05 * ceil16 and sweep <= 1.05 * ceil16
+    print(f"inner-loop ceiling {ceil16:.3e} (hc 16), {ceil8:.3e} (hc 8); steady state {rates[(16, 512)]:.3e}; "
           f"sweep n=2e5 {sweep:.3e} evals/s")
