@@ -29,16 +29,24 @@ if ROOT not in sys.path:
 
 import workloads  # noqa: E402
 
-# MI355X: 256 CUs at 2.4 GHz.  Per CU and clock the vector units retire 128
-# FP32 lanes of add/mul/fma (157.3 TFLOP/s counting an FMA as 2) and 32 lanes
-# of v_exp_f32; the library's issue-rate probe (kde_issue_rates, run in every
-# default line) measures both on the part with unpacked FP32 instructions.
-# The exponential does not overlap the plain stream (measured), so one LSCV
-# (pair, h) term -- 1 mul + 1 exp + 1 add + 1 fma -- is bounded by
-#   1 / (3 / (CUS * 128 * f) + 1 / (CUS * 32 * f)).
+# MI355X: 256 CUs at 2.4 GHz.  The published FP32 vector peak, 157.3 TFLOP/s
+# counting an FMA as 2, is 128 FP32 lanes of add/mul/fma per CU and clock,
+# reached with packed (two-wide) instructions; unpacked instructions retire
+# half that, 64 lanes, and v_exp_f32 retires 32 lanes.  The library's
+# issue-rate probe (kde_issue_rates, run in every default line) measures the
+# unpacked and exp2 rates on the part (62.7 and 31.0 lanes per clock and CU).
+# One LSCV (pair, h) term is 1 mul + 1 exp2 + 1 add + 1 fma.  The peak the
+# roofline reports is the chip's bound for that mix at its published FP32
+# rate, with the exponential not overlapping plain issue:
+#   R = 1 / (3 / (CUS * 128 * f) + 1 / (CUS * 32 * f)) = 11.23e12 terms/s.
+# This build compiles without packed FP32 instructions, so the ceiling it can
+# reach is the same mix at the unpacked rate, R_unpacked = 7.86e12 terms/s;
+# the line reports the kernel against both.
 CUS, CLOCK_HZ = 256, 2.4e9
 VALU_LANES, TRANS_LANES = 128, 32
+UNPACKED_LANES = 64
 LSCV_PEAK = 1.0 / (3.0 / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ))  # 11.23e12/s
+LSCV_PEAK_UNPACKED = 1.0 / (3.0 / (CUS * UNPACKED_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ))
 # The psi pass at the same issue model.  With the samples pre-scaled by 1/g
 # (one O(n) pass per stage) a pair needs sub, mul (w = u^2), mul (exp2
 # argument), r/2 Horner ops for He_r in w and two fma (the term and its
@@ -47,6 +55,8 @@ LSCV_PEAK = 1.0 / (3.0 / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANE
 # is their harmonic mean (6.55e12 pairs/s).
 PSI_PLAIN = (9, 8, 7)
 PSI_PEAK = 3.0 / sum(p / (CUS * VALU_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ) for p in PSI_PLAIN)
+PSI_PEAK_UNPACKED = 3.0 / sum(p / (CUS * UNPACKED_LANES * CLOCK_HZ) + 1.0 / (CUS * TRANS_LANES * CLOCK_HZ)
+                              for p in PSI_PLAIN)
 FP32_PEAK_TFLOPS = 157.3
 LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 
@@ -207,15 +217,16 @@ def _lscv_kernel(ctx, args, n, n_h):
     if args.precision != "mixed":
         return "k_lscv_units_f64<8>"
     if args.prune > 0:
-        hc = ctx.autotune(n, n_h)[0] if args.autotune > 0 else (args.hc if args.hc > 0 else 16)
+        hc = ctx.autotune(n, n_h)[0][0] if args.autotune > 0 else (args.hc if args.hc > 0 else 16)
         return f"k_lscv_units_prune<{hc}>"
     if args.autotune > 0:
-        return f"k_lscv_units_f32<{ctx.autotune(n, n_h)[0]}>"
+        hc, tj = ctx.autotune(n, n_h)[0]
+        return f"k_lscv_units_f32_queue<{hc}, {tj}>"
     if args.mfma > 0:
         return "k_lscv_units_mfma"
     hc = args.hc if args.hc > 0 else 16
     # the dense pass runs as one persistent launch unless switched off
-    return f"k_lscv_units_f32<{hc}>" if getattr(args, "persistent", -1) == 0 else f"k_lscv_units_f32_queue<{hc}>"
+    return f"k_lscv_units_f32<{hc}>" if getattr(args, "persistent", -1) == 0 else f"k_lscv_units_f32_queue<{hc}, 512>"
 
 
 def batch_bench(args):
@@ -436,35 +447,44 @@ def served_block(kde, args, stream, n_lo: float = 2e3, n_hi: float = 2e6):
     _apply_options(ctx, args)
     ctx.batch(reqs[:1])  # warm-up: code objects, allocations
     arrivals = [a.t for a in stream]
-    plain = run_plain(ctx, arrivals, "plain at arrival times")
-    out["plain"] = summary(*plain)
-    served = run_served(ctx, arrivals, "served at arrival times")
-    out["served"] = summary(*served)
-    cap = out["plain"]["req_per_s"]
-    scale = args.rate / (0.7 * cap)
+    lm_only = getattr(args, "lm_rate", 0.0) > 0
+    if lm_only:
+        # load-matched runs only, at a rate the caller states (0.7 x a plain
+        # capacity measured elsewhere)
+        lm_rate = args.lm_rate
+    else:
+        plain = run_plain(ctx, arrivals, "plain at arrival times")
+        out["plain"] = summary(*plain)
+        served = run_served(ctx, arrivals, "served at arrival times")
+        out["served"] = summary(*served)
+        lm_rate = 0.7 * out["plain"]["req_per_s"]
+    scale = args.rate / lm_rate
     matched = [t * scale for t in arrivals]
-    log(f"{elapsed():.0f} s: served: load-matched at {0.7 * cap:.3f} req/s")
+    log(f"{elapsed():.0f} s: served: load-matched at {lm_rate:.3f} req/s")
     plain_lm = run_plain(ctx, matched, "plain load-matched")
     out["plain_load_matched"] = summary(*plain_lm)
     served_lm = run_served(ctx, matched, "served load-matched")
     out["served_load_matched"] = summary(*served_lm)
     ctx.close()
     ns = [a.spec.n for a in stream]
-    return {
+    res = {
         "requests": len(reqs),
         "stream": f"first {len(reqs)} requests of the seeded served stream (seed 1998005, Poisson {args.rate:g} "
                   f"req/s over 60 s, n log-uniform in [{n_lo:g}, {n_hi:g}]; this prefix has n from {min(ns)} to "
                   f"{max(ns)})",
         "pair_evals": evals,
-        "load_matched_rate_req_s": 0.7 * cap,
+        "load_matched_rate_req_s": lm_rate,
         **out,
-        "speedup_req_s": out["served"]["req_per_s"] / out["plain"]["req_per_s"],
         "speedup_req_s_load_matched": out["served_load_matched"]["req_per_s"] /
                                       out["plain_load_matched"]["req_per_s"],
-        "results_bitwise_equal_plain": same(plain[2], served[2]) and same(plain[2], served_lm[2]),
+        "results_bitwise_equal_plain": same(plain_lm[2], served_lm[2]) and
+                                       (lm_only or same(plain[2], served[2])),
         "p99_note": f"p99 over {len(reqs)} latencies (linear interpolation between the two largest)"
                     if len(reqs) < 100 else f"p99 over {len(reqs)} latencies",
     }
+    if not lm_only:
+        res["speedup_req_s"] = out["served"]["req_per_s"] / out["plain"]["req_per_s"]
+    return res
 
 
 def served_bench(args):
@@ -474,11 +494,12 @@ def served_bench(args):
     n_lo, n_hi = (2e3, 2e6) if args.workload == "served" else (2e3, 6e4)
     stream = workloads.served_stream(args.requests, rate=args.rate, n_lo=n_lo, n_hi=n_hi)
     blk = served_block(kde, args, stream, n_lo, n_hi)
+    head = blk["served"] if "served" in blk else blk["served_load_matched"]
     return {
         "metric": "served req/s + p99 latency vs plain",
-        "value": blk["served"]["req_per_s"],
+        "value": head["req_per_s"],
         "unit": "req/s",
-        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": blk["served"]["makespan_s"] * 1e3,
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": head["makespan_s"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "requests": blk["requests"], "rate_req_s": args.rate,
@@ -501,7 +522,8 @@ def issue_probe(kde):
     return {**{k: r[k] for k in ("clock_hz", "cus")},
             "lanes_per_clk_cu": {k: r[k] for k in ("add_f32", "mul_f32", "fma_f32", "exp_f32")},
             "lscv_terms_per_clk_cu": {"spread": r["lscv_mix"], "zero": r["lscv_mix_zero"]},
-            "assumed_lanes_per_clk_cu": {"plain_f32": VALU_LANES, "exp_f32": TRANS_LANES}}
+            "assumed_lanes_per_clk_cu": {"plain_f32_packed": VALU_LANES, "plain_f32_unpacked": UNPACKED_LANES,
+                                         "exp_f32": TRANS_LANES}}
 
 
 def main():
@@ -521,6 +543,9 @@ def main():
     ap.add_argument("--served-budget-s", type=float, default=220.0,
                     help="single-column workloads: seconds of the budget reserved for the served block")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrival rate of the stream (req/s)")
+    ap.add_argument("--lm-rate", type=float, default=0.0,
+                    help="served workloads: run only the load-matched pair, at this rate (req/s; 0 = measure the "
+                         "plain capacity first and run all four)")
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--aging-ms", type=int, default=0, help="served: aging time constant of the SRPT order (0 = off)")
@@ -655,7 +680,7 @@ def main():
         # the ceiling of its inner loop run from one LDS tile, and the issue
         # rates of the part
         hc = args.hc if args.hc > 0 else 16
-        steady = ctx.autotune(n, n_h)[1][hc]
+        steady = ctx.autotune(n, n_h)[1][(hc, 512)]
         ceiling = ctx.lscv_ceiling(hc)
         probe = issue_probe(kde)
     ctx.close()
@@ -699,6 +724,8 @@ def main():
             "avg_launch_ms": ms / max(launches, 1),
             "evals_per_launch": performed_k / max(launches, 1),
             "fp32_flop_frac": achieved * LSCV_FLOP_PER_EVAL / (FP32_PEAK_TFLOPS * 1e12),
+            "peak_unpacked": LSCV_PEAK_UNPACKED / 1e12,
+            "frac_of_peak_unpacked": achieved / LSCV_PEAK_UNPACKED,
             "steady_state": None if steady is None else steady / 1e12,
             "inner_loop_ceiling": None if ceiling is None else ceiling / 1e12,
             "frac_of_inner_loop_ceiling": None if ceiling is None else achieved / ceiling,
@@ -706,7 +733,9 @@ def main():
         },
         "psi_kernel": {"launches": p_launches, "ms": p_ms, "evals": p_evals,
                        "achieved": p_evals / (p_ms * 1e-3) / 1e12 if p_ms > 0 else None, "peak": PSI_PEAK / 1e12,
-                       "unit": "Tpair/s", "frac": p_evals / (p_ms * 1e-3) / PSI_PEAK if p_ms > 0 else None},
+                       "unit": "Tpair/s", "frac": p_evals / (p_ms * 1e-3) / PSI_PEAK if p_ms > 0 else None,
+                       "peak_unpacked": PSI_PEAK_UNPACKED / 1e12,
+                       "frac_of_peak_unpacked": p_evals / (p_ms * 1e-3) / PSI_PEAK_UNPACKED if p_ms > 0 else None},
         "result": {"h_plugin": h_pi, "h_lscv": float(w.grid[int(np.argmin(g))]), "k_lscv": int(np.argmin(g))},
         "prune": None if args.prune <= 0 else {
             "performed_frac": skipped[-1][1],
