@@ -62,18 +62,19 @@ LSCV_FLOP_PER_EVAL = 5.0                  # mul + exp + add + fma(2)
 
 # HBM bytes per LSCV launch of this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, each scaled by the ratio the same counter shows for a
-# plain 1 GiB copy (fetch x2.0, write x1.0).  Valid only for the kernel
-# source they were taken on; reported as null once that source changes.
-# The kernels, their shared header and the planner's work-item code (which sizes the units, and so
-# the partial-sum writes per launch) decide the traffic.
+# plain 1 GiB copy (fetch x2.0, write x1.0).  Valid only for the sources they
+# were taken on; reported as null once those change.  The kernels, their
+# shared header and the runtime (the planner sizes the units, and so the
+# partial-sum writes; the persistent pass's grouping decides which die reads
+# which part of the column) decide the traffic.  One launch is one whole
+# LSCV pass of the step (the persistent form).
 TRAFFIC_SOURCES = ("kde_internal.h", "kde_kernels.hip", "kde_runtime.hip")
-PLANNER_BEGIN, PLANNER_END = "// ---- work items", "size_t take("
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
-    "kernel": "k_lscv_units_f32<16>",
-    "sources_sha256": "54f97a7fbab376e2ee898de726bf7fd84d802f5d2d4e2536f618a7cffa4fd30d",
-    "fetch_bytes": 2.6887e+07,
-    "write_bytes": 8.5991e+06,
+    "kernel": "k_lscv_units_f32_queue<16, 512>",
+    "sources_sha256": "96c16e97f2e78f2a21b4f50fd08d90366d558e4fc80a33fd046dc5c43d9078d0",
+    "fetch_bytes": 1.93965e+08,
+    "write_bytes": 1.15480e+09,
 }
 
 
@@ -84,11 +85,7 @@ def measured_traffic(workload: str, kernel: str):
 
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
-        text = open(os.path.join(ROOT, "paper_1505_01998_amd", "csrc", f), "rb").read()
-        if f == "kde_runtime.hip":
-            a, e = text.find(PLANNER_BEGIN.encode()), text.find(PLANNER_END.encode())
-            text = text[a:e] if 0 <= a < e else text
-        h.update(text)
+        h.update(open(os.path.join(ROOT, "paper_1505_01998_amd", "csrc", f), "rb").read())
     sha = h.hexdigest()
     t = MEASURED_TRAFFIC
     if sha != t["sources_sha256"] or workload != t["workload"] or kernel != t["kernel"]:
