@@ -145,9 +145,39 @@ def test_batch_512_uneven_columns(kde):
     print(f"batch-512: {t_batch:.2f} s, {pairs * (128 + 3) / t_batch:.3e} pair-evals/s")
     if os.path.exists(GOLDEN_B512):
         _check_stored_oracle(out, specs)
+    if os.path.exists(GOLDEN_B512_LARGE):
+        _check_stored_large(out, specs)
 
 
 GOLDEN_B512 = os.path.join(os.path.dirname(__file__), "golden", "batch_512_small_oracle.npz")
+GOLDEN_B512_LARGE = os.path.join(os.path.dirname(__file__), "golden", "batch_512_large_oracle.json")
+
+
+def _check_stored_large(out, specs):
+    """8 seeded columns of the batch with n > 20,000 against the oracle's
+    stored values (tests/golden/make_batch_512_large.py): sigma, h_rot, psi_r,
+    pilots and h_PI, and g(h) at the selected index +-2; the selected index
+    of eq. (LSCV-finalH) must be the oracle's minimum over that window."""
+    import json
+
+    ref = json.load(open(GOLDEN_B512_LARGE))["columns"]
+    worst = 0.0
+    for key, v in ref.items():
+        k = int(key)
+        r = out[k]
+        assert specs[k].n == v["n"]
+        assert r.sigma == pytest.approx(v["sigma"], rel=1e-12)
+        assert r.h_rot == pytest.approx(v["h_rot"], rel=1e-12)
+        for s in range(3):
+            assert r.plugin.psi[s] == pytest.approx(v["psi"][s], rel=TOL), (k, s)
+            assert r.plugin.g[s] == pytest.approx(v["g_pilot"][s], rel=TOL), (k, s)
+        assert r.h_plugin == pytest.approx(v["h_plugin"], rel=TOL), k
+        idx = v["idx"]
+        err = np.abs(r.g[idx] - np.array(v["g"])) / np.array(v["gscale"])
+        worst = max(worst, float(err.max()))
+        assert err.max() <= TOL, (k, err.max())
+        assert r.k_lscv == v["selected"] == idx[int(np.argmin(v["g"]))], (k, r.k_lscv, idx, v["g"])
+    print(f"batch-512 large columns vs stored oracle: {len(ref)} columns, max |dg|/gscale {worst:.2e}")
 
 
 def _check_stored_oracle(out, specs):
