@@ -188,6 +188,8 @@ def _requests_of(kde, cols, grid=None, stages=None):
 def _apply_options(ctx, args):
     if args.hc > 0:
         ctx.set_option("lscv_hc", args.hc)
+    if getattr(args, "tj", -1) > 0:
+        ctx.set_option("lscv_tj", args.tj)
     if args.seg >= 0:
         ctx.set_option("seg", args.seg)
     if args.mfma >= 0:
@@ -222,8 +224,9 @@ def _lscv_kernel(ctx, args, n, n_h):
     if args.mfma > 0:
         return "k_lscv_units_mfma"
     hc = args.hc if args.hc > 0 else 16
+    tj = args.tj if getattr(args, "tj", -1) > 0 else 512
     # the dense pass runs as one persistent launch unless switched off
-    return f"k_lscv_units_f32<{hc}>" if getattr(args, "persistent", -1) == 0 else f"k_lscv_units_f32_queue<{hc}, 512>"
+    return f"k_lscv_units_f32<{hc}>" if getattr(args, "persistent", -1) == 0 else f"k_lscv_units_f32_queue<{hc}, {tj}>"
 
 
 def batch_bench(args):
@@ -558,6 +561,8 @@ def main():
     ap.add_argument("--accuracy", type=int, default=1,
                     help="compare the mixed form with the all-FP64 GPU form after the timed steps (1/0)")
     ap.add_argument("--hc", type=int, default=-1, help="bandwidths per LSCV pass (8, 16, 32; -1 = default)")
+    ap.add_argument("--tj", type=int, default=-1,
+                    help="samples per LDS tile of the persistent LSCV sweep (256, 512, 1024; -1 = default)")
     ap.add_argument("--seg", type=int, default=-1, help="j-range per work item (-1 = automatic, 0 = whole rows)")
     ap.add_argument("--mfma", type=int, default=-1, help="LSCV arguments on the matrix cores (1/0; -1 = default)")
     ap.add_argument("--prune", type=int, default=-1,

@@ -201,9 +201,10 @@ kde_status kde_ctx_graph_stats(kde_ctx* ctx, int64_t* captures, int64_t* replays
  * a column shaped like n samples with an n_h-point grid (rows of an evenly
  * spread column of min(n, 8192) samples in buffers of the context; B and 2B
  * units differenced) and caches the fastest per shape (quarter octave of n,
- * n_h) in the context; the default (16, 512) is kept unless another is 2%
- * faster.  A variant is a candidate only if its trial partial sums for the
- * first 8 bandwidths are bitwise those of the default: the variant never
+ * n_h) in the context (each variant timed twice, keeping its better rate);
+ * the default (16, 512) is kept unless another is 3% faster.  A variant is
+ * a candidate only if its trial partial sums for the first 8 bandwidths are
+ * bitwise those of the default (in both trials): the variant never
  * changes a result, since items and summation order do not depend on it.
  * out->hc and out->tj receive the choice, out->evals_per_s[v] the measured
  * rate of variant v in the order above (pair-term evaluations per second,

@@ -43,7 +43,7 @@ def test_variants_bitwise_equal(kde):
 def test_autotune_choice_and_cache(kde):
     """Every variant of the persistent sweep runs and passes the tuner's
     bitwise parity gate; the choice is the default (16, 512) unless another
-    variant is 2% faster; a second call for the same shape, or for a column in
+    variant is 3% faster; a second call for the same shape, or for a column in
     the same quarter octave of n, returns the cached decision at once."""
     with kde.Context(0) as c:
         t0 = time.perf_counter()
@@ -58,10 +58,10 @@ def test_autotune_choice_and_cache(kde):
     assert set(rates) == set(kde.TUNE_VARIANTS)
     assert all(v > 1e11 for v in rates.values())
     assert all(parity.values())
-    # the default is kept unless another variant is 2% faster
+    # the default is kept unless another variant is 3% faster
     assert rates[choice] >= rates[(16, 512)]
     if choice != (16, 512):
-        assert rates[choice] > 1.02 * rates[(16, 512)]
+        assert rates[choice] > 1.03 * rates[(16, 512)]
     assert again == (choice, rates, parity) and near == (choice, rates, parity)
     assert t2 - t1 < 0.05
 
