@@ -141,21 +141,24 @@ __device__ __forceinline__ double herm_w64<8>(double w) {
   return __builtin_fma(p, w, 105.0);
 }
 
-// He_r(0) for the kernel-derivative value K^(r)(0) = He_r(0) / sqrt(2 pi).
+// He_r(0) = (-1)^(r/2) (r-1)!! for even r, from the recurrence
+// He_{k+1}(0) = -k He_{k-1}(0) with He_0(0) = 1: the kernel-derivative value
+// K^(r)(0) = He_r(0) / sqrt(2 pi) (r = 4, 6, 8) and the normal-scale
+// functionals below (r = 8, 10).
 __device__ __forceinline__ double herm_at0(int r) {
-  return r == 4 ? 3.0 : (r == 6 ? -15.0 : (r == 8 ? 105.0 : 0.0));
+  double h = 1.0;
+  for (int k = 1; k < r; k += 2) h *= -(double)k;
+  return h;
 }
 
-// Normal-scale functional psi_r for N(0, sigma^2):
-// (-1)^(r/2) r! / ((2 sigma)^(r+1) (r/2)! sqrt(pi)); r = 8 gives 105 / (32 sqrt(pi) sigma^9).
+// Normal-scale functional psi_r of N(0, sigma^2): the integral of f^(r) f
+// for the normal density is He_r(0) / (2^(r/2+1) sqrt(pi) sigma^(r+1)) (the
+// convolution of two N(0, sigma^2) densities is N(0, 2 sigma^2), whose r-th
+// derivative at 0 is He_r(0) / (sqrt(2 pi) (sqrt(2) sigma)^(r+1))); r = 8
+// gives the printed 105 / (32 sqrt(pi) sigma^9).
 __device__ double psi_normal_scale(int r, double sigma) {
-  double num = 1.0, den = 1.0;
-  for (int k = 2; k <= r; ++k) num *= (double)k;
-  for (int k = 2; k <= r / 2; ++k) den *= (double)k;
-  const double sgn = ((r / 2) % 2 == 0) ? 1.0 : -1.0;
-  return sgn * num / (pow(2.0 * sigma, (double)(r + 1)) * den * sqrt(kPi));
+  return herm_at0(r) / (ldexp(1.0, r / 2 + 1) * sqrt(kPi) * pow(sigma, (double)(r + 1)));
 }
-
 
 // ------------------------------------------------------------------ statistics
 __device__ __forceinline__ double load_raw(const ColDesc& c, int i) {
