@@ -72,9 +72,9 @@ TRAFFIC_SOURCES = ("kde_internal.h", "kde_kernels.hip", "kde_runtime.hip")
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32_queue<16, 512>",
-    "sources_sha256": "96c16e97f2e78f2a21b4f50fd08d90366d558e4fc80a33fd046dc5c43d9078d0",
-    "fetch_bytes": 1.93965e+08,
-    "write_bytes": 1.15480e+09,
+    "sources_sha256": "74db5659364b20715f72fdc26c4921382fb5d252b913edb959b8af26b3eabb34",
+    "fetch_bytes": 1.73144e+08,
+    "write_bytes": 1.24963e+09,
 }
 
 

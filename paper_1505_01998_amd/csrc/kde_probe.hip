@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kProbeThreads) void k_issue(float a, float b, int i
 // The LSCV term mix: for a pair distance t and 16 bandwidth coefficients
 // c_k, e = exp2(t c_k), S1 += e, S2 += e e (one mul, one exp, one add, one
 // fma per term), then the next distance t + dt (one add per 16 terms).  With
-// t0 = dt = 0 every exponential is of zero.
+// t0 = dt = 0 every exponential is of zero.  Each term is issued in program
+// order behind a scheduling barrier, as in the LSCV sweep's inner loop.
 __global__ __launch_bounds__(kProbeThreads) void k_issue_mix(float t0, float dt, float c0, int iters,
                                                              float* __restrict__ out) {
   constexpr int HC = 16;
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_issue_mix(float t0, float dt,
         const float e = __builtin_amdgcn_exp2f(t * ck[k]);
         s1[k] += e;
         s2[k] = __builtin_fmaf(e, e, s2[k]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
