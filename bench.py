@@ -72,9 +72,9 @@ TRAFFIC_SOURCES = ("kde_internal.h", "kde_kernels.hip", "kde_runtime.hip")
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32_queue<16, 512>",
-    "sources_sha256": "74db5659364b20715f72fdc26c4921382fb5d252b913edb959b8af26b3eabb34",
-    "fetch_bytes": 1.73144e+08,
-    "write_bytes": 1.24963e+09,
+    "sources_sha256": "5271cd8e2b13ca261ab2f1f93d8fa3d57d87314954b43d51d6e86c30b93eced0",
+    "fetch_bytes": 1.71359e+08,
+    "write_bytes": 1.24511e+09,
 }
 
 

@@ -564,42 +564,50 @@ __global__ __launch_bounds__(kThreads) void k_lscv_prep(const ColDesc* __restric
   }
 }
 
+// Four consecutive j of a run (one float4 of the LDS tile) against the
+// lane's sample, for the HC bandwidths.  FIRST: the run's first pair starts
+// the plain sums (S1 = e, S2 = e e instead of adding them to zero: the same
+// values, as e is never -0), which saves clearing 2 HC registers per run.
+template <int HC, bool MASK, bool FIRST>
+__device__ __forceinline__ void lscv_quad(const float4 v, int jg, float xi, int i, const float (&ck)[HC],
+                                          float (&r1)[HC], float (&r2)[HC]) {
+  const float xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const float d = xi - xs[u];
+    float t = d * d;
+    if (MASK) t = (jg + u > i) ? t : kInfF;
+    // One term at a time, in program order: mul, exp2, then its two
+    // consumers.  A wave then holds one exponential in flight and waits on
+    // it while the SIMD's other waves issue plain instructions; measured on
+    // gfx950 this overlaps more of the transcendental unit's time than
+    // exponentials issued back to back (the compiler's own order, which
+    // also pairs them at pair boundaries): +1% at HC = 16, +13% at HC = 8.
+    // The barrier only fixes the order; the arithmetic and the summation
+    // order are unchanged.
+#pragma unroll
+    for (int k = 0; k < HC; ++k) {
+      const float e = __builtin_amdgcn_exp2f(t * ck[k]);
+      if (FIRST && u == 0) {
+        r1[k] = e;
+        r2[k] = e * e;
+      } else {
+        r1[k] += e;
+        r2[k] = __builtin_fmaf(e, e, r2[k]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 template <int HC, bool MASK>
 __device__ __forceinline__ void lscv_run(const float4* __restrict__ tile, int jl, int jg, float xi, int i,
                                          const float (&ck)[HC], float (&a1)[HC], float (&c1)[HC], float (&a2)[HC],
                                          float (&c2)[HC]) {
   float r1[HC], r2[HC];
-#pragma unroll
-  for (int k = 0; k < HC; ++k) {
-    r1[k] = 0.f;
-    r2[k] = 0.f;
-  }
-#pragma unroll 2
-  for (int q = 0; q < kRun / 4; ++q) {
-    const float4 v = tile[(jl >> 2) + q];
-    const float xs[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float d = xi - xs[u];
-      float t = d * d;
-      if (MASK) t = (jg + 4 * q + u > i) ? t : kInfF;
-      // One term at a time, in program order: mul, exp2, then its two
-      // consumers.  A wave then holds one exponential in flight and waits on
-      // it while the SIMD's other waves issue plain instructions; measured on
-      // gfx950 this overlaps more of the transcendental unit's time than
-      // exponentials issued back to back (the compiler's own order, which
-      // also pairs them at pair boundaries): +1% at HC = 16, +13% at HC = 8.
-      // The barrier only fixes the order; the arithmetic and the summation
-      // order are unchanged.
-#pragma unroll
-      for (int k = 0; k < HC; ++k) {
-        const float e = __builtin_amdgcn_exp2f(t * ck[k]);
-        r1[k] += e;
-        r2[k] = __builtin_fmaf(e, e, r2[k]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
+  lscv_quad<HC, MASK, true>(tile[jl >> 2], jg, xi, i, ck, r1, r2);
+#pragma unroll 3
+  for (int q = 1; q < kRun / 4; ++q) lscv_quad<HC, MASK, false>(tile[(jl >> 2) + q], jg + 4 * q, xi, i, ck, r1, r2);
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
     kahan_add(a1[k], c1[k], r1[k]);
