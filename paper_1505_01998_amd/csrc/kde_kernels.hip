@@ -23,11 +23,14 @@
 // when the block's partial sums are formed.
 //
 // Precision (mixed form).  Pair terms are FP32 (v_exp_f32).  Each lane sums
-// 64 consecutive j in plain FP32, then folds that run into a Kahan-
-// compensated FP32 accumulator.  Lane accumulators are converted to FP64 and
-// reduced across the wave (butterfly shuffles), the block (LDS, fixed order)
-// and the work items (a separate row-reduction kernel, fixed order), so the
-// result is deterministic and independent of scheduling.  The FP64 form
+// 64 consecutive j in plain FP32, then folds that run into an FP64
+// accumulator (the LSCV sweep: a conversion and an FP64 add, which issue at
+// the unpacked FP32 rate, half the cost of a compensated FP32 fold) or a
+// Kahan-compensated FP32 one (the psi pass, two sums per 64 pairs).  Lane
+// accumulators are reduced in FP64 across the wave (butterfly shuffles), the
+// block (LDS, fixed order) and the work items (a separate row-reduction
+// kernel, fixed order), so the result is deterministic and independent of
+// scheduling.  The FP64 form
 // computes every term and sum in FP64.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -602,16 +605,16 @@ __device__ __forceinline__ void lscv_quad(const float4 v, int jg, float xi, int 
 
 template <int HC, bool MASK>
 __device__ __forceinline__ void lscv_run(const float4* __restrict__ tile, int jl, int jg, float xi, int i,
-                                         const float (&ck)[HC], float (&a1)[HC], float (&c1)[HC], float (&a2)[HC],
-                                         float (&c2)[HC]) {
+                                         const float (&ck)[HC], double (&a1)[HC], double (&a2)[HC]) {
   float r1[HC], r2[HC];
   lscv_quad<HC, MASK, true>(tile[jl >> 2], jg, xi, i, ck, r1, r2);
 #pragma unroll 3
   for (int q = 1; q < kRun / 4; ++q) lscv_quad<HC, MASK, false>(tile[(jl >> 2) + q], jg + 4 * q, xi, i, ck, r1, r2);
+  // the run's sums into the lane's FP64 accumulators
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    kahan_add(a1[k], c1[k], r1[k]);
-    kahan_add(a2[k], c2[k], r2[k]);
+    a1[k] += (double)r1[k];
+    a2[k] += (double)r2[k];
   }
 }
 
@@ -636,11 +639,12 @@ __device__ __forceinline__ void lscv_unit_f32(const ColDesc* __restrict__ cols, 
   const float xi = (i < n) ? x[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
   const float* cc = c.c32 + u.chunk * HC;
-  float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
+  float ck[HC];
+  double a1[HC], a2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
     ck[k] = uniform_f32(cc[k]);
-    a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
+    a1[k] = a2[k] = 0.0;
   }
   for (int t0 = u.j_begin; t0 < u.j_end; t0 += TJ) {
     const int te = min(t0 + TJ, u.j_end);
@@ -650,17 +654,17 @@ __device__ __forceinline__ void lscv_unit_f32(const ColDesc* __restrict__ cols, 
     int js = max(t0, wave_i0);
     if (js < te) {
       if (js == wave_i0) {
-        lscv_run<HC, true>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
+        lscv_run<HC, true>(tile, js - t0, js, xi, i, ck, a1, a2);
         js += kRun;
       }
-      for (; js < te; js += kRun) lscv_run<HC, false>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
+      for (; js < te; js += kRun) lscv_run<HC, false>(tile, js - t0, js, xi, i, ck, a1, a2);
     }
   }
   const bool valid = i < n;
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    const double v1 = wave_sum(valid ? (double)a1[k] - (double)c1[k] : 0.0);
-    const double v2 = wave_sum(valid ? (double)a2[k] - (double)c2[k] : 0.0);
+    const double v1 = wave_sum(valid ? a1[k] : 0.0);
+    const double v2 = wave_sum(valid ? a2[k] : 0.0);
     if (lane == 0) {
       red[wave][2 * k] = v1;
       red[wave][2 * k + 1] = v2;
@@ -739,17 +743,18 @@ __global__ __launch_bounds__(kThreads) void k_lscv_ceiling(const float* __restri
   for (int q = tid; q < kBJ / 4; q += kThreads) tile[q] = reinterpret_cast<const float4*>(x)[q];
   __syncthreads();
   const float xi = x[tid] + 0.5f;
-  float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
+  float ck[HC];
+  double a1[HC], a2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
     ck[k] = uniform_f32(c32[k]);
-    a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
+    a1[k] = a2[k] = 0.0;
   }
   for (int r = 0; r < reps; ++r)
-    for (int js = 0; js < kBJ; js += kRun) lscv_run<HC, false>(tile, js, js, xi, 0, ck, a1, c1, a2, c2);
+    for (int js = 0; js < kBJ; js += kRun) lscv_run<HC, false>(tile, js, js, xi, 0, ck, a1, a2);
   double v = 0.0;
 #pragma unroll
-  for (int k = 0; k < HC; ++k) v += ((double)a1[k] - (double)c1[k]) + ((double)a2[k] - (double)c2[k]);
+  for (int k = 0; k < HC; ++k) v += (a1[k]) + (a2[k]);
   v = wave_sum(v);
   if ((tid & 63) == 0) out[(int64_t)blockIdx.x * (kThreads / 64) + (tid >> 6)] = v;
 }
@@ -789,11 +794,12 @@ void k_lscv_units_prune(const ColDesc* __restrict__ cols, const Unit* __restrict
   const float xi = (i < n) ? x[i] : 0.f;
   const int wave_i0 = row0 + wave * 64;
   const float* cc = c.c32 + u.chunk * HC;
-  float ck[HC], a1[HC], c1[HC], a2[HC], c2[HC];
+  float ck[HC];
+  double a1[HC], a2[HC];
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
     ck[k] = uniform_f32(cc[k]);
-    a1[k] = c1[k] = a2[k] = c2[k] = 0.f;
+    a1[k] = a2[k] = 0.0;
   }
   for (int t0 = u.j_begin; t0 < j_end; t0 += kBJ) {
     __syncthreads();
@@ -803,10 +809,10 @@ void k_lscv_units_prune(const ColDesc* __restrict__ cols, const Unit* __restrict
     const int te = t0 + kBJ;
     if (js < te) {
       if (js == wave_i0) {
-        lscv_run<HC, true>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
+        lscv_run<HC, true>(tile, js - t0, js, xi, i, ck, a1, a2);
         js += kRun;
       }
-      for (; js < te; js += kRun) lscv_run<HC, false>(tile, js - t0, js, xi, i, ck, a1, c1, a2, c2);
+      for (; js < te; js += kRun) lscv_run<HC, false>(tile, js - t0, js, xi, i, ck, a1, a2);
     }
   }
   if (tid == 0 && j_end < u.j_end && j_end < n) {
@@ -818,8 +824,8 @@ void k_lscv_units_prune(const ColDesc* __restrict__ cols, const Unit* __restrict
   const bool valid = i < n;
 #pragma unroll
   for (int k = 0; k < HC; ++k) {
-    const double v1 = wave_sum(valid ? (double)a1[k] - (double)c1[k] : 0.0);
-    const double v2 = wave_sum(valid ? (double)a2[k] - (double)c2[k] : 0.0);
+    const double v1 = wave_sum(valid ? a1[k] : 0.0);
+    const double v2 = wave_sum(valid ? a2[k] : 0.0);
     if (lane == 0) {
       red[wave][2 * k] = v1;
       red[wave][2 * k + 1] = v2;
