@@ -702,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_units_f32(const ColDesc* __re
 // launch covers a whole pass; the longest units start first wherever a
 // block frees up.  next[0 .. kQueueGroups) must be 0 at launch.
 template <int HC, int TJ>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 1))) void
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 2))) void
 k_lscv_units_f32_queue(const ColDesc* __restrict__ cols, const Unit* __restrict__ units,
                        const int* __restrict__ group_begin, int* __restrict__ next) {
   __shared__ float4 tile[TJ / 4];
@@ -766,7 +766,7 @@ __global__ __launch_bounds__(kThreads) void k_lscv_ceiling(const float* __restri
 // tile is farther still); the sweep stops there and the skipped pairs are
 // counted exactly.
 template <int HC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 1)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HC <= 16 ? 4 : 2)))
 void k_lscv_units_prune(const ColDesc* __restrict__ cols, const Unit* __restrict__ units, int u0) {
   const Unit u = units[u0 + blockIdx.x];
   const ColDesc c = cols[u.col];
