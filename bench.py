@@ -177,7 +177,38 @@ def cpu_baseline(w, x, budget_s: float):
         "kind": "oracle",
         "sample": f"LSCV g(h) over the full {w.grid.size}-point grid on the first {n_s} samples "
                   f"of the {w.name} column ({evals:.3e} evals, {dt:.1f} s)",
+        "plain_1k": plain_1k_oracle_times(),
     }
+
+
+def plain_1k_oracle_times(reps: int = 3):
+    """The whole method on the CPU-sized workload (n = 1,000: rule of thumb,
+    two-stage plug-in, LSCV over 100 h and its argmin) by the oracle, on one
+    core and on all of them (mean seconds of `reps` runs)."""
+    import oracle
+
+    w = workloads.workload("plain-1k")
+    x = w.column()
+
+    def run():
+        oracle.bw_rot(x)
+        oracle.bw_plugin(x, w.stages)
+        oracle.argmin(oracle.lscv_curve(x, w.grid).g)
+
+    all_cores = oracle.num_threads()
+    out = {}
+    try:
+        for tag, t in (("one_core_s", 1), ("all_cores_s", all_cores)):
+            oracle.set_threads(t)
+            run()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                run()
+            out[tag] = (time.perf_counter() - t0) / reps
+    finally:
+        oracle.set_threads(all_cores)
+    out["cores"] = all_cores
+    return out
 
 
 def _requests_of(kde, cols, grid=None, stages=None):
