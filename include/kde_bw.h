@@ -224,10 +224,12 @@ kde_status kde_autotune(kde_ctx* ctx, int64_t n, int32_t n_h, kde_tune_info* out
 /* Measures the ceiling of the LSCV sweep's inner loop on this device: the
  * kernel's own per-(pair, h) code (Section 4.5: the pair distance formed once
  * and reused for hc bandwidths; FP32 exp2, S1 add, S2 fma, 64-term runs
- * folded with compensation) repeated over one LDS tile staged once, without
- * tile staging, barriers, masks or partial-sum writes.  *evals_per_s
- * receives its pair-term evaluations per second (one ~0.1 s launch, timed
- * with events on the context's stream).  The rate bounds what the sweep can
+ * folded into FP64) repeated over one LDS tile staged once, without tile
+ * staging, barriers, masks or partial-sum writes.  *evals_per_s receives its
+ * pair-term evaluations per second: launches of R and 2R repetitions (~0.1
+ * and ~0.25 s) timed with events on the context's stream, the rate taken
+ * over the extra R of the second so that launch start and drain cancel.
+ * The rate bounds what the sweep can
  * reach with this instruction mix.  It measures the mixed form's kernel
  * whatever the context's precision.  KDE_E_INVAL for hc other than 8, 16,
  * 32; KDE_E_BUSY while a server runs. */
