@@ -309,6 +309,11 @@ def batch_bench(args):
         "columns_per_s": len(specs) / t_batch,
         "plain": {"columns_per_s": len(specs) / t_plain, "value": evals / t_plain, "seconds": t_plain},
         "speedup_vs_plain": t_plain / t_batch,
+        # plug-in stages whose pair sum was re-taken in FP64 (condition number
+        # above the fp64_kappa threshold), of columns x stages
+        "psi_fp64_reruns": {"stages": sum(1 for r in out for p in r.plugin.precision_used if p == kde.KDE_PREC_FP64),
+                            "columns": sum(1 for r in out if kde.KDE_PREC_FP64 in r.plugin.precision_used),
+                            "of_stages": len(out) * workloads.BATCH_STAGES, "of_columns": len(out)},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": LSCV_PEAK / 1e12, "unit": "Teval/s",
                      "frac": achieved / LSCV_PEAK, "traffic": None, "kernel": kernel,
                      "launches": launches, "avg_launch_ms": ms / max(launches, 1)},
