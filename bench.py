@@ -72,9 +72,9 @@ TRAFFIC_SOURCES = ("kde_internal.h", "kde_kernels.hip", "kde_runtime.hip")
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32_queue<16, 512>",
-    "sources_sha256": "14376e246c8798ad63870272e51f86c3877da4bb2fd3091bd270b25ace8452b3",
-    "fetch_bytes": 1.72349e+08,
-    "write_bytes": 1.16429e+09,
+    "sources_sha256": "d462ae2cbb7874bd9cf4754900d7e0e944db7ed762f9d99951f83be9f39be7b6",
+    "fetch_bytes": 1.71920e+08,
+    "write_bytes": 1.14624e+09,
 }
 
 

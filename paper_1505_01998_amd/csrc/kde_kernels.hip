@@ -586,10 +586,14 @@ __device__ __forceinline__ void lscv_quad(const float4 v, int jg, float xi, int 
     // gfx950 this overlaps more of the transcendental unit's time than
     // exponentials issued back to back (the compiler's own order, which
     // also pairs them at pair boundaries): +1% at HC = 16, +13% at HC = 8.
-    // The barrier only fixes the order; the arithmetic and the summation
-    // order are unchanged.
+    // The wave raises its issue priority from the exponential until both
+    // consumers have issued, so that a wave whose exponential has completed
+    // goes ahead of waves starting a new term: +8% at HC = 16, +10% at
+    // HC = 8.  The barrier and the priority only fix the order of issue;
+    // the arithmetic and the summation order are unchanged.
 #pragma unroll
     for (int k = 0; k < HC; ++k) {
+      __builtin_amdgcn_s_setprio(1);
       const float e = __builtin_amdgcn_exp2f(t * ck[k]);
       if (FIRST && u == 0) {
         r1[k] = e;
@@ -598,6 +602,7 @@ __device__ __forceinline__ void lscv_quad(const float4 v, int jg, float xi, int 
         r1[k] += e;
         r2[k] = __builtin_fmaf(e, e, r2[k]);
       }
+      __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_sched_barrier(0);
     }
   }

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(kProbeThreads) void k_issue(float a, float b, int i
 // c_k, e = exp2(t c_k), S1 += e, S2 += e e (one mul, one exp, one add, one
 // fma per term), then the next distance t + dt (one add per 16 terms).  With
 // t0 = dt = 0 every exponential is of zero.  Each term is issued in program
-// order behind a scheduling barrier, as in the LSCV sweep's inner loop.
+// order behind a scheduling barrier, with the wave's priority raised from the
+// exponential to its consumers, as in the LSCV sweep's inner loop.
 __global__ __launch_bounds__(kProbeThreads) void k_issue_mix(float t0, float dt, float c0, int iters,
                                                              float* __restrict__ out) {
   constexpr int HC = 16;
@@ -78,9 +79,11 @@ __global__ __launch_bounds__(kProbeThreads) void k_issue_mix(float t0, float dt,
       t = t + dt;
 #pragma unroll
       for (int k = 0; k < HC; ++k) {
+        __builtin_amdgcn_s_setprio(1);
         const float e = __builtin_amdgcn_exp2f(t * ck[k]);
         s1[k] += e;
         s2[k] = __builtin_fmaf(e, e, s2[k]);
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
