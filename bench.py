@@ -72,7 +72,7 @@ TRAFFIC_SOURCES = ("kde_internal.h", "kde_kernels.hip", "kde_runtime.hip")
 MEASURED_TRAFFIC = {
     "workload": "lognormal-1m",
     "kernel": "k_lscv_units_f32_queue<16, 512>",
-    "sources_sha256": "d462ae2cbb7874bd9cf4754900d7e0e944db7ed762f9d99951f83be9f39be7b6",
+    "sources_sha256": "331fd9f42e6a0e5f0ee7c45868e630c3797f1e1b5cea1f62cb8610dc8401afd6",
     "fetch_bytes": 1.71920e+08,
     "write_bytes": 1.14624e+09,
 }

@@ -404,10 +404,14 @@ __device__ __forceinline__ void psi_run(const float4* __restrict__ tile, int jl,
       float w = d * d;
       if (CLAMP) w = fminf(w, kWMax);
       if (MASK) w = (jg + 4 * q + u > i) ? w : kWMax;
+      // issue priority raised from the exponential to its two consumers,
+      // as in the LSCV sweep (order of issue only; +29% on this pass)
+      __builtin_amdgcn_s_setprio(1);
       const float e = __builtin_amdgcn_exp2f(w * kPsiExp2);
       const float hw = herm_w<R>(w);
       rs = __builtin_fmaf(hw, e, rs);
       ra = __builtin_fmaf(fabsf(hw), e, ra);
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   kahan_add(aS, cS, rs);
